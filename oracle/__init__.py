@@ -1,0 +1,25 @@
+"""Plain CPU FP64 oracle of the HHG P1 multigrid hot path.
+
+TEST INFRASTRUCTURE ONLY.  Nothing in the product library imports, links or
+calls this package; only the tests, the smoke check and the benchmark's CPU
+baseline leg use it.  It shares no code with the HIP path.
+
+It works on one global vector per level (every micro-vertex once, in the
+canonical order) with sparse matrices assembled element by element, which is
+the plain definition of what the structured, ghost-layered, matrix-free HIP
+path computes:
+
+  mesh.py       macro mesh -> refined levels, canonical numbering (paper
+                sec. 2.1, 3.1, 3.2)
+  assemble.py   P1 stiffness / mass matrices from element matrices (sec. 4.1,
+                4.2: a stencil is a row of the stiffness matrix)
+  mg.py         staged multicolour Gauss-Seidel, residual, restriction,
+                prolongation, Jacobi-PCG coarse solve, V-cycle, solve loop
+                (sec. 4.3)
+  pointwise.py  one-row-at-a-time evaluation for sampled checks at full size
+  net.py        the learned smoother's forward/backward (not in the paper)
+
+Parity status of each function is stated in its docstring; functions with no
+independent pin say "parity unpinned".
+"""
+from .mesh import MacroMesh, Level  # noqa: F401
