@@ -1,0 +1,253 @@
+/*
+ * hhg.h - C ABI of the MI355X (gfx950) hierarchical-hybrid-grid P1 multigrid
+ * library.
+ *
+ * The method (Kohl et al., "A Scalable and Modular Software Architecture for
+ * Finite Elements on Hierarchical Hybrid Grids"):
+ *   - an unstructured triangular macro mesh is turned into a graph of
+ *     macro-vertices, macro-edges and macro-faces (sec. 2.1);
+ *   - every macro-face is refined uniformly by joining edge midpoints, so a
+ *     macro-edge at level l carries n = 2^l + 1 micro-vertices (sec. 1.1, 3.1);
+ *   - each unknown is owned by exactly one primitive; neighbours keep
+ *     read-only ghost copies that are refreshed by communication along the
+ *     primitive graph, the higher-dimensional primitive fixing the order
+ *     (sec. 2.2, 2.4, 3.3);
+ *   - the operator is applied matrix-free with one constant stencil per
+ *     primitive, vertices then edges then faces (sec. 4.2, Alg. 3);
+ *   - geometric multigrid on the nested levels with pointwise smoothers,
+ *     grid transfers and a Krylov coarse solver (sec. 4.3).
+ *
+ * Conventions shared by every call:
+ *   - Return value: HHG_OK (0) or a negative HHG_E* code; the thread-local
+ *     text of the last error is returned by hhg_last_error().
+ *   - Ownership: the library owns the opaque hhg_mesh and its host metadata.
+ *     The caller owns every device buffer (fields and the workspace) and
+ *     every stream; the library only borrows device pointers, which must stay
+ *     valid until the work enqueued on the stream has finished.  The library
+ *     never allocates or frees device memory.
+ *   - Streams: `stream` is a hipStream_t (NULL = the default stream).  Calls
+ *     enqueue work and return, except hhg_solve, which synchronises the
+ *     stream once per iteration to read an 8-byte residual norm.
+ *   - Concurrency: one mesh object is not thread-safe; separate meshes are
+ *     independent.  Calls sharing one bound workspace must not overlap.
+ *   - Fields: a field of level l is a device array of hhg_field_elems()
+ *     elements of the chosen dtype in the library's level layout (faces,
+ *     then edges, then vertices, each with its ghost copies).  Only the
+ *     conversion calls hhg_from_canonical / hhg_to_canonical relate it to the
+ *     canonical order.
+ *   - Canonical order of level l: macro-vertices by id; then macro-edges
+ *     sorted by (lower vertex id, higher vertex id), each with its interior
+ *     points k = 1..n-2 counted from the lower vertex; then macro-faces in
+ *     input order, each with its interior points (i, j), j = 1..n-3,
+ *     i = 1..n-2-j, j-major, where face-local point (i, j) sits at
+ *     x0 + i/(n-1) (x1 - x0) + j/(n-1) (x2 - x0) after the face has been
+ *     made counter-clockwise (vertices 2 and 3 swapped if needed).
+ *   - Dirichlet data: every macro-edge with a single adjacent face, and its
+ *     two vertices, is a Dirichlet boundary.  Entries of u at Dirichlet
+ *     points hold the boundary values; they are read, never written.
+ */
+#ifndef HHG_H
+#define HHG_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* status codes */
+#define HHG_OK        0
+#define HHG_EINVAL   -1   /* bad argument, level, mesh, op or dtype        */
+#define HHG_ENOMEM   -2   /* workspace missing, too small or unbound        */
+#define HHG_EHIP     -3   /* HIP runtime error (message holds its text)     */
+#define HHG_ENOTCONV -4   /* iteration cap or divergence; stats are filled  */
+
+/* element types of fields */
+#define HHG_F64  0
+#define HHG_F32  1
+#define HHG_BF16 2
+
+/* operators */
+#define HHG_OP_LAPLACE   0   /* -div grad, P1 stiffness (k = 1)              */
+#define HHG_OP_DIFFUSION 1   /* -div(k grad), k from hhg_set_coefficient     */
+#define HHG_OP_MASS      2   /* P1 consistent mass matrix                    */
+
+/* smoothers */
+#define HHG_SMOOTH_GS  0     /* staged multicolour Gauss-Seidel              */
+#define HHG_SMOOTH_NET 1     /* learned face smoother (GS on edges/vertices) */
+
+/* workspace feature bits */
+#define HHG_FEAT_F64  1u     /* FP64 multigrid hierarchy                     */
+#define HHG_FEAT_MP   2u     /* FP32 hierarchy for mixed-precision refinement */
+#define HHG_FEAT_VARK 4u     /* per-level coefficient fields                 */
+#define HHG_FEAT_NET  8u     /* learned-smoother buffers                     */
+
+/* solver modes */
+#define HHG_MODE_PLAIN_FP64 0
+#define HHG_MODE_MP_IR      1
+#define HHG_MODE_LEARNED    2
+
+typedef struct hhg_mesh hhg_mesh;
+
+typedef struct {
+    int32_t mode;              /* HHG_MODE_*                                  */
+    int32_t op;                /* HHG_OP_LAPLACE or HHG_OP_DIFFUSION          */
+    double rtol;               /* stop when |f - A u| <= rtol |f - A u0|      */
+    int32_t max_iters;         /* cycle (or refinement step) cap              */
+    int32_t nu1, nu2;          /* pre- and post-smoothing sweeps              */
+    double* res_history;       /* optional host buffer for |r_k|, k = 0..     */
+    int32_t history_capacity;  /* entries available in res_history           */
+} hhg_solve_opts;
+
+typedef struct {
+    int32_t iters;             /* V-cycles (or refinement steps) done         */
+    int32_t converged;         /* 1 if rtol was reached                       */
+    int32_t smoother_used;     /* HHG_SMOOTH_* actually used                  */
+    int32_t fallback;          /* 1 if the learned smoother was dropped       */
+    double res0;               /* |f - A u0| over interior points             */
+    double rel_res;            /* final |f - A u| / res0                      */
+    double ms;                 /* host wall time of the call                  */
+} hhg_solve_stats;
+
+/* Text of the last error raised on the calling thread ("" if none). */
+const char* hhg_last_error(void);
+
+/*
+ * Build the macro-primitive graph (sec. 2.1) and the refinement layouts of
+ * levels 1..max_level (sec. 3.1, 3.2).
+ *   vxy[2*n_vertices]  host, vertex coordinates (x, y), read during the call
+ *   tri[3*n_faces]     host, vertex ids of each triangle; clockwise faces are
+ *                      reoriented
+ *   coarse_level       multigrid coarsest level, 1 <= coarse_level <= max_level
+ *   max_level          finest level, 1 <= max_level <= 12
+ *   out                receives the new mesh; destroy with hhg_destroy_mesh
+ * Errors: HHG_EINVAL for zero-area faces, an edge with more than two faces,
+ * out-of-range ids or levels, or a vertex with more than 16 edges.
+ */
+int hhg_setup_mesh(const double* vxy, int32_t n_vertices, const int32_t* tri,
+                   int32_t n_faces, int32_t max_level, int32_t coarse_level,
+                   hhg_mesh** out);
+
+/* Free a mesh (NULL is allowed).  Device buffers are the caller's. */
+void hhg_destroy_mesh(hhg_mesh* mesh);
+
+/*
+ * Bytes of device workspace needed for a set of HHG_FEAT_* features: index
+ * and geometry tables, the coarse-level fields of the hierarchy and solver
+ * scratch.  *bytes receives the size.
+ */
+int hhg_workspace_bytes(const hhg_mesh* mesh, uint32_t features, size_t* bytes);
+
+/*
+ * Bind a caller-owned device buffer of at least hhg_workspace_bytes(features)
+ * bytes (256-byte aligned) and upload the tables into it on `stream`.  The
+ * buffer must stay alive and unused by the caller while the mesh uses it.
+ * Errors: HHG_ENOMEM if bytes is too small, HHG_EHIP on a failed upload.
+ */
+int hhg_bind_workspace(hhg_mesh* mesh, uint32_t features, void* dptr,
+                       size_t bytes, void* stream);
+
+/* Number of elements of one field of `level` in the library layout. */
+int hhg_field_elems(const hhg_mesh* mesh, int32_t level, int64_t* n);
+
+/* Interior (non-Dirichlet) and all canonical points of `level`. */
+int hhg_n_dofs(const hhg_mesh* mesh, int32_t level, int64_t* n_interior,
+               int64_t* n_all);
+
+/*
+ * Canonical micro-vertex coordinates of `level` into the host buffer
+ * xy[2*n_all] (edge points on the straight macro-edge, face points by the
+ * affine face map; sec. 3.1).
+ */
+int hhg_coords(const hhg_mesh* mesh, int32_t level, double* xy);
+
+/*
+ * Layout conversion (sec. 3.2: the indexing function maps the topological
+ * enumeration to memory).  `canon` is a device array of n_all values of
+ * `dtype`; `field` a device field of the same dtype.  from_canonical writes
+ * every owned value and every ghost copy; to_canonical reads owned values.
+ */
+int hhg_from_canonical(const hhg_mesh* mesh, int32_t level, int32_t dtype,
+                       const void* canon, void* field, void* stream);
+int hhg_to_canonical(const hhg_mesh* mesh, int32_t level, int32_t dtype,
+                     const void* field, void* canon, void* stream);
+
+/*
+ * Nodal coefficient k > 0 of -div(k grad u) at the finest level, a device
+ * array of n_all(max_level) doubles in canonical order.  Coarser levels take
+ * it by injection.  Needs a workspace bound with HHG_FEAT_VARK.  Enables
+ * HHG_OP_DIFFUSION (on-the-fly stencils, paper sec. 1.1 and 4.2).
+ */
+int hhg_set_coefficient(hhg_mesh* mesh, const double* k_canon, void* stream);
+
+/*
+ * y = A x on `level` (Alg. 3, sec. 4.2): interior rows get the stencil
+ * result, Dirichlet rows are set to 0; all ghost copies of y are refreshed.
+ * x and y are fields of `dtype` (F64 or F32); x must have consistent ghosts
+ * (every library call leaves them so).  x and y must not alias.
+ */
+int hhg_apply(const hhg_mesh* mesh, int32_t level, int32_t op, int32_t dtype,
+              const void* x, void* y, void* stream);
+
+/*
+ * r = f - A u on interior points (0 on Dirichlet points) into field r, and
+ * optionally |r|_2 over interior points (each unknown once, sec. 4.1 Alg. 2)
+ * into the device double *norm (NULL to skip).
+ */
+int hhg_residual(const hhg_mesh* mesh, int32_t level, int32_t op, int32_t dtype,
+                 const void* u, const void* f, void* r, double* norm,
+                 void* stream);
+
+/*
+ * `sweeps` Gauss-Seidel sweeps on `level` (sec. 2.4, 3.2, 4.3): stages
+ * A = macro-vertices and even-k edge points, B = odd-k edge points, then the
+ * face colours, each stage updated at once; backward != 0 reverses the
+ * stage order.  u (in/out) and f are fields of `dtype`.
+ * smoother HHG_SMOOTH_NET replaces the face stages by the learned smoother.
+ */
+int hhg_smooth(const hhg_mesh* mesh, int32_t level, int32_t op,
+               int32_t smoother, int32_t dtype, void* u, const void* f,
+               int32_t sweeps, int32_t backward, void* stream);
+
+/*
+ * One V(nu1, nu2) cycle from `level` down to the coarse level (sec. 4.3):
+ * nu1 forward sweeps, residual and restriction (transpose of linear
+ * interpolation), recursion with zero initial guess, linear prolongation and
+ * correction, nu2 backward sweeps; Jacobi-PCG on the coarse level.  Uses the
+ * bound workspace for coarse fields (HHG_FEAT_F64 for dtype F64, HHG_FEAT_MP
+ * for F32).
+ */
+int hhg_vcycle(const hhg_mesh* mesh, int32_t level, int32_t op,
+               int32_t smoother, int32_t dtype, void* u, const void* f,
+               int32_t nu1, int32_t nu2, void* stream);
+
+/*
+ * Solve A u = f on the finest level to a relative residual opts->rtol
+ * (sec. 4.3: multigrid as a solver).  u, f are FP64 fields; u holds the
+ * initial guess and the Dirichlet values.  Modes: plain FP64 V-cycles;
+ * mixed-precision iterative refinement (FP64 residual and update, FP32
+ * V-cycle on the correction, FP64 coarse CG); learned smoother inside the
+ * mixed-precision loop with Gauss-Seidel fallback.  Returns HHG_ENOTCONV if
+ * max_iters is reached or the residual stops decreasing; stats are filled in
+ * every case.
+ */
+int hhg_solve(hhg_mesh* mesh, const hhg_solve_opts* opts, void* u,
+              const void* f, hhg_solve_stats* stats, void* stream);
+
+/*
+ * Per-kernel timing of the finest-level smoother launches, for profiling:
+ * enable != 0 records a HIP event pair around every finest-level face
+ * smoother launch on its stream; hhg_timing_read returns the number of
+ * launches and their summed duration in ms since the last reset (it
+ * synchronises the recorded events).  Disabled by default.
+ */
+int hhg_timing_enable(hhg_mesh* mesh, int32_t enable);
+int hhg_timing_read(hhg_mesh* mesh, int64_t* launches, double* total_ms,
+                    int32_t reset);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* HHG_H */

@@ -1,0 +1,217 @@
+"""ctypes binding of libhhg.so: the C ABI declared in include/hhg.h.
+
+Argument marshalling only: every computation runs in the HIP library.  Device
+buffers are torch tensors (or raw integer pointers); streams default to the
+current torch stream.  Every call raises HHGError on a non-zero status.
+"""
+import ctypes
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libhhg.so")
+
+HHG_OK, HHG_EINVAL, HHG_ENOMEM, HHG_EHIP, HHG_ENOTCONV = 0, -1, -2, -3, -4
+HHG_F64, HHG_F32, HHG_BF16 = 0, 1, 2
+HHG_OP_LAPLACE, HHG_OP_DIFFUSION, HHG_OP_MASS = 0, 1, 2
+HHG_SMOOTH_GS, HHG_SMOOTH_NET = 0, 1
+HHG_FEAT_F64, HHG_FEAT_MP, HHG_FEAT_VARK, HHG_FEAT_NET = 1, 2, 4, 8
+HHG_MODE_PLAIN_FP64, HHG_MODE_MP_IR, HHG_MODE_LEARNED = 0, 1, 2
+
+_c = ctypes
+_vp = _c.c_void_p
+_i32 = _c.c_int32
+_i64 = _c.c_int64
+
+
+class hhg_solve_opts(_c.Structure):
+    _fields_ = [("mode", _i32), ("op", _i32), ("rtol", _c.c_double), ("max_iters", _i32),
+                ("nu1", _i32), ("nu2", _i32), ("res_history", _c.POINTER(_c.c_double)),
+                ("history_capacity", _i32)]
+
+
+class hhg_solve_stats(_c.Structure):
+    _fields_ = [("iters", _i32), ("converged", _i32), ("smoother_used", _i32),
+                ("fallback", _i32), ("res0", _c.c_double), ("rel_res", _c.c_double),
+                ("ms", _c.c_double)]
+
+
+# name -> (restype, argtypes); restype int unless stated
+_SIGS = {
+    "hhg_last_error": (_c.c_char_p, []),
+    "hhg_setup_mesh": (_c.c_int, [_vp, _i32, _vp, _i32, _i32, _i32, _c.POINTER(_vp)]),
+    "hhg_destroy_mesh": (None, [_vp]),
+    "hhg_workspace_bytes": (_c.c_int, [_vp, _c.c_uint32, _c.POINTER(_c.c_size_t)]),
+    "hhg_bind_workspace": (_c.c_int, [_vp, _c.c_uint32, _vp, _c.c_size_t, _vp]),
+    "hhg_field_elems": (_c.c_int, [_vp, _i32, _c.POINTER(_i64)]),
+    "hhg_n_dofs": (_c.c_int, [_vp, _i32, _c.POINTER(_i64), _c.POINTER(_i64)]),
+    "hhg_coords": (_c.c_int, [_vp, _i32, _vp]),
+    "hhg_from_canonical": (_c.c_int, [_vp, _i32, _i32, _vp, _vp, _vp]),
+    "hhg_to_canonical": (_c.c_int, [_vp, _i32, _i32, _vp, _vp, _vp]),
+    "hhg_set_coefficient": (_c.c_int, [_vp, _vp, _vp]),
+    "hhg_apply": (_c.c_int, [_vp, _i32, _i32, _i32, _vp, _vp, _vp]),
+    "hhg_residual": (_c.c_int, [_vp, _i32, _i32, _i32, _vp, _vp, _vp, _vp, _vp]),
+    "hhg_smooth": (_c.c_int, [_vp, _i32, _i32, _i32, _i32, _vp, _vp, _i32, _i32, _vp]),
+    "hhg_vcycle": (_c.c_int, [_vp, _i32, _i32, _i32, _i32, _vp, _vp, _i32, _i32, _vp]),
+    "hhg_solve": (_c.c_int, [_vp, _c.POINTER(hhg_solve_opts), _vp, _vp,
+                             _c.POINTER(hhg_solve_stats), _vp]),
+    "hhg_timing_enable": (_c.c_int, [_vp, _i32]),
+    "hhg_timing_read": (_c.c_int, [_vp, _c.POINTER(_i64), _c.POINTER(_c.c_double), _i32]),
+}
+
+_lib = None
+
+
+def lib():
+    """Load libhhg.so (fails loudly if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError("libhhg.so is not built; run `python -m paper_1805_10167_amd.build`")
+        L = _c.CDLL(LIB_PATH)
+        for name, (res, args) in _SIGS.items():
+            fn = getattr(L, name)
+            fn.restype = res
+            fn.argtypes = args
+        _lib = L
+    return _lib
+
+
+class HHGError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__("HHG error %d: %s" % (code, msg))
+        self.code = code
+
+
+def _check(rc):
+    if rc != HHG_OK:
+        raise HHGError(rc, lib().hhg_last_error().decode())
+    return rc
+
+
+def _ptr(x):
+    """Device/host pointer of a torch tensor, numpy array, int or None."""
+    if x is None:
+        return None
+    if isinstance(x, int):
+        return x
+    if isinstance(x, np.ndarray):
+        return x.ctypes.data
+    return x.data_ptr()
+
+
+def _stream(stream):
+    if stream is None:
+        import torch
+        return torch.cuda.current_stream().cuda_stream
+    if isinstance(stream, int):
+        return stream
+    return stream.cuda_stream
+
+
+# ---------------------------------------------------------------- raw calls
+
+def hhg_last_error():
+    return lib().hhg_last_error().decode()
+
+
+def hhg_setup_mesh(vxy, tri, max_level, coarse_level):
+    vxy = np.ascontiguousarray(vxy, dtype=np.float64)
+    tri = np.ascontiguousarray(tri, dtype=np.int32)
+    h = _vp()
+    _check(lib().hhg_setup_mesh(vxy.ctypes.data, len(vxy), tri.ctypes.data, len(tri),
+                                max_level, coarse_level, _c.byref(h)))
+    return h.value
+
+
+def hhg_destroy_mesh(h):
+    lib().hhg_destroy_mesh(h)
+
+
+def hhg_workspace_bytes(h, features):
+    n = _c.c_size_t()
+    _check(lib().hhg_workspace_bytes(h, features, _c.byref(n)))
+    return n.value
+
+
+def hhg_bind_workspace(h, features, ws, nbytes=None, stream=None):
+    if nbytes is None:
+        nbytes = ws.numel() * ws.element_size()
+    _check(lib().hhg_bind_workspace(h, features, _ptr(ws), nbytes, _stream(stream)))
+
+
+def hhg_field_elems(h, level):
+    n = _i64()
+    _check(lib().hhg_field_elems(h, level, _c.byref(n)))
+    return n.value
+
+
+def hhg_n_dofs(h, level):
+    a, b = _i64(), _i64()
+    _check(lib().hhg_n_dofs(h, level, _c.byref(a), _c.byref(b)))
+    return a.value, b.value
+
+
+def hhg_coords(h, level):
+    _, n_all = hhg_n_dofs(h, level)
+    xy = np.empty((n_all, 2), dtype=np.float64)
+    _check(lib().hhg_coords(h, level, xy.ctypes.data))
+    return xy
+
+
+def hhg_from_canonical(h, level, dtype, canon, field, stream=None):
+    _check(lib().hhg_from_canonical(h, level, dtype, _ptr(canon), _ptr(field), _stream(stream)))
+
+
+def hhg_to_canonical(h, level, dtype, field, canon, stream=None):
+    _check(lib().hhg_to_canonical(h, level, dtype, _ptr(field), _ptr(canon), _stream(stream)))
+
+
+def hhg_set_coefficient(h, k_canon, stream=None):
+    _check(lib().hhg_set_coefficient(h, _ptr(k_canon), _stream(stream)))
+
+
+def hhg_apply(h, level, op, dtype, x, y, stream=None):
+    _check(lib().hhg_apply(h, level, op, dtype, _ptr(x), _ptr(y), _stream(stream)))
+
+
+def hhg_residual(h, level, op, dtype, u, f, r, norm=None, stream=None):
+    _check(lib().hhg_residual(h, level, op, dtype, _ptr(u), _ptr(f), _ptr(r), _ptr(norm),
+                              _stream(stream)))
+
+
+def hhg_smooth(h, level, op, smoother, dtype, u, f, sweeps=1, backward=0, stream=None):
+    _check(lib().hhg_smooth(h, level, op, smoother, dtype, _ptr(u), _ptr(f), sweeps,
+                            int(backward), _stream(stream)))
+
+
+def hhg_vcycle(h, level, op, smoother, dtype, u, f, nu1, nu2, stream=None):
+    _check(lib().hhg_vcycle(h, level, op, smoother, dtype, _ptr(u), _ptr(f), nu1, nu2,
+                            _stream(stream)))
+
+
+def hhg_solve(h, u, f, mode=HHG_MODE_PLAIN_FP64, op=HHG_OP_LAPLACE, rtol=1e-8, max_iters=100,
+              nu1=3, nu2=3, history=True, stream=None):
+    """Returns (status, stats dict, residual history list)."""
+    hist = np.zeros(max_iters + 1) if history else None
+    o = hhg_solve_opts(mode, op, rtol, max_iters, nu1, nu2,
+                       hist.ctypes.data_as(_c.POINTER(_c.c_double)) if history else None,
+                       len(hist) if history else 0)
+    st = hhg_solve_stats()
+    rc = lib().hhg_solve(h, _c.byref(o), _ptr(u), _ptr(f), _c.byref(st), _stream(stream))
+    if rc not in (HHG_OK, HHG_ENOTCONV):
+        _check(rc)
+    stats = {k: getattr(st, k) for k, _ in hhg_solve_stats._fields_}
+    hl = list(hist[:st.iters + 1]) if history else []
+    return rc, stats, hl
+
+
+def hhg_timing_enable(h, enable):
+    _check(lib().hhg_timing_enable(h, int(enable)))
+
+
+def hhg_timing_read(h, reset=True):
+    n, ms = _i64(), _c.c_double()
+    _check(lib().hhg_timing_read(h, _c.byref(n), _c.byref(ms), int(reset)))
+    return n.value, ms.value

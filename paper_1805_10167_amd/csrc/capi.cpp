@@ -1,0 +1,532 @@
+// C ABI of the HHG P1 library and the host drivers of the multigrid cycle
+// (sec. 4.3): V-cycle recursion, solve loop and mixed-precision iterative
+// refinement.  All device work is done by the kernels in kernels.hip.
+#include <hip/hip_runtime.h>
+
+#include <chrono>
+#include <cmath>
+#include <cstring>
+#include <new>
+#include <string>
+
+#include "../../include/hhg.h"
+#include "hhg_kernels.hpp"
+#include "hhg_mesh.hpp"
+
+using namespace hhg;
+
+namespace {
+
+thread_local std::string g_err;
+
+int fail(int code, const std::string& msg) {
+    g_err = msg;
+    return code;
+}
+
+int hip_fail(hipError_t e, const char* where) {
+    return fail(HHG_EHIP, std::string(where) + ": " + hipGetErrorString(e));
+}
+
+#define HIP_CHECK(expr, where)                          \
+    do {                                                \
+        hipError_t e_ = (expr);                         \
+        if (e_ != hipSuccess) return hip_fail(e_, where); \
+    } while (0)
+
+// Lay out (or size, with a null base) everything the workspace holds.
+void carve(hhg_mesh* M, uint32_t feat, Carver& c) {
+    MeshData& m = M->m;
+    M->d_faces = (FaceInfo*)c.take(sizeof(FaceInfo) * m.F);
+    M->d_edges = (EdgeInfo*)c.take(sizeof(EdgeInfo) * m.E);
+    M->d_verts = (VertexInfo*)c.take(sizeof(VertexInfo) * m.V);
+    M->d_iedges = (int32_t*)c.take(sizeof(int32_t) * (m.iedges.size() + 1));
+    M->d_iverts = (int32_t*)c.take(sizeof(int32_t) * (m.iverts.size() + 1));
+    for (int l = 1; l <= m.L; ++l) {
+        LevelHost& H = m.lv[l];
+        H.d_row_off = (int32_t*)c.take(sizeof(int32_t) * H.row_off.size());
+        H.d_tiles = (int2*)c.take(sizeof(int2) * (H.tiles.size() + 1));
+        H.d_gdst = (int64_t*)c.take(sizeof(int64_t) * (H.gdst.size() + 1));
+        H.d_gsrc = (int64_t*)c.take(sizeof(int64_t) * (H.gsrc.size() + 1));
+    }
+    CoarseDev& C = M->coarse;
+    C.N = m.Nc;
+    C.W = m.Wc;
+    const size_t NW = (size_t)m.Nc * m.Wc;
+    C.owner = (const int64_t*)c.take(sizeof(int64_t) * m.Nc);
+    C.kind = (const int32_t*)c.take(sizeof(int32_t) * m.Nc);
+    C.prim = (const int32_t*)c.take(sizeof(int32_t) * m.Nc);
+    C.pa = (const int32_t*)c.take(sizeof(int32_t) * m.Nc);
+    C.pb = (const int32_t*)c.take(sizeof(int32_t) * m.Nc);
+    C.cols = (const int32_t*)c.take(sizeof(int32_t) * NW);
+    C.vals = (double*)c.take(sizeof(double) * NW);                  // Laplace
+    M->coarse_vals_diff = (double*)c.take(sizeof(double) * NW);     // diffusion
+    C.vec = (double*)c.take(sizeof(double) * 5 * (size_t)m.Nc);
+    M->n_partials = 8192 + 1024;
+    M->partials = (double*)c.take(sizeof(double) * M->n_partials);
+    M->dscalars = (double*)c.take(sizeof(double) * 64);
+    for (int l = 0; l <= MAXLEVEL; ++l) {
+        M->u64[l] = M->f64[l] = M->r64[l] = nullptr;
+        M->u32[l] = M->f32[l] = M->r32[l] = nullptr;
+        M->kap64[l] = nullptr;
+        M->kap32[l] = nullptr;
+    }
+    auto fld = [&](int l, size_t esz) { return c.take(esz * (size_t)m.lv[l].total); };
+    if (feat & (HHG_FEAT_F64 | HHG_FEAT_MP)) M->r64[m.L] = fld(m.L, 8);
+    if (feat & HHG_FEAT_F64) {
+        for (int l = m.lc; l < m.L; ++l) {
+            M->u64[l] = fld(l, 8);
+            M->f64[l] = fld(l, 8);
+            M->r64[l] = fld(l, 8);
+        }
+    }
+    if (feat & HHG_FEAT_MP) {
+        if (!(feat & HHG_FEAT_F64))
+            for (int l = m.lc; l <= m.L; ++l)
+                if (!M->r64[l]) M->r64[l] = fld(l, 8);   // FP64 coarse residual
+        for (int l = m.lc; l <= m.L; ++l) {
+            M->u32[l] = fld(l, 4);
+            M->f32[l] = fld(l, 4);
+            M->r32[l] = fld(l, 4);
+        }
+    }
+    if (feat & HHG_FEAT_VARK) {
+        for (int l = 1; l <= m.L; ++l) {
+            M->kap64[l] = (double*)fld(l, 8);
+            if (feat & HHG_FEAT_MP) M->kap32[l] = (float*)fld(l, 4);
+        }
+    }
+}
+
+template <class V>
+hipError_t upload(void* dst, const V& v, hipStream_t s) {
+    if (v.empty()) return hipSuccess;
+    return hipMemcpyAsync(dst, v.data(), sizeof(v[0]) * v.size(), hipMemcpyHostToDevice, s);
+}
+
+bool level_ok(const hhg_mesh* M, int level) { return level >= 1 && level <= M->m.L; }
+bool dtype_ok(int dt) { return dt == HHG_F64 || dt == HHG_F32; }
+bool op_ok(const hhg_mesh* M, int op) {
+    if (op == HHG_OP_LAPLACE || op == HHG_OP_MASS) return true;
+    return op == HHG_OP_DIFFUSION && M->kappa_set;
+}
+
+int check_common(const hhg_mesh* M, int level, int dtype) {
+    if (!M) return fail(HHG_EINVAL, "null mesh");
+    if (!M->bound) return fail(HHG_ENOMEM, "no workspace bound");
+    if (!level_ok(M, level)) return fail(HHG_EINVAL, "level out of range");
+    if (!dtype_ok(dtype)) return fail(HHG_EINVAL, "dtype must be HHG_F64 or HHG_F32");
+    return HHG_OK;
+}
+
+int check_op(const hhg_mesh* M, int op, int dtype) {
+    if (op == HHG_OP_DIFFUSION && !M->kappa_set)
+        return fail(HHG_EINVAL, "HHG_OP_DIFFUSION needs hhg_set_coefficient first");
+    if (op == HHG_OP_DIFFUSION && dtype == HHG_F32 && !(M->features & HHG_FEAT_MP))
+        return fail(HHG_EINVAL, "FP32 diffusion needs a workspace bound with HHG_FEAT_MP");
+    if (!op_ok(M, op)) return fail(HHG_EINVAL, "unknown operator");
+    return HHG_OK;
+}
+
+// fields of the hierarchy for a dtype
+void* level_u(const hhg_mesh* M, int l, int dt) { return dt == HHG_F64 ? M->u64[l] : M->u32[l]; }
+void* level_f(const hhg_mesh* M, int l, int dt) { return dt == HHG_F64 ? M->f64[l] : M->f32[l]; }
+void* level_r(const hhg_mesh* M, int l, int dt) { return dt == HHG_F64 ? M->r64[l] : M->r32[l]; }
+
+int smooth_impl(const hhg_mesh* M, int level, int op, int smoother, int dt, void* u, const void* f,
+                int sweeps, int backward, hipStream_t s) {
+    (void)smoother;
+    for (int i = 0; i < sweeps; ++i)
+        HIP_CHECK(launch_gs_sweep(M, level, op, dt, u, f, backward, s), "smooth");
+    return HHG_OK;
+}
+
+int vcycle_rec(const hhg_mesh* M, int level, int op, int smoother, int dt, void* u, const void* f,
+               int nu1, int nu2, hipStream_t s) {
+    const int lc = M->m.lc;
+    const double* vals = op == HHG_OP_DIFFUSION ? M->coarse_vals_diff : M->coarse.vals;
+    if (level == lc) {
+        HIP_CHECK(launch_coarse_solve(M, op, dt, u, f, vals, s), "coarse solve");
+        return HHG_OK;
+    }
+    int rc = smooth_impl(M, level, op, smoother, dt, u, f, nu1, 0, s);
+    if (rc) return rc;
+    void* r = level_r(M, level, dt);
+    void* uc = level_u(M, level - 1, dt);
+    void* fc = level_f(M, level - 1, dt);
+    HIP_CHECK(launch_residual(M, level, op, dt, u, f, r, nullptr, GM_FACE | GM_EODD, s), "residual");
+    HIP_CHECK(launch_restrict(M, level, dt, r, fc, s), "restrict");
+    HIP_CHECK(launch_fill(uc, M->m.lv[level - 1].total, dt, 0.0, s), "fill");
+    rc = vcycle_rec(M, level - 1, op, smoother, dt, uc, fc, nu1, nu2, s);
+    if (rc) return rc;
+    HIP_CHECK(launch_prolong_add(M, level, dt, uc, u, s), "prolong");
+    return smooth_impl(M, level, op, smoother, dt, u, f, nu2, 1, s);
+}
+
+int read_scalar(const double* d, double* h, hipStream_t s) {
+    HIP_CHECK(hipMemcpyAsync(h, d, sizeof(double), hipMemcpyDeviceToHost, s), "norm readback");
+    HIP_CHECK(hipStreamSynchronize(s), "norm readback");
+    return HHG_OK;
+}
+
+}  // namespace
+
+hhg::LevelDev hhg_mesh::dev(int level) const {
+    const LevelHost& H = m.lv[level];
+    LevelDev L{};
+    L.level = level;
+    L.n = H.n;
+    L.F = m.F; L.E = m.E; L.V = m.V;
+    L.ghost_off = H.ghost_off;
+    L.ghost_stride = H.ghost_stride;
+    L.vert_stride = (int32_t)H.vert_stride;
+    L.ntiles = (int32_t)H.tiles.size();
+    L.n_iedges = (int32_t)m.iedges.size();
+    L.n_iverts = (int32_t)m.iverts.size();
+    L.face_stride = H.face_stride;
+    L.edge_stride = H.edge_stride;
+    L.face_base = H.face_base;
+    L.edge_base = H.edge_base;
+    L.vert_base = H.vert_base;
+    L.total = H.total;
+    for (int c = 0; c <= G_NCLS; ++c) L.gcls[c] = H.gcls[c];
+    L.can_edge_base = H.can_edge_base;
+    L.can_face_base = H.can_face_base;
+    L.n_all = H.n_all;
+    L.inv4l = std::ldexp(1.0, -2 * level);
+    L.row_off = H.d_row_off;
+    L.tiles = H.d_tiles;
+    L.faces = d_faces;
+    L.edges = d_edges;
+    L.verts = d_verts;
+    L.iedges = d_iedges;
+    L.iverts = d_iverts;
+    L.gdst = H.d_gdst;
+    L.gsrc = H.d_gsrc;
+    return L;
+}
+
+extern "C" {
+
+const char* hhg_last_error(void) { return g_err.c_str(); }
+
+int hhg_setup_mesh(const double* vxy, int32_t n_vertices, const int32_t* tri, int32_t n_faces,
+                   int32_t max_level, int32_t coarse_level, hhg_mesh** out) {
+    if (!vxy || !tri || !out) return fail(HHG_EINVAL, "null argument");
+    *out = nullptr;
+    hhg_mesh* M = new (std::nothrow) hhg_mesh();
+    if (!M) return fail(HHG_ENOMEM, "host allocation failed");
+    std::string err;
+    try {
+        err = M->m.build(vxy, n_vertices, tri, n_faces, max_level, coarse_level);
+    } catch (const std::exception& ex) {
+        err = std::string("setup failed: ") + ex.what();
+    }
+    if (!err.empty()) {
+        delete M;
+        return fail(HHG_EINVAL, err);
+    }
+    *out = M;
+    return HHG_OK;
+}
+
+void hhg_destroy_mesh(hhg_mesh* mesh) {
+    if (!mesh) return;
+    for (auto& ev : mesh->t_events) {
+        (void)hipEventDestroy((hipEvent_t)ev.first);
+        (void)hipEventDestroy((hipEvent_t)ev.second);
+    }
+    delete mesh;
+}
+
+int hhg_workspace_bytes(const hhg_mesh* mesh, uint32_t features, size_t* bytes) {
+    if (!mesh || !bytes) return fail(HHG_EINVAL, "null argument");
+    if (features & ~(HHG_FEAT_F64 | HHG_FEAT_MP | HHG_FEAT_VARK | HHG_FEAT_NET))
+        return fail(HHG_EINVAL, "unknown feature bits");
+    hhg_mesh tmp;
+    tmp.m = mesh->m;
+    Carver c(nullptr);
+    carve(&tmp, features, c);
+    *bytes = c.off + 256;
+    return HHG_OK;
+}
+
+int hhg_bind_workspace(hhg_mesh* M, uint32_t features, void* dptr, size_t bytes, void* stream) {
+    if (!M || !dptr) return fail(HHG_EINVAL, "null argument");
+    size_t need = 0;
+    int rc = hhg_workspace_bytes(M, features, &need);
+    if (rc) return rc;
+    if (bytes < need) return fail(HHG_ENOMEM, "workspace too small: need " + std::to_string(need));
+    if ((uintptr_t)dptr % 256) return fail(HHG_EINVAL, "workspace must be 256-byte aligned");
+    hipStream_t s = (hipStream_t)stream;
+    Carver c(dptr);
+    carve(M, features, c);
+    MeshData& m = M->m;
+    HIP_CHECK(upload(M->d_faces, m.faces, s), "upload");
+    HIP_CHECK(upload(M->d_edges, m.edges, s), "upload");
+    HIP_CHECK(upload(M->d_verts, m.verts, s), "upload");
+    HIP_CHECK(upload(M->d_iedges, m.iedges, s), "upload");
+    HIP_CHECK(upload(M->d_iverts, m.iverts, s), "upload");
+    for (int l = 1; l <= m.L; ++l) {
+        LevelHost& H = m.lv[l];
+        HIP_CHECK(upload(H.d_row_off, H.row_off, s), "upload");
+        HIP_CHECK(upload(H.d_tiles, H.tiles, s), "upload");
+        HIP_CHECK(upload(H.d_gdst, H.gdst, s), "upload");
+        HIP_CHECK(upload(H.d_gsrc, H.gsrc, s), "upload");
+    }
+    CoarseDev& C = M->coarse;
+    HIP_CHECK(upload((void*)C.owner, m.c_owner, s), "upload");
+    HIP_CHECK(upload((void*)C.kind, m.c_kind, s), "upload");
+    HIP_CHECK(upload((void*)C.prim, m.c_prim, s), "upload");
+    HIP_CHECK(upload((void*)C.pa, m.c_pa, s), "upload");
+    HIP_CHECK(upload((void*)C.pb, m.c_pb, s), "upload");
+    HIP_CHECK(upload((void*)C.cols, m.c_cols, s), "upload");
+    M->ws = (char*)dptr;
+    M->ws_bytes = bytes;
+    M->features = features;
+    M->bound = true;
+    M->kappa_set = false;
+    HIP_CHECK(launch_coarse_extract(M, OP_LAPLACE, C.vals, s), "coarse operator");
+    HIP_CHECK(hipStreamSynchronize(s), "bind");
+    return HHG_OK;
+}
+
+int hhg_field_elems(const hhg_mesh* M, int32_t level, int64_t* n) {
+    if (!M || !n) return fail(HHG_EINVAL, "null argument");
+    if (!level_ok(M, level)) return fail(HHG_EINVAL, "level out of range");
+    *n = M->m.lv[level].total;
+    return HHG_OK;
+}
+
+int hhg_n_dofs(const hhg_mesh* M, int32_t level, int64_t* n_interior, int64_t* n_all) {
+    if (!M) return fail(HHG_EINVAL, "null mesh");
+    if (!level_ok(M, level)) return fail(HHG_EINVAL, "level out of range");
+    if (n_interior) *n_interior = M->m.lv[level].n_int;
+    if (n_all) *n_all = M->m.lv[level].n_all;
+    return HHG_OK;
+}
+
+int hhg_coords(const hhg_mesh* M, int32_t level, double* xy) {
+    if (!M || !xy) return fail(HHG_EINVAL, "null argument");
+    if (!level_ok(M, level)) return fail(HHG_EINVAL, "level out of range");
+    const MeshData& m = M->m;
+    const LevelHost& H = m.lv[level];
+    const int n = H.n;
+    for (int v = 0; v < m.V; ++v) {
+        xy[2 * v] = m.vxy[2 * v];
+        xy[2 * v + 1] = m.vxy[2 * v + 1];
+    }
+    for (int e = 0; e < m.E; ++e) {
+        const double* a = &m.vxy[2 * m.edges[e].a];
+        const double* b = &m.vxy[2 * m.edges[e].b];
+        for (int k = 1; k <= n - 2; ++k) {
+            const double t = (double)k / (n - 1);
+            const int64_t c = H.can_edge_base + (int64_t)e * (n - 2) + (k - 1);
+            xy[2 * c] = a[0] + t * (b[0] - a[0]);
+            xy[2 * c + 1] = a[1] + t * (b[1] - a[1]);
+        }
+    }
+    const int64_t nfi = (int64_t)(n - 2) * (n - 3) / 2;
+    for (int f = 0; f < m.F; ++f) {
+        const double* x0 = &m.vxy[2 * m.tri[f][0]];
+        const double* x1 = &m.vxy[2 * m.tri[f][1]];
+        const double* x2 = &m.vxy[2 * m.tri[f][2]];
+        int64_t c = H.can_face_base + (int64_t)f * nfi;
+        for (int j = 1; j <= n - 3; ++j)
+            for (int i = 1; i <= n - 2 - j; ++i, ++c) {
+                const double si = (double)i / (n - 1), sj = (double)j / (n - 1);
+                xy[2 * c] = x0[0] + si * (x1[0] - x0[0]) + sj * (x2[0] - x0[0]);
+                xy[2 * c + 1] = x0[1] + si * (x1[1] - x0[1]) + sj * (x2[1] - x0[1]);
+            }
+    }
+    return HHG_OK;
+}
+
+int hhg_from_canonical(const hhg_mesh* M, int32_t level, int32_t dtype, const void* canon,
+                       void* field, void* stream) {
+    int rc = check_common(M, level, dtype);
+    if (rc) return rc;
+    if (!canon || !field) return fail(HHG_EINVAL, "null buffer");
+    HIP_CHECK(launch_canon(M, level, dtype, canon, field, 0, (hipStream_t)stream), "from_canonical");
+    return HHG_OK;
+}
+
+int hhg_to_canonical(const hhg_mesh* M, int32_t level, int32_t dtype, const void* field,
+                     void* canon, void* stream) {
+    int rc = check_common(M, level, dtype);
+    if (rc) return rc;
+    if (!canon || !field) return fail(HHG_EINVAL, "null buffer");
+    HIP_CHECK(launch_canon(M, level, dtype, field, canon, 1, (hipStream_t)stream), "to_canonical");
+    return HHG_OK;
+}
+
+int hhg_set_coefficient(hhg_mesh* M, const double* k_canon, void* stream) {
+    if (!M || !k_canon) return fail(HHG_EINVAL, "null argument");
+    if (!M->bound) return fail(HHG_ENOMEM, "no workspace bound");
+    if (!(M->features & HHG_FEAT_VARK)) return fail(HHG_EINVAL, "workspace lacks HHG_FEAT_VARK");
+    hipStream_t s = (hipStream_t)stream;
+    const int L = M->m.L;
+    HIP_CHECK(launch_canon(M, L, HHG_F64, k_canon, M->kap64[L], 0, s), "coefficient");
+    for (int l = L; l > 1; --l) HIP_CHECK(launch_inject(M, l, HHG_F64, M->kap64[l], M->kap64[l - 1], s), "inject");
+    if (M->features & HHG_FEAT_MP)
+        for (int l = 1; l <= L; ++l)
+            HIP_CHECK(launch_f64_to_f32(M->kap64[l], M->kap32[l], M->m.lv[l].total, s), "coefficient f32");
+    M->kappa_set = true;
+    HIP_CHECK(launch_coarse_extract(M, OP_DIFFUSION, M->coarse_vals_diff, s), "coarse operator");
+    return HHG_OK;
+}
+
+int hhg_apply(const hhg_mesh* M, int32_t level, int32_t op, int32_t dtype, const void* x, void* y,
+              void* stream) {
+    int rc = check_common(M, level, dtype);
+    if (rc) return rc;
+    if ((rc = check_op(M, op, dtype))) return rc;
+    if (!x || !y || x == y) return fail(HHG_EINVAL, "x and y must be distinct buffers");
+    HIP_CHECK(launch_apply(M, level, op, dtype, x, y, (hipStream_t)stream), "apply");
+    return HHG_OK;
+}
+
+int hhg_residual(const hhg_mesh* M, int32_t level, int32_t op, int32_t dtype, const void* u,
+                 const void* f, void* r, double* norm, void* stream) {
+    int rc = check_common(M, level, dtype);
+    if (rc) return rc;
+    if ((rc = check_op(M, op, dtype))) return rc;
+    if (op == HHG_OP_MASS) return fail(HHG_EINVAL, "residual needs a stiffness operator");
+    if (!u || !f || !r) return fail(HHG_EINVAL, "null buffer");
+    HIP_CHECK(launch_residual(M, level, op, dtype, u, f, r, norm, GM_ALL, (hipStream_t)stream),
+              "residual");
+    return HHG_OK;
+}
+
+int hhg_smooth(const hhg_mesh* M, int32_t level, int32_t op, int32_t smoother, int32_t dtype,
+               void* u, const void* f, int32_t sweeps, int32_t backward, void* stream) {
+    int rc = check_common(M, level, dtype);
+    if (rc) return rc;
+    if ((rc = check_op(M, op, dtype))) return rc;
+    if (op == HHG_OP_MASS) return fail(HHG_EINVAL, "smoothing needs a stiffness operator");
+    if (smoother != HHG_SMOOTH_GS) return fail(HHG_EINVAL, "unknown smoother");
+    if (sweeps < 0 || !u || !f) return fail(HHG_EINVAL, "bad arguments");
+    return smooth_impl(M, level, op, smoother, dtype, u, f, sweeps, backward, (hipStream_t)stream);
+}
+
+int hhg_vcycle(const hhg_mesh* M, int32_t level, int32_t op, int32_t smoother, int32_t dtype,
+               void* u, const void* f, int32_t nu1, int32_t nu2, void* stream) {
+    int rc = check_common(M, level, dtype);
+    if (rc) return rc;
+    if ((rc = check_op(M, op, dtype))) return rc;
+    if (op == HHG_OP_MASS) return fail(HHG_EINVAL, "multigrid needs a stiffness operator");
+    if (smoother != HHG_SMOOTH_GS) return fail(HHG_EINVAL, "unknown smoother");
+    if (level < M->m.lc) return fail(HHG_EINVAL, "level below the coarse level");
+    if (dtype == HHG_F64 && !(M->features & HHG_FEAT_F64))
+        return fail(HHG_ENOMEM, "workspace lacks HHG_FEAT_F64");
+    if (dtype == HHG_F32 && !(M->features & HHG_FEAT_MP))
+        return fail(HHG_ENOMEM, "workspace lacks HHG_FEAT_MP");
+    if (nu1 < 0 || nu2 < 0 || !u || !f) return fail(HHG_EINVAL, "bad arguments");
+    return vcycle_rec(M, level, op, smoother, dtype, u, f, nu1, nu2, (hipStream_t)stream);
+}
+
+int hhg_solve(hhg_mesh* M, const hhg_solve_opts* o, void* u, const void* f, hhg_solve_stats* st,
+              void* stream) {
+    if (!M || !o || !u || !f || !st) return fail(HHG_EINVAL, "null argument");
+    auto t0 = std::chrono::steady_clock::now();
+    std::memset(st, 0, sizeof(*st));
+    g_err.clear();
+    const int L = M->m.L;
+    int rc = check_common(M, L, HHG_F64);
+    if (rc) return rc;
+    if ((rc = check_op(M, o->op, HHG_F64))) return rc;
+    if (o->op == HHG_OP_MASS) return fail(HHG_EINVAL, "solve needs a stiffness operator");
+    if (o->mode != HHG_MODE_PLAIN_FP64 && o->mode != HHG_MODE_MP_IR)
+        return fail(HHG_EINVAL, "unknown solve mode");
+    if (o->mode == HHG_MODE_PLAIN_FP64 && !(M->features & HHG_FEAT_F64))
+        return fail(HHG_ENOMEM, "workspace lacks HHG_FEAT_F64");
+    if (o->mode == HHG_MODE_MP_IR && !(M->features & HHG_FEAT_MP))
+        return fail(HHG_ENOMEM, "workspace lacks HHG_FEAT_MP");
+    if (o->max_iters < 0 || o->nu1 < 0 || o->nu2 < 0 || !(o->rtol >= 0))
+        return fail(HHG_EINVAL, "bad solve options");
+    if (o->op == HHG_OP_DIFFUSION && o->mode == HHG_MODE_MP_IR && !M->kap32[L])
+        return fail(HHG_EINVAL, "FP32 coefficient missing");
+    hipStream_t s = (hipStream_t)stream;
+    double* dnorm = M->dscalars;
+    double* r64 = (double*)M->r64[L];
+    auto norm_now = [&](double* out) -> int {
+        HIP_CHECK(launch_residual(M, L, o->op, HHG_F64, u, f, r64, dnorm, 0, s), "residual");
+        return read_scalar(dnorm, out, s);
+    };
+    double r0 = 0.0;
+    if ((rc = norm_now(&r0))) return rc;
+    st->res0 = r0;
+    st->smoother_used = HHG_SMOOTH_GS;
+    if (o->res_history && o->history_capacity > 0) o->res_history[0] = r0;
+    if (r0 == 0.0) {
+        st->converged = 1;
+        st->rel_res = 0.0;
+        st->ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+        return HHG_OK;
+    }
+    double prev = r0;
+    int rising = 0;
+    int status = HHG_ENOTCONV;
+    const int64_t nL = M->m.lv[L].total;
+    for (int it = 0; it < o->max_iters; ++it) {
+        if (o->mode == HHG_MODE_PLAIN_FP64) {
+            rc = vcycle_rec(M, L, o->op, HHG_SMOOTH_GS, HHG_F64, u, f, o->nu1, o->nu2, s);
+        } else {
+            // mixed precision: FP32 V-cycle on A e = r, FP64 residual and update
+            float* r32 = (float*)M->f32[L];
+            float* e32 = (float*)M->u32[L];
+            HIP_CHECK(launch_f64_to_f32(r64, r32, nL, s), "downcast");
+            HIP_CHECK(launch_fill(e32, nL, HHG_F32, 0.0, s), "fill");
+            rc = vcycle_rec(M, L, o->op, HHG_SMOOTH_GS, HHG_F32, e32, r32, o->nu1, o->nu2, s);
+            if (!rc) HIP_CHECK(launch_add_f32_to_f64((double*)u, e32, nL, s), "update");
+        }
+        if (rc) return rc;
+        double rn = 0.0;
+        if ((rc = norm_now(&rn))) return rc;
+        st->iters = it + 1;
+        st->rel_res = rn / r0;
+        if (o->res_history && it + 1 < o->history_capacity) o->res_history[it + 1] = rn;
+        if (!std::isfinite(rn)) {
+            g_err = "residual is not finite";
+            break;
+        }
+        if (rn <= o->rtol * r0) {
+            st->converged = 1;
+            status = HHG_OK;
+            break;
+        }
+        rising = (rn > prev) ? rising + 1 : 0;
+        if (rising >= 3) {
+            g_err = "residual grew in 3 consecutive cycles";
+            break;
+        }
+        prev = rn;
+    }
+    if (status == HHG_ENOTCONV && g_err.empty()) g_err = "iteration cap reached";
+    st->ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+    return status;
+}
+
+int hhg_timing_enable(hhg_mesh* M, int32_t enable) {
+    if (!M) return fail(HHG_EINVAL, "null mesh");
+    M->timing = enable != 0;
+    return HHG_OK;
+}
+
+int hhg_timing_read(hhg_mesh* M, int64_t* launches, double* total_ms, int32_t reset) {
+    if (!M) return fail(HHG_EINVAL, "null mesh");
+    double tot = 0.0;
+    for (int64_t i = 0; i < M->t_launches; ++i) {
+        hipEvent_t a = (hipEvent_t)M->t_events[i].first, b = (hipEvent_t)M->t_events[i].second;
+        HIP_CHECK(hipEventSynchronize(b), "timing");
+        float ms = 0.f;
+        HIP_CHECK(hipEventElapsedTime(&ms, a, b), "timing");
+        tot += ms;
+    }
+    if (launches) *launches = M->t_launches;
+    if (total_ms) *total_ms = tot;
+    if (reset) M->t_launches = 0;
+    return HHG_OK;
+}
+
+}  // extern "C"

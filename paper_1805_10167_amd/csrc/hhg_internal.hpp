@@ -1,0 +1,128 @@
+// Internal data structures of the HHG P1 library: macro-primitive tables
+// (sec. 2.1-2.3 of the paper), per-level layouts (sec. 3.1-3.2) and the ghost
+// copy table that realises the process-local direct-copy path of the
+// communication layer (sec. 2.4, 3.3).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+namespace hhg {
+
+constexpr int MAXDEG = 16;      // incident macro-edges per macro-vertex
+constexpr int MAXLEVEL = 12;
+constexpr int PAD = 16;         // row/segment padding in elements
+constexpr int TILE_I = 64;      // generic face tile: 64 (i) x 4 (j) points
+constexpr int TILE_J = 4;
+
+inline int64_t pad_up(int64_t x, int64_t p) { return (x + p - 1) / p * p; }
+
+// Ghost-copy classes, by the kind of the owning point.  A stage of the
+// smoother refreshes only the copies of the points it changed.
+enum GhostClass { G_VERT = 0, G_EEVEN = 1, G_EODD = 2, G_FACE = 3, G_NCLS = 4 };
+enum { GM_VERT = 1, GM_EEVEN = 2, GM_EODD = 4, GM_FACE = 8, GM_ALL = 15 };
+
+// Face sides: 0 = v0->v1 (j = 0), 1 = v0->v2 (i = 0), 2 = v1->v2 (i+j = n-1).
+struct FaceInfo {
+    double cot[3];        // cotangent of the angle at v0, v1, v2
+    double area;          // macro-face area
+    int32_t vtx[3];
+    int32_t edge[3];      // macro-edge on each side
+    int32_t slot[3];      // which ghost row of that edge this face fills
+    int32_t rev[3];       // 1: edge parameter k runs against the side
+    int32_t bside[3];     // side is a Dirichlet edge
+    int32_t bvtx[3];      // vertex is Dirichlet
+    int32_t colour_rule;  // 0: (i-j) mod 3, 1: (i+j) mod 2, 2: i mod 2, 3: j mod 2
+    int32_t ncolours;     // 3, or 2 for a face with an exact right angle
+};
+
+// A macro-edge runs from a to b (a < b).  For each adjacent face s the
+// micro-triangle (k, k+1, g_s[k]) is a translate of the scaled macro-face,
+// with angles cL at k (= angle at a), cH at k+1 (= angle at b) and cA at the
+// apex g_s[k] (the third vertex).  g_s[m] is the near-row point adjacent to
+// edge points m and m+1.
+struct EdgeInfo {
+    int32_t a, b;
+    int32_t nf;           // adjacent faces: 1 = boundary (Dirichlet), 2 = interior
+    int32_t boundary;
+    int32_t face[2];
+    int32_t side[2];
+    int32_t rev[2];
+    double cA[2], cL[2], cH[2];
+    double area[2];       // macro-face areas
+    int32_t vslot[2];     // ghost slot of this edge at vertex a and at vertex b
+    int32_t pad_;
+};
+
+// A macro-vertex keeps one ghost copy per incident edge: the edge point one
+// micro-edge away from it.  For edge q and each face s of that edge, the
+// corner micro-triangle (v, q-point, partner-point) has angle cA opposite
+// the micro-edge v -> q-point.
+struct VertexInfo {
+    int32_t deg;
+    int32_t boundary;
+    int32_t edge[MAXDEG];
+    int32_t at_a[MAXDEG];
+    int32_t nfe[MAXDEG];
+    int32_t partner[MAXDEG][2];
+    double cA[MAXDEG][2];
+    double area[MAXDEG][2];
+};
+
+// Per-level view passed to kernels by value.
+struct LevelDev {
+    int32_t level, n;
+    int32_t F, E, V;
+    int32_t ghost_off, ghost_stride, vert_stride;
+    int32_t ntiles, n_iedges, n_iverts, pad0;
+    int64_t face_stride, edge_stride;
+    int64_t face_base, edge_base, vert_base, total;
+    int64_t gcls[G_NCLS + 1];
+    int64_t can_edge_base, can_face_base, n_all;
+    double inv4l;                     // 1 / 4^level: micro/macro area ratio
+    const int32_t* row_off;           // [n + 1] start of row j inside a face
+    const int2* tiles;                // 64 x 4 tiles that meet the interior
+    const FaceInfo* faces;
+    const EdgeInfo* edges;
+    const VertexInfo* verts;
+    const int32_t* iedges;            // interior edge ids
+    const int32_t* iverts;            // interior vertex ids
+    const int64_t* gdst;              // ghost copies: field[gdst] = field[gsrc]
+    const int64_t* gsrc;
+};
+
+// Coarse-level Jacobi-PCG data: interior points in canonical order, each
+// with up to W stencil neighbours in an ELL table (column -1 = Dirichlet).
+struct CoarseDev {
+    int32_t N, W;
+    const int64_t* owner;     // [N] field offset of the owned value
+    const int32_t* kind;      // [N] 0 vertex, 1 edge, 2 face
+    const int32_t* prim;      // [N] primitive id
+    const int32_t* pa;        // [N] face i / edge k
+    const int32_t* pb;        // [N] face j
+    const int32_t* cols;      // [N * W]
+    double* vals;             // [N * W] filled on the device per operator
+    double* vec;              // [5 * N] CG scratch (x, r, z, p, q)
+};
+
+struct LevelHost {
+    int level = 0, n = 0;
+    int64_t face_stride = 0, edge_stride = 0, vert_stride = 0;
+    int64_t face_base = 0, edge_base = 0, vert_base = 0, total = 0;
+    int32_t ghost_off = 0, ghost_stride = 0;
+    std::vector<int32_t> row_off;
+    std::vector<int2> tiles;
+    std::vector<int64_t> gdst, gsrc;
+    int64_t gcls[G_NCLS + 1] = {0, 0, 0, 0, 0};
+    int64_t n_all = 0, n_int = 0, can_edge_base = 0, can_face_base = 0;
+    // device copies (inside the bound workspace)
+    int32_t* d_row_off = nullptr;
+    int2* d_tiles = nullptr;
+    int64_t* d_gdst = nullptr;
+    int64_t* d_gsrc = nullptr;
+};
+
+}  // namespace hhg

@@ -1,0 +1,50 @@
+// Launchers of the HIP kernels of the HHG P1 hot path.  Every launcher
+// enqueues on the given stream and returns the launch status.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include "hhg_mesh.hpp"
+
+namespace hhg {
+
+enum { OP_LAPLACE = 0, OP_DIFFUSION = 1, OP_MASS = 2 };
+enum { DT_F64 = 0, DT_F32 = 1 };
+
+// field[copy] = field[owner] for the ghost classes in `mask` (GM_*).
+hipError_t launch_sync(const hhg_mesh* M, int level, int dtype, void* x, int mask,
+                       hipStream_t s);
+// y = A x (interior rows), 0 on Dirichlet rows, ghosts of y refreshed.
+hipError_t launch_apply(const hhg_mesh* M, int level, int op, int dtype, const void* x,
+                        void* y, hipStream_t s);
+// r = f - A u on interior points, 0 on Dirichlet points; optional |r|_2 into
+// the device double *norm; `sync_mask` refreshes those ghost classes of r.
+hipError_t launch_residual(const hhg_mesh* M, int level, int op, int dtype, const void* u,
+                           const void* f, void* r, double* norm, int sync_mask,
+                           hipStream_t s);
+// One forward or backward staged Gauss-Seidel sweep.
+hipError_t launch_gs_sweep(const hhg_mesh* M, int level, int op, int dtype, void* u,
+                           const void* f, int backward, hipStream_t s);
+// fc (level-1) = P^T r (level), r with refreshed FACE and EODD ghosts.
+hipError_t launch_restrict(const hhg_mesh* M, int level, int dtype, const void* r, void* fc,
+                           hipStream_t s);
+// u (level) += P uc (level-1) on interior points; ghosts of u refreshed.
+hipError_t launch_prolong_add(const hhg_mesh* M, int level, int dtype, const void* uc,
+                              void* u, hipStream_t s);
+hipError_t launch_fill(void* x, int64_t n, int dtype, double v, hipStream_t s);
+// ELL values of the coarse operator for `op` into `vals`.
+hipError_t launch_coarse_extract(const hhg_mesh* M, int op, double* vals, hipStream_t s);
+// u += PCG(A_int, (f - A u)_int) on the coarse level, ghosts refreshed.
+hipError_t launch_coarse_solve(const hhg_mesh* M, int op, int dtype, void* u, const void* f,
+                               const double* vals, hipStream_t s);
+// Canonical <-> layout conversion (to_canon = 1: field -> canonical).
+hipError_t launch_canon(const hhg_mesh* M, int level, int dtype, const void* src, void* dst,
+                        int to_canon, hipStream_t s);
+// Coarse coefficient by injection from level to level-1, ghosts refreshed.
+hipError_t launch_inject(const hhg_mesh* M, int level, int dtype, const void* kf, void* kc,
+                         hipStream_t s);
+// Elementwise conversions over whole fields.
+hipError_t launch_f64_to_f32(const double* src, float* dst, int64_t n, hipStream_t s);
+hipError_t launch_add_f32_to_f64(double* u, const float* e, int64_t n, hipStream_t s);
+
+}  // namespace hhg

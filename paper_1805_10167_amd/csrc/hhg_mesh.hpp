@@ -1,0 +1,114 @@
+// Host-side mesh object behind the opaque hhg_mesh handle.
+#pragma once
+
+#include <array>
+#include <cstddef>
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "hhg_internal.hpp"
+
+namespace hhg {
+
+// Bump allocator over the caller's workspace (or a dry run to size it).
+struct Carver {
+    char* base;
+    size_t off = 0;
+    explicit Carver(void* b) : base(static_cast<char*>(b)) {}
+    void* take(size_t bytes) {
+        off = (size_t)pad_up((int64_t)off, 256);
+        void* p = base ? base + off : nullptr;
+        off += bytes;
+        return p;
+    }
+};
+
+// Owner of a face-local point: the primitive that holds the unique value.
+struct Owner {
+    int kind;   // 0 vertex, 1 edge point, 2 face interior
+    int prim;   // vertex / edge / face id
+    int k;      // edge parameter (kind 1)
+    int i, j;   // face-local coordinates (kind 2)
+};
+
+struct MeshData {
+    int V = 0, E = 0, F = 0, L = 0, lc = 0, maxdeg = 0;
+    std::vector<double> vxy;
+    std::vector<std::array<int, 3>> tri;            // counter-clockwise
+    std::vector<std::array<int, 2>> edge_v;         // (a, b), a < b
+    std::vector<FaceInfo> faces;
+    std::vector<EdgeInfo> edges;
+    std::vector<VertexInfo> verts;
+    std::vector<int32_t> iedges, iverts;
+    std::vector<LevelHost> lv;                      // index = level
+
+    // coarse-level CG tables (host)
+    int32_t Nc = 0, Wc = 0;
+    std::vector<int64_t> c_owner;
+    std::vector<int32_t> c_kind, c_prim, c_pa, c_pb, c_cols;
+
+    // ---- geometry/indexing helpers (host)
+    static void side_point(int side, int t, int d, int n, int& i, int& j);
+    Owner owner_of(int f, int i, int j, int n) const;
+    int64_t owner_offset(const LevelHost& L, const Owner& o) const;
+    int64_t canonical_of(const LevelHost& L, const Owner& o) const;
+    int64_t face_off(const LevelHost& L, int f, int i, int j) const {
+        return L.face_base + (int64_t)f * L.face_stride + L.row_off[j] + i;
+    }
+    int64_t edge_off(const LevelHost& L, int e, int k) const {
+        return L.edge_base + (int64_t)e * L.edge_stride + k;
+    }
+    int64_t ghost_off(const LevelHost& L, int e, int s, int g) const {
+        return L.edge_base + (int64_t)e * L.edge_stride + L.ghost_off +
+               (int64_t)s * L.ghost_stride + g;
+    }
+    int64_t vert_off(const LevelHost& L, int v, int slot) const {
+        return L.vert_base + (int64_t)v * L.vert_stride + slot;
+    }
+
+    // Build everything; returns "" on success or an error message.
+    std::string build(const double* vxy, int nv, const int32_t* tri, int nf,
+                      int max_level, int coarse_level);
+    void build_level(int level);
+    void build_coarse();
+};
+
+}  // namespace hhg
+
+// Workspace-resident state of one mesh.
+struct hhg_mesh {
+    hhg::MeshData m;
+    uint32_t features = 0;
+    bool bound = false;
+    char* ws = nullptr;
+    size_t ws_bytes = 0;
+    // device tables
+    hhg::FaceInfo* d_faces = nullptr;
+    hhg::EdgeInfo* d_edges = nullptr;
+    hhg::VertexInfo* d_verts = nullptr;
+    int32_t* d_iedges = nullptr;
+    int32_t* d_iverts = nullptr;
+    hhg::CoarseDev coarse{};              // vals: Laplace operator
+    double* coarse_vals_diff = nullptr;   // diffusion operator
+    // fields per level (index = level); finest-level u, f come from the caller
+    void* u64[hhg::MAXLEVEL + 1] = {};
+    void* f64[hhg::MAXLEVEL + 1] = {};
+    void* r64[hhg::MAXLEVEL + 1] = {};
+    void* u32[hhg::MAXLEVEL + 1] = {};
+    void* f32[hhg::MAXLEVEL + 1] = {};
+    void* r32[hhg::MAXLEVEL + 1] = {};
+    double* kap64[hhg::MAXLEVEL + 1] = {};
+    float* kap32[hhg::MAXLEVEL + 1] = {};
+    bool kappa_set = false;
+    double* partials = nullptr;   // reduction partial sums
+    int64_t n_partials = 0;
+    double* dscalars = nullptr;   // small device scalars (norms, dots)
+    // timing of finest-level face smoother launches
+    bool timing = false;
+    int64_t t_launches = 0;
+    double t_ms = 0.0;
+    std::vector<std::pair<void*, void*>> t_events;
+
+    hhg::LevelDev dev(int level) const;
+};

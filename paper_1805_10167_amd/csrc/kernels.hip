@@ -1,0 +1,884 @@
+// HIP kernels (gfx950) of the HHG P1 hot path: stencil apply (Alg. 3),
+// staged multicolour Gauss-Seidel, residual, restriction, prolongation,
+// ghost-copy refresh, norms, coarse Jacobi-PCG and layout conversion.
+//
+// Stencils follow from the P1 stiffness matrix (a stencil is a row of it,
+// sec. 1.1 / 4.2).  On a macro-face every micro-triangle is a translate of
+// the scaled macro-face or of its point reflection, so with constant k the
+// face-interior stencil is
+//   centre 2 (c0 + c1 + c2), (i+-1, j): -c2, (i, j+-1): -c1,
+//   (i+1, j-1) and (i-1, j+1): -c0,
+// with c_m the cotangent of the macro-face angle at vertex m.  With a
+// variable coefficient each micro-triangle T contributes -1/2 kbar_T cot to
+// the weight of the micro-edge opposite the angle, kbar_T being the mean of
+// the nodal k at T's corners (computed on the fly, sec. 1.1).
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+#include "hhg_kernels.hpp"
+
+namespace hhg {
+
+constexpr int NT = 256;              // threads per block of the point kernels
+constexpr int MAX_FACE_BLOCKS = 8192;
+constexpr int MAX_LOW_BLOCKS = 1024;
+
+// ------------------------------------------------------------------ helpers
+
+__device__ __forceinline__ int64_t face_base(const LevelDev& L, int f) {
+    return L.face_base + (int64_t)f * L.face_stride;
+}
+__device__ __forceinline__ int64_t edge_main(const LevelDev& L, int e) {
+    return L.edge_base + (int64_t)e * L.edge_stride;
+}
+__device__ __forceinline__ int64_t edge_ghost(const LevelDev& L, int e, int s) {
+    return L.edge_base + (int64_t)e * L.edge_stride + L.ghost_off + (int64_t)s * L.ghost_stride;
+}
+__device__ __forceinline__ int64_t vert_off(const LevelDev& L, int v) {
+    return L.vert_base + (int64_t)v * L.vert_stride;
+}
+
+__device__ __forceinline__ int face_colour(int rule, int i, int j) {
+    switch (rule) {
+        case 1: return (i + j) & 1;
+        case 2: return i & 1;
+        case 3: return j & 1;
+        default: return ((i - j) % 3 + 3) % 3;
+    }
+}
+
+__device__ __forceinline__ double wave_sum(double v) {
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+
+// Deterministic block sum (fixed reduction tree); every thread gets lane 0's
+// value of the final wave.
+template <int NTH>
+__device__ __forceinline__ double block_sum(double v, double* sm) {
+    v = wave_sum(v);
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    __syncthreads();
+    if (lane == 0) sm[w] = v;
+    __syncthreads();
+    if (threadIdx.x < 64) {
+        double t = (threadIdx.x < NTH / 64) ? sm[threadIdx.x] : 0.0;
+        t = wave_sum(t);
+        if (threadIdx.x == 0) sm[NTH / 64] = t;
+    }
+    __syncthreads();
+    return sm[NTH / 64];
+}
+
+// ------------------------------------------------------------------ stencils
+
+template <class T>
+struct W7 { T c, e, w, n, s, se, nw; };   // face point weights
+
+template <class T>
+struct WE { T c, al, ah, l0, h0, l1, h1; };   // edge point weights
+
+// Face-interior weights at offset p; up/dn: offsets to the row above/below.
+template <class T>
+__device__ __forceinline__ W7<T> face_weights(int op, const FaceInfo& fi, double inv4l,
+                                              const T* kap, int64_t p, int64_t up, int64_t dn) {
+    W7<T> w;
+    if (op == OP_MASS) {
+        const T a = (T)(fi.area * inv4l), o = (T)(fi.area * inv4l / 6.0);
+        w.c = a; w.e = w.w = w.n = w.s = w.se = w.nw = o;
+        return w;
+    }
+    const T c0 = (T)fi.cot[0], c1 = (T)fi.cot[1], c2 = (T)fi.cot[2];
+    if (op == OP_LAPLACE) {
+        w.c = (T)(2.0 * (fi.cot[0] + fi.cot[1] + fi.cot[2]));
+        w.e = w.w = -c2;
+        w.n = w.s = -c1;
+        w.se = w.nw = -c0;
+        return w;
+    }
+    const T k0 = kap[p], kE = kap[p + 1], kW = kap[p - 1], kN = kap[p + up], kS = kap[p - dn];
+    const T kSE = kap[p - dn + 1], kNW = kap[p + up - 1];
+    const T third = (T)(1.0 / 3.0), h = (T)0.5;
+    // the six micro-triangles around the point
+    const T t1 = (k0 + kE + kN) * third;     // up   (i, j)
+    const T t2 = (kSE + kE + k0) * third;    // down (i, j-1)
+    const T t3 = (kW + k0 + kNW) * third;    // up   (i-1, j)
+    const T t4 = (kS + k0 + kW) * third;     // down (i-1, j-1)
+    const T t5 = (k0 + kN + kNW) * third;    // down (i-1, j)
+    const T t6 = (kS + kSE + k0) * third;    // up   (i, j-1)
+    w.e = -h * c2 * (t1 + t2);
+    w.w = -h * c2 * (t3 + t4);
+    w.n = -h * c1 * (t1 + t5);
+    w.s = -h * c1 * (t6 + t4);
+    w.se = -h * c0 * (t6 + t2);
+    w.nw = -h * c0 * (t3 + t5);
+    w.c = -(w.e + w.w + w.n + w.s + w.se + w.nw);
+    return w;
+}
+
+// Interior-edge point k: neighbours k-1, k+1 on the edge and g_s[k-1], g_s[k]
+// in the ghost row of face s (s = 0, 1).
+template <class T>
+__device__ __forceinline__ WE<T> edge_weights(int op, const EdgeInfo& ei, double inv4l,
+                                              const T* kap, int64_t m, int64_t g0, int64_t g1,
+                                              int k) {
+    WE<T> w;
+    if (op == OP_MASS) {
+        const double a0 = ei.area[0] * inv4l, a1 = ei.area[1] * inv4l;
+        w.al = w.ah = (T)((a0 + a1) / 12.0);
+        w.l0 = w.h0 = (T)(a0 / 6.0);
+        w.l1 = w.h1 = (T)(a1 / 6.0);
+        w.c = (T)((a0 + a1) / 2.0);
+        return w;
+    }
+    if (op == OP_LAPLACE) {
+        w.al = w.ah = (T)(-0.5 * (ei.cA[0] + ei.cA[1]));
+        w.l0 = (T)(-ei.cL[0]); w.h0 = (T)(-ei.cH[0]);
+        w.l1 = (T)(-ei.cL[1]); w.h1 = (T)(-ei.cH[1]);
+        w.c = (T)(ei.cA[0] + ei.cL[0] + ei.cH[0] + ei.cA[1] + ei.cL[1] + ei.cH[1]);
+        return w;
+    }
+    const T third = (T)(1.0 / 3.0), h = (T)0.5;
+    const T km = kap[m + k - 1], k0 = kap[m + k], kp = kap[m + k + 1];
+    const T a0 = kap[g0 + k - 1], b0 = kap[g0 + k];
+    const T a1 = kap[g1 + k - 1], b1 = kap[g1 + k];
+    // per face s: T1(k) = (k, k+1, g[k]), T1(k-1) = (k-1, k, g[k-1]),
+    // T2(k) = (k, g[k], g[k-1])
+    const T t1_0 = (k0 + kp + b0) * third, t1m_0 = (km + k0 + a0) * third, t2_0 = (k0 + b0 + a0) * third;
+    const T t1_1 = (k0 + kp + b1) * third, t1m_1 = (km + k0 + a1) * third, t2_1 = (k0 + b1 + a1) * third;
+    const T cA0 = (T)ei.cA[0], cA1 = (T)ei.cA[1];
+    w.al = -h * (cA0 * t1m_0 + cA1 * t1m_1);
+    w.ah = -h * (cA0 * t1_0 + cA1 * t1_1);
+    w.h0 = -h * (T)ei.cH[0] * (t1_0 + t2_0);
+    w.l0 = -h * (T)ei.cL[0] * (t2_0 + t1m_0);
+    w.h1 = -h * (T)ei.cH[1] * (t1_1 + t2_1);
+    w.l1 = -h * (T)ei.cL[1] * (t2_1 + t1m_1);
+    w.c = -(w.al + w.ah + w.l0 + w.h0 + w.l1 + w.h1);
+    return w;
+}
+
+// Weight of interior vertex v towards its ghost slot q (the edge point next
+// to v on incident edge q).
+template <class T>
+__device__ __forceinline__ T vertex_weight(int op, const VertexInfo& vi, double inv4l,
+                                           const T* kap, int64_t vb, int q) {
+    if (op == OP_MASS)
+        return (T)((vi.area[q][0] + vi.area[q][1]) * inv4l / 12.0);
+    if (op == OP_LAPLACE)
+        return (T)(-0.5 * (vi.cA[q][0] + vi.cA[q][1]));
+    const T third = (T)(1.0 / 3.0);
+    const T kv = kap[vb], kq = kap[vb + 1 + q];
+    T s = (T)0;
+    for (int f = 0; f < vi.nfe[q]; ++f) {
+        const T kp = kap[vb + 1 + vi.partner[q][f]];
+        s += (T)vi.cA[q][f] * ((kv + kq + kp) * third);
+    }
+    return (T)-0.5 * s;
+}
+
+// ------------------------------------------------------------------ kernels
+
+// Copy ghost entries [lo, hi) of the ghost table.
+template <class T>
+__global__ __launch_bounds__(NT) void k_sync(T* __restrict__ x, const int64_t* __restrict__ dst,
+                                             const int64_t* __restrict__ src, int64_t lo, int64_t hi) {
+    for (int64_t t = lo + blockIdx.x * (int64_t)NT + threadIdx.x; t < hi; t += (int64_t)gridDim.x * NT)
+        x[dst[t]] = x[src[t]];
+}
+
+template <class T>
+__global__ __launch_bounds__(NT) void k_fill(T* __restrict__ x, int64_t n, T v) {
+    for (int64_t t = blockIdx.x * (int64_t)NT + threadIdx.x; t < n; t += (int64_t)gridDim.x * NT)
+        x[t] = v;
+}
+
+// Generic loop over face-interior points in 64 x 4 tiles.
+#define FACE_TILE_LOOP(L)                                                                   \
+    const int n = (L).n;                                                                    \
+    const int ti_ = threadIdx.x & (TILE_I - 1), tj_ = threadIdx.x / TILE_I;                 \
+    const int64_t nitems_ = (int64_t)(L).F * (L).ntiles;                                    \
+    for (int64_t it_ = blockIdx.x; it_ < nitems_; it_ += gridDim.x) {                      \
+        const int face = (int)(it_ / (L).ntiles);                                           \
+        const int2 tl_ = (L).tiles[it_ % (L).ntiles];                                       \
+        const int i = tl_.x * TILE_I + ti_, j = tl_.y * TILE_J + tj_;                       \
+        if (!(i >= 1 && j >= 1 && i + j <= n - 2)) continue;                                \
+        const FaceInfo& fi = (L).faces[face];                                               \
+        const int64_t p = face_base((L), face) + (L).row_off[j] + i;                        \
+        const int64_t up = (L).row_off[j + 1] - (L).row_off[j];                             \
+        const int64_t dn = (L).row_off[j] - (L).row_off[j - 1];
+
+#define FACE_TILE_END }
+
+template <class T>
+__global__ __launch_bounds__(NT) void k_face_apply(LevelDev L, int op, const T* __restrict__ x,
+                                                   T* __restrict__ y, const T* __restrict__ kap) {
+    FACE_TILE_LOOP(L)
+    (void)fi;
+    const W7<T> w = face_weights<T>(op, fi, L.inv4l, kap, p, up, dn);
+    y[p] = w.c * x[p] + w.e * x[p + 1] + w.w * x[p - 1] + w.n * x[p + up] + w.s * x[p - dn] +
+           w.se * x[p - dn + 1] + w.nw * x[p + up - 1];
+    FACE_TILE_END
+}
+
+// Edge and vertex rows of y = A x.  Thread space: E*(n-2) edge points, then V.
+template <class T>
+__global__ __launch_bounds__(NT) void k_low_apply(LevelDev L, int op, const T* __restrict__ x,
+                                                  T* __restrict__ y, const T* __restrict__ kap) {
+    const int n = L.n;
+    const int64_t ne = (int64_t)L.E * (n - 2);
+    for (int64_t t = blockIdx.x * (int64_t)NT + threadIdx.x; t < ne + L.V; t += (int64_t)gridDim.x * NT) {
+        if (t < ne) {
+            const int e = (int)(t / (n - 2)), k = (int)(t % (n - 2)) + 1;
+            const EdgeInfo& ei = L.edges[e];
+            const int64_t m = edge_main(L, e);
+            if (ei.boundary) { y[m + k] = (T)0; continue; }
+            const int64_t g0 = edge_ghost(L, e, 0), g1 = edge_ghost(L, e, 1);
+            const WE<T> w = edge_weights<T>(op, ei, L.inv4l, kap, m, g0, g1, k);
+            y[m + k] = w.c * x[m + k] + w.al * x[m + k - 1] + w.ah * x[m + k + 1] +
+                       w.l0 * x[g0 + k - 1] + w.h0 * x[g0 + k] + w.l1 * x[g1 + k - 1] + w.h1 * x[g1 + k];
+        } else {
+            const int v = (int)(t - ne);
+            const VertexInfo& vi = L.verts[v];
+            const int64_t vb = vert_off(L, v);
+            if (vi.boundary) { y[vb] = (T)0; continue; }
+            T s = (T)0, c = (T)0;
+            for (int q = 0; q < vi.deg; ++q) {
+                const T wq = vertex_weight<T>(op, vi, L.inv4l, kap, vb, q);
+                s += wq * x[vb + 1 + q];
+                c += wq;
+            }
+            c = (op == OP_MASS) ? c : -c;
+            y[vb] = c * x[vb] + s;
+        }
+    }
+}
+
+template <class T>
+__global__ __launch_bounds__(NT) void k_face_residual(LevelDev L, int op, const T* __restrict__ u,
+                                                      const T* __restrict__ f, T* __restrict__ r,
+                                                      const T* __restrict__ kap, double* partials) {
+    __shared__ double sm[NT / 64 + 1];
+    double acc = 0.0;
+    {
+        FACE_TILE_LOOP(L)
+        const W7<T> w = face_weights<T>(op, fi, L.inv4l, kap, p, up, dn);
+        const T au = w.c * u[p] + w.e * u[p + 1] + w.w * u[p - 1] + w.n * u[p + up] + w.s * u[p - dn] +
+                     w.se * u[p - dn + 1] + w.nw * u[p + up - 1];
+        const T rv = f[p] - au;
+        r[p] = rv;
+        acc += (double)rv * (double)rv;
+        FACE_TILE_END
+    }
+    if (partials) {
+        const double s = block_sum<NT>(acc, sm);
+        if (threadIdx.x == 0) partials[blockIdx.x] = s;
+    }
+}
+
+template <class T>
+__global__ __launch_bounds__(NT) void k_low_residual(LevelDev L, int op, const T* __restrict__ u,
+                                                     const T* __restrict__ f, T* __restrict__ r,
+                                                     const T* __restrict__ kap, double* partials) {
+    __shared__ double sm[NT / 64 + 1];
+    const int n = L.n;
+    const int64_t ne = (int64_t)L.E * (n - 2);
+    double acc = 0.0;
+    for (int64_t t = blockIdx.x * (int64_t)NT + threadIdx.x; t < ne + L.V; t += (int64_t)gridDim.x * NT) {
+        if (t < ne) {
+            const int e = (int)(t / (n - 2)), k = (int)(t % (n - 2)) + 1;
+            const EdgeInfo& ei = L.edges[e];
+            const int64_t m = edge_main(L, e);
+            if (ei.boundary) { r[m + k] = (T)0; continue; }
+            const int64_t g0 = edge_ghost(L, e, 0), g1 = edge_ghost(L, e, 1);
+            const WE<T> w = edge_weights<T>(op, ei, L.inv4l, kap, m, g0, g1, k);
+            const T au = w.c * u[m + k] + w.al * u[m + k - 1] + w.ah * u[m + k + 1] +
+                         w.l0 * u[g0 + k - 1] + w.h0 * u[g0 + k] + w.l1 * u[g1 + k - 1] + w.h1 * u[g1 + k];
+            const T rv = f[m + k] - au;
+            r[m + k] = rv;
+            acc += (double)rv * (double)rv;
+        } else {
+            const int v = (int)(t - ne);
+            const VertexInfo& vi = L.verts[v];
+            const int64_t vb = vert_off(L, v);
+            if (vi.boundary) { r[vb] = (T)0; continue; }
+            T s = (T)0, c = (T)0;
+            for (int q = 0; q < vi.deg; ++q) {
+                const T wq = vertex_weight<T>(op, vi, L.inv4l, kap, vb, q);
+                s += wq * u[vb + 1 + q];
+                c += wq;
+            }
+            c = (op == OP_MASS) ? c : -c;
+            const T rv = f[vb] - (c * u[vb] + s);
+            r[vb] = rv;
+            acc += (double)rv * (double)rv;
+        }
+    }
+    if (partials) {
+        const double s = block_sum<NT>(acc, sm);
+        if (threadIdx.x == 0) partials[blockIdx.x] = s;
+    }
+}
+
+// Sum partials[0, count) in a fixed order; optional square root.
+__global__ __launch_bounds__(1024) void k_reduce_final(const double* __restrict__ partials,
+                                                       int64_t count, double* out, int do_sqrt) {
+    __shared__ double sm[1024 / 64 + 1];
+    double a = 0.0;
+    for (int64_t t = threadIdx.x; t < count; t += 1024) a += partials[t];
+    const double s = block_sum<1024>(a, sm);
+    if (threadIdx.x == 0) *out = do_sqrt ? sqrt(s) : s;
+}
+
+// One face colour of the Gauss-Seidel sweep (all faces at once).
+template <class T>
+__global__ __launch_bounds__(NT) void k_face_gs_colour(LevelDev L, int op, T* __restrict__ u,
+                                                       const T* __restrict__ f,
+                                                       const T* __restrict__ kap, int colour) {
+    FACE_TILE_LOOP(L)
+    if (face_colour(fi.colour_rule, i, j) != colour) continue;
+    const W7<T> w = face_weights<T>(op, fi, L.inv4l, kap, p, up, dn);
+    const T off = w.e * u[p + 1] + w.w * u[p - 1] + w.n * u[p + up] + w.s * u[p - dn] +
+                  w.se * u[p - dn + 1] + w.nw * u[p + up - 1];
+    u[p] = (f[p] - off) / w.c;
+    FACE_TILE_END
+}
+
+// Stage A (stage = 0): interior vertices and even-k points of interior
+// edges; stage B (stage = 1): odd-k points.  Points of a stage are updated
+// at once from the values before the stage.
+template <class T>
+__global__ __launch_bounds__(NT) void k_low_gs(LevelDev L, int op, T* __restrict__ u,
+                                               const T* __restrict__ f, const T* __restrict__ kap,
+                                               int stage) {
+    const int n = L.n;
+    const int64_t ne = (int64_t)L.n_iedges * (n - 2);
+    const int64_t nv = stage == 0 ? L.n_iverts : 0;
+    for (int64_t t = blockIdx.x * (int64_t)NT + threadIdx.x; t < ne + nv; t += (int64_t)gridDim.x * NT) {
+        if (t < ne) {
+            const int e = L.iedges[t / (n - 2)], k = (int)(t % (n - 2)) + 1;
+            if ((k & 1) != stage) continue;
+            const EdgeInfo& ei = L.edges[e];
+            const int64_t m = edge_main(L, e), g0 = edge_ghost(L, e, 0), g1 = edge_ghost(L, e, 1);
+            const WE<T> w = edge_weights<T>(op, ei, L.inv4l, kap, m, g0, g1, k);
+            const T off = w.al * u[m + k - 1] + w.ah * u[m + k + 1] + w.l0 * u[g0 + k - 1] +
+                          w.h0 * u[g0 + k] + w.l1 * u[g1 + k - 1] + w.h1 * u[g1 + k];
+            u[m + k] = (f[m + k] - off) / w.c;
+        } else {
+            const int v = L.iverts[t - ne];
+            const VertexInfo& vi = L.verts[v];
+            const int64_t vb = vert_off(L, v);
+            T s = (T)0, c = (T)0;
+            for (int q = 0; q < vi.deg; ++q) {
+                const T wq = vertex_weight<T>(op, vi, L.inv4l, kap, vb, q);
+                s += wq * u[vb + 1 + q];
+                c += wq;
+            }
+            c = (op == OP_MASS) ? c : -c;
+            u[vb] = (f[vb] - s) / c;
+        }
+    }
+}
+
+// Restriction of face-interior coarse points: fc(I,J) = r(2I,2J) + 1/2 sum of
+// the six fine neighbours (transpose of linear interpolation).
+template <class T>
+__global__ __launch_bounds__(NT) void k_face_restrict(LevelDev Lf, LevelDev Lc, const T* __restrict__ r,
+                                                      T* __restrict__ fc) {
+    FACE_TILE_LOOP(Lc)
+    (void)fi; (void)up; (void)dn;
+    const int jf = 2 * j;
+    const int64_t q = face_base(Lf, face) + Lf.row_off[jf] + 2 * i;
+    const int64_t upf = Lf.row_off[jf + 1] - Lf.row_off[jf];
+    const int64_t dnf = Lf.row_off[jf] - Lf.row_off[jf - 1];
+    const T nb = r[q + 1] + r[q - 1] + r[q + upf] + r[q - dnf] + r[q - dnf + 1] + r[q + upf - 1];
+    fc[p] = r[q] + (T)0.5 * nb;
+    FACE_TILE_END
+}
+
+template <class T>
+__global__ __launch_bounds__(NT) void k_low_restrict(LevelDev Lf, LevelDev Lc, const T* __restrict__ r,
+                                                     T* __restrict__ fc) {
+    const int nc = Lc.n;
+    const int64_t ne = (int64_t)Lc.E * (nc - 2);
+    for (int64_t t = blockIdx.x * (int64_t)NT + threadIdx.x; t < ne + Lc.V; t += (int64_t)gridDim.x * NT) {
+        if (t < ne) {
+            const int e = (int)(t / (nc - 2)), K = (int)(t % (nc - 2)) + 1;
+            const int64_t mc = edge_main(Lc, e);
+            if (Lc.edges[e].boundary) { fc[mc + K] = (T)0; continue; }
+            const int64_t m = edge_main(Lf, e), g0 = edge_ghost(Lf, e, 0), g1 = edge_ghost(Lf, e, 1);
+            const int k = 2 * K;
+            const T nb = r[m + k - 1] + r[m + k + 1] + r[g0 + k - 1] + r[g0 + k] + r[g1 + k - 1] + r[g1 + k];
+            fc[mc + K] = r[m + k] + (T)0.5 * nb;
+        } else {
+            const int v = (int)(t - ne);
+            const VertexInfo& vi = Lc.verts[v];
+            const int64_t vc = vert_off(Lc, v);
+            if (vi.boundary) { fc[vc] = (T)0; continue; }
+            const int64_t vf = vert_off(Lf, v);
+            T nb = (T)0;
+            for (int q = 0; q < vi.deg; ++q) nb += r[vf + 1 + q];
+            fc[vc] = r[vf] + (T)0.5 * nb;
+        }
+    }
+}
+
+// u += P uc at fine face-interior points.  A fine point coincides with a
+// coarse point or is the midpoint of a coarse micro-edge.
+template <class T>
+__global__ __launch_bounds__(NT) void k_face_prolong(LevelDev Lf, LevelDev Lc, const T* __restrict__ uc,
+                                                     T* __restrict__ u) {
+    FACE_TILE_LOOP(Lf)
+    (void)fi; (void)up; (void)dn;
+    const int64_t cb = face_base(Lc, face);
+    const int I = i >> 1, J = j >> 1;
+    T c;
+    if (!(i & 1) && !(j & 1)) {
+        c = uc[cb + Lc.row_off[J] + I];
+    } else if ((i & 1) && !(j & 1)) {
+        c = (T)0.5 * (uc[cb + Lc.row_off[J] + I] + uc[cb + Lc.row_off[J] + I + 1]);
+    } else if (!(i & 1) && (j & 1)) {
+        c = (T)0.5 * (uc[cb + Lc.row_off[J] + I] + uc[cb + Lc.row_off[J + 1] + I]);
+    } else {
+        c = (T)0.5 * (uc[cb + Lc.row_off[J] + I + 1] + uc[cb + Lc.row_off[J + 1] + I]);
+    }
+    u[p] += c;
+    FACE_TILE_END
+}
+
+template <class T>
+__global__ __launch_bounds__(NT) void k_low_prolong(LevelDev Lf, LevelDev Lc, const T* __restrict__ uc,
+                                                    T* __restrict__ u) {
+    const int n = Lf.n;
+    const int64_t ne = (int64_t)Lf.n_iedges * (n - 2);
+    for (int64_t t = blockIdx.x * (int64_t)NT + threadIdx.x; t < ne + Lf.n_iverts; t += (int64_t)gridDim.x * NT) {
+        if (t < ne) {
+            const int e = Lf.iedges[t / (n - 2)], k = (int)(t % (n - 2)) + 1;
+            const int64_t m = edge_main(Lf, e), mc = edge_main(Lc, e);
+            const T c = (k & 1) ? (T)0.5 * (uc[mc + (k >> 1)] + uc[mc + (k >> 1) + 1]) : uc[mc + (k >> 1)];
+            u[m + k] += c;
+        } else {
+            const int v = Lf.iverts[t - ne];
+            u[vert_off(Lf, v)] += uc[vert_off(Lc, v)];
+        }
+    }
+}
+
+// Canonical <-> layout.  to_canon = 0: field[owner] = canon; 1: reverse.
+template <class T>
+__global__ __launch_bounds__(NT) void k_face_canon(LevelDev L, const T* __restrict__ src,
+                                                   T* __restrict__ dst, int to_canon) {
+    FACE_TILE_LOOP(L)
+    (void)fi; (void)up; (void)dn;
+    const int64_t nfi = (int64_t)(n - 2) * (n - 3) / 2;
+    const int64_t before = (int64_t)(j - 1) * (n - 2) - (int64_t)(j - 1) * j / 2;
+    const int64_t c = L.can_face_base + (int64_t)face * nfi + before + (i - 1);
+    if (to_canon) dst[c] = src[p]; else dst[p] = src[c];
+    FACE_TILE_END
+}
+
+template <class T>
+__global__ __launch_bounds__(NT) void k_low_canon(LevelDev L, const T* __restrict__ src,
+                                                  T* __restrict__ dst, int to_canon) {
+    const int n = L.n;
+    const int64_t ne = (int64_t)L.E * (n - 2);
+    for (int64_t t = blockIdx.x * (int64_t)NT + threadIdx.x; t < ne + L.V; t += (int64_t)gridDim.x * NT) {
+        int64_t p, c;
+        if (t < ne) {
+            const int e = (int)(t / (n - 2)), k = (int)(t % (n - 2)) + 1;
+            p = edge_main(L, e) + k;
+            c = L.can_edge_base + t;
+        } else {
+            const int v = (int)(t - ne);
+            p = vert_off(L, v);
+            c = v;
+        }
+        if (to_canon) dst[c] = src[p]; else dst[p] = src[c];
+    }
+}
+
+// Injection of owned values: coarse point = coincident fine point.
+template <class T>
+__global__ __launch_bounds__(NT) void k_face_inject(LevelDev Lf, LevelDev Lc, const T* __restrict__ kf,
+                                                    T* __restrict__ kc) {
+    FACE_TILE_LOOP(Lc)
+    (void)fi; (void)up; (void)dn;
+    kc[p] = kf[face_base(Lf, face) + Lf.row_off[2 * j] + 2 * i];
+    FACE_TILE_END
+}
+
+template <class T>
+__global__ __launch_bounds__(NT) void k_low_inject(LevelDev Lf, LevelDev Lc, const T* __restrict__ kf,
+                                                   T* __restrict__ kc) {
+    const int nc = Lc.n;
+    const int64_t ne = (int64_t)Lc.E * (nc - 2);
+    for (int64_t t = blockIdx.x * (int64_t)NT + threadIdx.x; t < ne + Lc.V; t += (int64_t)gridDim.x * NT) {
+        if (t < ne) {
+            const int e = (int)(t / (nc - 2)), K = (int)(t % (nc - 2)) + 1;
+            kc[edge_main(Lc, e) + K] = kf[edge_main(Lf, e) + 2 * K];
+        } else {
+            const int v = (int)(t - ne);
+            kc[vert_off(Lc, v)] = kf[vert_off(Lf, v)];
+        }
+    }
+}
+
+// ELL values of the coarse operator, in the order [centre, neighbours...]
+// used by the host-built column table.
+__global__ __launch_bounds__(NT) void k_coarse_extract(LevelDev L, CoarseDev C, int op,
+                                                       const double* __restrict__ kap,
+                                                       double* __restrict__ vals) {
+    const int n = L.n;
+    for (int p = blockIdx.x * NT + threadIdx.x; p < C.N; p += gridDim.x * NT) {
+        double* v = vals + (int64_t)p * C.W;
+        for (int w = 0; w < C.W; ++w) v[w] = 0.0;
+        const int kind = C.kind[p], prim = C.prim[p];
+        if (kind == 2) {
+            const int i = C.pa[p], j = C.pb[p];
+            const int64_t q = face_base(L, prim) + L.row_off[j] + i;
+            const int64_t up = L.row_off[j + 1] - L.row_off[j], dn = L.row_off[j] - L.row_off[j - 1];
+            const W7<double> w = face_weights<double>(op, L.faces[prim], L.inv4l, kap, q, up, dn);
+            v[0] = w.c; v[1] = w.e; v[2] = w.w; v[3] = w.n; v[4] = w.s; v[5] = w.se; v[6] = w.nw;
+        } else if (kind == 1) {
+            const int k = C.pa[p];
+            const int64_t m = edge_main(L, prim), g0 = edge_ghost(L, prim, 0), g1 = edge_ghost(L, prim, 1);
+            const WE<double> w = edge_weights<double>(op, L.edges[prim], L.inv4l, kap, m, g0, g1, k);
+            v[0] = w.c; v[1] = w.al; v[2] = w.ah; v[3] = w.l0; v[4] = w.h0; v[5] = w.l1; v[6] = w.h1;
+        } else {
+            const VertexInfo& vi = L.verts[prim];
+            const int64_t vb = vert_off(L, prim);
+            double c = 0.0;
+            for (int q = 0; q < vi.deg; ++q) {
+                const double wq = vertex_weight<double>(op, vi, L.inv4l, kap, vb, q);
+                v[1 + q] = wq;
+                c += wq;
+            }
+            v[0] = (op == OP_MASS) ? c : -c;
+        }
+        (void)n;
+    }
+}
+
+// Jacobi-preconditioned CG from zero on the coarse interior system (one
+// workgroup); b is read from the residual field, u[owner] += x at the end.
+template <class T>
+__global__ __launch_bounds__(1024) void k_coarse_pcg(CoarseDev C, const double* __restrict__ vals,
+                                                     const T* __restrict__ rf, T* __restrict__ uf,
+                                                     double tol, int maxit) {
+    __shared__ double sm[1024 / 64 + 1];
+    const int N = C.N, W = C.W, tid = threadIdx.x;
+    double* x = C.vec;
+    double* r = x + N;
+    double* z = r + N;
+    double* p = z + N;
+    double* q = p + N;
+    double bb = 0.0;
+    for (int a = tid; a < N; a += 1024) {
+        const double b = (double)rf[C.owner[a]];
+        x[a] = 0.0;
+        r[a] = b;
+        bb += b * b;
+    }
+    bb = block_sum<1024>(bb, sm);
+    const double bn = sqrt(bb);
+    if (bn == 0.0) return;
+    double rz = 0.0;
+    for (int a = tid; a < N; a += 1024) {
+        z[a] = r[a] / vals[(int64_t)a * W];
+        p[a] = z[a];
+        rz += r[a] * z[a];
+    }
+    rz = block_sum<1024>(rz, sm);
+    for (int it = 0; it < maxit; ++it) {
+        double pq = 0.0;
+        for (int a = tid; a < N; a += 1024) {
+            double s = 0.0;
+            for (int w = 0; w < W; ++w) {
+                const int c = C.cols[(int64_t)a * W + w];
+                if (c >= 0) s += vals[(int64_t)a * W + w] * p[c];
+            }
+            q[a] = s;
+            pq += p[a] * s;
+        }
+        pq = block_sum<1024>(pq, sm);
+        const double alpha = rz / pq;
+        double rr = 0.0;
+        for (int a = tid; a < N; a += 1024) {
+            x[a] += alpha * p[a];
+            r[a] -= alpha * q[a];
+            rr += r[a] * r[a];
+        }
+        rr = block_sum<1024>(rr, sm);
+        if (sqrt(rr) <= tol * bn) break;
+        double rzn = 0.0;
+        for (int a = tid; a < N; a += 1024) {
+            z[a] = r[a] / vals[(int64_t)a * W];
+            rzn += r[a] * z[a];
+        }
+        rzn = block_sum<1024>(rzn, sm);
+        const double beta = rzn / rz;
+        rz = rzn;
+        for (int a = tid; a < N; a += 1024) p[a] = z[a] + beta * p[a];
+        __syncthreads();
+    }
+    __syncthreads();
+    for (int a = tid; a < N; a += 1024) uf[C.owner[a]] += (T)x[a];
+}
+
+__global__ __launch_bounds__(NT) void k_f64_to_f32(const double* __restrict__ s, float* __restrict__ d,
+                                                   int64_t n) {
+    for (int64_t t = blockIdx.x * (int64_t)NT + threadIdx.x; t < n; t += (int64_t)gridDim.x * NT)
+        d[t] = (float)s[t];
+}
+
+__global__ __launch_bounds__(NT) void k_add_f32_to_f64(double* __restrict__ u, const float* __restrict__ e,
+                                                       int64_t n) {
+    for (int64_t t = blockIdx.x * (int64_t)NT + threadIdx.x; t < n; t += (int64_t)gridDim.x * NT)
+        u[t] += (double)e[t];
+}
+
+// ------------------------------------------------------------------ launchers
+
+static inline int grid_for(int64_t items, int cap) {
+    int64_t g = (items + NT - 1) / NT;
+    if (g < 1) g = 1;
+    if (g > cap) g = cap;
+    return (int)g;
+}
+static inline int face_grid(const LevelDev& L) {
+    int64_t g = (int64_t)L.F * L.ntiles;
+    if (g < 1) g = 1;
+    return (int)(g > MAX_FACE_BLOCKS ? MAX_FACE_BLOCKS : g);
+}
+static inline int64_t low_items(const LevelDev& L) { return (int64_t)L.E * (L.n - 2) + L.V; }
+
+template <class T>
+static const T* kap_of(const hhg_mesh* M, int level);
+template <>
+const double* kap_of<double>(const hhg_mesh* M, int level) { return M->kap64[level]; }
+template <>
+const float* kap_of<float>(const hhg_mesh* M, int level) { return M->kap32[level]; }
+
+hipError_t launch_sync(const hhg_mesh* M, int level, int dtype, void* x, int mask, hipStream_t s) {
+    const LevelDev L = M->dev(level);
+    // classes are stored contiguously in the order VERT, EEVEN, EODD, FACE
+    int c = 0;
+    while (c < G_NCLS) {
+        if (!(mask & (1 << c))) { ++c; continue; }
+        int c2 = c;
+        while (c2 < G_NCLS && (mask & (1 << c2))) ++c2;
+        const int64_t lo = L.gcls[c], hi = L.gcls[c2];
+        if (hi > lo) {
+            const int g = grid_for(hi - lo, 4096);
+            if (dtype == DT_F64)
+                k_sync<double><<<g, NT, 0, s>>>((double*)x, L.gdst, L.gsrc, lo, hi);
+            else
+                k_sync<float><<<g, NT, 0, s>>>((float*)x, L.gdst, L.gsrc, lo, hi);
+        }
+        c = c2;
+    }
+    return hipGetLastError();
+}
+
+template <class T>
+static hipError_t apply_t(const hhg_mesh* M, int level, int op, const T* x, T* y, hipStream_t s) {
+    const LevelDev L = M->dev(level);
+    const T* kap = kap_of<T>(M, level);
+    k_face_apply<T><<<face_grid(L), NT, 0, s>>>(L, op, x, y, kap);
+    k_low_apply<T><<<grid_for(low_items(L), MAX_LOW_BLOCKS), NT, 0, s>>>(L, op, x, y, kap);
+    return launch_sync(M, level, sizeof(T) == 8 ? DT_F64 : DT_F32, y, GM_ALL, s);
+}
+
+hipError_t launch_apply(const hhg_mesh* M, int level, int op, int dtype, const void* x, void* y,
+                        hipStream_t s) {
+    if (dtype == DT_F64) return apply_t<double>(M, level, op, (const double*)x, (double*)y, s);
+    return apply_t<float>(M, level, op, (const float*)x, (float*)y, s);
+}
+
+template <class T>
+static hipError_t residual_t(const hhg_mesh* M, int level, int op, const T* u, const T* f, T* r,
+                             double* norm, int sync_mask, hipStream_t s) {
+    const LevelDev L = M->dev(level);
+    const T* kap = kap_of<T>(M, level);
+    const int gf = face_grid(L), gl = grid_for(low_items(L), MAX_LOW_BLOCKS);
+    double* part = norm ? M->partials : nullptr;
+    k_face_residual<T><<<gf, NT, 0, s>>>(L, op, u, f, r, kap, part);
+    k_low_residual<T><<<gl, NT, 0, s>>>(L, op, u, f, r, kap, part ? part + gf : nullptr);
+    if (norm) k_reduce_final<<<1, 1024, 0, s>>>(M->partials, gf + gl, norm, 1);
+    if (sync_mask) return launch_sync(M, level, sizeof(T) == 8 ? DT_F64 : DT_F32, r, sync_mask, s);
+    return hipGetLastError();
+}
+
+hipError_t launch_residual(const hhg_mesh* M, int level, int op, int dtype, const void* u,
+                           const void* f, void* r, double* norm, int sync_mask, hipStream_t s) {
+    if (dtype == DT_F64)
+        return residual_t<double>(M, level, op, (const double*)u, (const double*)f, (double*)r, norm,
+                                  sync_mask, s);
+    return residual_t<float>(M, level, op, (const float*)u, (const float*)f, (float*)r, norm,
+                             sync_mask, s);
+}
+
+struct TimingScope {
+    const hhg_mesh* M;
+    hipStream_t s;
+    bool on;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    TimingScope(const hhg_mesh* m, hipStream_t st, bool enable) : M(m), s(st), on(enable) {
+        if (!on) return;
+        hhg_mesh* mm = const_cast<hhg_mesh*>(M);
+        size_t idx = (size_t)mm->t_launches;
+        if (idx >= mm->t_events.size()) {
+            hipEvent_t a, b;
+            (void)hipEventCreate(&a);
+            (void)hipEventCreate(&b);
+            mm->t_events.emplace_back((void*)a, (void*)b);
+        }
+        e0 = (hipEvent_t)mm->t_events[idx].first;
+        e1 = (hipEvent_t)mm->t_events[idx].second;
+        (void)hipEventRecord(e0, s);
+    }
+    ~TimingScope() {
+        if (!on) return;
+        (void)hipEventRecord(e1, s);
+        const_cast<hhg_mesh*>(M)->t_launches++;
+    }
+};
+
+template <class T>
+static hipError_t gs_t(const hhg_mesh* M, int level, int op, T* u, const T* f, int backward,
+                       hipStream_t s) {
+    const LevelDev L = M->dev(level);
+    const T* kap = kap_of<T>(M, level);
+    const int dt = sizeof(T) == 8 ? DT_F64 : DT_F32;
+    const int gl = grid_for((int64_t)L.n_iedges * (L.n - 2) + L.n_iverts, MAX_LOW_BLOCKS);
+    const bool timed = M->timing && level == M->m.L;
+    auto faces = [&]() {
+        TimingScope ts(M, s, timed);
+        for (int c = 0; c < 3; ++c) {
+            const int col = backward ? 2 - c : c;
+            k_face_gs_colour<T><<<face_grid(L), NT, 0, s>>>(L, op, u, f, kap, col);
+        }
+    };
+    hipError_t e;
+    if (!backward) {
+        k_low_gs<T><<<gl, NT, 0, s>>>(L, op, u, f, kap, 0);
+        if ((e = launch_sync(M, level, dt, u, GM_VERT | GM_EEVEN, s)) != hipSuccess) return e;
+        k_low_gs<T><<<gl, NT, 0, s>>>(L, op, u, f, kap, 1);
+        if ((e = launch_sync(M, level, dt, u, GM_EODD, s)) != hipSuccess) return e;
+        faces();
+        return launch_sync(M, level, dt, u, GM_FACE, s);
+    }
+    faces();
+    if ((e = launch_sync(M, level, dt, u, GM_FACE, s)) != hipSuccess) return e;
+    k_low_gs<T><<<gl, NT, 0, s>>>(L, op, u, f, kap, 1);
+    if ((e = launch_sync(M, level, dt, u, GM_EODD, s)) != hipSuccess) return e;
+    k_low_gs<T><<<gl, NT, 0, s>>>(L, op, u, f, kap, 0);
+    return launch_sync(M, level, dt, u, GM_VERT | GM_EEVEN, s);
+}
+
+hipError_t launch_gs_sweep(const hhg_mesh* M, int level, int op, int dtype, void* u, const void* f,
+                           int backward, hipStream_t s) {
+    if (dtype == DT_F64) return gs_t<double>(M, level, op, (double*)u, (const double*)f, backward, s);
+    return gs_t<float>(M, level, op, (float*)u, (const float*)f, backward, s);
+}
+
+template <class T>
+static hipError_t restrict_t(const hhg_mesh* M, int level, const T* r, T* fc, hipStream_t s) {
+    const LevelDev Lf = M->dev(level), Lc = M->dev(level - 1);
+    k_face_restrict<T><<<face_grid(Lc), NT, 0, s>>>(Lf, Lc, r, fc);
+    k_low_restrict<T><<<grid_for(low_items(Lc), MAX_LOW_BLOCKS), NT, 0, s>>>(Lf, Lc, r, fc);
+    return hipGetLastError();
+}
+
+hipError_t launch_restrict(const hhg_mesh* M, int level, int dtype, const void* r, void* fc,
+                           hipStream_t s) {
+    if (dtype == DT_F64) return restrict_t<double>(M, level, (const double*)r, (double*)fc, s);
+    return restrict_t<float>(M, level, (const float*)r, (float*)fc, s);
+}
+
+template <class T>
+static hipError_t prolong_t(const hhg_mesh* M, int level, const T* uc, T* u, hipStream_t s) {
+    const LevelDev Lf = M->dev(level), Lc = M->dev(level - 1);
+    k_face_prolong<T><<<face_grid(Lf), NT, 0, s>>>(Lf, Lc, uc, u);
+    k_low_prolong<T><<<grid_for((int64_t)Lf.n_iedges * (Lf.n - 2) + Lf.n_iverts, MAX_LOW_BLOCKS), NT, 0, s>>>(
+        Lf, Lc, uc, u);
+    return launch_sync(M, level, sizeof(T) == 8 ? DT_F64 : DT_F32, u, GM_ALL, s);
+}
+
+hipError_t launch_prolong_add(const hhg_mesh* M, int level, int dtype, const void* uc, void* u,
+                              hipStream_t s) {
+    if (dtype == DT_F64) return prolong_t<double>(M, level, (const double*)uc, (double*)u, s);
+    return prolong_t<float>(M, level, (const float*)uc, (float*)u, s);
+}
+
+hipError_t launch_fill(void* x, int64_t n, int dtype, double v, hipStream_t s) {
+    const int g = grid_for(n, 4096);
+    if (dtype == DT_F64) k_fill<double><<<g, NT, 0, s>>>((double*)x, n, v);
+    else k_fill<float><<<g, NT, 0, s>>>((float*)x, n, (float)v);
+    return hipGetLastError();
+}
+
+hipError_t launch_coarse_extract(const hhg_mesh* M, int op, double* vals, hipStream_t s) {
+    const LevelDev L = M->dev(M->m.lc);
+    k_coarse_extract<<<grid_for(M->coarse.N, 64), NT, 0, s>>>(L, M->coarse, op, M->kap64[M->m.lc], vals);
+    return hipGetLastError();
+}
+
+template <class T>
+static hipError_t coarse_t(const hhg_mesh* M, int op, T* u, const T* f, const double* vals,
+                           hipStream_t s) {
+    const int lc = M->m.lc;
+    T* r = (T*)(sizeof(T) == 8 ? M->r64[lc] : M->r32[lc]);
+    hipError_t e = residual_t<T>(M, lc, op, u, f, r, nullptr, 0, s);
+    if (e != hipSuccess) return e;
+    k_coarse_pcg<T><<<1, 1024, 0, s>>>(M->coarse, vals, r, u, 1e-14, 4 * M->coarse.N);
+    return launch_sync(M, lc, sizeof(T) == 8 ? DT_F64 : DT_F32, u, GM_ALL, s);
+}
+
+hipError_t launch_coarse_solve(const hhg_mesh* M, int op, int dtype, void* u, const void* f,
+                               const double* vals, hipStream_t s) {
+    if (dtype == DT_F64) return coarse_t<double>(M, op, (double*)u, (const double*)f, vals, s);
+    return coarse_t<float>(M, op, (float*)u, (const float*)f, vals, s);
+}
+
+template <class T>
+static hipError_t canon_t(const hhg_mesh* M, int level, const T* src, T* dst, int to_canon,
+                          hipStream_t s) {
+    const LevelDev L = M->dev(level);
+    k_face_canon<T><<<face_grid(L), NT, 0, s>>>(L, src, dst, to_canon);
+    k_low_canon<T><<<grid_for(low_items(L), MAX_LOW_BLOCKS), NT, 0, s>>>(L, src, dst, to_canon);
+    if (!to_canon) return launch_sync(M, level, sizeof(T) == 8 ? DT_F64 : DT_F32, dst, GM_ALL, s);
+    return hipGetLastError();
+}
+
+hipError_t launch_canon(const hhg_mesh* M, int level, int dtype, const void* src, void* dst,
+                        int to_canon, hipStream_t s) {
+    if (dtype == DT_F64) return canon_t<double>(M, level, (const double*)src, (double*)dst, to_canon, s);
+    return canon_t<float>(M, level, (const float*)src, (float*)dst, to_canon, s);
+}
+
+template <class T>
+static hipError_t inject_t(const hhg_mesh* M, int level, const T* kf, T* kc, hipStream_t s) {
+    const LevelDev Lf = M->dev(level), Lc = M->dev(level - 1);
+    k_face_inject<T><<<face_grid(Lc), NT, 0, s>>>(Lf, Lc, kf, kc);
+    k_low_inject<T><<<grid_for(low_items(Lc), MAX_LOW_BLOCKS), NT, 0, s>>>(Lf, Lc, kf, kc);
+    return launch_sync(M, level - 1, sizeof(T) == 8 ? DT_F64 : DT_F32, kc, GM_ALL, s);
+}
+
+hipError_t launch_inject(const hhg_mesh* M, int level, int dtype, const void* kf, void* kc,
+                         hipStream_t s) {
+    if (dtype == DT_F64) return inject_t<double>(M, level, (const double*)kf, (double*)kc, s);
+    return inject_t<float>(M, level, (const float*)kf, (float*)kc, s);
+}
+
+hipError_t launch_f64_to_f32(const double* src, float* dst, int64_t n, hipStream_t s) {
+    k_f64_to_f32<<<grid_for(n, 4096), NT, 0, s>>>(src, dst, n);
+    return hipGetLastError();
+}
+
+hipError_t launch_add_f32_to_f64(double* u, const float* e, int64_t n, hipStream_t s) {
+    k_add_f32_to_f64<<<grid_for(n, 4096), NT, 0, s>>>(u, e, n);
+    return hipGetLastError();
+}
+
+}  // namespace hhg

@@ -1,0 +1,386 @@
+// Host setup of the macro-primitive graph (sec. 2.1), the per-level field
+// layouts (sec. 3.1, 3.2) and the ghost-copy table (sec. 2.2, 3.3).
+//
+// Layout of one field of level l (n = 2^l + 1 points per macro-edge):
+//   faces    : F blocks; face-local row j (n - j points, i = 0..n-1-j) starts
+//              at row_off[j], rows padded to 16 elements.  The ring (i = 0,
+//              j = 0, i + j = n - 1) holds ghost copies of edge and vertex
+//              values, the interior is owned by the face.
+//   edges    : E blocks of [main: k = 0..n-1 | ghost row 0 | ghost row 1].
+//              k = 1..n-2 are owned, k = 0 and n-1 are copies of the two
+//              vertices.  Ghost row s holds the n-1 near-row points of the
+//              edge's s-th face, in edge order: g[m] touches edge points m
+//              and m+1.
+//   vertices : V blocks of [value | one copy per incident edge of the edge
+//              point next to the vertex].
+// Every copy has exactly one owner; the ghost table lists (copy, owner)
+// offset pairs grouped by the kind of owner, so that each smoother stage can
+// refresh just the copies of the points it changed.
+#pragma clang fp contract(off)
+
+#include <algorithm>
+#include <cmath>
+#include <map>
+#include <numeric>
+#include <tuple>
+
+#include "hhg_mesh.hpp"
+
+namespace hhg {
+
+void MeshData::side_point(int side, int t, int d, int n, int& i, int& j) {
+    if (side == 0) {
+        i = t; j = d;
+    } else if (side == 1) {
+        i = d; j = t;
+    } else {
+        i = n - 1 - d - t; j = t;
+    }
+}
+
+static inline int side_start(int side) { return side == 2 ? 1 : 0; }
+static inline int side_end(int side) { return side == 0 ? 1 : 2; }
+static inline int side_third(int side) { return 2 - side; }
+
+Owner MeshData::owner_of(int f, int i, int j, int n) const {
+    const FaceInfo& fi = faces[f];
+    Owner o{0, 0, 0, i, j};
+    if (i == 0 && j == 0) { o.kind = 0; o.prim = fi.vtx[0]; return o; }
+    if (i == n - 1 && j == 0) { o.kind = 0; o.prim = fi.vtx[1]; return o; }
+    if (i == 0 && j == n - 1) { o.kind = 0; o.prim = fi.vtx[2]; return o; }
+    int side = -1, t = 0;
+    if (j == 0) { side = 0; t = i; }
+    else if (i == 0) { side = 1; t = j; }
+    else if (i + j == n - 1) { side = 2; t = j; }
+    if (side < 0) { o.kind = 2; o.prim = f; return o; }
+    o.kind = 1;
+    o.prim = fi.edge[side];
+    o.k = fi.rev[side] ? n - 1 - t : t;
+    return o;
+}
+
+int64_t MeshData::owner_offset(const LevelHost& L, const Owner& o) const {
+    if (o.kind == 0) return vert_off(L, o.prim, 0);
+    if (o.kind == 1) return edge_off(L, o.prim, o.k);
+    return face_off(L, o.prim, o.i, o.j);
+}
+
+int64_t MeshData::canonical_of(const LevelHost& L, const Owner& o) const {
+    const int n = L.n;
+    if (o.kind == 0) return o.prim;
+    if (o.kind == 1) {
+        if (o.k == 0) return edges[o.prim].a;
+        if (o.k == n - 1) return edges[o.prim].b;
+        return L.can_edge_base + (int64_t)o.prim * (n - 2) + (o.k - 1);
+    }
+    const int64_t nfi = (int64_t)(n - 2) * (n - 3) / 2;
+    const int64_t j = o.j;
+    const int64_t before = (j - 1) * (n - 2) - (j - 1) * j / 2;
+    return L.can_face_base + (int64_t)o.prim * nfi + before + (o.i - 1);
+}
+
+std::string MeshData::build(const double* in_vxy, int nv, const int32_t* in_tri,
+                            int nf, int max_level, int coarse_level) {
+    if (nv < 3 || nf < 1) return "need at least 3 vertices and 1 face";
+    if (max_level < 1 || max_level > MAXLEVEL) return "max_level must be in 1..12";
+    if (coarse_level < 1 || coarse_level > max_level)
+        return "coarse_level must be in 1..max_level";
+    V = nv; F = nf; L = max_level; lc = coarse_level;
+    vxy.assign(in_vxy, in_vxy + 2 * (size_t)nv);
+    tri.resize(nf);
+    for (int f = 0; f < nf; ++f) {
+        int a = in_tri[3 * f], b = in_tri[3 * f + 1], c = in_tri[3 * f + 2];
+        if (a < 0 || b < 0 || c < 0 || a >= nv || b >= nv || c >= nv)
+            return "vertex id out of range in face " + std::to_string(f);
+        if (a == b || b == c || a == c) return "repeated vertex in face " + std::to_string(f);
+        double e1x = vxy[2 * b] - vxy[2 * a], e1y = vxy[2 * b + 1] - vxy[2 * a + 1];
+        double e2x = vxy[2 * c] - vxy[2 * a], e2y = vxy[2 * c + 1] - vxy[2 * a + 1];
+        double det = e1x * e2y - e1y * e2x;
+        if (det == 0.0 || !std::isfinite(det)) return "zero-area face " + std::to_string(f);
+        if (det < 0.0) std::swap(b, c);   // make it counter-clockwise
+        tri[f] = {a, b, c};
+    }
+    // macro-edges from sorted vertex pairs (sec. 2.1)
+    std::map<std::pair<int, int>, std::vector<int>> faces_of;
+    for (int f = 0; f < nf; ++f)
+        for (int s = 0; s < 3; ++s) {
+            int p = tri[f][side_start(s)], q = tri[f][side_end(s)];
+            faces_of[{std::min(p, q), std::max(p, q)}].push_back(f);
+        }
+    E = (int)faces_of.size();
+    std::map<std::pair<int, int>, int> edge_id;
+    edge_v.clear();
+    edges.assign(E, EdgeInfo{});
+    for (auto& kv : faces_of) {
+        if (kv.second.size() > 2) return "non-manifold macro-edge";
+        int e = (int)edge_v.size();
+        edge_id[kv.first] = e;
+        edge_v.push_back({kv.first.first, kv.first.second});
+        EdgeInfo& ei = edges[e];
+        ei.a = kv.first.first;
+        ei.b = kv.first.second;
+        ei.nf = (int)kv.second.size();
+        ei.boundary = ei.nf == 1;
+    }
+    std::vector<char> vbnd(V, 0);
+    for (int e = 0; e < E; ++e)
+        if (edges[e].boundary) { vbnd[edges[e].a] = 1; vbnd[edges[e].b] = 1; }
+
+    faces.assign(F, FaceInfo{});
+    std::vector<int> fill(E, 0);
+    for (int f = 0; f < F; ++f) {
+        FaceInfo& fi = faces[f];
+        double x[3][2];
+        for (int k = 0; k < 3; ++k) {
+            fi.vtx[k] = tri[f][k];
+            x[k][0] = vxy[2 * tri[f][k]];
+            x[k][1] = vxy[2 * tri[f][k] + 1];
+        }
+        double dots[3];
+        for (int k = 0; k < 3; ++k) {
+            const double* p0 = x[k];
+            const double* p1 = x[(k + 1) % 3];
+            const double* p2 = x[(k + 2) % 3];
+            double ax = p1[0] - p0[0], ay = p1[1] - p0[1];
+            double bx = p2[0] - p0[0], by = p2[1] - p0[1];
+            double dot = ax * bx + ay * by;
+            double crs = std::fabs(ax * by - ay * bx);
+            dots[k] = dot;
+            fi.cot[k] = dot / crs;
+        }
+        {
+            double e1x = x[1][0] - x[0][0], e1y = x[1][1] - x[0][1];
+            double e2x = x[2][0] - x[0][0], e2y = x[2][1] - x[0][1];
+            fi.area = 0.5 * std::fabs(e1x * e2y - e1y * e2x);
+        }
+        // multicolour ordering: 3 colours (i - j) mod 3, or the parity rule of
+        // the lattice direction whose weight vanishes at an exact right angle
+        if (dots[0] == 0.0) { fi.colour_rule = 1; fi.ncolours = 2; }
+        else if (dots[1] == 0.0) { fi.colour_rule = 2; fi.ncolours = 2; }
+        else if (dots[2] == 0.0) { fi.colour_rule = 3; fi.ncolours = 2; }
+        else { fi.colour_rule = 0; fi.ncolours = 3; }
+        for (int s = 0; s < 3; ++s) {
+            int p = tri[f][side_start(s)], q = tri[f][side_end(s)];
+            int e = edge_id[{std::min(p, q), std::max(p, q)}];
+            EdgeInfo& ei = edges[e];
+            int slot = fill[e]++;
+            fi.edge[s] = e;
+            fi.slot[s] = slot;
+            fi.rev[s] = (p != ei.a);
+            fi.bside[s] = ei.boundary;
+            ei.face[slot] = f;
+            ei.side[slot] = s;
+            ei.rev[slot] = fi.rev[s];
+            int la = (p == ei.a) ? side_start(s) : side_end(s);
+            int lb = (p == ei.a) ? side_end(s) : side_start(s);
+            ei.cA[slot] = fi.cot[side_third(s)];
+            ei.cL[slot] = fi.cot[la];
+            ei.cH[slot] = fi.cot[lb];
+            ei.area[slot] = fi.area;
+        }
+        for (int k = 0; k < 3; ++k) fi.bvtx[k] = vbnd[fi.vtx[k]];
+    }
+    // macro-vertices and their incident edges (sorted by edge id)
+    verts.assign(V, VertexInfo{});
+    maxdeg = 0;
+    for (int e = 0; e < E; ++e) {
+        for (int end = 0; end < 2; ++end) {
+            int v = end == 0 ? edges[e].a : edges[e].b;
+            VertexInfo& vi = verts[v];
+            if (vi.deg >= MAXDEG) return "a macro-vertex has more than 16 macro-edges";
+            edges[e].vslot[end] = vi.deg;
+            vi.edge[vi.deg] = e;
+            vi.at_a[vi.deg] = (end == 0);
+            vi.nfe[vi.deg] = edges[e].nf;
+            vi.deg++;
+        }
+    }
+    for (int v = 0; v < V; ++v) {
+        VertexInfo& vi = verts[v];
+        vi.boundary = vbnd[v];
+        if (vi.deg == 0) return "isolated vertex " + std::to_string(v);
+        maxdeg = std::max(maxdeg, vi.deg);
+        for (int q = 0; q < vi.deg; ++q) {
+            const EdgeInfo& ei = edges[vi.edge[q]];
+            for (int s = 0; s < 2; ++s) {
+                vi.partner[q][s] = -1;
+                vi.cA[q][s] = 0.0;
+                vi.area[q][s] = 0.0;
+                if (s >= ei.nf) continue;
+                const FaceInfo& fi = faces[ei.face[s]];
+                // the other side of that face through v
+                int other = -1;
+                for (int s2 = 0; s2 < 3; ++s2) {
+                    if (s2 == ei.side[s]) continue;
+                    if (tri[ei.face[s]][side_start(s2)] == v || tri[ei.face[s]][side_end(s2)] == v)
+                        other = fi.edge[s2];
+                }
+                int pslot = -1;
+                for (int q2 = 0; q2 < vi.deg; ++q2)
+                    if (vi.edge[q2] == other) pslot = q2;
+                if (pslot < 0) return "inconsistent vertex fan";
+                vi.partner[q][s] = pslot;
+                vi.cA[q][s] = ei.cA[s];
+                vi.area[q][s] = ei.area[s];
+            }
+        }
+    }
+    iedges.clear();
+    iverts.clear();
+    for (int e = 0; e < E; ++e)
+        if (!edges[e].boundary) iedges.push_back(e);
+    for (int v = 0; v < V; ++v)
+        if (!verts[v].boundary) iverts.push_back(v);
+
+    lv.assign(L + 1, LevelHost{});
+    for (int l = 1; l <= L; ++l) build_level(l);
+    build_coarse();
+    return "";
+}
+
+void MeshData::build_level(int level) {
+    LevelHost& H = lv[level];
+    const int n = (1 << level) + 1;
+    H.level = level;
+    H.n = n;
+    H.row_off.assign(n + 1, 0);
+    for (int j = 0; j < n; ++j) H.row_off[j + 1] = H.row_off[j] + (int32_t)pad_up(n - j, PAD);
+    H.face_stride = H.row_off[n];
+    H.ghost_off = (int32_t)pad_up(n, PAD);
+    H.ghost_stride = (int32_t)pad_up(n - 1, PAD);
+    H.edge_stride = H.ghost_off + 2 * (int64_t)H.ghost_stride;
+    H.vert_stride = pad_up(1 + maxdeg, PAD);
+    H.face_base = 0;
+    H.edge_base = (int64_t)F * H.face_stride;
+    H.vert_base = H.edge_base + (int64_t)E * H.edge_stride;
+    H.total = pad_up(H.vert_base + (int64_t)V * H.vert_stride, 64);
+    const int64_t nfi = (int64_t)(n - 2) * (n - 3) / 2;
+    H.n_all = V + (int64_t)E * (n - 2) + (int64_t)F * nfi;
+    H.n_int = (int64_t)iverts.size() + (int64_t)iedges.size() * (n - 2) + (int64_t)F * nfi;
+    H.can_edge_base = V;
+    H.can_face_base = V + (int64_t)E * (n - 2);
+
+    // tiles of TILE_I x TILE_J face-local points that contain interior points
+    H.tiles.clear();
+    for (int tj = 0; tj * TILE_J <= n - 3; ++tj)
+        for (int ti = 0; ti * TILE_I <= n - 3; ++ti) {
+            int imin = std::max(ti * TILE_I, 1), jmin = std::max(tj * TILE_J, 1);
+            if (imin + jmin <= n - 2) H.tiles.push_back(make_int2(ti, tj));
+        }
+
+    // ghost table
+    std::vector<std::tuple<int, int64_t, int64_t>> ent;
+    auto cls_of = [&](const Owner& o) {
+        if (o.kind == 0) return (int)G_VERT;
+        if (o.kind == 1) return (o.k % 2 == 0) ? (int)G_EEVEN : (int)G_EODD;
+        return (int)G_FACE;
+    };
+    for (int f = 0; f < F; ++f) {
+        // ring: corners and the three sides
+        int ci[3] = {0, n - 1, 0}, cj[3] = {0, 0, n - 1};
+        for (int c = 0; c < 3; ++c) {
+            Owner o = owner_of(f, ci[c], cj[c], n);
+            ent.emplace_back(G_VERT, face_off(H, f, ci[c], cj[c]), owner_offset(H, o));
+        }
+        for (int s = 0; s < 3; ++s)
+            for (int t = 1; t <= n - 2; ++t) {
+                int i, j;
+                side_point(s, t, 0, n, i, j);
+                Owner o = owner_of(f, i, j, n);
+                ent.emplace_back(cls_of(o), face_off(H, f, i, j), owner_offset(H, o));
+            }
+    }
+    for (int e = 0; e < E; ++e) {
+        const EdgeInfo& ei = edges[e];
+        ent.emplace_back(G_VERT, edge_off(H, e, 0), vert_off(H, ei.a, 0));
+        ent.emplace_back(G_VERT, edge_off(H, e, n - 1), vert_off(H, ei.b, 0));
+        if (ei.boundary) continue;
+        for (int s = 0; s < ei.nf; ++s) {
+            for (int g = 0; g <= n - 2; ++g) {
+                int t = ei.rev[s] ? n - 2 - g : g;
+                int i, j;
+                side_point(ei.side[s], t, 1, n, i, j);
+                Owner o = owner_of(ei.face[s], i, j, n);
+                ent.emplace_back(cls_of(o), ghost_off(H, e, s, g), owner_offset(H, o));
+            }
+        }
+    }
+    for (int v = 0; v < V; ++v) {
+        const VertexInfo& vi = verts[v];
+        for (int q = 0; q < vi.deg; ++q) {
+            int k = vi.at_a[q] ? 1 : n - 2;
+            ent.emplace_back(G_EODD, vert_off(H, v, 1 + q), edge_off(H, vi.edge[q], k));
+        }
+    }
+    std::stable_sort(ent.begin(), ent.end());
+    H.gdst.resize(ent.size());
+    H.gsrc.resize(ent.size());
+    for (int c = 0; c <= G_NCLS; ++c) H.gcls[c] = 0;
+    for (size_t x = 0; x < ent.size(); ++x) {
+        H.gdst[x] = std::get<1>(ent[x]);
+        H.gsrc[x] = std::get<2>(ent[x]);
+        H.gcls[std::get<0>(ent[x]) + 1] = (int64_t)x + 1;
+    }
+    for (int c = 1; c <= G_NCLS; ++c) H.gcls[c] = std::max(H.gcls[c], H.gcls[c - 1]);
+}
+
+void MeshData::build_coarse() {
+    const LevelHost& H = lv[lc];
+    const int n = H.n;
+    Wc = std::max(7, 1 + maxdeg);
+    std::vector<int32_t> compact(H.n_all, -1);
+    c_owner.clear(); c_kind.clear(); c_prim.clear(); c_pa.clear(); c_pb.clear();
+    auto add = [&](const Owner& o) {
+        compact[canonical_of(H, o)] = (int32_t)c_owner.size();
+        c_owner.push_back(owner_offset(H, o));
+        c_kind.push_back(o.kind);
+        c_prim.push_back(o.prim);
+        c_pa.push_back(o.kind == 1 ? o.k : o.i);
+        c_pb.push_back(o.j);
+    };
+    // canonical order restricted to interior points
+    for (int v = 0; v < V; ++v)
+        if (!verts[v].boundary) add(Owner{0, v, 0, 0, 0});
+    for (int e = 0; e < E; ++e)
+        if (!edges[e].boundary)
+            for (int k = 1; k <= n - 2; ++k) add(Owner{1, e, k, 0, 0});
+    for (int f = 0; f < F; ++f)
+        for (int j = 1; j <= n - 3; ++j)
+            for (int i = 1; i <= n - 2 - j; ++i) add(Owner{2, f, 0, i, j});
+    Nc = (int32_t)c_owner.size();
+    c_cols.assign((size_t)Nc * Wc, -1);
+    auto col = [&](const Owner& o) { return compact[canonical_of(H, o)]; };
+    auto edge_pt = [&](int e, int k) {
+        if (k == 0) return Owner{0, edges[e].a, 0, 0, 0};
+        if (k == n - 1) return Owner{0, edges[e].b, 0, 0, 0};
+        return Owner{1, e, k, 0, 0};
+    };
+    for (int p = 0; p < Nc; ++p) {
+        int32_t* cp = &c_cols[(size_t)p * Wc];
+        cp[0] = p;
+        if (c_kind[p] == 0) {
+            const VertexInfo& vi = verts[c_prim[p]];
+            for (int q = 0; q < vi.deg; ++q)
+                cp[1 + q] = col(edge_pt(vi.edge[q], vi.at_a[q] ? 1 : n - 2));
+        } else if (c_kind[p] == 1) {
+            int e = c_prim[p], k = c_pa[p];
+            const EdgeInfo& ei = edges[e];
+            cp[1] = col(edge_pt(e, k - 1));
+            cp[2] = col(edge_pt(e, k + 1));
+            for (int s = 0; s < 2; ++s)
+                for (int d = 0; d < 2; ++d) {
+                    int g = k - 1 + d;
+                    int t = ei.rev[s] ? n - 2 - g : g;
+                    int i, j;
+                    side_point(ei.side[s], t, 1, n, i, j);
+                    cp[3 + 2 * s + d] = col(owner_of(ei.face[s], i, j, n));
+                }
+        } else {
+            int f = c_prim[p], i = c_pa[p], j = c_pb[p];
+            const int di[6] = {1, -1, 0, 0, 1, -1}, dj[6] = {0, 0, 1, -1, -1, 1};
+            for (int w = 0; w < 6; ++w) cp[1 + w] = col(owner_of(f, i + di[w], j + dj[w], n));
+        }
+    }
+}
+
+}  // namespace hhg

@@ -1,0 +1,44 @@
+"""Shared helpers of the GPU parity tests: build the library mesh and the
+oracle hierarchy on the same seeded inputs and compare canonical vectors."""
+import functools
+import sys
+
+import numpy as np
+
+import hhg_inputs as hi
+
+
+def rel_err(a, b):
+    """max |a - b| / max |b| (b = oracle)."""
+    a = np.asarray(a, dtype=np.float64)
+    b = np.asarray(b, dtype=np.float64)
+    den = np.abs(b).max()
+    return float(np.abs(a - b).max() / (den if den > 0 else 1.0))
+
+
+def log(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+@functools.lru_cache(maxsize=8)
+def oracle_hierarchy(name, L, lc, kappa_seed=None):
+    from oracle.mesh import MacroMesh
+    from oracle.mg import Hierarchy
+    vxy, tri = hi.mesh_by_name(name)
+    kap = None
+    if kappa_seed is not None:
+        from oracle.mesh import Level
+        lv = Level(MacroMesh(vxy, tri), L)
+        kap = np.exp(hi.grf_eval(lv.xy, kappa_seed))
+    return Hierarchy(MacroMesh(vxy, tri), L, lc, kap)
+
+
+def gpu_mesh(name, L, lc, features):
+    import paper_1805_10167_amd as P
+    vxy, tri = hi.mesh_by_name(name)
+    return P.Mesh(vxy, tri, L, lc, features)
+
+
+def to_np(t):
+    return t.detach().cpu().numpy().astype(np.float64)

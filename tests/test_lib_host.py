@@ -1,0 +1,82 @@
+"""Host-side checks of the C-ABI library that need no GPU: the shared
+library loads, exports every symbol include/hhg.h declares, and its mesh setup
+(host code only) agrees with the oracle's numbering and geometry."""
+import os
+import re
+
+import numpy as np
+import pytest
+
+import hhg_inputs as hi
+from oracle.mesh import Level, MacroMesh
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+P = pytest.importorskip("paper_1805_10167_amd")
+
+
+def _declared_symbols():
+    text = open(os.path.join(ROOT, "include", "hhg.h")).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(hhg_[a-z0-9_]+)\s*\(", text)))
+
+
+def test_library_exports_every_declared_symbol():
+    lib = P.lib()
+    names = _declared_symbols()
+    assert len(names) >= 15
+    missing = [n for n in names if not hasattr(lib, n)]
+    assert not missing, missing
+
+
+@pytest.mark.parametrize("name", ["square", "annulus64", "annulus128"])
+@pytest.mark.parametrize("level", [1, 2, 3, 5])
+def test_counts_and_coordinates_match_oracle(name, level):
+    vxy, tri = hi.mesh_by_name(name)
+    h = P.hhg_setup_mesh(vxy, tri, max(level, 2), 1)
+    try:
+        lv = Level(MacroMesh(vxy, tri), level)
+        ni, na = P.hhg_n_dofs(h, level)
+        assert (ni, na) == (lv.interior_count(), lv.n_all)
+        xy = P.hhg_coords(h, level)
+        assert np.abs(xy - lv.xy).max() <= 1e-15
+        assert P.hhg_field_elems(h, level) >= na
+    finally:
+        P.hhg_destroy_mesh(h)
+
+
+def test_paper_count_at_level6():
+    """2145 points per face at level 6 (sec. 5.2): n_all of one face."""
+    vxy = np.array([[0.0, 0.0], [1.0, 0.0], [0.0, 1.0]])
+    h = P.hhg_setup_mesh(vxy, [[0, 1, 2]], 6, 2)
+    try:
+        assert P.hhg_n_dofs(h, 6)[1] == 2145
+    finally:
+        P.hhg_destroy_mesh(h)
+
+
+def test_setup_errors():
+    with pytest.raises(P.HHGError) as e:
+        P.hhg_setup_mesh([[0, 0], [1, 0], [2, 0]], [[0, 1, 2]], 3, 2)
+    assert e.value.code == P.HHG_EINVAL
+    vxy = [[0, 0], [1, 0], [0, 1], [0, -1], [1, 1]]
+    with pytest.raises(P.HHGError):
+        P.hhg_setup_mesh(vxy, [[0, 1, 2], [0, 1, 3], [0, 1, 4]], 3, 2)
+    with pytest.raises(P.HHGError):
+        P.hhg_setup_mesh(*hi.unit_square(), 13, 2)
+    with pytest.raises(P.HHGError):
+        P.hhg_setup_mesh(*hi.unit_square(), 4, 5)
+    with pytest.raises(P.HHGError):
+        P.hhg_setup_mesh([[0, 0], [1, 0], [0, 1]], [[0, 1, 7]], 3, 2)
+    assert "out of range" in P.hhg_last_error()
+
+
+def test_unbound_mesh_rejects_compute_calls():
+    h = P.hhg_setup_mesh(*hi.unit_square(), 3, 2)
+    try:
+        assert P.hhg_workspace_bytes(h, P.HHG_FEAT_F64) > 0
+        rc = P.lib().hhg_apply(h, 3, 0, 0, None, None, None)
+        assert rc == P.HHG_ENOMEM
+        with pytest.raises(P.HHGError):
+            P.hhg_workspace_bytes(h, 1 << 7)
+    finally:
+        P.hhg_destroy_mesh(h)
