@@ -7,6 +7,7 @@
 #include <cmath>
 #include <cstring>
 #include <new>
+#include <utility>
 #include <string>
 
 #include "../../include/hhg.h"
@@ -46,6 +47,7 @@ void carve(hhg_mesh* M, uint32_t feat, Carver& c) {
         LevelHost& H = m.lv[l];
         H.d_row_off = (int32_t*)c.take(sizeof(int32_t) * H.row_off.size());
         H.d_tiles = (int2*)c.take(sizeof(int2) * (H.tiles.size() + 1));
+        H.d_gs_tiles = (int2*)c.take(sizeof(int2) * (H.gs_tiles.size() + 1));
         H.d_gdst = (int64_t*)c.take(sizeof(int64_t) * (H.gdst.size() + 1));
         H.d_gsrc = (int64_t*)c.take(sizeof(int64_t) * (H.gsrc.size() + 1));
     }
@@ -70,6 +72,7 @@ void carve(hhg_mesh* M, uint32_t feat, Carver& c) {
         M->u32[l] = M->f32[l] = M->r32[l] = nullptr;
         M->kap64[l] = nullptr;
         M->kap32[l] = nullptr;
+        M->a64[l] = M->a32[l] = nullptr;
     }
     auto fld = [&](int l, size_t esz) { return c.take(esz * (size_t)m.lv[l].total); };
     if (feat & (HHG_FEAT_F64 | HHG_FEAT_MP)) M->r64[m.L] = fld(m.L, 8);
@@ -89,6 +92,10 @@ void carve(hhg_mesh* M, uint32_t feat, Carver& c) {
             M->f32[l] = fld(l, 4);
             M->r32[l] = fld(l, 4);
         }
+    }
+    for (int l = 1; l <= m.L; ++l) {
+        if (feat & HHG_FEAT_F64) M->a64[l] = fld(l, 8);
+        if (feat & HHG_FEAT_MP) M->a32[l] = fld(l, 4);
     }
     if (feat & HHG_FEAT_VARK) {
         for (int l = 1; l <= m.L; ++l) {
@@ -133,34 +140,54 @@ void* level_u(const hhg_mesh* M, int l, int dt) { return dt == HHG_F64 ? M->u64[
 void* level_f(const hhg_mesh* M, int l, int dt) { return dt == HHG_F64 ? M->f64[l] : M->f32[l]; }
 void* level_r(const hhg_mesh* M, int l, int dt) { return dt == HHG_F64 ? M->r64[l] : M->r32[l]; }
 
-int smooth_impl(const hhg_mesh* M, int level, int op, int smoother, int dt, void* u, const void* f,
-                int sweeps, int backward, hipStream_t s) {
-    (void)smoother;
-    for (int i = 0; i < sweeps; ++i)
-        HIP_CHECK(launch_gs_sweep(M, level, op, dt, u, f, backward, s), "smooth");
+void* level_alt(const hhg_mesh* M, int l, int dt) { return dt == HHG_F64 ? M->a64[l] : M->a32[l]; }
+
+// `sweeps` sweeps alternating between the buffers x and y; *out receives the
+// buffer that holds the result (x for an even number of sweeps).
+int smooth_pp(const hhg_mesh* M, int level, int op, int dt, void* x, void* y, const void* f,
+              int sweeps, int backward, hipStream_t s, void** out) {
+    for (int i = 0; i < sweeps; ++i) {
+        HIP_CHECK(launch_gs_sweep(M, level, op, dt, x, y, f, backward, s), "smooth");
+        std::swap(x, y);
+    }
+    *out = x;
+    return HHG_OK;
+}
+
+int copy_field(const hhg_mesh* M, int level, int dt, void* dst, const void* src, hipStream_t s) {
+    const size_t bytes = (size_t)M->m.lv[level].total * (dt == HHG_F64 ? 8 : 4);
+    HIP_CHECK(hipMemcpyAsync(dst, src, bytes, hipMemcpyDeviceToDevice, s), "copy");
     return HHG_OK;
 }
 
 int vcycle_rec(const hhg_mesh* M, int level, int op, int smoother, int dt, void* u, const void* f,
                int nu1, int nu2, hipStream_t s) {
+    (void)smoother;
     const int lc = M->m.lc;
     const double* vals = op == HHG_OP_DIFFUSION ? M->coarse_vals_diff : M->coarse.vals;
     if (level == lc) {
         HIP_CHECK(launch_coarse_solve(M, op, dt, u, f, vals, s), "coarse solve");
         return HHG_OK;
     }
-    int rc = smooth_impl(M, level, op, smoother, dt, u, f, nu1, 0, s);
+    void* alt = level_alt(M, level, dt);
+    void* cur = nullptr;
+    int rc = smooth_pp(M, level, op, dt, u, alt, f, nu1, 0, s, &cur);
     if (rc) return rc;
+    void* other = cur == u ? alt : u;
     void* r = level_r(M, level, dt);
     void* uc = level_u(M, level - 1, dt);
     void* fc = level_f(M, level - 1, dt);
-    HIP_CHECK(launch_residual(M, level, op, dt, u, f, r, nullptr, GM_FACE | GM_EODD, s), "residual");
+    HIP_CHECK(launch_residual(M, level, op, dt, cur, f, r, nullptr, GM_FACE | GM_EODD, s), "residual");
     HIP_CHECK(launch_restrict(M, level, dt, r, fc, s), "restrict");
     HIP_CHECK(launch_fill(uc, M->m.lv[level - 1].total, dt, 0.0, s), "fill");
     rc = vcycle_rec(M, level - 1, op, smoother, dt, uc, fc, nu1, nu2, s);
     if (rc) return rc;
-    HIP_CHECK(launch_prolong_add(M, level, dt, uc, u, s), "prolong");
-    return smooth_impl(M, level, op, smoother, dt, u, f, nu2, 1, s);
+    HIP_CHECK(launch_prolong_add(M, level, dt, uc, cur, s), "prolong");
+    void* fin = nullptr;
+    rc = smooth_pp(M, level, op, dt, cur, other, f, nu2, 1, s, &fin);
+    if (rc) return rc;
+    if (fin != u) return copy_field(M, level, dt, u, fin, s);
+    return HHG_OK;
 }
 
 int read_scalar(const double* d, double* h, hipStream_t s) {
@@ -181,6 +208,7 @@ hhg::LevelDev hhg_mesh::dev(int level) const {
     L.ghost_stride = H.ghost_stride;
     L.vert_stride = (int32_t)H.vert_stride;
     L.ntiles = (int32_t)H.tiles.size();
+    L.n_gs_tiles = (int32_t)H.gs_tiles.size();
     L.n_iedges = (int32_t)m.iedges.size();
     L.n_iverts = (int32_t)m.iverts.size();
     L.face_stride = H.face_stride;
@@ -196,6 +224,7 @@ hhg::LevelDev hhg_mesh::dev(int level) const {
     L.inv4l = std::ldexp(1.0, -2 * level);
     L.row_off = H.d_row_off;
     L.tiles = H.d_tiles;
+    L.gs_tiles = H.d_gs_tiles;
     L.faces = d_faces;
     L.edges = d_edges;
     L.verts = d_verts;
@@ -271,6 +300,7 @@ int hhg_bind_workspace(hhg_mesh* M, uint32_t features, void* dptr, size_t bytes,
         LevelHost& H = m.lv[l];
         HIP_CHECK(upload(H.d_row_off, H.row_off, s), "upload");
         HIP_CHECK(upload(H.d_tiles, H.tiles, s), "upload");
+        HIP_CHECK(upload(H.d_gs_tiles, H.gs_tiles, s), "upload");
         HIP_CHECK(upload(H.d_gdst, H.gdst, s), "upload");
         HIP_CHECK(upload(H.d_gsrc, H.gsrc, s), "upload");
     }
@@ -406,7 +436,14 @@ int hhg_smooth(const hhg_mesh* M, int32_t level, int32_t op, int32_t smoother, i
     if (op == HHG_OP_MASS) return fail(HHG_EINVAL, "smoothing needs a stiffness operator");
     if (smoother != HHG_SMOOTH_GS) return fail(HHG_EINVAL, "unknown smoother");
     if (sweeps < 0 || !u || !f) return fail(HHG_EINVAL, "bad arguments");
-    return smooth_impl(M, level, op, smoother, dtype, u, f, sweeps, backward, (hipStream_t)stream);
+    void* alt = level_alt(M, level, dtype);
+    if (!alt) return fail(HHG_ENOMEM, dtype == HHG_F64 ? "workspace lacks HHG_FEAT_F64"
+                                                       : "workspace lacks HHG_FEAT_MP");
+    hipStream_t s = (hipStream_t)stream;
+    void* fin = nullptr;
+    if ((rc = smooth_pp(M, level, op, dtype, u, alt, f, sweeps, backward != 0, s, &fin))) return rc;
+    if (fin != u) return copy_field(M, level, dtype, u, fin, s);
+    return HHG_OK;
 }
 
 int hhg_vcycle(const hhg_mesh* M, int32_t level, int32_t op, int32_t smoother, int32_t dtype,

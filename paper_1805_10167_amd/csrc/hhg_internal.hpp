@@ -17,6 +17,11 @@ constexpr int MAXLEVEL = 12;
 constexpr int PAD = 16;         // row/segment padding in elements
 constexpr int TILE_I = 64;      // generic face tile: 64 (i) x 4 (j) points
 constexpr int TILE_J = 4;
+// fused smoother tile: GS_TI x GS_TJ updated points plus a halo of GS_H on
+// every side, so that an LDS row holds GS_TI + 2 GS_H = 128 values
+constexpr int GS_H = 3;
+constexpr int GS_TI = 128 - 2 * GS_H;
+constexpr int GS_TJ = 32;
 
 inline int64_t pad_up(int64_t x, int64_t p) { return (x + p - 1) / p * p; }
 
@@ -77,7 +82,7 @@ struct LevelDev {
     int32_t level, n;
     int32_t F, E, V;
     int32_t ghost_off, ghost_stride, vert_stride;
-    int32_t ntiles, n_iedges, n_iverts, pad0;
+    int32_t ntiles, n_iedges, n_iverts, n_gs_tiles;
     int64_t face_stride, edge_stride;
     int64_t face_base, edge_base, vert_base, total;
     int64_t gcls[G_NCLS + 1];
@@ -85,6 +90,7 @@ struct LevelDev {
     double inv4l;                     // 1 / 4^level: micro/macro area ratio
     const int32_t* row_off;           // [n + 1] start of row j inside a face
     const int2* tiles;                // 64 x 4 tiles that meet the interior
+    const int2* gs_tiles;             // smoother tiles covering the whole face
     const FaceInfo* faces;
     const EdgeInfo* edges;
     const VertexInfo* verts;
@@ -115,12 +121,14 @@ struct LevelHost {
     int32_t ghost_off = 0, ghost_stride = 0;
     std::vector<int32_t> row_off;
     std::vector<int2> tiles;
+    std::vector<int2> gs_tiles;
     std::vector<int64_t> gdst, gsrc;
     int64_t gcls[G_NCLS + 1] = {0, 0, 0, 0, 0};
     int64_t n_all = 0, n_int = 0, can_edge_base = 0, can_face_base = 0;
     // device copies (inside the bound workspace)
     int32_t* d_row_off = nullptr;
     int2* d_tiles = nullptr;
+    int2* d_gs_tiles = nullptr;
     int64_t* d_gdst = nullptr;
     int64_t* d_gsrc = nullptr;
 };

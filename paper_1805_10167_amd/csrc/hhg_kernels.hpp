@@ -22,8 +22,9 @@ hipError_t launch_apply(const hhg_mesh* M, int level, int op, int dtype, const v
 hipError_t launch_residual(const hhg_mesh* M, int level, int op, int dtype, const void* u,
                            const void* f, void* r, double* norm, int sync_mask,
                            hipStream_t s);
-// One forward or backward staged Gauss-Seidel sweep.
-hipError_t launch_gs_sweep(const hhg_mesh* M, int level, int op, int dtype, void* u,
+// One forward or backward staged Gauss-Seidel sweep from field x into field y
+// (x is used as scratch; y receives the complete result).
+hipError_t launch_gs_sweep(const hhg_mesh* M, int level, int op, int dtype, void* x, void* y,
                            const void* f, int backward, hipStream_t s);
 // fc (level-1) = P^T r (level), r with refreshed FACE and EODD ghosts.
 hipError_t launch_restrict(const hhg_mesh* M, int level, int dtype, const void* r, void* fc,

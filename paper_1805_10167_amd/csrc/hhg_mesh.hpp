@@ -98,6 +98,8 @@ struct hhg_mesh {
     void* u32[hhg::MAXLEVEL + 1] = {};
     void* f32[hhg::MAXLEVEL + 1] = {};
     void* r32[hhg::MAXLEVEL + 1] = {};
+    void* a64[hhg::MAXLEVEL + 1] = {};   // second buffer of the ping-pong smoother
+    void* a32[hhg::MAXLEVEL + 1] = {};
     double* kap64[hhg::MAXLEVEL + 1] = {};
     float* kap32[hhg::MAXLEVEL + 1] = {};
     bool kappa_set = false;

@@ -39,6 +39,17 @@ __device__ __forceinline__ int64_t vert_off(const LevelDev& L, int v) {
     return L.vert_base + (int64_t)v * L.vert_stride;
 }
 
+// Start of face-local row j: rows hold n - j values padded to 16, so the
+// offset is 16 * sum_{m = n-j+1}^{n} ceil(m / 16); with
+// S(N) = sum_{m=1}^{N} ceil(m/16) = 8 q (q+1) + t (q+1), N = 16 q + t.
+__device__ __forceinline__ int ceil16_sum(int N) {
+    const int q = N >> 4, t = N & 15;
+    return 8 * q * (q + 1) + t * (q + 1);
+}
+__device__ __forceinline__ int row_start(int n, int j) {
+    return 16 * (ceil16_sum(n) - ceil16_sum(n - j));
+}
+
 __device__ __forceinline__ int face_colour(int rule, int i, int j) {
     switch (rule) {
         case 1: return (i + j) & 1;
@@ -204,9 +215,9 @@ __global__ __launch_bounds__(NT) void k_fill(T* __restrict__ x, int64_t n, T v) 
         const int i = tl_.x * TILE_I + ti_, j = tl_.y * TILE_J + tj_;                       \
         if (!(i >= 1 && j >= 1 && i + j <= n - 2)) continue;                                \
         const FaceInfo& fi = (L).faces[face];                                               \
-        const int64_t p = face_base((L), face) + (L).row_off[j] + i;                        \
-        const int64_t up = (L).row_off[j + 1] - (L).row_off[j];                             \
-        const int64_t dn = (L).row_off[j] - (L).row_off[j - 1];
+        const int64_t p = face_base((L), face) + row_start(n, j) + i;                        \
+        const int64_t up = row_start(n, j + 1) - row_start(n, j);                             \
+        const int64_t dn = row_start(n, j) - row_start(n, j - 1);
 
 #define FACE_TILE_END }
 
@@ -330,18 +341,136 @@ __global__ __launch_bounds__(1024) void k_reduce_final(const double* __restrict_
     if (threadIdx.x == 0) *out = do_sqrt ? sqrt(s) : s;
 }
 
-// One face colour of the Gauss-Seidel sweep (all faces at once).
-template <class T>
-__global__ __launch_bounds__(NT) void k_face_gs_colour(LevelDev L, int op, T* __restrict__ u,
-                                                       const T* __restrict__ f,
-                                                       const T* __restrict__ kap, int colour) {
-    FACE_TILE_LOOP(L)
-    if (face_colour(fi.colour_rule, i, j) != colour) continue;
-    const W7<T> w = face_weights<T>(op, fi, L.inv4l, kap, p, up, dn);
-    const T off = w.e * u[p + 1] + w.w * u[p - 1] + w.n * u[p + up] + w.s * u[p - dn] +
-                  w.se * u[p - dn + 1] + w.nw * u[p + up - 1];
-    u[p] = (f[p] - off) / w.c;
-    FACE_TILE_END
+// Fused multicolour face smoother.  A tile of GS_TI x GS_TJ points plus a
+// halo of GS_H points sits in LDS; colour stage s (of ncol) is applied on
+// the tile grown by ncol - 1 - s points, so every stage sees exactly the
+// values that separate colour passes over the whole face would give it, and
+// u, f are read once and u written once per sweep.  Tiles would otherwise
+// read halo points a neighbour tile has already overwritten, so the sweep
+// reads uin and writes uout; the same launch copies the face rings, edge
+// points and vertex blocks into uout and writes the near-edge rows into
+// uout's edge ghost rows, leaving uout a complete, consistent field.
+constexpr int GS_W = GS_TI + 2 * GS_H;          // 128 values per LDS row
+constexpr int GS_R = GS_TJ + 2 * GS_H;          // LDS rows
+constexpr int GS_NT = 256;
+constexpr int GS_RPT = (GS_R + 1) / 2;          // rows per thread
+constexpr int GS_COPY_BLOCKS = 32;
+
+template <class T, bool VARK>
+__global__ __launch_bounds__(GS_NT) void k_face_gs_fused(LevelDev L, const T* __restrict__ uin,
+                                                         T* __restrict__ uout, const T* __restrict__ f,
+                                                         const T* __restrict__ kap, int backward,
+                                                         int nblk_tiles) {
+    __shared__ T us[GS_R][GS_W];
+    __shared__ T ks[VARK ? GS_R : 1][VARK ? GS_W : 1];
+    const int G = gridDim.x;                              // multiple of 8
+    const int b = blockIdx.x;
+    const int logical = (b & 7) * (G >> 3) + (b >> 3);    // contiguous tiles per XCD
+    const int tx = threadIdx.x & (GS_W - 1), ty = threadIdx.x / GS_W;
+    const int n = L.n;
+    if (logical >= nblk_tiles) {
+        // edge points (k = 0..n-1) and vertex blocks
+        const int cb = logical - nblk_tiles, ncb = G - nblk_tiles;
+        const int64_t ne = (int64_t)L.E * n, nv = (int64_t)L.V * L.vert_stride;
+        for (int64_t t = (int64_t)cb * GS_NT + threadIdx.x; t < ne + nv; t += (int64_t)ncb * GS_NT) {
+            const int64_t off = t < ne ? L.edge_base + (t / n) * L.edge_stride + (t % n)
+                                       : L.vert_base + (t - ne);
+            uout[off] = uin[off];
+        }
+        return;
+    }
+    const int face = logical / L.n_gs_tiles;
+    const int2 tl = L.gs_tiles[logical % L.n_gs_tiles];
+    const int i0 = tl.x * GS_TI - GS_H, j0 = tl.y * GS_TJ - GS_H;   // LDS origin
+    const FaceInfo& fi = L.faces[face];
+    const int64_t fb = face_base(L, face);
+    // issue every load of the tile before the first use: u (and k) with the
+    // full halo, f on the region of the first colour stage
+    T ur[GS_RPT], fr[GS_RPT], kr[VARK ? GS_RPT : 1];
+#pragma unroll
+    for (int q = 0; q < GS_RPT; ++q) {
+        const int r = ty + 2 * q, j = j0 + r, i = i0 + tx;
+        const bool in = r < GS_R && j >= 0 && j < n && i >= 0 && i <= n - 1 - j;
+        const bool inner = r >= 1 && r < GS_R - 1 && tx >= 1 && tx < GS_W - 1 && j >= 1 && i >= 1 &&
+                           i + j <= n - 2;
+        const int64_t p = fb + row_start(n, j < 0 ? 0 : (j > n ? n : j)) + i;
+        ur[q] = in ? uin[p] : (T)0;
+        fr[q] = inner ? f[p] : (T)0;
+        if (VARK) kr[VARK ? q : 0] = in ? kap[p] : (T)0;
+    }
+#pragma unroll
+    for (int q = 0; q < GS_RPT; ++q) {
+        const int r = ty + 2 * q;
+        if (r < GS_R) {
+            us[r][tx] = ur[q];
+            if (VARK) ks[VARK ? r : 0][VARK ? tx : 0] = kr[VARK ? q : 0];
+        }
+    }
+    const W7<T> w = face_weights<T>(OP_LAPLACE, fi, L.inv4l, (const T*)nullptr, 0, 0, 0);
+    const T invc = (T)1 / w.c;
+    const int ncol = fi.ncolours, rule = fi.colour_rule;
+    __syncthreads();
+    for (int s = 0; s < ncol; ++s) {
+        const int colour = backward ? ncol - 1 - s : s;
+        const int h = ncol - 1 - s;
+        const int lo = GS_H - h, hi_i = GS_H + GS_TI + h, hi_j = GS_H + GS_TJ + h;
+#pragma unroll
+        for (int q = 0; q < GS_RPT; ++q) {
+            const int r = ty + 2 * q;
+            if (r < lo || r >= hi_j || tx < lo || tx >= hi_i) continue;
+            const int j = j0 + r, i = i0 + tx;
+            if (!(j >= 1 && i >= 1 && i + j <= n - 2) || face_colour(rule, i, j) != colour) continue;
+            const T uE = us[r][tx + 1], uW = us[r][tx - 1], uN = us[r + 1][tx], uS = us[r - 1][tx];
+            const T uSE = us[r - 1][tx + 1], uNW = us[r + 1][tx - 1];
+            T val;
+            if (VARK) {
+                const T c0 = (T)fi.cot[0], c1 = (T)fi.cot[1], c2 = (T)fi.cot[2];
+                const T k0 = ks[r][tx], kE = ks[r][tx + 1], kW = ks[r][tx - 1], kN = ks[r + 1][tx];
+                const T kS = ks[r - 1][tx], kSE = ks[r - 1][tx + 1], kNW = ks[r + 1][tx - 1];
+                const T third = (T)(1.0 / 3.0), hf = (T)0.5;
+                const T t1 = (k0 + kE + kN) * third, t2 = (kSE + kE + k0) * third;
+                const T t3 = (kW + k0 + kNW) * third, t4 = (kS + k0 + kW) * third;
+                const T t5 = (k0 + kN + kNW) * third, t6 = (kS + kSE + k0) * third;
+                const T we = -hf * c2 * (t1 + t2), ww = -hf * c2 * (t3 + t4);
+                const T wn = -hf * c1 * (t1 + t5), ws = -hf * c1 * (t6 + t4);
+                const T wse = -hf * c0 * (t6 + t2), wnw = -hf * c0 * (t3 + t5);
+                const T wc = -(we + ww + wn + ws + wse + wnw);
+                val = (fr[q] - (we * uE + ww * uW + wn * uN + ws * uS + wse * uSE + wnw * uNW)) / wc;
+            } else {
+                val = (fr[q] - (w.e * (uE + uW) + w.n * (uN + uS) + w.se * (uSE + uNW))) * invc;
+            }
+            us[r][tx] = val;
+        }
+        __syncthreads();
+    }
+    // tile points (interior updated, ring copied) to uout
+    for (int r = GS_H + ty; r < GS_H + GS_TJ; r += 2) {
+        const int j = j0 + r, i = i0 + tx;
+        if (tx >= GS_H && tx < GS_H + GS_TI && j < n && i <= n - 1 - j)
+            uout[fb + row_start(n, j) + i] = us[r][tx];
+    }
+    // near-edge rows into the edge ghost rows of uout (edge order)
+    if (!fi.bside[0] && tl.y == 0) {            // (m, 1)
+        for (int t = threadIdx.x; t < GS_TI; t += GS_NT) {
+            const int m = tl.x * GS_TI + t;
+            if (m <= n - 2)
+                uout[edge_ghost(L, fi.edge[0], fi.slot[0]) + (fi.rev[0] ? n - 2 - m : m)] = us[1 - j0][GS_H + t];
+        }
+    }
+    if (!fi.bside[1] && tl.x == 0) {            // (1, m)
+        for (int t = threadIdx.x; t < GS_TJ; t += GS_NT) {
+            const int m = tl.y * GS_TJ + t;
+            if (m <= n - 2)
+                uout[edge_ghost(L, fi.edge[1], fi.slot[1]) + (fi.rev[1] ? n - 2 - m : m)] = us[GS_H + t][1 - i0];
+        }
+    }
+    if (!fi.bside[2]) {                         // (n-2-m, m)
+        for (int t = threadIdx.x; t < GS_TJ; t += GS_NT) {
+            const int m = tl.y * GS_TJ + t, i = n - 2 - m;
+            if (m <= n - 2 && i >= tl.x * GS_TI && i < tl.x * GS_TI + GS_TI)
+                uout[edge_ghost(L, fi.edge[2], fi.slot[2]) + (fi.rev[2] ? n - 2 - m : m)] = us[GS_H + t][i - i0];
+        }
+    }
 }
 
 // Stage A (stage = 0): interior vertices and even-k points of interior
@@ -388,9 +517,10 @@ __global__ __launch_bounds__(NT) void k_face_restrict(LevelDev Lf, LevelDev Lc, 
     FACE_TILE_LOOP(Lc)
     (void)fi; (void)up; (void)dn;
     const int jf = 2 * j;
-    const int64_t q = face_base(Lf, face) + Lf.row_off[jf] + 2 * i;
-    const int64_t upf = Lf.row_off[jf + 1] - Lf.row_off[jf];
-    const int64_t dnf = Lf.row_off[jf] - Lf.row_off[jf - 1];
+    const int nf_ = Lf.n;
+    const int64_t q = face_base(Lf, face) + row_start(nf_, jf) + 2 * i;
+    const int64_t upf = row_start(nf_, jf + 1) - row_start(nf_, jf);
+    const int64_t dnf = row_start(nf_, jf) - row_start(nf_, jf - 1);
     const T nb = r[q + 1] + r[q - 1] + r[q + upf] + r[q - dnf] + r[q - dnf + 1] + r[q + upf - 1];
     fc[p] = r[q] + (T)0.5 * nb;
     FACE_TILE_END
@@ -431,16 +561,17 @@ __global__ __launch_bounds__(NT) void k_face_prolong(LevelDev Lf, LevelDev Lc, c
     FACE_TILE_LOOP(Lf)
     (void)fi; (void)up; (void)dn;
     const int64_t cb = face_base(Lc, face);
+    const int nc_ = Lc.n;
     const int I = i >> 1, J = j >> 1;
     T c;
     if (!(i & 1) && !(j & 1)) {
-        c = uc[cb + Lc.row_off[J] + I];
+        c = uc[cb + row_start(nc_, J) + I];
     } else if ((i & 1) && !(j & 1)) {
-        c = (T)0.5 * (uc[cb + Lc.row_off[J] + I] + uc[cb + Lc.row_off[J] + I + 1]);
+        c = (T)0.5 * (uc[cb + row_start(nc_, J) + I] + uc[cb + row_start(nc_, J) + I + 1]);
     } else if (!(i & 1) && (j & 1)) {
-        c = (T)0.5 * (uc[cb + Lc.row_off[J] + I] + uc[cb + Lc.row_off[J + 1] + I]);
+        c = (T)0.5 * (uc[cb + row_start(nc_, J) + I] + uc[cb + row_start(nc_, J + 1) + I]);
     } else {
-        c = (T)0.5 * (uc[cb + Lc.row_off[J] + I + 1] + uc[cb + Lc.row_off[J + 1] + I]);
+        c = (T)0.5 * (uc[cb + row_start(nc_, J) + I + 1] + uc[cb + row_start(nc_, J + 1) + I]);
     }
     u[p] += c;
     FACE_TILE_END
@@ -503,7 +634,7 @@ __global__ __launch_bounds__(NT) void k_face_inject(LevelDev Lf, LevelDev Lc, co
                                                     T* __restrict__ kc) {
     FACE_TILE_LOOP(Lc)
     (void)fi; (void)up; (void)dn;
-    kc[p] = kf[face_base(Lf, face) + Lf.row_off[2 * j] + 2 * i];
+    kc[p] = kf[face_base(Lf, face) + row_start(Lf.n, 2 * j) + 2 * i];
     FACE_TILE_END
 }
 
@@ -535,8 +666,8 @@ __global__ __launch_bounds__(NT) void k_coarse_extract(LevelDev L, CoarseDev C, 
         const int kind = C.kind[p], prim = C.prim[p];
         if (kind == 2) {
             const int i = C.pa[p], j = C.pb[p];
-            const int64_t q = face_base(L, prim) + L.row_off[j] + i;
-            const int64_t up = L.row_off[j + 1] - L.row_off[j], dn = L.row_off[j] - L.row_off[j - 1];
+            const int64_t q = face_base(L, prim) + row_start(n, j) + i;
+            const int64_t up = row_start(n, j + 1) - row_start(n, j), dn = row_start(n, j) - row_start(n, j - 1);
             const W7<double> w = face_weights<double>(op, L.faces[prim], L.inv4l, kap, q, up, dn);
             v[0] = w.c; v[1] = w.e; v[2] = w.w; v[3] = w.n; v[4] = w.s; v[5] = w.se; v[6] = w.nw;
         } else if (kind == 1) {
@@ -745,41 +876,43 @@ struct TimingScope {
 };
 
 template <class T>
-static hipError_t gs_t(const hhg_mesh* M, int level, int op, T* u, const T* f, int backward,
+static hipError_t gs_t(const hhg_mesh* M, int level, int op, T* x, T* y, const T* f, int backward,
                        hipStream_t s) {
     const LevelDev L = M->dev(level);
     const T* kap = kap_of<T>(M, level);
     const int dt = sizeof(T) == 8 ? DT_F64 : DT_F32;
     const int gl = grid_for((int64_t)L.n_iedges * (L.n - 2) + L.n_iverts, MAX_LOW_BLOCKS);
     const bool timed = M->timing && level == M->m.L;
-    auto faces = [&]() {
+    const int ntile_blocks = L.F * L.n_gs_tiles;
+    const int g = (ntile_blocks + GS_COPY_BLOCKS + 7) / 8 * 8;
+    auto faces = [&]() -> hipError_t {
         TimingScope ts(M, s, timed);
-        for (int c = 0; c < 3; ++c) {
-            const int col = backward ? 2 - c : c;
-            k_face_gs_colour<T><<<face_grid(L), NT, 0, s>>>(L, op, u, f, kap, col);
-        }
+        if (op == OP_DIFFUSION)
+            k_face_gs_fused<T, true><<<g, GS_NT, 0, s>>>(L, x, y, f, kap, backward, ntile_blocks);
+        else
+            k_face_gs_fused<T, false><<<g, GS_NT, 0, s>>>(L, x, y, f, kap, backward, ntile_blocks);
+        return hipGetLastError();
     };
     hipError_t e;
     if (!backward) {
-        k_low_gs<T><<<gl, NT, 0, s>>>(L, op, u, f, kap, 0);
-        if ((e = launch_sync(M, level, dt, u, GM_VERT | GM_EEVEN, s)) != hipSuccess) return e;
-        k_low_gs<T><<<gl, NT, 0, s>>>(L, op, u, f, kap, 1);
-        if ((e = launch_sync(M, level, dt, u, GM_EODD, s)) != hipSuccess) return e;
-        faces();
-        return launch_sync(M, level, dt, u, GM_FACE, s);
+        k_low_gs<T><<<gl, NT, 0, s>>>(L, op, x, f, kap, 0);
+        if ((e = launch_sync(M, level, dt, x, GM_VERT | GM_EEVEN, s)) != hipSuccess) return e;
+        k_low_gs<T><<<gl, NT, 0, s>>>(L, op, x, f, kap, 1);
+        if ((e = launch_sync(M, level, dt, x, GM_EODD, s)) != hipSuccess) return e;
+        return faces();
     }
-    faces();
-    if ((e = launch_sync(M, level, dt, u, GM_FACE, s)) != hipSuccess) return e;
-    k_low_gs<T><<<gl, NT, 0, s>>>(L, op, u, f, kap, 1);
-    if ((e = launch_sync(M, level, dt, u, GM_EODD, s)) != hipSuccess) return e;
-    k_low_gs<T><<<gl, NT, 0, s>>>(L, op, u, f, kap, 0);
-    return launch_sync(M, level, dt, u, GM_VERT | GM_EEVEN, s);
+    if ((e = faces()) != hipSuccess) return e;
+    k_low_gs<T><<<gl, NT, 0, s>>>(L, op, y, f, kap, 1);
+    if ((e = launch_sync(M, level, dt, y, GM_EODD, s)) != hipSuccess) return e;
+    k_low_gs<T><<<gl, NT, 0, s>>>(L, op, y, f, kap, 0);
+    return launch_sync(M, level, dt, y, GM_VERT | GM_EEVEN, s);
 }
 
-hipError_t launch_gs_sweep(const hhg_mesh* M, int level, int op, int dtype, void* u, const void* f,
-                           int backward, hipStream_t s) {
-    if (dtype == DT_F64) return gs_t<double>(M, level, op, (double*)u, (const double*)f, backward, s);
-    return gs_t<float>(M, level, op, (float*)u, (const float*)f, backward, s);
+hipError_t launch_gs_sweep(const hhg_mesh* M, int level, int op, int dtype, void* x, void* y,
+                           const void* f, int backward, hipStream_t s) {
+    if (dtype == DT_F64)
+        return gs_t<double>(M, level, op, (double*)x, (double*)y, (const double*)f, backward, s);
+    return gs_t<float>(M, level, op, (float*)x, (float*)y, (const float*)f, backward, s);
 }
 
 template <class T>

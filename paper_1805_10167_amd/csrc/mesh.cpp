@@ -268,6 +268,13 @@ void MeshData::build_level(int level) {
             if (imin + jmin <= n - 2) H.tiles.push_back(make_int2(ti, tj));
         }
 
+    // smoother tiles over the whole face triangle (ring included), column by
+    // column so that consecutive tiles are vertical neighbours
+    H.gs_tiles.clear();
+    for (int ti = 0; ti * GS_TI <= n - 1; ++ti)
+        for (int tj = 0; tj * GS_TJ <= n - 1; ++tj)
+            if (ti * GS_TI + tj * GS_TJ <= n - 1) H.gs_tiles.push_back(make_int2(ti, tj));
+
     // ghost table
     std::vector<std::tuple<int, int64_t, int64_t>> ent;
     auto cls_of = [&](const Owner& o) {

@@ -93,8 +93,8 @@ def test_residual_and_norm(name, L):
     assert abs(nrm.item() - np.linalg.norm(ro)) <= F64_TOL * np.linalg.norm(ro)
 
 
-@pytest.mark.parametrize("name,L", CASES)
-@pytest.mark.parametrize("backward,sweeps", [(0, 1), (1, 1), (0, 2)])
+@pytest.mark.parametrize("name,L", CASES + [("annulus64", 7), ("square", 7)])
+@pytest.mark.parametrize("backward,sweeps", [(0, 1), (1, 1), (0, 2), (1, 3)])
 def test_smooth_parity(name, L, backward, sweeps):
     import paper_1805_10167_amd as P
     log("smooth %s L=%d bwd=%d sweeps=%d" % (name, L, backward, sweeps))
@@ -116,7 +116,8 @@ def test_smooth_parity(name, L, backward, sweeps):
 
 @pytest.mark.parametrize("name,L,nu", [("square", 5, (2, 2)), ("annulus64", 4, (1, 1)),
                                        ("annulus64", 6, (3, 3)), ("annulus128", 4, (3, 3)),
-                                       ("annulus64", 6, (2, 0))])
+                                       ("annulus64", 6, (2, 0)), ("annulus64", 7, (3, 3)),
+                                       ("annulus128", 7, (1, 2))])
 def test_vcycle_parity(name, L, nu):
     import paper_1805_10167_amd as P
     log("vcycle %s L=%d nu=%s" % (name, L, nu))
