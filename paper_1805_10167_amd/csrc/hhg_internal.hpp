@@ -18,10 +18,11 @@ constexpr int PAD = 16;         // row/segment padding in elements
 constexpr int TILE_I = 64;      // generic face tile: 64 (i) x 4 (j) points
 constexpr int TILE_J = 4;
 // fused smoother tile: GS_TI x GS_TJ updated points plus a halo of GS_H on
-// every side, so that an LDS row holds GS_TI + 2 GS_H = 128 values
+// every side, so that an LDS row holds GS_TI + 2 GS_H = 192 values (three
+// per lane of a wave)
 constexpr int GS_H = 3;
-constexpr int GS_TI = 128 - 2 * GS_H;
-constexpr int GS_TJ = 32;
+constexpr int GS_TI = 192 - 2 * GS_H;
+constexpr int GS_TJ = 24;
 
 inline int64_t pad_up(int64_t x, int64_t p) { return (x + p - 1) / p * p; }
 

@@ -34,6 +34,7 @@ struct Owner {
 
 struct MeshData {
     int V = 0, E = 0, F = 0, L = 0, lc = 0, maxdeg = 0;
+    int nfaces2 = 0;   // faces smoothed with two colours (exact right angle)
     std::vector<double> vxy;
     std::vector<std::array<int, 3>> tri;            // counter-clockwise
     std::vector<std::array<int, 2>> edge_v;         // (a, b), a < b

@@ -350,25 +350,200 @@ __global__ __launch_bounds__(1024) void k_reduce_final(const double* __restrict_
 // reads uin and writes uout; the same launch copies the face rings, edge
 // points and vertex blocks into uout and writes the near-edge rows into
 // uout's edge ghost rows, leaving uout a complete, consistent field.
-constexpr int GS_W = GS_TI + 2 * GS_H;          // 128 values per LDS row
+constexpr int GS_W = GS_TI + 2 * GS_H;          // 192 values per LDS row
 constexpr int GS_R = GS_TJ + 2 * GS_H;          // LDS rows
-constexpr int GS_NT = 256;
-constexpr int GS_RPT = (GS_R + 1) / 2;          // rows per thread
+constexpr int GS_NT = 512;                      // threads per block
+constexpr int GS_NW = GS_NT / 64;               // waves per block
+constexpr int GS_RPW = (GS_R + GS_NW - 1) / GS_NW;   // LDS rows loaded per wave
 constexpr int GS_COPY_BLOCKS = 32;
 
+__device__ __forceinline__ int pmod(int a, int m) { return ((a % m) + m) % m; }
+
+// Wave index inside the block, as a wave-uniform (scalar) value.
+__device__ __forceinline__ int wave_id() { return __builtin_amdgcn_readfirstlane(threadIdx.x >> 6); }
+
+// Stage update of one face point at LDS position (r, tx).
 template <class T, bool VARK>
+__device__ __forceinline__ T gs_point(const FaceInfo& fi, const W7<T>& w, T invc, T fv,
+                                      T (*us)[GS_W], T (*ks)[GS_W], int r, int tx) {
+    const T uE = us[r][tx + 1], uW = us[r][tx - 1], uN = us[r + 1][tx], uS = us[r - 1][tx];
+    const T uSE = us[r - 1][tx + 1], uNW = us[r + 1][tx - 1];
+    if (!VARK) return (fv - (w.e * (uE + uW) + w.n * (uN + uS) + w.se * (uSE + uNW))) * invc;
+    const T c0 = (T)fi.cot[0], c1 = (T)fi.cot[1], c2 = (T)fi.cot[2];
+    const T k0 = ks[r][tx], kE = ks[r][tx + 1], kW = ks[r][tx - 1], kN = ks[r + 1][tx];
+    const T kS = ks[r - 1][tx], kSE = ks[r - 1][tx + 1], kNW = ks[r + 1][tx - 1];
+    const T third = (T)(1.0 / 3.0), hf = (T)0.5;
+    const T t1 = (k0 + kE + kN) * third, t2 = (kSE + kE + k0) * third;
+    const T t3 = (kW + k0 + kNW) * third, t4 = (kS + k0 + kW) * third;
+    const T t5 = (k0 + kN + kNW) * third, t6 = (kS + kSE + k0) * third;
+    const T we = -hf * c2 * (t1 + t2), ww = -hf * c2 * (t3 + t4);
+    const T wn = -hf * c1 * (t1 + t5), ws = -hf * c1 * (t6 + t4);
+    const T wse = -hf * c0 * (t6 + t2), wnw = -hf * c0 * (t3 + t5);
+    const T wc = -(we + ww + wn + ws + wse + wnw);
+    return (fv - (we * uE + ww * uW + wn * uN + ws * uS + wse * uSE + wnw * uNW)) / wc;
+}
+
+// Tile rows into registers: wave w takes LDS rows w + GS_NW q, lane l columns
+// l, l + 64, l + 128.  The caller stores them to LDS after issuing f loads.
+template <class T, bool VARK>
+__device__ __forceinline__ void gs_load_u(int n, int i0, int j0, int64_t fb, const T* __restrict__ uin,
+                                          const T* __restrict__ kap, T (*ur)[3], T (*kr)[3]) {
+    const int wv = wave_id(), lane = threadIdx.x & 63;
+#pragma unroll
+    for (int q = 0; q < GS_RPW; ++q) {
+        const int r = wv + GS_NW * q, j = j0 + r;
+        const int64_t rb = fb + row_start(n, j < 0 ? 0 : (j > n ? n : j));
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            const int i = i0 + lane + 64 * c;
+            const bool in = r < GS_R && j >= 0 && j < n && i >= 0 && i <= n - 1 - j;
+            ur[q][c] = in ? uin[rb + i] : (T)0;
+            if (VARK) kr[q][c] = in ? kap[rb + i] : (T)0;
+        }
+    }
+}
+
+template <class T, bool VARK>
+__device__ __forceinline__ void gs_store_u(T (*us)[GS_W], T (*ks)[GS_W], T (*ur)[3], T (*kr)[3]) {
+    const int wv = wave_id(), lane = threadIdx.x & 63;
+#pragma unroll
+    for (int q = 0; q < GS_RPW; ++q) {
+        const int r = wv + GS_NW * q;
+        if (r < GS_R) {
+#pragma unroll
+            for (int c = 0; c < 3; ++c) {
+                us[r][lane + 64 * c] = ur[q][c];
+                if (VARK) ks[r][lane + 64 * c] = kr[q][c];
+            }
+        }
+    }
+}
+
+// Three colours ((i - j) mod 3): wave w handles LDS rows lo + w + GS_NW it of
+// the stage region.  In a row the colour-c points are every third column and
+// lane l owns columns 3 l .. 3 l + 2, so each lane updates exactly one point
+// per row; the row, the colour offset and the bounds are wave-uniform.
+constexpr int GS_IT3 = (GS_TJ + 4 + GS_NW - 1) / GS_NW;
+
+template <class T, bool VARK>
+__device__ __forceinline__ void gs_tile3(const LevelDev& L, const FaceInfo& fi, int n, int i0, int j0,
+                                         int64_t fb, const T* __restrict__ uin, const T* __restrict__ f,
+                                         const T* __restrict__ kap, int backward, T (*us)[GS_W],
+                                         T (*ks)[GS_W]) {
+    const int wv = wave_id(), lane = threadIdx.x & 63;
+    T ur[GS_RPW][3], kr[VARK ? GS_RPW : 1][3], fr[3][GS_IT3];
+    gs_load_u<T, VARK>(n, i0, j0, fb, uin, kap, ur, kr);
+#pragma unroll
+    for (int s = 0; s < 3; ++s) {
+        const int c = backward ? 2 - s : s, h = 2 - s;
+        const int lo = GS_H - h, hi_i = GS_H + GS_TI + h, hi_j = GS_H + GS_TJ + h;
+#pragma unroll
+        for (int it = 0; it < GS_IT3; ++it) {
+            const int r = lo + wv + GS_NW * it, j = j0 + r;
+            const int tx = pmod(c + j - i0, 3) + 3 * lane, i = i0 + tx;
+            const bool upd = r < hi_j && tx >= lo && tx < hi_i && j >= 1 && i >= 1 && i + j <= n - 2;
+            fr[s][it] = upd ? f[fb + row_start(n, upd ? j : 0) + i] : (T)0;
+        }
+    }
+    gs_store_u<T, VARK>(us, ks, ur, kr);
+    const W7<T> w = face_weights<T>(OP_LAPLACE, fi, L.inv4l, (const T*)nullptr, 0, 0, 0);
+    const T invc = (T)1 / w.c;
+    __syncthreads();
+#pragma unroll
+    for (int s = 0; s < 3; ++s) {
+        const int c = backward ? 2 - s : s, h = 2 - s;
+        const int lo = GS_H - h, hi_i = GS_H + GS_TI + h, hi_j = GS_H + GS_TJ + h;
+#pragma unroll
+        for (int it = 0; it < GS_IT3; ++it) {
+            const int r = lo + wv + GS_NW * it, j = j0 + r;
+            if (r >= hi_j) break;
+            int tx = pmod(c + j - i0, 3) + 3 * lane;
+            const int i = i0 + tx;
+            const bool upd = tx >= lo && tx < hi_i && j >= 1 && i >= 1 && i + j <= n - 2;
+            tx = upd ? tx : GS_H;     // keep the neighbour reads inside the tile
+            const T val = gs_point<T, VARK>(fi, w, invc, fr[s][it], us, ks, r, tx);
+            if (upd) us[r][tx] = val;
+        }
+        __syncthreads();
+    }
+}
+
+// Two colours (faces with an exact right angle): slots map densely onto the
+// colour-c points, every second column or every second row.
+constexpr int GS_IT2 = ((GS_TJ + 2) * (GS_W / 2) + GS_NT - 1) / GS_NT;
+
+__device__ __forceinline__ bool gs_decode2(int idx, int rule, int c, int h, int i0, int j0, int& r,
+                                           int& tx) {
+    const int lo = GS_H - h, hi_i = GS_H + GS_TI + h, hi_j = GS_H + GS_TJ + h;
+    if (rule == 3) {
+        const int rr = idx / GS_W, m = idx - rr * GS_W;
+        r = lo + pmod(c - (j0 + lo), 2) + 2 * rr;
+        tx = m;
+        if (tx < lo) return false;
+    } else {
+        const int rr = idx / (GS_W / 2), m = idx - rr * (GS_W / 2);
+        r = lo + rr;
+        const int off = rule == 1 ? pmod(c - (j0 + r) - i0, 2) : pmod(c - i0, 2);
+        tx = lo + pmod(off - lo, 2) + 2 * m;
+    }
+    return r < hi_j && tx < hi_i;
+}
+
+template <class T, bool VARK>
+__device__ __forceinline__ void gs_tile2(const LevelDev& L, const FaceInfo& fi, int n, int i0, int j0,
+                                         int64_t fb, const T* __restrict__ uin, const T* __restrict__ f,
+                                         const T* __restrict__ kap, int backward, T (*us)[GS_W],
+                                         T (*ks)[GS_W]) {
+    const int rule = fi.colour_rule;
+    T ur[GS_RPW][3], kr[VARK ? GS_RPW : 1][3], fr[2][GS_IT2];
+    gs_load_u<T, VARK>(n, i0, j0, fb, uin, kap, ur, kr);
+#pragma unroll
+    for (int s = 0; s < 2; ++s) {
+        const int c = backward ? 1 - s : s, h = 1 - s;
+#pragma unroll
+        for (int it = 0; it < GS_IT2; ++it) {
+            int r, tx;
+            const bool ok = gs_decode2(threadIdx.x + it * GS_NT, rule, c, h, i0, j0, r, tx);
+            const int j = j0 + r, i = i0 + tx;
+            const bool upd = ok && j >= 1 && i >= 1 && i + j <= n - 2;
+            fr[s][it] = upd ? f[fb + row_start(n, upd ? j : 0) + i] : (T)0;
+        }
+    }
+    gs_store_u<T, VARK>(us, ks, ur, kr);
+    const W7<T> w = face_weights<T>(OP_LAPLACE, fi, L.inv4l, (const T*)nullptr, 0, 0, 0);
+    const T invc = (T)1 / w.c;
+    __syncthreads();
+#pragma unroll
+    for (int s = 0; s < 2; ++s) {
+        const int c = backward ? 1 - s : s, h = 1 - s;
+#pragma unroll
+        for (int it = 0; it < GS_IT2; ++it) {
+            int r, tx;
+            const bool ok = gs_decode2(threadIdx.x + it * GS_NT, rule, c, h, i0, j0, r, tx);
+            const int j = j0 + r, i = i0 + tx;
+            if (!(ok && j >= 1 && i >= 1 && i + j <= n - 2)) continue;
+            us[r][tx] = gs_point<T, VARK>(fi, w, invc, fr[s][it], us, ks, r, tx);
+        }
+        __syncthreads();
+    }
+}
+
+// NCOL selects the faces this launch handles (3: general faces, 2: faces
+// with a right angle); copies of edge and vertex blocks are done by the
+// extra blocks of the launch with with_copy = 1.
+template <class T, bool VARK, int NCOL>
 __global__ __launch_bounds__(GS_NT) void k_face_gs_fused(LevelDev L, const T* __restrict__ uin,
                                                          T* __restrict__ uout, const T* __restrict__ f,
                                                          const T* __restrict__ kap, int backward,
-                                                         int nblk_tiles) {
+                                                         int nblk_tiles, int with_copy) {
     __shared__ T us[GS_R][GS_W];
-    __shared__ T ks[VARK ? GS_R : 1][VARK ? GS_W : 1];
+    __shared__ T ks[VARK ? GS_R : 1][GS_W];
     const int G = gridDim.x;                              // multiple of 8
     const int b = blockIdx.x;
     const int logical = (b & 7) * (G >> 3) + (b >> 3);    // contiguous tiles per XCD
-    const int tx = threadIdx.x & (GS_W - 1), ty = threadIdx.x / GS_W;
     const int n = L.n;
     if (logical >= nblk_tiles) {
+        if (!with_copy) return;
         // edge points (k = 0..n-1) and vertex blocks
         const int cb = logical - nblk_tiles, ncb = G - nblk_tiles;
         const int64_t ne = (int64_t)L.E * n, nv = (int64_t)L.V * L.vert_stride;
@@ -380,74 +555,26 @@ __global__ __launch_bounds__(GS_NT) void k_face_gs_fused(LevelDev L, const T* __
         return;
     }
     const int face = logical / L.n_gs_tiles;
+    const FaceInfo& fi = L.faces[face];
+    if (fi.ncolours != NCOL) return;
     const int2 tl = L.gs_tiles[logical % L.n_gs_tiles];
     const int i0 = tl.x * GS_TI - GS_H, j0 = tl.y * GS_TJ - GS_H;   // LDS origin
-    const FaceInfo& fi = L.faces[face];
     const int64_t fb = face_base(L, face);
-    // issue every load of the tile before the first use: u (and k) with the
-    // full halo, f on the region of the first colour stage
-    T ur[GS_RPT], fr[GS_RPT], kr[VARK ? GS_RPT : 1];
-#pragma unroll
-    for (int q = 0; q < GS_RPT; ++q) {
-        const int r = ty + 2 * q, j = j0 + r, i = i0 + tx;
-        const bool in = r < GS_R && j >= 0 && j < n && i >= 0 && i <= n - 1 - j;
-        const bool inner = r >= 1 && r < GS_R - 1 && tx >= 1 && tx < GS_W - 1 && j >= 1 && i >= 1 &&
-                           i + j <= n - 2;
-        const int64_t p = fb + row_start(n, j < 0 ? 0 : (j > n ? n : j)) + i;
-        ur[q] = in ? uin[p] : (T)0;
-        fr[q] = inner ? f[p] : (T)0;
-        if (VARK) kr[VARK ? q : 0] = in ? kap[p] : (T)0;
-    }
-#pragma unroll
-    for (int q = 0; q < GS_RPT; ++q) {
-        const int r = ty + 2 * q;
-        if (r < GS_R) {
-            us[r][tx] = ur[q];
-            if (VARK) ks[VARK ? r : 0][VARK ? tx : 0] = kr[VARK ? q : 0];
-        }
-    }
-    const W7<T> w = face_weights<T>(OP_LAPLACE, fi, L.inv4l, (const T*)nullptr, 0, 0, 0);
-    const T invc = (T)1 / w.c;
-    const int ncol = fi.ncolours, rule = fi.colour_rule;
-    __syncthreads();
-    for (int s = 0; s < ncol; ++s) {
-        const int colour = backward ? ncol - 1 - s : s;
-        const int h = ncol - 1 - s;
-        const int lo = GS_H - h, hi_i = GS_H + GS_TI + h, hi_j = GS_H + GS_TJ + h;
-#pragma unroll
-        for (int q = 0; q < GS_RPT; ++q) {
-            const int r = ty + 2 * q;
-            if (r < lo || r >= hi_j || tx < lo || tx >= hi_i) continue;
-            const int j = j0 + r, i = i0 + tx;
-            if (!(j >= 1 && i >= 1 && i + j <= n - 2) || face_colour(rule, i, j) != colour) continue;
-            const T uE = us[r][tx + 1], uW = us[r][tx - 1], uN = us[r + 1][tx], uS = us[r - 1][tx];
-            const T uSE = us[r - 1][tx + 1], uNW = us[r + 1][tx - 1];
-            T val;
-            if (VARK) {
-                const T c0 = (T)fi.cot[0], c1 = (T)fi.cot[1], c2 = (T)fi.cot[2];
-                const T k0 = ks[r][tx], kE = ks[r][tx + 1], kW = ks[r][tx - 1], kN = ks[r + 1][tx];
-                const T kS = ks[r - 1][tx], kSE = ks[r - 1][tx + 1], kNW = ks[r + 1][tx - 1];
-                const T third = (T)(1.0 / 3.0), hf = (T)0.5;
-                const T t1 = (k0 + kE + kN) * third, t2 = (kSE + kE + k0) * third;
-                const T t3 = (kW + k0 + kNW) * third, t4 = (kS + k0 + kW) * third;
-                const T t5 = (k0 + kN + kNW) * third, t6 = (kS + kSE + k0) * third;
-                const T we = -hf * c2 * (t1 + t2), ww = -hf * c2 * (t3 + t4);
-                const T wn = -hf * c1 * (t1 + t5), ws = -hf * c1 * (t6 + t4);
-                const T wse = -hf * c0 * (t6 + t2), wnw = -hf * c0 * (t3 + t5);
-                const T wc = -(we + ww + wn + ws + wse + wnw);
-                val = (fr[q] - (we * uE + ww * uW + wn * uN + ws * uS + wse * uSE + wnw * uNW)) / wc;
-            } else {
-                val = (fr[q] - (w.e * (uE + uW) + w.n * (uN + uS) + w.se * (uSE + uNW))) * invc;
-            }
-            us[r][tx] = val;
-        }
-        __syncthreads();
-    }
+    if (NCOL == 3)
+        gs_tile3<T, VARK>(L, fi, n, i0, j0, fb, uin, f, kap, backward, us, VARK ? ks : nullptr);
+    else
+        gs_tile2<T, VARK>(L, fi, n, i0, j0, fb, uin, f, kap, backward, us, VARK ? ks : nullptr);
+    const int wv = wave_id(), lane = threadIdx.x & 63;
     // tile points (interior updated, ring copied) to uout
-    for (int r = GS_H + ty; r < GS_H + GS_TJ; r += 2) {
-        const int j = j0 + r, i = i0 + tx;
-        if (tx >= GS_H && tx < GS_H + GS_TI && j < n && i <= n - 1 - j)
-            uout[fb + row_start(n, j) + i] = us[r][tx];
+    for (int r = GS_H + wv; r < GS_H + GS_TJ; r += GS_NW) {
+        const int j = j0 + r;
+        if (j >= n) break;
+        const int64_t rb = fb + row_start(n, j);
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            const int tx = lane + 64 * c, i = i0 + tx;
+            if (tx >= GS_H && tx < GS_H + GS_TI && i <= n - 1 - j) uout[rb + i] = us[r][tx];
+        }
     }
     // near-edge rows into the edge ghost rows of uout (edge order)
     if (!fi.bside[0] && tl.y == 0) {            // (m, 1)
@@ -756,6 +883,111 @@ __global__ __launch_bounds__(1024) void k_coarse_pcg(CoarseDev C, const double* 
     for (int a = tid; a < N; a += 1024) uf[C.owner[a]] += (T)x[a];
 }
 
+// Block sum of two values at once (same fixed tree as block_sum).
+template <int NTH>
+__device__ __forceinline__ void block_sum2(double& a, double& b, double* sm) {
+    a = wave_sum(a);
+    b = wave_sum(b);
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int nw = (blockDim.x + 63) >> 6;
+    __syncthreads();
+    if (lane == 0) { sm[w] = a; sm[NTH / 64 + w] = b; }
+    __syncthreads();
+    if (threadIdx.x < 64) {
+        double ta = (threadIdx.x < nw) ? sm[threadIdx.x] : 0.0;
+        double tb = (threadIdx.x < nw) ? sm[NTH / 64 + threadIdx.x] : 0.0;
+        ta = wave_sum(ta);
+        tb = wave_sum(tb);
+        if (threadIdx.x == 0) { sm[2 * (NTH / 64)] = ta; sm[2 * (NTH / 64) + 1] = tb; }
+    }
+    __syncthreads();
+    a = sm[2 * (NTH / 64)];
+    b = sm[2 * (NTH / 64) + 1];
+}
+
+// Register-resident Jacobi-PCG for coarse systems with N <= CG_RPT * 1024
+// rows and at most CG_W stencil entries per row.  Each thread owns rows
+// tid + k * blockDim.x; only the search direction is shared (LDS).  Same
+// recurrences and stopping rule as k_coarse_pcg.
+constexpr int CG_RPT = 2;
+constexpr int CG_W = 8;
+constexpr int CG_MAXN = CG_RPT * 1024;
+
+template <class T>
+__global__ __launch_bounds__(1024) void k_coarse_pcg_reg(CoarseDev C, const double* __restrict__ vals,
+                                                         const T* __restrict__ rf, T* __restrict__ uf,
+                                                         double tol, int maxit) {
+    __shared__ double ps[CG_MAXN];
+    __shared__ double sm[2 * (1024 / 64) + 2];
+    const int N = C.N, W = C.W, nt = blockDim.x, tid = threadIdx.x;
+    double x[CG_RPT], r[CG_RPT], z[CG_RPT], p[CG_RPT], dinv[CG_RPT], av[CG_RPT][CG_W];
+    int ac[CG_RPT][CG_W];
+    double bb = 0.0;
+#pragma unroll
+    for (int k = 0; k < CG_RPT; ++k) {
+        const int a = tid + k * nt;
+        const bool own = a < N;
+        x[k] = 0.0;
+        r[k] = own ? (double)rf[C.owner[a]] : 0.0;
+        dinv[k] = own ? 1.0 / vals[(int64_t)a * W] : 0.0;
+#pragma unroll
+        for (int w = 0; w < CG_W; ++w) {
+            const bool in = own && w < W;
+            ac[k][w] = in ? C.cols[(int64_t)a * W + w] : -1;
+            av[k][w] = in ? vals[(int64_t)a * W + w] : 0.0;
+        }
+        bb += r[k] * r[k];
+    }
+    double rz = 0.0;
+#pragma unroll
+    for (int k = 0; k < CG_RPT; ++k) {
+        z[k] = dinv[k] * r[k];
+        p[k] = z[k];
+        rz += r[k] * z[k];
+    }
+    block_sum2<1024>(bb, rz, sm);
+    const double bn = sqrt(bb);
+    if (bn == 0.0) return;
+    for (int it = 0; it < maxit; ++it) {
+#pragma unroll
+        for (int k = 0; k < CG_RPT; ++k)
+            if (tid + k * nt < N) ps[tid + k * nt] = p[k];
+        __syncthreads();
+        double q[CG_RPT], pq = 0.0, dummy = 0.0;
+#pragma unroll
+        for (int k = 0; k < CG_RPT; ++k) {
+            double s = 0.0;
+#pragma unroll
+            for (int w = 0; w < CG_W; ++w)
+                if (ac[k][w] >= 0) s += av[k][w] * ps[ac[k][w]];
+            q[k] = s;
+            pq += p[k] * s;
+        }
+        block_sum2<1024>(pq, dummy, sm);
+        const double alpha = rz / pq;
+        double rr = 0.0, rzn = 0.0;
+#pragma unroll
+        for (int k = 0; k < CG_RPT; ++k) {
+            x[k] += alpha * p[k];
+            r[k] -= alpha * q[k];
+            z[k] = dinv[k] * r[k];
+            rr += r[k] * r[k];
+            rzn += r[k] * z[k];
+        }
+        block_sum2<1024>(rr, rzn, sm);
+        if (sqrt(rr) <= tol * bn) break;
+        const double beta = rzn / rz;
+        rz = rzn;
+#pragma unroll
+        for (int k = 0; k < CG_RPT; ++k) p[k] = z[k] + beta * p[k];
+    }
+#pragma unroll
+    for (int k = 0; k < CG_RPT; ++k) {
+        const int a = tid + k * nt;
+        if (a < N) uf[C.owner[a]] += (T)x[k];
+    }
+}
+
 __global__ __launch_bounds__(NT) void k_f64_to_f32(const double* __restrict__ s, float* __restrict__ d,
                                                    int64_t n) {
     for (int64_t t = blockIdx.x * (int64_t)NT + threadIdx.x; t < n; t += (int64_t)gridDim.x * NT)
@@ -885,12 +1117,19 @@ static hipError_t gs_t(const hhg_mesh* M, int level, int op, T* x, T* y, const T
     const bool timed = M->timing && level == M->m.L;
     const int ntile_blocks = L.F * L.n_gs_tiles;
     const int g = (ntile_blocks + GS_COPY_BLOCKS + 7) / 8 * 8;
+    const int g2 = (ntile_blocks + 7) / 8 * 8;
+    const bool has2 = M->m.nfaces2 > 0;
     auto faces = [&]() -> hipError_t {
         TimingScope ts(M, s, timed);
-        if (op == OP_DIFFUSION)
-            k_face_gs_fused<T, true><<<g, GS_NT, 0, s>>>(L, x, y, f, kap, backward, ntile_blocks);
-        else
-            k_face_gs_fused<T, false><<<g, GS_NT, 0, s>>>(L, x, y, f, kap, backward, ntile_blocks);
+        if (op == OP_DIFFUSION) {
+            k_face_gs_fused<T, true, 3><<<g, GS_NT, 0, s>>>(L, x, y, f, kap, backward, ntile_blocks, 1);
+            if (has2)
+                k_face_gs_fused<T, true, 2><<<g2, GS_NT, 0, s>>>(L, x, y, f, kap, backward, ntile_blocks, 0);
+        } else {
+            k_face_gs_fused<T, false, 3><<<g, GS_NT, 0, s>>>(L, x, y, f, kap, backward, ntile_blocks, 1);
+            if (has2)
+                k_face_gs_fused<T, false, 2><<<g2, GS_NT, 0, s>>>(L, x, y, f, kap, backward, ntile_blocks, 0);
+        }
         return hipGetLastError();
     };
     hipError_t e;
@@ -964,7 +1203,14 @@ static hipError_t coarse_t(const hhg_mesh* M, int op, T* u, const T* f, const do
     T* r = (T*)(sizeof(T) == 8 ? M->r64[lc] : M->r32[lc]);
     hipError_t e = residual_t<T>(M, lc, op, u, f, r, nullptr, 0, s);
     if (e != hipSuccess) return e;
-    k_coarse_pcg<T><<<1, 1024, 0, s>>>(M->coarse, vals, r, u, 1e-14, 4 * M->coarse.N);
+    const int N = M->coarse.N;
+    if (N <= CG_MAXN && M->coarse.W <= CG_W) {
+        int nt = (N + CG_RPT - 1) / CG_RPT;
+        nt = (nt + 63) / 64 * 64;
+        k_coarse_pcg_reg<T><<<1, nt, 0, s>>>(M->coarse, vals, r, u, 1e-14, 4 * N);
+    } else {
+        k_coarse_pcg<T><<<1, 1024, 0, s>>>(M->coarse, vals, r, u, 1e-14, 4 * N);
+    }
     return launch_sync(M, lc, sizeof(T) == 8 ? DT_F64 : DT_F32, u, GM_ALL, s);
 }
 

@@ -127,6 +127,7 @@ std::string MeshData::build(const double* in_vxy, int nv, const int32_t* in_tri,
         if (edges[e].boundary) { vbnd[edges[e].a] = 1; vbnd[edges[e].b] = 1; }
 
     faces.assign(F, FaceInfo{});
+    nfaces2 = 0;
     std::vector<int> fill(E, 0);
     for (int f = 0; f < F; ++f) {
         FaceInfo& fi = faces[f];
@@ -159,6 +160,7 @@ std::string MeshData::build(const double* in_vxy, int nv, const int32_t* in_tri,
         else if (dots[1] == 0.0) { fi.colour_rule = 2; fi.ncolours = 2; }
         else if (dots[2] == 0.0) { fi.colour_rule = 3; fi.ncolours = 2; }
         else { fi.colour_rule = 0; fi.ncolours = 3; }
+        if (fi.ncolours == 2) ++nfaces2;
         for (int s = 0; s < 3; ++s) {
             int p = tri[f][side_start(s)], q = tri[f][side_end(s)];
             int e = edge_id[{std::min(p, q), std::max(p, q)}];
