@@ -177,9 +177,8 @@ int vcycle_rec(const hhg_mesh* M, int level, int op, int smoother, int dt, void*
     void* r = level_r(M, level, dt);
     void* uc = level_u(M, level - 1, dt);
     void* fc = level_f(M, level - 1, dt);
-    HIP_CHECK(launch_residual(M, level, op, dt, cur, f, r, nullptr, GM_FACE | GM_EODD, s), "residual");
-    HIP_CHECK(launch_restrict(M, level, dt, r, fc, s), "restrict");
-    HIP_CHECK(launch_fill(uc, M->m.lv[level - 1].total, dt, 0.0, s), "fill");
+    HIP_CHECK(launch_residual(M, level, op, dt, cur, f, r, nullptr, s), "residual");
+    HIP_CHECK(launch_restrict(M, level, dt, r, fc, uc, s), "restrict");
     rc = vcycle_rec(M, level - 1, op, smoother, dt, uc, fc, nu1, nu2, s);
     if (rc) return rc;
     HIP_CHECK(launch_prolong_add(M, level, dt, uc, cur, s), "prolong");
@@ -423,8 +422,7 @@ int hhg_residual(const hhg_mesh* M, int32_t level, int32_t op, int32_t dtype, co
     if ((rc = check_op(M, op, dtype))) return rc;
     if (op == HHG_OP_MASS) return fail(HHG_EINVAL, "residual needs a stiffness operator");
     if (!u || !f || !r) return fail(HHG_EINVAL, "null buffer");
-    HIP_CHECK(launch_residual(M, level, op, dtype, u, f, r, norm, GM_ALL, (hipStream_t)stream),
-              "residual");
+    HIP_CHECK(launch_residual(M, level, op, dtype, u, f, r, norm, (hipStream_t)stream), "residual");
     return HHG_OK;
 }
 
@@ -487,7 +485,7 @@ int hhg_solve(hhg_mesh* M, const hhg_solve_opts* o, void* u, const void* f, hhg_
     double* dnorm = M->dscalars;
     double* r64 = (double*)M->r64[L];
     auto norm_now = [&](double* out) -> int {
-        HIP_CHECK(launch_residual(M, L, o->op, HHG_F64, u, f, r64, dnorm, 0, s), "residual");
+        HIP_CHECK(launch_residual(M, L, o->op, HHG_F64, u, f, r64, dnorm, s), "residual");
         return read_scalar(dnorm, out, s);
     };
     double r0 = 0.0;

@@ -60,6 +60,13 @@ struct EdgeInfo {
     double cA[2], cL[2], cH[2];
     double area[2];       // macro-face areas
     int32_t vslot[2];     // ghost slot of this edge at vertex a and at vertex b
+    // In face s the edge point next to vertex a (end 0) or b (end 1) is the
+    // first/last entry of the ghost row of the other edge of that face
+    // through the vertex: edge id (-1 if it is a boundary edge), its ghost
+    // row, and 1 if that entry is position 0 (else n-2).
+    int32_t cg_edge[2][2];
+    int32_t cg_slot[2][2];
+    int32_t cg_first[2][2];
     int32_t pad_;
 };
 
@@ -76,6 +83,10 @@ struct VertexInfo {
     int32_t partner[MAXDEG][2];
     double cA[MAXDEG][2];
     double area[MAXDEG][2];
+    int32_t nfc;                  // incident faces and the vertex's corner in each
+    int32_t fc_face[MAXDEG];
+    int32_t fc_corner[MAXDEG];    // 0: (0,0), 1: (n-1,0), 2: (0,n-1)
+    int32_t pad_;
 };
 
 // Per-level view passed to kernels by value.
@@ -90,7 +101,7 @@ struct LevelDev {
     int64_t can_edge_base, can_face_base, n_all;
     double inv4l;                     // 1 / 4^level: micro/macro area ratio
     const int32_t* row_off;           // [n + 1] start of row j inside a face
-    const int2* tiles;                // 64 x 4 tiles that meet the interior
+    const int2* tiles;                // 64 x 4 tiles covering the whole face
     const int2* gs_tiles;             // smoother tiles covering the whole face
     const FaceInfo* faces;
     const EdgeInfo* edges;

@@ -17,19 +17,18 @@ hipError_t launch_sync(const hhg_mesh* M, int level, int dtype, void* x, int mas
 // y = A x (interior rows), 0 on Dirichlet rows, ghosts of y refreshed.
 hipError_t launch_apply(const hhg_mesh* M, int level, int op, int dtype, const void* x,
                         void* y, hipStream_t s);
-// r = f - A u on interior points, 0 on Dirichlet points; optional |r|_2 into
-// the device double *norm; `sync_mask` refreshes those ghost classes of r.
+// r = f - A u on interior points, 0 on Dirichlet points, with all copies of
+// r; optional |r|_2 over interior points into the device double *norm.
 hipError_t launch_residual(const hhg_mesh* M, int level, int op, int dtype, const void* u,
-                           const void* f, void* r, double* norm, int sync_mask,
-                           hipStream_t s);
+                           const void* f, void* r, double* norm, hipStream_t s);
 // One forward or backward staged Gauss-Seidel sweep from field x into field y
 // (x is used as scratch; y receives the complete result).
 hipError_t launch_gs_sweep(const hhg_mesh* M, int level, int op, int dtype, void* x, void* y,
                            const void* f, int backward, hipStream_t s);
-// fc (level-1) = P^T r (level), r with refreshed FACE and EODD ghosts.
+// fc (level-1) = P^T r (level) from r with its copies; uc (level-1) = 0.
 hipError_t launch_restrict(const hhg_mesh* M, int level, int dtype, const void* r, void* fc,
-                           hipStream_t s);
-// u (level) += P uc (level-1) on interior points; ghosts of u refreshed.
+                           void* uc, hipStream_t s);
+// u (level) += P uc (level-1) on interior points, copies included.
 hipError_t launch_prolong_add(const hhg_mesh* M, int level, int dtype, const void* uc,
                               void* u, hipStream_t s);
 hipError_t launch_fill(void* x, int64_t n, int dtype, double v, hipStream_t s);

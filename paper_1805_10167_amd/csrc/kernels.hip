@@ -221,111 +221,164 @@ __global__ __launch_bounds__(NT) void k_fill(T* __restrict__ x, int64_t n, T v) 
 
 #define FACE_TILE_END }
 
-template <class T>
-__global__ __launch_bounds__(NT) void k_face_apply(LevelDev L, int op, const T* __restrict__ x,
-                                                   T* __restrict__ y, const T* __restrict__ kap) {
-    FACE_TILE_LOOP(L)
-    (void)fi;
-    const W7<T> w = face_weights<T>(op, fi, L.inv4l, kap, p, up, dn);
-    y[p] = w.c * x[p] + w.e * x[p + 1] + w.w * x[p - 1] + w.n * x[p + up] + w.s * x[p - dn] +
-           w.se * x[p - dn + 1] + w.nw * x[p + up - 1];
-    FACE_TILE_END
+// ------------------------------------------------------------------ pushes
+// A kernel that writes an owned value also writes its ghost copies (the
+// process-local direct copy of the communication layer; the writer takes
+// care of the receiver's order).
+
+__device__ __forceinline__ void side_point0(int side, int t, int n, int& i, int& j) {
+    if (side == 0) { i = t; j = 0; }
+    else if (side == 1) { i = 0; j = t; }
+    else { i = n - 1 - t; j = t; }
 }
 
-// Edge and vertex rows of y = A x.  Thread space: E*(n-2) edge points, then V.
+// Copies of edge point k: face rings, the vertex ghost (k = 1 or n-2) and,
+// with `corners`, the first/last ghost-row entry of the neighbouring edges.
 template <class T>
-__global__ __launch_bounds__(NT) void k_low_apply(LevelDev L, int op, const T* __restrict__ x,
-                                                  T* __restrict__ y, const T* __restrict__ kap) {
+__device__ __forceinline__ void push_edge(const LevelDev& L, T* x, const EdgeInfo& ei, int k, T val,
+                                          bool corners) {
     const int n = L.n;
-    const int64_t ne = (int64_t)L.E * (n - 2);
-    for (int64_t t = blockIdx.x * (int64_t)NT + threadIdx.x; t < ne + L.V; t += (int64_t)gridDim.x * NT) {
-        if (t < ne) {
-            const int e = (int)(t / (n - 2)), k = (int)(t % (n - 2)) + 1;
-            const EdgeInfo& ei = L.edges[e];
-            const int64_t m = edge_main(L, e);
-            if (ei.boundary) { y[m + k] = (T)0; continue; }
-            const int64_t g0 = edge_ghost(L, e, 0), g1 = edge_ghost(L, e, 1);
-            const WE<T> w = edge_weights<T>(op, ei, L.inv4l, kap, m, g0, g1, k);
-            y[m + k] = w.c * x[m + k] + w.al * x[m + k - 1] + w.ah * x[m + k + 1] +
-                       w.l0 * x[g0 + k - 1] + w.h0 * x[g0 + k] + w.l1 * x[g1 + k - 1] + w.h1 * x[g1 + k];
-        } else {
-            const int v = (int)(t - ne);
-            const VertexInfo& vi = L.verts[v];
-            const int64_t vb = vert_off(L, v);
-            if (vi.boundary) { y[vb] = (T)0; continue; }
-            T s = (T)0, c = (T)0;
-            for (int q = 0; q < vi.deg; ++q) {
-                const T wq = vertex_weight<T>(op, vi, L.inv4l, kap, vb, q);
-                s += wq * x[vb + 1 + q];
-                c += wq;
-            }
-            c = (op == OP_MASS) ? c : -c;
-            y[vb] = c * x[vb] + s;
+    for (int s = 0; s < ei.nf; ++s) {
+        int i, j;
+        side_point0(ei.side[s], ei.rev[s] ? n - 1 - k : k, n, i, j);
+        x[face_base(L, ei.face[s]) + row_start(n, j) + i] = val;
+    }
+    if (k == 1) x[vert_off(L, ei.a) + 1 + ei.vslot[0]] = val;
+    if (k == n - 2) x[vert_off(L, ei.b) + 1 + ei.vslot[1]] = val;
+    if (!corners) return;
+    for (int end = 0; end < 2; ++end) {
+        if (k != (end == 0 ? 1 : n - 2)) continue;
+        for (int s = 0; s < ei.nf; ++s) {
+            const int e2 = ei.cg_edge[s][end];
+            if (e2 >= 0) x[edge_ghost(L, e2, ei.cg_slot[s][end]) + (ei.cg_first[s][end] ? 0 : n - 2)] = val;
         }
     }
 }
 
+// Copies of a vertex value: edge end slots and face ring corners.
 template <class T>
-__global__ __launch_bounds__(NT) void k_face_residual(LevelDev L, int op, const T* __restrict__ u,
-                                                      const T* __restrict__ f, T* __restrict__ r,
-                                                      const T* __restrict__ kap, double* partials) {
+__device__ __forceinline__ void push_vertex(const LevelDev& L, T* x, const VertexInfo& vi, T val) {
+    const int n = L.n;
+    for (int q = 0; q < vi.deg; ++q) x[edge_main(L, vi.edge[q]) + (vi.at_a[q] ? 0 : n - 1)] = val;
+    for (int c = 0; c < vi.nfc; ++c) {
+        const int cr = vi.fc_corner[c];
+        x[face_base(L, vi.fc_face[c]) + row_start(n, cr == 2 ? n - 1 : 0) + (cr == 1 ? n - 1 : 0)] = val;
+    }
+}
+
+// Copies of face point (i, j) in the ghost rows of the face's edges.
+template <class T>
+__device__ __forceinline__ void push_face_near(const LevelDev& L, T* x, const FaceInfo& fi, int i, int j,
+                                               T val) {
+    const int n = L.n;
+    if (j == 1 && i <= n - 2 && !fi.bside[0])
+        x[edge_ghost(L, fi.edge[0], fi.slot[0]) + (fi.rev[0] ? n - 2 - i : i)] = val;
+    if (i == 1 && j <= n - 2 && !fi.bside[1])
+        x[edge_ghost(L, fi.edge[1], fi.slot[1]) + (fi.rev[1] ? n - 2 - j : j)] = val;
+    if (i + j == n - 2 && !fi.bside[2])
+        x[edge_ghost(L, fi.edge[2], fi.slot[2]) + (fi.rev[2] ? n - 2 - j : j)] = val;
+}
+
+// Face-point loop over the 64 x 4 tiles of every face, grid-stride over the
+// first gf blocks; yields all points of the triangle.
+#define FACE_ALL_LOOP(L, GF)                                                                \
+    const int n = (L).n;                                                                    \
+    const int ti_ = threadIdx.x & (TILE_I - 1), tj_ = threadIdx.x / TILE_I;                 \
+    const int64_t nitems_ = (int64_t)(L).F * (L).ntiles;                                    \
+    for (int64_t it_ = blockIdx.x; it_ < nitems_; it_ += (GF)) {                           \
+        const int face = (int)(it_ / (L).ntiles);                                           \
+        const int2 tl_ = (L).tiles[it_ % (L).ntiles];                                       \
+        const int i = tl_.x * TILE_I + ti_, j = tl_.y * TILE_J + tj_;                       \
+        if (j >= n || i > n - 1 - j) continue;                                              \
+        const bool interior = i >= 1 && j >= 1 && i + j <= n - 2;                           \
+        const FaceInfo& fi = (L).faces[face];                                               \
+        const int64_t p = face_base((L), face) + row_start(n, j) + i;
+
+// Edge points (every edge, k = 1..n-2) then vertices, grid-stride over the
+// blocks [B0, gridDim.x).
+#define LOW_LOOP(L, B0)                                                                      \
+    const int nl_ = (L).n;                                                                   \
+    const int64_t ne_ = (int64_t)(L).E * (nl_ - 2);                                          \
+    const int64_t stride_ = (int64_t)(gridDim.x - (B0)) * NT;                                \
+    for (int64_t t = (int64_t)(blockIdx.x - (B0)) * NT + threadIdx.x; t < ne_ + (L).V; t += stride_)
+
+template <class T>
+__device__ __forceinline__ T edge_apply(int op, const LevelDev& L, const EdgeInfo& ei, const T* x,
+                                        const T* kap, int64_t m, int64_t g0, int64_t g1, int k) {
+    const WE<T> w = edge_weights<T>(op, ei, L.inv4l, kap, m, g0, g1, k);
+    return w.c * x[m + k] + w.al * x[m + k - 1] + w.ah * x[m + k + 1] + w.l0 * x[g0 + k - 1] +
+           w.h0 * x[g0 + k] + w.l1 * x[g1 + k - 1] + w.h1 * x[g1 + k];
+}
+
+template <class T>
+__device__ __forceinline__ T vertex_apply(int op, const LevelDev& L, const VertexInfo& vi, const T* x,
+                                          const T* kap, int64_t vb) {
+    T s = (T)0, c = (T)0;
+    for (int q = 0; q < vi.deg; ++q) {
+        const T wq = vertex_weight<T>(op, vi, L.inv4l, kap, vb, q);
+        s += wq * x[vb + 1 + q];
+        c += wq;
+    }
+    c = (op == OP_MASS) ? c : -c;
+    return c * x[vb] + s;
+}
+
+// y = A x on interior rows (0 on Dirichlet rows) with all copies of y.
+// With f and partials: r = f - A u instead, and per-block sums of r^2.
+template <class T, bool RES>
+__global__ __launch_bounds__(NT) void k_apply(LevelDev L, int op, const T* __restrict__ x,
+                                              const T* __restrict__ f, T* __restrict__ y,
+                                              const T* __restrict__ kap, int gf, double* partials) {
     __shared__ double sm[NT / 64 + 1];
     double acc = 0.0;
-    {
-        FACE_TILE_LOOP(L)
+    if ((int)blockIdx.x < gf) {
+        FACE_ALL_LOOP(L, gf)
+        if (!interior) continue;
+        const int64_t up = row_start(n, j + 1) - row_start(n, j);
+        const int64_t dn = row_start(n, j) - row_start(n, j - 1);
         const W7<T> w = face_weights<T>(op, fi, L.inv4l, kap, p, up, dn);
-        const T au = w.c * u[p] + w.e * u[p + 1] + w.w * u[p - 1] + w.n * u[p + up] + w.s * u[p - dn] +
-                     w.se * u[p - dn + 1] + w.nw * u[p + up - 1];
-        const T rv = f[p] - au;
-        r[p] = rv;
-        acc += (double)rv * (double)rv;
-        FACE_TILE_END
-    }
-    if (partials) {
-        const double s = block_sum<NT>(acc, sm);
-        if (threadIdx.x == 0) partials[blockIdx.x] = s;
-    }
-}
-
-template <class T>
-__global__ __launch_bounds__(NT) void k_low_residual(LevelDev L, int op, const T* __restrict__ u,
-                                                     const T* __restrict__ f, T* __restrict__ r,
-                                                     const T* __restrict__ kap, double* partials) {
-    __shared__ double sm[NT / 64 + 1];
-    const int n = L.n;
-    const int64_t ne = (int64_t)L.E * (n - 2);
-    double acc = 0.0;
-    for (int64_t t = blockIdx.x * (int64_t)NT + threadIdx.x; t < ne + L.V; t += (int64_t)gridDim.x * NT) {
-        if (t < ne) {
-            const int e = (int)(t / (n - 2)), k = (int)(t % (n - 2)) + 1;
-            const EdgeInfo& ei = L.edges[e];
-            const int64_t m = edge_main(L, e);
-            if (ei.boundary) { r[m + k] = (T)0; continue; }
-            const int64_t g0 = edge_ghost(L, e, 0), g1 = edge_ghost(L, e, 1);
-            const WE<T> w = edge_weights<T>(op, ei, L.inv4l, kap, m, g0, g1, k);
-            const T au = w.c * u[m + k] + w.al * u[m + k - 1] + w.ah * u[m + k + 1] +
-                         w.l0 * u[g0 + k - 1] + w.h0 * u[g0 + k] + w.l1 * u[g1 + k - 1] + w.h1 * u[g1 + k];
-            const T rv = f[m + k] - au;
-            r[m + k] = rv;
-            acc += (double)rv * (double)rv;
-        } else {
-            const int v = (int)(t - ne);
-            const VertexInfo& vi = L.verts[v];
-            const int64_t vb = vert_off(L, v);
-            if (vi.boundary) { r[vb] = (T)0; continue; }
-            T s = (T)0, c = (T)0;
-            for (int q = 0; q < vi.deg; ++q) {
-                const T wq = vertex_weight<T>(op, vi, L.inv4l, kap, vb, q);
-                s += wq * u[vb + 1 + q];
-                c += wq;
+        T v = w.c * x[p] + w.e * x[p + 1] + w.w * x[p - 1] + w.n * x[p + up] + w.s * x[p - dn] +
+              w.se * x[p - dn + 1] + w.nw * x[p + up - 1];
+        if (RES) {
+            v = f[p] - v;
+            acc += (double)v * (double)v;
+        }
+        y[p] = v;
+        push_face_near(L, y, fi, i, j, v);
+        }
+    } else {
+        LOW_LOOP(L, gf) {
+            T v = (T)0;
+            if (t < ne_) {
+                const int e = (int)(t / (nl_ - 2)), k = (int)(t % (nl_ - 2)) + 1;
+                const EdgeInfo& ei = L.edges[e];
+                const int64_t m = edge_main(L, e);
+                if (!ei.boundary) {
+                    v = edge_apply<T>(op, L, ei, x, kap, m, edge_ghost(L, e, 0), edge_ghost(L, e, 1), k);
+                    if (RES) {
+                        v = f[m + k] - v;
+                        acc += (double)v * (double)v;
+                    }
+                }
+                y[m + k] = v;
+                push_edge(L, y, ei, k, v, true);
+            } else {
+                const int vv = (int)(t - ne_);
+                const VertexInfo& vi = L.verts[vv];
+                const int64_t vb = vert_off(L, vv);
+                if (!vi.boundary) {
+                    v = vertex_apply<T>(op, L, vi, x, kap, vb);
+                    if (RES) {
+                        v = f[vb] - v;
+                        acc += (double)v * (double)v;
+                    }
+                }
+                y[vb] = v;
+                push_vertex(L, y, vi, v);
             }
-            c = (op == OP_MASS) ? c : -c;
-            const T rv = f[vb] - (c * u[vb] + s);
-            r[vb] = rv;
-            acc += (double)rv * (double)rv;
         }
     }
-    if (partials) {
+    if (RES && partials) {
         const double s = block_sum<NT>(acc, sm);
         if (threadIdx.x == 0) partials[blockIdx.x] = s;
     }
@@ -601,8 +654,11 @@ __global__ __launch_bounds__(GS_NT) void k_face_gs_fused(LevelDev L, const T* __
 }
 
 // Stage A (stage = 0): interior vertices and even-k points of interior
-// edges; stage B (stage = 1): odd-k points.  Points of a stage are updated
-// at once from the values before the stage.
+// edges; stage B (stage = 1): odd-k points.  The points of a stage are
+// updated at once from the values before the stage; every update writes
+// its copies.  Odd points next to a vertex of two edges of one face read
+// each other in stage B, so stage B leaves those ghost-row copies alone and
+// stage A (which reads none of them) refreshes them.
 template <class T>
 __global__ __launch_bounds__(NT) void k_low_gs(LevelDev L, int op, T* __restrict__ u,
                                                const T* __restrict__ f, const T* __restrict__ kap,
@@ -613,17 +669,33 @@ __global__ __launch_bounds__(NT) void k_low_gs(LevelDev L, int op, T* __restrict
     for (int64_t t = blockIdx.x * (int64_t)NT + threadIdx.x; t < ne + nv; t += (int64_t)gridDim.x * NT) {
         if (t < ne) {
             const int e = L.iedges[t / (n - 2)], k = (int)(t % (n - 2)) + 1;
-            if ((k & 1) != stage) continue;
             const EdgeInfo& ei = L.edges[e];
-            const int64_t m = edge_main(L, e), g0 = edge_ghost(L, e, 0), g1 = edge_ghost(L, e, 1);
+            const int64_t m = edge_main(L, e);
+            if ((k & 1) != stage) {
+                if (stage == 0 && (k == 1 || k == n - 2)) {
+                    const T v = u[m + k];
+                    for (int end = 0; end < 2; ++end) {
+                        if (k != (end == 0 ? 1 : n - 2)) continue;
+                        for (int s = 0; s < ei.nf; ++s) {
+                            const int e2 = ei.cg_edge[s][end];
+                            if (e2 >= 0)
+                                u[edge_ghost(L, e2, ei.cg_slot[s][end]) + (ei.cg_first[s][end] ? 0 : n - 2)] = v;
+                        }
+                    }
+                }
+                continue;
+            }
+            const int64_t g0 = edge_ghost(L, e, 0), g1 = edge_ghost(L, e, 1);
             const WE<T> w = edge_weights<T>(op, ei, L.inv4l, kap, m, g0, g1, k);
             const T off = w.al * u[m + k - 1] + w.ah * u[m + k + 1] + w.l0 * u[g0 + k - 1] +
                           w.h0 * u[g0 + k] + w.l1 * u[g1 + k - 1] + w.h1 * u[g1 + k];
-            u[m + k] = (f[m + k] - off) / w.c;
+            const T v = (f[m + k] - off) / w.c;
+            u[m + k] = v;
+            push_edge(L, u, ei, k, v, false);
         } else {
-            const int v = L.iverts[t - ne];
-            const VertexInfo& vi = L.verts[v];
-            const int64_t vb = vert_off(L, v);
+            const int vv = L.iverts[t - ne];
+            const VertexInfo& vi = L.verts[vv];
+            const int64_t vb = vert_off(L, vv);
             T s = (T)0, c = (T)0;
             for (int q = 0; q < vi.deg; ++q) {
                 const T wq = vertex_weight<T>(op, vi, L.inv4l, kap, vb, q);
@@ -631,93 +703,122 @@ __global__ __launch_bounds__(NT) void k_low_gs(LevelDev L, int op, T* __restrict
                 c += wq;
             }
             c = (op == OP_MASS) ? c : -c;
-            u[vb] = (f[vb] - s) / c;
+            const T v = (f[vb] - s) / c;
+            u[vb] = v;
+            push_vertex(L, u, vi, v);
         }
     }
 }
 
-// Restriction of face-interior coarse points: fc(I,J) = r(2I,2J) + 1/2 sum of
-// the six fine neighbours (transpose of linear interpolation).
+// Restriction, the transpose of linear interpolation: a coarse point gets
+// the fine residual at its own position plus half of it at each fine
+// neighbour; zero at coarse Dirichlet points.  r carries its ghost copies.
+// Blocks [0, gf): coarse face points; [gf, gl): coarse edge and vertex
+// points; [gl, gridDim.x): zero the coarse correction uc.
 template <class T>
-__global__ __launch_bounds__(NT) void k_face_restrict(LevelDev Lf, LevelDev Lc, const T* __restrict__ r,
-                                                      T* __restrict__ fc) {
-    FACE_TILE_LOOP(Lc)
-    (void)fi; (void)up; (void)dn;
-    const int jf = 2 * j;
-    const int nf_ = Lf.n;
-    const int64_t q = face_base(Lf, face) + row_start(nf_, jf) + 2 * i;
-    const int64_t upf = row_start(nf_, jf + 1) - row_start(nf_, jf);
-    const int64_t dnf = row_start(nf_, jf) - row_start(nf_, jf - 1);
-    const T nb = r[q + 1] + r[q - 1] + r[q + upf] + r[q - dnf] + r[q - dnf + 1] + r[q + upf - 1];
-    fc[p] = r[q] + (T)0.5 * nb;
-    FACE_TILE_END
-}
-
-template <class T>
-__global__ __launch_bounds__(NT) void k_low_restrict(LevelDev Lf, LevelDev Lc, const T* __restrict__ r,
-                                                     T* __restrict__ fc) {
-    const int nc = Lc.n;
-    const int64_t ne = (int64_t)Lc.E * (nc - 2);
-    for (int64_t t = blockIdx.x * (int64_t)NT + threadIdx.x; t < ne + Lc.V; t += (int64_t)gridDim.x * NT) {
-        if (t < ne) {
-            const int e = (int)(t / (nc - 2)), K = (int)(t % (nc - 2)) + 1;
-            const int64_t mc = edge_main(Lc, e);
-            if (Lc.edges[e].boundary) { fc[mc + K] = (T)0; continue; }
-            const int64_t m = edge_main(Lf, e), g0 = edge_ghost(Lf, e, 0), g1 = edge_ghost(Lf, e, 1);
-            const int k = 2 * K;
-            const T nb = r[m + k - 1] + r[m + k + 1] + r[g0 + k - 1] + r[g0 + k] + r[g1 + k - 1] + r[g1 + k];
-            fc[mc + K] = r[m + k] + (T)0.5 * nb;
-        } else {
-            const int v = (int)(t - ne);
-            const VertexInfo& vi = Lc.verts[v];
-            const int64_t vc = vert_off(Lc, v);
-            if (vi.boundary) { fc[vc] = (T)0; continue; }
-            const int64_t vf = vert_off(Lf, v);
-            T nb = (T)0;
-            for (int q = 0; q < vi.deg; ++q) nb += r[vf + 1 + q];
-            fc[vc] = r[vf] + (T)0.5 * nb;
+__global__ __launch_bounds__(NT) void k_restrict(LevelDev Lf, LevelDev Lc, const T* __restrict__ r,
+                                                 T* __restrict__ fc, T* __restrict__ uc, int64_t uc_n,
+                                                 int gf, int gl) {
+    if ((int)blockIdx.x < gf) {
+        FACE_ALL_LOOP(Lc, gf)
+        (void)fi;
+        if (!interior) continue;
+        const int nf_ = Lf.n, jf = 2 * j;
+        const int64_t q = face_base(Lf, face) + row_start(nf_, jf) + 2 * i;
+        const int64_t upf = row_start(nf_, jf + 1) - row_start(nf_, jf);
+        const int64_t dnf = row_start(nf_, jf) - row_start(nf_, jf - 1);
+        const T nb = r[q + 1] + r[q - 1] + r[q + upf] + r[q - dnf] + r[q - dnf + 1] + r[q + upf - 1];
+        fc[p] = r[q] + (T)0.5 * nb;
         }
-    }
-}
-
-// u += P uc at fine face-interior points.  A fine point coincides with a
-// coarse point or is the midpoint of a coarse micro-edge.
-template <class T>
-__global__ __launch_bounds__(NT) void k_face_prolong(LevelDev Lf, LevelDev Lc, const T* __restrict__ uc,
-                                                     T* __restrict__ u) {
-    FACE_TILE_LOOP(Lf)
-    (void)fi; (void)up; (void)dn;
-    const int64_t cb = face_base(Lc, face);
-    const int nc_ = Lc.n;
-    const int I = i >> 1, J = j >> 1;
-    T c;
-    if (!(i & 1) && !(j & 1)) {
-        c = uc[cb + row_start(nc_, J) + I];
-    } else if ((i & 1) && !(j & 1)) {
-        c = (T)0.5 * (uc[cb + row_start(nc_, J) + I] + uc[cb + row_start(nc_, J) + I + 1]);
-    } else if (!(i & 1) && (j & 1)) {
-        c = (T)0.5 * (uc[cb + row_start(nc_, J) + I] + uc[cb + row_start(nc_, J + 1) + I]);
+    } else if ((int)blockIdx.x < gl) {
+        const int nc = Lc.n;
+        const int64_t ne = (int64_t)Lc.E * (nc - 2);
+        for (int64_t t = (int64_t)(blockIdx.x - gf) * NT + threadIdx.x; t < ne + Lc.V;
+             t += (int64_t)(gl - gf) * NT) {
+            if (t < ne) {
+                const int e = (int)(t / (nc - 2)), K = (int)(t % (nc - 2)) + 1;
+                const int64_t mc = edge_main(Lc, e);
+                if (Lc.edges[e].boundary) { fc[mc + K] = (T)0; continue; }
+                const int64_t m = edge_main(Lf, e), g0 = edge_ghost(Lf, e, 0), g1 = edge_ghost(Lf, e, 1);
+                const int k = 2 * K;
+                const T nb = r[m + k - 1] + r[m + k + 1] + r[g0 + k - 1] + r[g0 + k] + r[g1 + k - 1] +
+                             r[g1 + k];
+                fc[mc + K] = r[m + k] + (T)0.5 * nb;
+            } else {
+                const int v = (int)(t - ne);
+                const VertexInfo& vi = Lc.verts[v];
+                const int64_t vc = vert_off(Lc, v);
+                if (vi.boundary) { fc[vc] = (T)0; continue; }
+                const int64_t vf = vert_off(Lf, v);
+                T nb = (T)0;
+                for (int q = 0; q < vi.deg; ++q) nb += r[vf + 1 + q];
+                fc[vc] = r[vf] + (T)0.5 * nb;
+            }
+        }
     } else {
-        c = (T)0.5 * (uc[cb + row_start(nc_, J) + I + 1] + uc[cb + row_start(nc_, J + 1) + I]);
+        for (int64_t t = (int64_t)(blockIdx.x - gl) * NT + threadIdx.x; t < uc_n;
+             t += (int64_t)(gridDim.x - gl) * NT)
+            uc[t] = (T)0;
     }
-    u[p] += c;
-    FACE_TILE_END
 }
 
+// u += P uc.  A fine point coincides with a coarse point or is the midpoint
+// of a coarse micro-edge.  Every holder of a copy updates it from its own
+// coarse copies (same operands, so the copies stay identical): faces their
+// whole triangle except Dirichlet points, pushing near-edge rows; edges
+// their points and end slots; vertices their value and ghost copies.
 template <class T>
-__global__ __launch_bounds__(NT) void k_low_prolong(LevelDev Lf, LevelDev Lc, const T* __restrict__ uc,
-                                                    T* __restrict__ u) {
-    const int n = Lf.n;
-    const int64_t ne = (int64_t)Lf.n_iedges * (n - 2);
-    for (int64_t t = blockIdx.x * (int64_t)NT + threadIdx.x; t < ne + Lf.n_iverts; t += (int64_t)gridDim.x * NT) {
-        if (t < ne) {
-            const int e = Lf.iedges[t / (n - 2)], k = (int)(t % (n - 2)) + 1;
-            const int64_t m = edge_main(Lf, e), mc = edge_main(Lc, e);
-            const T c = (k & 1) ? (T)0.5 * (uc[mc + (k >> 1)] + uc[mc + (k >> 1) + 1]) : uc[mc + (k >> 1)];
-            u[m + k] += c;
-        } else {
-            const int v = Lf.iverts[t - ne];
-            u[vert_off(Lf, v)] += uc[vert_off(Lc, v)];
+__global__ __launch_bounds__(NT) void k_prolong(LevelDev Lf, LevelDev Lc, const T* __restrict__ uc,
+                                                T* __restrict__ u, int gf) {
+    if ((int)blockIdx.x < gf) {
+        FACE_ALL_LOOP(Lf, gf)
+        bool dir;
+        if (interior) dir = false;
+        else if (j == 0 && i == 0) dir = fi.bvtx[0];
+        else if (j == 0 && i == n - 1) dir = fi.bvtx[1];
+        else if (i == 0 && j == n - 1) dir = fi.bvtx[2];
+        else if (j == 0) dir = fi.bside[0];
+        else if (i == 0) dir = fi.bside[1];
+        else dir = fi.bside[2];
+        T v = u[p];
+        if (!dir) {
+            const int nc_ = Lc.n;
+            const int64_t cb = face_base(Lc, face);
+            const int I = i >> 1, J = j >> 1;
+            T c;
+            if (!(i & 1) && !(j & 1)) c = uc[cb + row_start(nc_, J) + I];
+            else if ((i & 1) && !(j & 1))
+                c = (T)0.5 * (uc[cb + row_start(nc_, J) + I] + uc[cb + row_start(nc_, J) + I + 1]);
+            else if (!(i & 1) && (j & 1))
+                c = (T)0.5 * (uc[cb + row_start(nc_, J) + I] + uc[cb + row_start(nc_, J + 1) + I]);
+            else
+                c = (T)0.5 * (uc[cb + row_start(nc_, J) + I + 1] + uc[cb + row_start(nc_, J + 1) + I]);
+            v += c;
+            u[p] = v;
+        }
+        push_face_near(Lf, u, fi, i, j, v);
+        }
+    } else {
+        const int n = Lf.n;
+        const int64_t ne = (int64_t)Lf.n_iedges * (n - 2);
+        for (int64_t t = (int64_t)(blockIdx.x - gf) * NT + threadIdx.x; t < ne + Lf.n_iverts;
+             t += (int64_t)(gridDim.x - gf) * NT) {
+            if (t < ne) {
+                const int e = Lf.iedges[t / (n - 2)], k = (int)(t % (n - 2)) + 1;
+                const EdgeInfo& ei = Lf.edges[e];
+                const int64_t m = edge_main(Lf, e), mc = edge_main(Lc, e);
+                const T c = (k & 1) ? (T)0.5 * (uc[mc + (k >> 1)] + uc[mc + (k >> 1) + 1]) : uc[mc + (k >> 1)];
+                u[m + k] += c;
+                if (k == 1 && !Lf.verts[ei.a].boundary) u[m] += uc[mc];
+                if (k == n - 2 && !Lf.verts[ei.b].boundary) u[m + n - 1] += uc[mc + Lc.n - 1];
+            } else {
+                const int v = Lf.iverts[t - ne];
+                const VertexInfo& vi = Lf.verts[v];
+                const int64_t vf = vert_off(Lf, v), vc = vert_off(Lc, v);
+                const T cv = uc[vc];
+                u[vf] += cv;
+                for (int q = 0; q < vi.deg; ++q) u[vf + 1 + q] += (T)0.5 * (cv + uc[vc + 1 + q]);
+            }
         }
     }
 }
@@ -1046,10 +1147,9 @@ hipError_t launch_sync(const hhg_mesh* M, int level, int dtype, void* x, int mas
 template <class T>
 static hipError_t apply_t(const hhg_mesh* M, int level, int op, const T* x, T* y, hipStream_t s) {
     const LevelDev L = M->dev(level);
-    const T* kap = kap_of<T>(M, level);
-    k_face_apply<T><<<face_grid(L), NT, 0, s>>>(L, op, x, y, kap);
-    k_low_apply<T><<<grid_for(low_items(L), MAX_LOW_BLOCKS), NT, 0, s>>>(L, op, x, y, kap);
-    return launch_sync(M, level, sizeof(T) == 8 ? DT_F64 : DT_F32, y, GM_ALL, s);
+    const int gf = face_grid(L), gl = grid_for(low_items(L), MAX_LOW_BLOCKS);
+    k_apply<T, false><<<gf + gl, NT, 0, s>>>(L, op, x, nullptr, y, kap_of<T>(M, level), gf, nullptr);
+    return hipGetLastError();
 }
 
 hipError_t launch_apply(const hhg_mesh* M, int level, int op, int dtype, const void* x, void* y,
@@ -1060,25 +1160,20 @@ hipError_t launch_apply(const hhg_mesh* M, int level, int op, int dtype, const v
 
 template <class T>
 static hipError_t residual_t(const hhg_mesh* M, int level, int op, const T* u, const T* f, T* r,
-                             double* norm, int sync_mask, hipStream_t s) {
+                             double* norm, hipStream_t s) {
     const LevelDev L = M->dev(level);
-    const T* kap = kap_of<T>(M, level);
     const int gf = face_grid(L), gl = grid_for(low_items(L), MAX_LOW_BLOCKS);
-    double* part = norm ? M->partials : nullptr;
-    k_face_residual<T><<<gf, NT, 0, s>>>(L, op, u, f, r, kap, part);
-    k_low_residual<T><<<gl, NT, 0, s>>>(L, op, u, f, r, kap, part ? part + gf : nullptr);
+    k_apply<T, true><<<gf + gl, NT, 0, s>>>(L, op, u, f, r, kap_of<T>(M, level), gf,
+                                            norm ? M->partials : nullptr);
     if (norm) k_reduce_final<<<1, 1024, 0, s>>>(M->partials, gf + gl, norm, 1);
-    if (sync_mask) return launch_sync(M, level, sizeof(T) == 8 ? DT_F64 : DT_F32, r, sync_mask, s);
     return hipGetLastError();
 }
 
 hipError_t launch_residual(const hhg_mesh* M, int level, int op, int dtype, const void* u,
-                           const void* f, void* r, double* norm, int sync_mask, hipStream_t s) {
+                           const void* f, void* r, double* norm, hipStream_t s) {
     if (dtype == DT_F64)
-        return residual_t<double>(M, level, op, (const double*)u, (const double*)f, (double*)r, norm,
-                                  sync_mask, s);
-    return residual_t<float>(M, level, op, (const float*)u, (const float*)f, (float*)r, norm,
-                             sync_mask, s);
+        return residual_t<double>(M, level, op, (const double*)u, (const double*)f, (double*)r, norm, s);
+    return residual_t<float>(M, level, op, (const float*)u, (const float*)f, (float*)r, norm, s);
 }
 
 struct TimingScope {
@@ -1112,7 +1207,6 @@ static hipError_t gs_t(const hhg_mesh* M, int level, int op, T* x, T* y, const T
                        hipStream_t s) {
     const LevelDev L = M->dev(level);
     const T* kap = kap_of<T>(M, level);
-    const int dt = sizeof(T) == 8 ? DT_F64 : DT_F32;
     const int gl = grid_for((int64_t)L.n_iedges * (L.n - 2) + L.n_iverts, MAX_LOW_BLOCKS);
     const bool timed = M->timing && level == M->m.L;
     const int ntile_blocks = L.F * L.n_gs_tiles;
@@ -1135,16 +1229,13 @@ static hipError_t gs_t(const hhg_mesh* M, int level, int op, T* x, T* y, const T
     hipError_t e;
     if (!backward) {
         k_low_gs<T><<<gl, NT, 0, s>>>(L, op, x, f, kap, 0);
-        if ((e = launch_sync(M, level, dt, x, GM_VERT | GM_EEVEN, s)) != hipSuccess) return e;
         k_low_gs<T><<<gl, NT, 0, s>>>(L, op, x, f, kap, 1);
-        if ((e = launch_sync(M, level, dt, x, GM_EODD, s)) != hipSuccess) return e;
         return faces();
     }
     if ((e = faces()) != hipSuccess) return e;
     k_low_gs<T><<<gl, NT, 0, s>>>(L, op, y, f, kap, 1);
-    if ((e = launch_sync(M, level, dt, y, GM_EODD, s)) != hipSuccess) return e;
     k_low_gs<T><<<gl, NT, 0, s>>>(L, op, y, f, kap, 0);
-    return launch_sync(M, level, dt, y, GM_VERT | GM_EEVEN, s);
+    return hipGetLastError();
 }
 
 hipError_t launch_gs_sweep(const hhg_mesh* M, int level, int op, int dtype, void* x, void* y,
@@ -1155,26 +1246,27 @@ hipError_t launch_gs_sweep(const hhg_mesh* M, int level, int op, int dtype, void
 }
 
 template <class T>
-static hipError_t restrict_t(const hhg_mesh* M, int level, const T* r, T* fc, hipStream_t s) {
+static hipError_t restrict_t(const hhg_mesh* M, int level, const T* r, T* fc, T* uc, hipStream_t s) {
     const LevelDev Lf = M->dev(level), Lc = M->dev(level - 1);
-    k_face_restrict<T><<<face_grid(Lc), NT, 0, s>>>(Lf, Lc, r, fc);
-    k_low_restrict<T><<<grid_for(low_items(Lc), MAX_LOW_BLOCKS), NT, 0, s>>>(Lf, Lc, r, fc);
+    const int gf = face_grid(Lc), gl = gf + grid_for(low_items(Lc), MAX_LOW_BLOCKS);
+    const int gz = grid_for(Lc.total, 2048);
+    k_restrict<T><<<gl + gz, NT, 0, s>>>(Lf, Lc, r, fc, uc, Lc.total, gf, gl);
     return hipGetLastError();
 }
 
-hipError_t launch_restrict(const hhg_mesh* M, int level, int dtype, const void* r, void* fc,
+hipError_t launch_restrict(const hhg_mesh* M, int level, int dtype, const void* r, void* fc, void* uc,
                            hipStream_t s) {
-    if (dtype == DT_F64) return restrict_t<double>(M, level, (const double*)r, (double*)fc, s);
-    return restrict_t<float>(M, level, (const float*)r, (float*)fc, s);
+    if (dtype == DT_F64) return restrict_t<double>(M, level, (const double*)r, (double*)fc, (double*)uc, s);
+    return restrict_t<float>(M, level, (const float*)r, (float*)fc, (float*)uc, s);
 }
 
 template <class T>
 static hipError_t prolong_t(const hhg_mesh* M, int level, const T* uc, T* u, hipStream_t s) {
     const LevelDev Lf = M->dev(level), Lc = M->dev(level - 1);
-    k_face_prolong<T><<<face_grid(Lf), NT, 0, s>>>(Lf, Lc, uc, u);
-    k_low_prolong<T><<<grid_for((int64_t)Lf.n_iedges * (Lf.n - 2) + Lf.n_iverts, MAX_LOW_BLOCKS), NT, 0, s>>>(
-        Lf, Lc, uc, u);
-    return launch_sync(M, level, sizeof(T) == 8 ? DT_F64 : DT_F32, u, GM_ALL, s);
+    const int gf = face_grid(Lf);
+    const int gl = grid_for((int64_t)Lf.n_iedges * (Lf.n - 2) + Lf.n_iverts, MAX_LOW_BLOCKS);
+    k_prolong<T><<<gf + gl, NT, 0, s>>>(Lf, Lc, uc, u, gf);
+    return hipGetLastError();
 }
 
 hipError_t launch_prolong_add(const hhg_mesh* M, int level, int dtype, const void* uc, void* u,
@@ -1201,7 +1293,7 @@ static hipError_t coarse_t(const hhg_mesh* M, int op, T* u, const T* f, const do
                            hipStream_t s) {
     const int lc = M->m.lc;
     T* r = (T*)(sizeof(T) == 8 ? M->r64[lc] : M->r32[lc]);
-    hipError_t e = residual_t<T>(M, lc, op, u, f, r, nullptr, 0, s);
+    hipError_t e = residual_t<T>(M, lc, op, u, f, r, nullptr, s);
     if (e != hipSuccess) return e;
     const int N = M->coarse.N;
     if (N <= CG_MAXN && M->coarse.W <= CG_W) {

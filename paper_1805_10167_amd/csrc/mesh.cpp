@@ -227,6 +227,38 @@ std::string MeshData::build(const double* in_vxy, int nv, const int32_t* in_tri,
             }
         }
     }
+    // ghost-row corner entries held by the other edge of each face
+    for (int e = 0; e < E; ++e) {
+        EdgeInfo& ei = edges[e];
+        for (int s = 0; s < 2; ++s)
+            for (int end = 0; end < 2; ++end) {
+                ei.cg_edge[s][end] = -1;
+                ei.cg_slot[s][end] = 0;
+                ei.cg_first[s][end] = 0;
+                if (s >= ei.nf) continue;
+                const int f = ei.face[s];
+                const int v = end == 0 ? ei.a : ei.b;
+                for (int s2 = 0; s2 < 3; ++s2) {
+                    if (s2 == ei.side[s]) continue;
+                    if (tri[f][side_start(s2)] != v && tri[f][side_end(s2)] != v) continue;
+                    const int e2 = faces[f].edge[s2];
+                    if (edges[e2].boundary) continue;
+                    ei.cg_edge[s][end] = e2;
+                    ei.cg_slot[s][end] = faces[f].slot[s2];
+                    ei.cg_first[s][end] = (edges[e2].a == v);
+                }
+            }
+    }
+    // faces around each vertex and the vertex's corner in them
+    for (int v = 0; v < V; ++v) verts[v].nfc = 0;
+    for (int f = 0; f < F; ++f)
+        for (int c = 0; c < 3; ++c) {
+            VertexInfo& vi = verts[tri[f][c]];
+            if (vi.nfc >= MAXDEG) return "a macro-vertex has more than 16 macro-faces";
+            vi.fc_face[vi.nfc] = f;
+            vi.fc_corner[vi.nfc] = c;
+            vi.nfc++;
+        }
     iedges.clear();
     iverts.clear();
     for (int e = 0; e < E; ++e)
@@ -262,13 +294,11 @@ void MeshData::build_level(int level) {
     H.can_edge_base = V;
     H.can_face_base = V + (int64_t)E * (n - 2);
 
-    // tiles of TILE_I x TILE_J face-local points that contain interior points
+    // tiles of TILE_I x TILE_J face-local points covering the whole face
     H.tiles.clear();
-    for (int tj = 0; tj * TILE_J <= n - 3; ++tj)
-        for (int ti = 0; ti * TILE_I <= n - 3; ++ti) {
-            int imin = std::max(ti * TILE_I, 1), jmin = std::max(tj * TILE_J, 1);
-            if (imin + jmin <= n - 2) H.tiles.push_back(make_int2(ti, tj));
-        }
+    for (int tj = 0; tj * TILE_J <= n - 1; ++tj)
+        for (int ti = 0; ti * TILE_I <= n - 1; ++ti)
+            if (ti * TILE_I + tj * TILE_J <= n - 1) H.tiles.push_back(make_int2(ti, tj));
 
     // smoother tiles over the whole face triangle (ring included), column by
     // column so that consecutive tiles are vertical neighbours
