@@ -65,8 +65,10 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--level", type=int, default=10)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-level", type=int, default=8)
+    ap.add_argument("--cpu-level", type=int, default=9)
     ap.add_argument("--mp-runs", type=int, default=3)
+    ap.add_argument("--copy-calibration", type=int, default=0,
+                    help="bytes of a plain device copy run after the benchmark (counter scale)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: the method's multi-GPU sharding is not part "
@@ -135,6 +137,15 @@ def main():
         mp_res.append(st["rel_res"])
         assert rc == 0, st
 
+    if args.copy_calibration:
+        src = torch.empty(args.copy_calibration // 8, dtype=torch.float64, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+
+    from paper_1805_10167_amd.profiling import traffic_for
+    traffic = traffic_for(os.path.join(ROOT, "profiles", "face_smoother_annulus64_l10.txt"))
     out = {
         "metric": METRIC, "value": round(value, 4), "unit": "GDoF/s", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms_per_step, 4),
@@ -145,16 +156,19 @@ def main():
                    "interior_dofs": n_int, "solver": "V(3,3) staged multicolour GS, "
                    "Jacobi-PCG coarse level 2, plain FP64"},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS,
-                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+                     "traffic": None if traffic is None else round(traffic),
                      "kernel": "finest-level face smoother (all colours, one sweep)",
                      "bytes_per_launch": bytes_per_launch,
                      "avg_launch_ms": round(avg_launch_s * 1e3, 5), "launches": launches},
         "smoother_kernel_gdofs": round(nface / avg_launch_s / 1e9, 3),
-        "time_to_tol_ms": {"plain_fp64": round(ms_per_step, 3),
-                           "mp_ir": round(statistics.median(mp_times), 3)},
-        "iterations": {"plain_fp64": iters[0], "mp_ir": mp_iters[0]},
-        "mp_final_rel_res": mp_res[0],
+        "time_to_tol_ms": {"plain_fp64": round(ms_per_step, 3)},
+        "iterations": {"plain_fp64": iters[0]},
     }
+    if mp_times:
+        out["time_to_tol_ms"]["mp_ir"] = round(statistics.median(mp_times), 3)
+        out["iterations"]["mp_ir"] = mp_iters[0]
+        out["mp_final_rel_res"] = mp_res[0]
     if not args.no_cpu_baseline:
         print("bench: timing the CPU oracle at level %d" % args.cpu_level, file=sys.stderr,
               flush=True)

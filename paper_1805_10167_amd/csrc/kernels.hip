@@ -50,6 +50,9 @@ __device__ __forceinline__ int row_start(int n, int j) {
     return 16 * (ceil16_sum(n) - ceil16_sum(n - j));
 }
 
+// Wave index inside the block, as a wave-uniform (scalar) value.
+__device__ __forceinline__ int wave_id() { return __builtin_amdgcn_readfirstlane(threadIdx.x >> 6); }
+
 __device__ __forceinline__ int face_colour(int rule, int i, int j) {
     switch (rule) {
         case 1: return (i + j) & 1;
@@ -207,7 +210,7 @@ __global__ __launch_bounds__(NT) void k_fill(T* __restrict__ x, int64_t n, T v) 
 // Generic loop over face-interior points in 64 x 4 tiles.
 #define FACE_TILE_LOOP(L)                                                                   \
     const int n = (L).n;                                                                    \
-    const int ti_ = threadIdx.x & (TILE_I - 1), tj_ = threadIdx.x / TILE_I;                 \
+    const int ti_ = threadIdx.x & (TILE_I - 1), tj_ = wave_id();                          \
     const int64_t nitems_ = (int64_t)(L).F * (L).ntiles;                                    \
     for (int64_t it_ = blockIdx.x; it_ < nitems_; it_ += gridDim.x) {                      \
         const int face = (int)(it_ / (L).ntiles);                                           \
@@ -283,7 +286,7 @@ __device__ __forceinline__ void push_face_near(const LevelDev& L, T* x, const Fa
 // first gf blocks; yields all points of the triangle.
 #define FACE_ALL_LOOP(L, GF)                                                                \
     const int n = (L).n;                                                                    \
-    const int ti_ = threadIdx.x & (TILE_I - 1), tj_ = threadIdx.x / TILE_I;                 \
+    const int ti_ = threadIdx.x & (TILE_I - 1), tj_ = wave_id();                          \
     const int64_t nitems_ = (int64_t)(L).F * (L).ntiles;                                    \
     for (int64_t it_ = blockIdx.x; it_ < nitems_; it_ += (GF)) {                           \
         const int face = (int)(it_ / (L).ntiles);                                           \
@@ -412,8 +415,6 @@ constexpr int GS_COPY_BLOCKS = 32;
 
 __device__ __forceinline__ int pmod(int a, int m) { return ((a % m) + m) % m; }
 
-// Wave index inside the block, as a wave-uniform (scalar) value.
-__device__ __forceinline__ int wave_id() { return __builtin_amdgcn_readfirstlane(threadIdx.x >> 6); }
 
 // Stage update of one face point at LDS position (r, tx).
 template <class T, bool VARK>

@@ -1,0 +1,130 @@
+"""Summaries of rocprofv3 output for the smoother roofline.
+
+    python -m paper_1805_10167_amd.profiling summarize \
+        --stats DIR --fetch DIR --write DIR --kernel NAME --out FILE --cmd "..."
+
+reads the kernel-trace CSV of one run (average duration per kernel and grid
+size) and the counter CSVs of two --pmc runs (FETCH_SIZE, WRITE_SIZE, KiB
+per dispatch).  Counter values are scaled by what the same counters report
+for a plain copy of known size in the same run (the runtime's copyBuffer
+kernel), so that they read as HBM bytes.  The summary records a hash of the
+kernel source; `traffic_for` returns the figures only while that source is
+unchanged.
+"""
+import argparse
+import csv
+import glob
+import hashlib
+import json
+import os
+from collections import defaultdict
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+KERNEL_SOURCE = os.path.join(HERE, "csrc", "kernels.hip")
+COPY_KERNEL = "__amd_rocclr_copyBuffer"
+
+
+def source_hash():
+    return hashlib.sha256(open(KERNEL_SOURCE, "rb").read()).hexdigest()[:16]
+
+
+def _csv(d, suffix):
+    files = glob.glob(os.path.join(d, "**", "*" + suffix), recursive=True)
+    if not files:
+        raise FileNotFoundError("no *%s under %s" % (suffix, d))
+    return list(csv.DictReader(open(files[0])))
+
+
+def kernel_durations(trace_dir):
+    """(kernel name, grid) -> list of durations in ns."""
+    out = defaultdict(list)
+    for r in _csv(trace_dir, "kernel_trace.csv"):
+        out[(r["Kernel_Name"], int(r["Grid_Size_X"]))].append(
+            int(r["End_Timestamp"]) - int(r["Start_Timestamp"]))
+    return out
+
+
+def counter_values(pmc_dir):
+    """(kernel name, grid) -> list of counter values (KiB per dispatch)."""
+    out = defaultdict(list)
+    for r in _csv(pmc_dir, "counter_collection.csv"):
+        out[(r["Kernel_Name"], int(r["Grid_Size"]))].append(float(r["Counter_Value"]))
+    return out
+
+
+def _largest(d, name):
+    keys = [k for k in d if k[0].startswith(name)]
+    if not keys:
+        raise KeyError(name)
+    return max(keys, key=lambda k: k[1])
+
+
+def summarize(stats_dir, fetch_dir, write_dir, kernel, copy_bytes, cmd):
+    dur = kernel_durations(stats_dir)
+    fetch = counter_values(fetch_dir)
+    write = counter_values(write_dir)
+    kd = _largest(dur, kernel)
+    kf, kw = _largest(fetch, kernel), _largest(write, kernel)
+    cf, cw = _largest(fetch, COPY_KERNEL), _largest(write, COPY_KERNEL)
+    mean = lambda v: sum(v) / len(v)
+    fetch_scale = copy_bytes / (mean(fetch[cf]) * 1024.0)
+    write_scale = copy_bytes / (mean(write[cw]) * 1024.0)
+    fetch_b = mean(fetch[kf]) * 1024.0 * fetch_scale
+    write_b = mean(write[kw]) * 1024.0 * write_scale
+    top = sorted(dur.items(), key=lambda kv: -sum(kv[1]))[:12]
+    return {
+        "kernel": kernel, "grid": kd[1], "dispatches": len(dur[kd]),
+        "avg_duration_us": mean(dur[kd]) / 1e3,
+        "fetch_bytes": fetch_b, "write_bytes": write_b, "traffic_bytes": fetch_b + write_b,
+        "fetch_scale": fetch_scale, "write_scale": write_scale,
+        "copy_bytes": copy_bytes, "source_hash": source_hash(), "command": cmd,
+        "top_kernels_us": [[k[0].split("(")[0][:80], k[1], len(v), sum(v) / 1e3, mean(v) / 1e3]
+                           for k, v in top],
+    }
+
+
+def write_summary(s, path):
+    lines = ["# rocprofv3 summary: %s (grid %d)" % (s["kernel"], s["grid"]), "",
+             "command: %s" % s["command"], "kernel source hash: %s" % s["source_hash"], "",
+             "average duration: %.2f us over %d dispatches" % (s["avg_duration_us"], s["dispatches"]),
+             "HBM fetch: %.1f MB, write: %.1f MB per dispatch" % (s["fetch_bytes"] / 1e6,
+                                                                 s["write_bytes"] / 1e6),
+             "counter scale (plain copy of %d bytes): FETCH_SIZE x%.3f, WRITE_SIZE x%.3f"
+             % (s["copy_bytes"], s["fetch_scale"], s["write_scale"]), "",
+             "top kernels by total time (name, grid, dispatches, total us, avg us):"]
+    for row in s["top_kernels_us"]:
+        lines.append("  %-80s %9d %6d %10.1f %9.2f" % tuple(row))
+    lines += ["", "json: " + json.dumps({k: v for k, v in s.items() if k != "top_kernels_us"})]
+    open(path, "w").write("\n".join(lines) + "\n")
+
+
+def traffic_for(path):
+    """HBM bytes per dispatch recorded in a summary, or None if the kernel
+    source has changed since (or the file is missing)."""
+    if not os.path.exists(path):
+        return None
+    for line in open(path):
+        if line.startswith("json: "):
+            s = json.loads(line[6:])
+            return s["traffic_bytes"] if s.get("source_hash") == source_hash() else None
+    return None
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("mode", choices=["summarize"])
+    ap.add_argument("--stats", required=True)
+    ap.add_argument("--fetch", required=True)
+    ap.add_argument("--write", required=True)
+    ap.add_argument("--kernel", required=True)
+    ap.add_argument("--copy-bytes", type=int, required=True)
+    ap.add_argument("--cmd", default="")
+    ap.add_argument("--out", required=True)
+    a = ap.parse_args()
+    s = summarize(a.stats, a.fetch, a.write, a.kernel, a.copy_bytes, a.cmd)
+    write_summary(s, a.out)
+    print(open(a.out).read())
+
+
+if __name__ == "__main__":
+    main()
