@@ -204,7 +204,9 @@ int hhg_residual(const hhg_mesh* mesh, int32_t level, int32_t op, int32_t dtype,
  * A = macro-vertices and even-k edge points, B = odd-k edge points, then the
  * face colours, each stage updated at once; backward != 0 reverses the
  * stage order.  u (in/out) and f are fields of `dtype`.
- * smoother HHG_SMOOTH_NET replaces the face stages by the learned smoother.
+ * smoother HHG_SMOOTH_NET (FP32 fields, weights set) keeps stages A and B
+ * and replaces the face stages by u += N(D^-1 (f - A u)); the backward
+ * sweep applies the face step first.
  */
 int hhg_smooth(const hhg_mesh* mesh, int32_t level, int32_t op,
                int32_t smoother, int32_t dtype, void* u, const void* f,
@@ -228,12 +230,73 @@ int hhg_vcycle(const hhg_mesh* mesh, int32_t level, int32_t op,
  * initial guess and the Dirichlet values.  Modes: plain FP64 V-cycles;
  * mixed-precision iterative refinement (FP64 residual and update, FP32
  * V-cycle on the correction, FP64 coarse CG); learned smoother inside the
- * mixed-precision loop with Gauss-Seidel fallback.  Returns HHG_ENOTCONV if
+ * mixed-precision loop with Gauss-Seidel fallback: the learned smoother runs
+ * only if a network is loaded and marked accepted, and a learned cycle that
+ * does not lower the residual (or makes it non-finite) is undone and the
+ * solve goes on with Gauss-Seidel (stats->fallback = 1; the undone cycle
+ * counts in stats->iters).  Returns HHG_ENOTCONV if
  * max_iters is reached or the residual stops decreasing; stats are filled in
  * every case.
  */
 int hhg_solve(hhg_mesh* mesh, const hhg_solve_opts* opts, void* u,
               const void* f, hhg_solve_stats* stats, void* stream);
+
+/*
+ * Jacobi-scaled residual rho = D^-1 (f - A u) on interior points (f != NULL)
+ * or rho = D^-1 u (f == NULL), 0 on Dirichlet points, all copies written;
+ * D is the diagonal of the operator (sec. 4.3: pointwise smoothers use the
+ * diagonal, which the stencils provide).  rho must not alias u or f.
+ */
+int hhg_jacobi(const hhg_mesh* mesh, int32_t level, int32_t op, int32_t dtype,
+               const void* u, const void* f, void* rho, void* stream);
+
+/*
+ * Dot product x^T y over the owned interior points of `level` (each unknown
+ * once), accumulated in FP64 in a fixed order, into the device double *out
+ * (sec. 4.1 Alg. 2: local dots per primitive, then a global sum).
+ */
+int hhg_dot(const hhg_mesh* mesh, int32_t level, int32_t dtype, const void* x,
+            const void* y, double* out, void* stream);
+
+/*
+ * z = alpha x + beta y over whole fields of `level` (sec. 4.1 Alg. 1,
+ * assign; purely local, copies stay consistent).  z may alias x or y.
+ */
+int hhg_axpby(const hhg_mesh* mesh, int32_t level, int32_t dtype, double alpha,
+              const void* x, double beta, const void* y, void* z, void* stream);
+
+/*
+ * Learned face smoother (not part of the paper; a smoother variant layered
+ * on the method).  N(rho) = HexConv(16->1)(ReLU(HexConv(1->16)(rho))) with
+ * 7-tap kernels over the offsets C, E, W, N, S, SE, NW of face-local (i, j),
+ * no biases, hidden layer on face-interior points only.  Weights: 224 FP32
+ * values, W1[16][7] then W2[16][7], held in the workspace (HHG_FEAT_NET,
+ * which needs HHG_FEAT_MP).  The forward pass uses BF16 MFMA operands with
+ * FP32 accumulation by default.
+ *
+ * hhg_net_set_weights: copy w[224] (host) in and reset the Adam moments.
+ * hhg_net_get_weights: copy the FP32 master weights out to w[224] (host).
+ * hhg_net_set_options: precision HHG_BF16 (MFMA) or HHG_F32 (reference
+ *   arithmetic for tests); accepted != 0 lets HHG_MODE_LEARNED use it.
+ * hhg_net_forward: out = N(rho) on face interiors, 0 elsewhere (FP32
+ *   fields of `level`, copies written).
+ * hhg_net_backward: dW[224] (device, accumulated) += gradient of
+ *   sum_p g(p) N(rho)(p) over face-interior p; deterministic reduction.
+ * hhg_net_adam_step: one Adam step (beta1 0.9, beta2 0.999, eps 1e-8,
+ *   bias-corrected, step >= 1) on the master weights with gradient grad
+ *   (device, 224 values).
+ * Errors: HHG_ENOMEM without HHG_FEAT_NET, HHG_EINVAL for wrong sizes or
+ * when no weights have been set.
+ */
+int hhg_net_set_weights(hhg_mesh* mesh, const float* w, int32_t n, void* stream);
+int hhg_net_get_weights(const hhg_mesh* mesh, float* w, int32_t n, void* stream);
+int hhg_net_set_options(hhg_mesh* mesh, int32_t precision, int32_t accepted);
+int hhg_net_forward(const hhg_mesh* mesh, int32_t level, const void* rho, void* out,
+                    void* stream);
+int hhg_net_backward(const hhg_mesh* mesh, int32_t level, const void* rho,
+                     const void* g, float* dW, void* stream);
+int hhg_net_adam_step(hhg_mesh* mesh, const float* grad, float lr, int32_t step,
+                      void* stream);
 
 /*
  * Per-kernel timing of the finest-level smoother launches, for profiling:

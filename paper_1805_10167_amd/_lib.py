@@ -56,6 +56,15 @@ _SIGS = {
     "hhg_vcycle": (_c.c_int, [_vp, _i32, _i32, _i32, _i32, _vp, _vp, _i32, _i32, _vp]),
     "hhg_solve": (_c.c_int, [_vp, _c.POINTER(hhg_solve_opts), _vp, _vp,
                              _c.POINTER(hhg_solve_stats), _vp]),
+    "hhg_jacobi": (_c.c_int, [_vp, _i32, _i32, _i32, _vp, _vp, _vp, _vp]),
+    "hhg_dot": (_c.c_int, [_vp, _i32, _i32, _vp, _vp, _vp, _vp]),
+    "hhg_axpby": (_c.c_int, [_vp, _i32, _i32, _c.c_double, _vp, _c.c_double, _vp, _vp, _vp]),
+    "hhg_net_set_weights": (_c.c_int, [_vp, _vp, _i32, _vp]),
+    "hhg_net_get_weights": (_c.c_int, [_vp, _vp, _i32, _vp]),
+    "hhg_net_set_options": (_c.c_int, [_vp, _i32, _i32]),
+    "hhg_net_forward": (_c.c_int, [_vp, _i32, _vp, _vp, _vp]),
+    "hhg_net_backward": (_c.c_int, [_vp, _i32, _vp, _vp, _vp, _vp]),
+    "hhg_net_adam_step": (_c.c_int, [_vp, _vp, _c.c_float, _i32, _vp]),
     "hhg_timing_enable": (_c.c_int, [_vp, _i32]),
     "hhg_timing_read": (_c.c_int, [_vp, _c.POINTER(_i64), _c.POINTER(_c.c_double), _i32]),
 }
@@ -205,6 +214,46 @@ def hhg_solve(h, u, f, mode=HHG_MODE_PLAIN_FP64, op=HHG_OP_LAPLACE, rtol=1e-8, m
     stats = {k: getattr(st, k) for k, _ in hhg_solve_stats._fields_}
     hl = list(hist[:st.iters + 1]) if history else []
     return rc, stats, hl
+
+
+def hhg_jacobi(h, level, op, dtype, u, f, rho, stream=None):
+    _check(lib().hhg_jacobi(h, level, op, dtype, _ptr(u), _ptr(f), _ptr(rho), _stream(stream)))
+
+
+def hhg_dot(h, level, dtype, x, y, out, stream=None):
+    _check(lib().hhg_dot(h, level, dtype, _ptr(x), _ptr(y), _ptr(out), _stream(stream)))
+
+
+def hhg_axpby(h, level, dtype, alpha, x, beta, y, z, stream=None):
+    _check(lib().hhg_axpby(h, level, dtype, alpha, _ptr(x), beta, _ptr(y), _ptr(z),
+                           _stream(stream)))
+
+
+def hhg_net_set_weights(h, w, stream=None):
+    w = np.ascontiguousarray(w, dtype=np.float32)
+    _check(lib().hhg_net_set_weights(h, w.ctypes.data, len(w), _stream(stream)))
+
+
+def hhg_net_get_weights(h, stream=None):
+    w = np.zeros(224, dtype=np.float32)
+    _check(lib().hhg_net_get_weights(h, w.ctypes.data, len(w), _stream(stream)))
+    return w
+
+
+def hhg_net_set_options(h, precision=HHG_BF16, accepted=0):
+    _check(lib().hhg_net_set_options(h, precision, int(accepted)))
+
+
+def hhg_net_forward(h, level, rho, out, stream=None):
+    _check(lib().hhg_net_forward(h, level, _ptr(rho), _ptr(out), _stream(stream)))
+
+
+def hhg_net_backward(h, level, rho, g, dW, stream=None):
+    _check(lib().hhg_net_backward(h, level, _ptr(rho), _ptr(g), _ptr(dW), _stream(stream)))
+
+
+def hhg_net_adam_step(h, grad, lr, step, stream=None):
+    _check(lib().hhg_net_adam_step(h, _ptr(grad), lr, step, _stream(stream)))
 
 
 def hhg_timing_enable(h, enable):

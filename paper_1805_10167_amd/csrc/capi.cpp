@@ -6,6 +6,7 @@
 #include <chrono>
 #include <cmath>
 #include <cstring>
+#include <algorithm>
 #include <new>
 #include <utility>
 #include <string>
@@ -48,6 +49,7 @@ void carve(hhg_mesh* M, uint32_t feat, Carver& c) {
         H.d_row_off = (int32_t*)c.take(sizeof(int32_t) * H.row_off.size());
         H.d_tiles = (int2*)c.take(sizeof(int2) * (H.tiles.size() + 1));
         H.d_gs_tiles = (int2*)c.take(sizeof(int2) * (H.gs_tiles.size() + 1));
+        H.d_net_tiles = (int2*)c.take(sizeof(int2) * (H.net_tiles.size() + 1));
         H.d_gdst = (int64_t*)c.take(sizeof(int64_t) * (H.gdst.size() + 1));
         H.d_gsrc = (int64_t*)c.take(sizeof(int64_t) * (H.gsrc.size() + 1));
     }
@@ -87,15 +89,28 @@ void carve(hhg_mesh* M, uint32_t feat, Carver& c) {
         if (!(feat & HHG_FEAT_F64))
             for (int l = m.lc; l <= m.L; ++l)
                 if (!M->r64[l]) M->r64[l] = fld(l, 8);   // FP64 coarse residual
-        for (int l = m.lc; l <= m.L; ++l) {
-            M->u32[l] = fld(l, 4);
-            M->f32[l] = fld(l, 4);
+        for (int l = 1; l <= m.L; ++l) {
+            if (l >= m.lc) {
+                M->u32[l] = fld(l, 4);
+                M->f32[l] = fld(l, 4);
+            }
             M->r32[l] = fld(l, 4);
         }
     }
     for (int l = 1; l <= m.L; ++l) {
         if (feat & HHG_FEAT_F64) M->a64[l] = fld(l, 8);
         if (feat & HHG_FEAT_MP) M->a32[l] = fld(l, 4);
+    }
+    M->net_w = M->net_m = M->net_v = M->net_partials = nullptr;
+    M->u_backup = nullptr;
+    if (feat & HHG_FEAT_NET) {
+        M->u_backup = (double*)fld(m.L, 8);
+        M->net_w = (float*)c.take(sizeof(float) * NET_NW);
+        M->net_m = (float*)c.take(sizeof(float) * NET_NW);
+        M->net_v = (float*)c.take(sizeof(float) * NET_NW);
+        size_t maxb = 1;
+        for (int l = 1; l <= m.L; ++l) maxb = std::max(maxb, (size_t)m.F * m.lv[l].net_tiles.size());
+        M->net_partials = (float*)c.take(sizeof(float) * NET_NW * maxb);
     }
     if (feat & HHG_FEAT_VARK) {
         for (int l = 1; l <= m.L; ++l) {
@@ -135,6 +150,15 @@ int check_op(const hhg_mesh* M, int op, int dtype) {
     return HHG_OK;
 }
 
+int check_smoother(const hhg_mesh* M, int smoother, int dtype) {
+    if (smoother == HHG_SMOOTH_GS) return HHG_OK;
+    if (smoother != HHG_SMOOTH_NET) return fail(HHG_EINVAL, "unknown smoother");
+    if (!(M->features & HHG_FEAT_NET)) return fail(HHG_ENOMEM, "workspace lacks HHG_FEAT_NET");
+    if (!M->net_loaded) return fail(HHG_EINVAL, "no network weights set");
+    if (dtype != HHG_F32) return fail(HHG_EINVAL, "the learned smoother runs on FP32 fields");
+    return HHG_OK;
+}
+
 // fields of the hierarchy for a dtype
 void* level_u(const hhg_mesh* M, int l, int dt) { return dt == HHG_F64 ? M->u64[l] : M->u32[l]; }
 void* level_f(const hhg_mesh* M, int l, int dt) { return dt == HHG_F64 ? M->f64[l] : M->f32[l]; }
@@ -142,11 +166,38 @@ void* level_r(const hhg_mesh* M, int l, int dt) { return dt == HHG_F64 ? M->r64[
 
 void* level_alt(const hhg_mesh* M, int l, int dt) { return dt == HHG_F64 ? M->a64[l] : M->a32[l]; }
 
-// `sweeps` sweeps alternating between the buffers x and y; *out receives the
-// buffer that holds the result (x for an even number of sweeps).
-int smooth_pp(const hhg_mesh* M, int level, int op, int dt, void* x, void* y, const void* f,
-              int sweeps, int backward, hipStream_t s, void** out) {
+// Learned-smoother sweep (FP32): Gauss-Seidel stages A and B on edges and
+// vertices, then u += N(D^-1 (f - A u)) on face interiors; the backward
+// sweep runs the face step first.  In place, rho in the level's r32 field.
+int net_sweep(const hhg_mesh* M, int level, int op, void* u, const void* f, int backward, hipStream_t s) {
+    float* rho = (float*)M->r32[level];
+    auto face_step = [&]() -> int {
+        HIP_CHECK(launch_jacobi(M, level, op, HHG_F32, u, f, rho, s), "net rho");
+        HIP_CHECK(launch_net_forward(M, level, rho, (float*)u, 1, M->net_mfma, s), "net step");
+        return HHG_OK;
+    };
+    int rc;
+    if (backward && (rc = face_step())) return rc;
+    HIP_CHECK(launch_low_gs(M, level, op, HHG_F32, u, f, backward ? 1 : 0, s), "stage");
+    HIP_CHECK(launch_low_gs(M, level, op, HHG_F32, u, f, backward ? 0 : 1, s), "stage");
+    if (!backward) {
+        // stage B left the ghost-row corner copies to its successor
+        HIP_CHECK(launch_low_gs(M, level, op, HHG_F32, u, f, 2, s), "corner copies");
+        if ((rc = face_step())) return rc;
+    }
+    return HHG_OK;
+}
+
+// `sweeps` sweeps; Gauss-Seidel sweeps alternate between the buffers x and
+// y, learned sweeps stay in x.  *out receives the buffer with the result.
+int smooth_pp(const hhg_mesh* M, int level, int op, int smoother, int dt, void* x, void* y,
+              const void* f, int sweeps, int backward, hipStream_t s, void** out) {
     for (int i = 0; i < sweeps; ++i) {
+        if (smoother == HHG_SMOOTH_NET) {
+            int rc = net_sweep(M, level, op, x, f, backward, s);
+            if (rc) return rc;
+            continue;
+        }
         HIP_CHECK(launch_gs_sweep(M, level, op, dt, x, y, f, backward, s), "smooth");
         std::swap(x, y);
     }
@@ -162,7 +213,6 @@ int copy_field(const hhg_mesh* M, int level, int dt, void* dst, const void* src,
 
 int vcycle_rec(const hhg_mesh* M, int level, int op, int smoother, int dt, void* u, const void* f,
                int nu1, int nu2, hipStream_t s) {
-    (void)smoother;
     const int lc = M->m.lc;
     const double* vals = op == HHG_OP_DIFFUSION ? M->coarse_vals_diff : M->coarse.vals;
     if (level == lc) {
@@ -171,7 +221,7 @@ int vcycle_rec(const hhg_mesh* M, int level, int op, int smoother, int dt, void*
     }
     void* alt = level_alt(M, level, dt);
     void* cur = nullptr;
-    int rc = smooth_pp(M, level, op, dt, u, alt, f, nu1, 0, s, &cur);
+    int rc = smooth_pp(M, level, op, smoother, dt, u, alt, f, nu1, 0, s, &cur);
     if (rc) return rc;
     void* other = cur == u ? alt : u;
     void* r = level_r(M, level, dt);
@@ -183,7 +233,7 @@ int vcycle_rec(const hhg_mesh* M, int level, int op, int smoother, int dt, void*
     if (rc) return rc;
     HIP_CHECK(launch_prolong_add(M, level, dt, uc, cur, s), "prolong");
     void* fin = nullptr;
-    rc = smooth_pp(M, level, op, dt, cur, other, f, nu2, 1, s, &fin);
+    rc = smooth_pp(M, level, op, smoother, dt, cur, other, f, nu2, 1, s, &fin);
     if (rc) return rc;
     if (fin != u) return copy_field(M, level, dt, u, fin, s);
     return HHG_OK;
@@ -208,6 +258,7 @@ hhg::LevelDev hhg_mesh::dev(int level) const {
     L.vert_stride = (int32_t)H.vert_stride;
     L.ntiles = (int32_t)H.tiles.size();
     L.n_gs_tiles = (int32_t)H.gs_tiles.size();
+    L.n_net_tiles = (int32_t)H.net_tiles.size();
     L.n_iedges = (int32_t)m.iedges.size();
     L.n_iverts = (int32_t)m.iverts.size();
     L.face_stride = H.face_stride;
@@ -224,6 +275,7 @@ hhg::LevelDev hhg_mesh::dev(int level) const {
     L.row_off = H.d_row_off;
     L.tiles = H.d_tiles;
     L.gs_tiles = H.d_gs_tiles;
+    L.net_tiles = H.d_net_tiles;
     L.faces = d_faces;
     L.edges = d_edges;
     L.verts = d_verts;
@@ -271,6 +323,8 @@ int hhg_workspace_bytes(const hhg_mesh* mesh, uint32_t features, size_t* bytes) 
     if (!mesh || !bytes) return fail(HHG_EINVAL, "null argument");
     if (features & ~(HHG_FEAT_F64 | HHG_FEAT_MP | HHG_FEAT_VARK | HHG_FEAT_NET))
         return fail(HHG_EINVAL, "unknown feature bits");
+    if ((features & HHG_FEAT_NET) && !(features & HHG_FEAT_MP))
+        return fail(HHG_EINVAL, "HHG_FEAT_NET needs HHG_FEAT_MP (the learned smoother runs in FP32)");
     hhg_mesh tmp;
     tmp.m = mesh->m;
     Carver c(nullptr);
@@ -300,6 +354,7 @@ int hhg_bind_workspace(hhg_mesh* M, uint32_t features, void* dptr, size_t bytes,
         HIP_CHECK(upload(H.d_row_off, H.row_off, s), "upload");
         HIP_CHECK(upload(H.d_tiles, H.tiles, s), "upload");
         HIP_CHECK(upload(H.d_gs_tiles, H.gs_tiles, s), "upload");
+        HIP_CHECK(upload(H.d_net_tiles, H.net_tiles, s), "upload");
         HIP_CHECK(upload(H.d_gdst, H.gdst, s), "upload");
         HIP_CHECK(upload(H.d_gsrc, H.gsrc, s), "upload");
     }
@@ -315,6 +370,8 @@ int hhg_bind_workspace(hhg_mesh* M, uint32_t features, void* dptr, size_t bytes,
     M->features = features;
     M->bound = true;
     M->kappa_set = false;
+    M->net_loaded = false;
+    M->net_accepted = false;
     HIP_CHECK(launch_coarse_extract(M, OP_LAPLACE, C.vals, s), "coarse operator");
     HIP_CHECK(hipStreamSynchronize(s), "bind");
     return HHG_OK;
@@ -432,14 +489,14 @@ int hhg_smooth(const hhg_mesh* M, int32_t level, int32_t op, int32_t smoother, i
     if (rc) return rc;
     if ((rc = check_op(M, op, dtype))) return rc;
     if (op == HHG_OP_MASS) return fail(HHG_EINVAL, "smoothing needs a stiffness operator");
-    if (smoother != HHG_SMOOTH_GS) return fail(HHG_EINVAL, "unknown smoother");
+    if ((rc = check_smoother(M, smoother, dtype))) return rc;
     if (sweeps < 0 || !u || !f) return fail(HHG_EINVAL, "bad arguments");
     void* alt = level_alt(M, level, dtype);
     if (!alt) return fail(HHG_ENOMEM, dtype == HHG_F64 ? "workspace lacks HHG_FEAT_F64"
                                                        : "workspace lacks HHG_FEAT_MP");
     hipStream_t s = (hipStream_t)stream;
     void* fin = nullptr;
-    if ((rc = smooth_pp(M, level, op, dtype, u, alt, f, sweeps, backward != 0, s, &fin))) return rc;
+    if ((rc = smooth_pp(M, level, op, smoother, dtype, u, alt, f, sweeps, backward != 0, s, &fin))) return rc;
     if (fin != u) return copy_field(M, level, dtype, u, fin, s);
     return HHG_OK;
 }
@@ -450,7 +507,7 @@ int hhg_vcycle(const hhg_mesh* M, int32_t level, int32_t op, int32_t smoother, i
     if (rc) return rc;
     if ((rc = check_op(M, op, dtype))) return rc;
     if (op == HHG_OP_MASS) return fail(HHG_EINVAL, "multigrid needs a stiffness operator");
-    if (smoother != HHG_SMOOTH_GS) return fail(HHG_EINVAL, "unknown smoother");
+    if ((rc = check_smoother(M, smoother, dtype))) return rc;
     if (level < M->m.lc) return fail(HHG_EINVAL, "level below the coarse level");
     if (dtype == HHG_F64 && !(M->features & HHG_FEAT_F64))
         return fail(HHG_ENOMEM, "workspace lacks HHG_FEAT_F64");
@@ -471,11 +528,13 @@ int hhg_solve(hhg_mesh* M, const hhg_solve_opts* o, void* u, const void* f, hhg_
     if (rc) return rc;
     if ((rc = check_op(M, o->op, HHG_F64))) return rc;
     if (o->op == HHG_OP_MASS) return fail(HHG_EINVAL, "solve needs a stiffness operator");
-    if (o->mode != HHG_MODE_PLAIN_FP64 && o->mode != HHG_MODE_MP_IR)
+    if (o->mode != HHG_MODE_PLAIN_FP64 && o->mode != HHG_MODE_MP_IR && o->mode != HHG_MODE_LEARNED)
         return fail(HHG_EINVAL, "unknown solve mode");
+    if (o->mode == HHG_MODE_LEARNED && !(M->features & HHG_FEAT_NET))
+        return fail(HHG_ENOMEM, "workspace lacks HHG_FEAT_NET");
     if (o->mode == HHG_MODE_PLAIN_FP64 && !(M->features & HHG_FEAT_F64))
         return fail(HHG_ENOMEM, "workspace lacks HHG_FEAT_F64");
-    if (o->mode == HHG_MODE_MP_IR && !(M->features & HHG_FEAT_MP))
+    if (o->mode != HHG_MODE_PLAIN_FP64 && !(M->features & HHG_FEAT_MP))
         return fail(HHG_ENOMEM, "workspace lacks HHG_FEAT_MP");
     if (o->max_iters < 0 || o->nu1 < 0 || o->nu2 < 0 || !(o->rtol >= 0))
         return fail(HHG_EINVAL, "bad solve options");
@@ -491,7 +550,13 @@ int hhg_solve(hhg_mesh* M, const hhg_solve_opts* o, void* u, const void* f, hhg_
     double r0 = 0.0;
     if ((rc = norm_now(&r0))) return rc;
     st->res0 = r0;
-    st->smoother_used = HHG_SMOOTH_GS;
+    // the learned smoother runs only when a network is loaded and accepted
+    int smoother = HHG_SMOOTH_GS;
+    if (o->mode == HHG_MODE_LEARNED) {
+        if (M->net_loaded && M->net_accepted) smoother = HHG_SMOOTH_NET;
+        else st->fallback = 1;
+    }
+    st->smoother_used = smoother;
     if (o->res_history && o->history_capacity > 0) o->res_history[0] = r0;
     if (r0 == 0.0) {
         st->converged = 1;
@@ -504,6 +569,10 @@ int hhg_solve(hhg_mesh* M, const hhg_solve_opts* o, void* u, const void* f, hhg_
     int status = HHG_ENOTCONV;
     const int64_t nL = M->m.lv[L].total;
     for (int it = 0; it < o->max_iters; ++it) {
+        const bool learned = smoother == HHG_SMOOTH_NET;
+        if (learned)
+            HIP_CHECK(hipMemcpyAsync(M->u_backup, u, sizeof(double) * nL, hipMemcpyDeviceToDevice, s),
+                      "backup");
         if (o->mode == HHG_MODE_PLAIN_FP64) {
             rc = vcycle_rec(M, L, o->op, HHG_SMOOTH_GS, HHG_F64, u, f, o->nu1, o->nu2, s);
         } else {
@@ -512,13 +581,24 @@ int hhg_solve(hhg_mesh* M, const hhg_solve_opts* o, void* u, const void* f, hhg_
             float* e32 = (float*)M->u32[L];
             HIP_CHECK(launch_f64_to_f32(r64, r32, nL, s), "downcast");
             HIP_CHECK(launch_fill(e32, nL, HHG_F32, 0.0, s), "fill");
-            rc = vcycle_rec(M, L, o->op, HHG_SMOOTH_GS, HHG_F32, e32, r32, o->nu1, o->nu2, s);
+            rc = vcycle_rec(M, L, o->op, smoother, HHG_F32, e32, r32, o->nu1, o->nu2, s);
             if (!rc) HIP_CHECK(launch_add_f32_to_f64((double*)u, e32, nL, s), "update");
         }
         if (rc) return rc;
         double rn = 0.0;
         if ((rc = norm_now(&rn))) return rc;
         st->iters = it + 1;
+        // learned smoother guard: a cycle that does not reduce the residual
+        // (or leaves it non-finite) is undone and the rest of the solve
+        // runs Gauss-Seidel
+        if (learned && !(rn <= prev)) {
+            HIP_CHECK(hipMemcpyAsync(u, M->u_backup, sizeof(double) * nL, hipMemcpyDeviceToDevice, s),
+                      "restore");
+            if ((rc = norm_now(&rn))) return rc;     // also refreshes r64
+            smoother = HHG_SMOOTH_GS;
+            st->fallback = 1;
+            st->smoother_used = HHG_SMOOTH_GS;
+        }
         st->rel_res = rn / r0;
         if (o->res_history && it + 1 < o->history_capacity) o->res_history[it + 1] = rn;
         if (!std::isfinite(rn)) {
@@ -540,6 +620,106 @@ int hhg_solve(hhg_mesh* M, const hhg_solve_opts* o, void* u, const void* f, hhg_
     if (status == HHG_ENOTCONV && g_err.empty()) g_err = "iteration cap reached";
     st->ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
     return status;
+}
+
+int hhg_jacobi(const hhg_mesh* M, int32_t level, int32_t op, int32_t dtype, const void* u,
+               const void* f, void* rho, void* stream) {
+    int rc = check_common(M, level, dtype);
+    if (rc) return rc;
+    if ((rc = check_op(M, op, dtype))) return rc;
+    if (op == HHG_OP_MASS) return fail(HHG_EINVAL, "needs a stiffness operator");
+    if (!u || !rho || u == rho || (f && f == rho)) return fail(HHG_EINVAL, "bad buffers");
+    HIP_CHECK(launch_jacobi(M, level, op, dtype, u, f, rho, (hipStream_t)stream), "jacobi");
+    return HHG_OK;
+}
+
+int hhg_dot(const hhg_mesh* M, int32_t level, int32_t dtype, const void* x, const void* y,
+            double* out, void* stream) {
+    int rc = check_common(M, level, dtype);
+    if (rc) return rc;
+    if (!x || !y || !out) return fail(HHG_EINVAL, "null buffer");
+    HIP_CHECK(launch_dot(M, level, dtype, x, y, out, (hipStream_t)stream), "dot");
+    return HHG_OK;
+}
+
+int hhg_axpby(const hhg_mesh* M, int32_t level, int32_t dtype, double alpha, const void* x,
+              double beta, const void* y, void* z, void* stream) {
+    int rc = check_common(M, level, dtype);
+    if (rc) return rc;
+    if (!x || !y || !z) return fail(HHG_EINVAL, "null buffer");
+    HIP_CHECK(launch_axpby(M->m.lv[level].total, dtype, alpha, x, beta, y, z, (hipStream_t)stream), "axpby");
+    return HHG_OK;
+}
+
+static int check_net(const hhg_mesh* M) {
+    if (!M) return fail(HHG_EINVAL, "null mesh");
+    if (!M->bound) return fail(HHG_ENOMEM, "no workspace bound");
+    if (!(M->features & HHG_FEAT_NET)) return fail(HHG_ENOMEM, "workspace lacks HHG_FEAT_NET");
+    return HHG_OK;
+}
+
+int hhg_net_set_weights(hhg_mesh* M, const float* w, int32_t n, void* stream) {
+    int rc = check_net(M);
+    if (rc) return rc;
+    if (!w || n != NET_NW) return fail(HHG_EINVAL, "expected 224 weights");
+    hipStream_t s = (hipStream_t)stream;
+    HIP_CHECK(hipMemcpyAsync(M->net_w, w, sizeof(float) * NET_NW, hipMemcpyHostToDevice, s), "weights");
+    HIP_CHECK(launch_fill(M->net_m, NET_NW, HHG_F32, 0.0, s), "adam state");
+    HIP_CHECK(launch_fill(M->net_v, NET_NW, HHG_F32, 0.0, s), "adam state");
+    HIP_CHECK(hipStreamSynchronize(s), "weights");
+    M->net_loaded = true;
+    return HHG_OK;
+}
+
+int hhg_net_get_weights(const hhg_mesh* M, float* w, int32_t n, void* stream) {
+    int rc = check_net(M);
+    if (rc) return rc;
+    if (!w || n != NET_NW) return fail(HHG_EINVAL, "expected 224 weights");
+    hipStream_t s = (hipStream_t)stream;
+    HIP_CHECK(hipMemcpyAsync(w, M->net_w, sizeof(float) * NET_NW, hipMemcpyDeviceToHost, s), "weights");
+    HIP_CHECK(hipStreamSynchronize(s), "weights");
+    return HHG_OK;
+}
+
+int hhg_net_set_options(hhg_mesh* M, int32_t precision, int32_t accepted) {
+    int rc = check_net(M);
+    if (rc) return rc;
+    if (precision != HHG_BF16 && precision != HHG_F32) return fail(HHG_EINVAL, "precision must be BF16 or F32");
+    M->net_mfma = precision == HHG_BF16;
+    M->net_accepted = accepted != 0;
+    return HHG_OK;
+}
+
+int hhg_net_forward(const hhg_mesh* M, int32_t level, const void* rho, void* out, void* stream) {
+    int rc = check_net(M);
+    if (rc) return rc;
+    if ((rc = check_common(M, level, HHG_F32))) return rc;
+    if (!M->net_loaded) return fail(HHG_EINVAL, "no network weights set");
+    if (!rho || !out || rho == out) return fail(HHG_EINVAL, "bad buffers");
+    hipStream_t s = (hipStream_t)stream;
+    HIP_CHECK(launch_fill(out, M->m.lv[level].total, HHG_F32, 0.0, s), "net forward");
+    HIP_CHECK(launch_net_forward(M, level, (const float*)rho, (float*)out, 0, M->net_mfma, s), "net forward");
+    return HHG_OK;
+}
+
+int hhg_net_backward(const hhg_mesh* M, int32_t level, const void* rho, const void* g, float* dW,
+                     void* stream) {
+    int rc = check_net(M);
+    if (rc) return rc;
+    if ((rc = check_common(M, level, HHG_F32))) return rc;
+    if (!M->net_loaded) return fail(HHG_EINVAL, "no network weights set");
+    if (!rho || !g || !dW) return fail(HHG_EINVAL, "null buffer");
+    HIP_CHECK(launch_net_backward(M, level, (const float*)rho, (const float*)g, dW, M->net_mfma,
+                                  (hipStream_t)stream), "net backward");
+    return HHG_OK;
+}
+
+int hhg_net_adam_step(hhg_mesh* M, const float* grad, float lr, int32_t step, void* stream) {
+    int rc = check_net(M);
+    if (rc) return rc;
+    if (!grad || step < 1 || !(lr > 0.f)) return fail(HHG_EINVAL, "bad Adam arguments");
+    HIP_CHECK(launch_net_adam(M, grad, lr, step, (hipStream_t)stream), "adam");
+    return HHG_OK;
 }
 
 int hhg_timing_enable(hhg_mesh* M, int32_t enable) {

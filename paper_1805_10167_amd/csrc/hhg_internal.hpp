@@ -23,6 +23,10 @@ constexpr int TILE_J = 4;
 constexpr int GS_H = 3;
 constexpr int GS_TI = 192 - 2 * GS_H;
 constexpr int GS_TJ = 24;
+// learned-smoother tile: NET_TI x NET_TJ output points
+constexpr int NET_TI = 60;
+constexpr int NET_TJ = 12;
+constexpr int NET_NW = 224;     // weights: W1[16][7] then W2[16][7]
 
 inline int64_t pad_up(int64_t x, int64_t p) { return (x + p - 1) / p * p; }
 
@@ -94,7 +98,7 @@ struct LevelDev {
     int32_t level, n;
     int32_t F, E, V;
     int32_t ghost_off, ghost_stride, vert_stride;
-    int32_t ntiles, n_iedges, n_iverts, n_gs_tiles;
+    int32_t ntiles, n_iedges, n_iverts, n_gs_tiles, n_net_tiles, pad1;
     int64_t face_stride, edge_stride;
     int64_t face_base, edge_base, vert_base, total;
     int64_t gcls[G_NCLS + 1];
@@ -103,6 +107,7 @@ struct LevelDev {
     const int32_t* row_off;           // [n + 1] start of row j inside a face
     const int2* tiles;                // 64 x 4 tiles covering the whole face
     const int2* gs_tiles;             // smoother tiles covering the whole face
+    const int2* net_tiles;            // learned-smoother tiles meeting the interior
     const FaceInfo* faces;
     const EdgeInfo* edges;
     const VertexInfo* verts;
@@ -134,6 +139,7 @@ struct LevelHost {
     std::vector<int32_t> row_off;
     std::vector<int2> tiles;
     std::vector<int2> gs_tiles;
+    std::vector<int2> net_tiles;
     std::vector<int64_t> gdst, gsrc;
     int64_t gcls[G_NCLS + 1] = {0, 0, 0, 0, 0};
     int64_t n_all = 0, n_int = 0, can_edge_base = 0, can_face_base = 0;
@@ -141,6 +147,7 @@ struct LevelHost {
     int32_t* d_row_off = nullptr;
     int2* d_tiles = nullptr;
     int2* d_gs_tiles = nullptr;
+    int2* d_net_tiles = nullptr;
     int64_t* d_gdst = nullptr;
     int64_t* d_gsrc = nullptr;
 };

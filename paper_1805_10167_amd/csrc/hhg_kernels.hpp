@@ -47,4 +47,26 @@ hipError_t launch_inject(const hhg_mesh* M, int level, int dtype, const void* kf
 hipError_t launch_f64_to_f32(const double* src, float* dst, int64_t n, hipStream_t s);
 hipError_t launch_add_f32_to_f64(double* u, const float* e, int64_t n, hipStream_t s);
 
+// One Gauss-Seidel stage on edges and vertices (0: A, 1: B), copies written.
+hipError_t launch_low_gs(const hhg_mesh* M, int level, int op, int dtype, void* u, const void* f,
+                         int stage, hipStream_t s);
+// Learned face smoother (net.hip).  mode 0: y = N(rho) on face interiors
+// (caller zeroes y first); mode 1: y += N(rho).  Copies are written.
+hipError_t launch_net_forward(const hhg_mesh* M, int level, const float* rho, float* y, int mode,
+                              bool mfma, hipStream_t s);
+// dW[224] += gradient of sum_p g(p) N(rho)(p) with respect to the weights.
+hipError_t launch_net_backward(const hhg_mesh* M, int level, const float* rho, const float* g,
+                               float* dW, bool bf16, hipStream_t s);
+hipError_t launch_net_adam(const hhg_mesh* M, const float* grad, float lr, int step, hipStream_t s);
+// rho = D^-1 (f - A u) (f != null) or rho = D^-1 u (f == null) on interior
+// points, 0 on Dirichlet points, copies included.
+hipError_t launch_jacobi(const hhg_mesh* M, int level, int op, int dtype, const void* u,
+                         const void* f, void* rho, hipStream_t s);
+// Deterministic dot product over owned interior points into *out (device).
+hipError_t launch_dot(const hhg_mesh* M, int level, int dtype, const void* x, const void* y,
+                      double* out, hipStream_t s);
+// z = alpha x + beta y over whole fields.
+hipError_t launch_axpby(int64_t n, int dtype, double alpha, const void* x, double beta, const void* y,
+                        void* z, hipStream_t s);
+
 }  // namespace hhg

@@ -104,6 +104,15 @@ struct hhg_mesh {
     double* kap64[hhg::MAXLEVEL + 1] = {};
     float* kap32[hhg::MAXLEVEL + 1] = {};
     bool kappa_set = false;
+    // learned smoother: FP32 master weights, Adam moments, scratch
+    float* net_w = nullptr;
+    float* net_m = nullptr;
+    float* net_v = nullptr;
+    float* net_partials = nullptr;
+    double* u_backup = nullptr;      // finest-level iterate before a learned cycle
+    bool net_loaded = false;
+    bool net_accepted = false;
+    bool net_mfma = true;         // BF16 MFMA forward (false: FP32, for tests)
     double* partials = nullptr;   // reduction partial sums
     int64_t n_partials = 0;
     double* dscalars = nullptr;   // small device scalars (norms, dots)

@@ -326,9 +326,11 @@ __device__ __forceinline__ T vertex_apply(int op, const LevelDev& L, const Verte
     return c * x[vb] + s;
 }
 
-// y = A x on interior rows (0 on Dirichlet rows) with all copies of y.
-// With f and partials: r = f - A u instead, and per-block sums of r^2.
-template <class T, bool RES>
+// Point operator of every interior row, with all copies of the result:
+//   MODE 0: y = A x              MODE 1: y = f - A x (+ per-block sums of y^2)
+//   MODE 2: y = (f - A x) / a_pp MODE 3: y = x / a_pp
+// and 0 on Dirichlet rows.
+template <class T, int MODE>
 __global__ __launch_bounds__(NT) void k_apply(LevelDev L, int op, const T* __restrict__ x,
                                               const T* __restrict__ f, T* __restrict__ y,
                                               const T* __restrict__ kap, int gf, double* partials) {
@@ -340,11 +342,15 @@ __global__ __launch_bounds__(NT) void k_apply(LevelDev L, int op, const T* __res
         const int64_t up = row_start(n, j + 1) - row_start(n, j);
         const int64_t dn = row_start(n, j) - row_start(n, j - 1);
         const W7<T> w = face_weights<T>(op, fi, L.inv4l, kap, p, up, dn);
-        T v = w.c * x[p] + w.e * x[p + 1] + w.w * x[p - 1] + w.n * x[p + up] + w.s * x[p - dn] +
-              w.se * x[p - dn + 1] + w.nw * x[p + up - 1];
-        if (RES) {
-            v = f[p] - v;
-            acc += (double)v * (double)v;
+        T v;
+        if (MODE == 3) {
+            v = x[p] / w.c;
+        } else {
+            v = w.c * x[p] + w.e * x[p + 1] + w.w * x[p - 1] + w.n * x[p + up] + w.s * x[p - dn] +
+                w.se * x[p - dn + 1] + w.nw * x[p + up - 1];
+            if (MODE >= 1) v = f[p] - v;
+            if (MODE == 1) acc += (double)v * (double)v;
+            if (MODE == 2) v = v / w.c;
         }
         y[p] = v;
         push_face_near(L, y, fi, i, j, v);
@@ -357,10 +363,16 @@ __global__ __launch_bounds__(NT) void k_apply(LevelDev L, int op, const T* __res
                 const EdgeInfo& ei = L.edges[e];
                 const int64_t m = edge_main(L, e);
                 if (!ei.boundary) {
-                    v = edge_apply<T>(op, L, ei, x, kap, m, edge_ghost(L, e, 0), edge_ghost(L, e, 1), k);
-                    if (RES) {
-                        v = f[m + k] - v;
-                        acc += (double)v * (double)v;
+                    const int64_t g0 = edge_ghost(L, e, 0), g1 = edge_ghost(L, e, 1);
+                    const WE<T> w = edge_weights<T>(op, ei, L.inv4l, kap, m, g0, g1, k);
+                    if (MODE == 3) {
+                        v = x[m + k] / w.c;
+                    } else {
+                        v = w.c * x[m + k] + w.al * x[m + k - 1] + w.ah * x[m + k + 1] + w.l0 * x[g0 + k - 1] +
+                            w.h0 * x[g0 + k] + w.l1 * x[g1 + k - 1] + w.h1 * x[g1 + k];
+                        if (MODE >= 1) v = f[m + k] - v;
+                        if (MODE == 1) acc += (double)v * (double)v;
+                        if (MODE == 2) v = v / w.c;
                     }
                 }
                 y[m + k] = v;
@@ -370,10 +382,20 @@ __global__ __launch_bounds__(NT) void k_apply(LevelDev L, int op, const T* __res
                 const VertexInfo& vi = L.verts[vv];
                 const int64_t vb = vert_off(L, vv);
                 if (!vi.boundary) {
-                    v = vertex_apply<T>(op, L, vi, x, kap, vb);
-                    if (RES) {
-                        v = f[vb] - v;
-                        acc += (double)v * (double)v;
+                    T s = (T)0, c = (T)0;
+                    for (int q = 0; q < vi.deg; ++q) {
+                        const T wq = vertex_weight<T>(op, vi, L.inv4l, kap, vb, q);
+                        s += wq * x[vb + 1 + q];
+                        c += wq;
+                    }
+                    c = (op == OP_MASS) ? c : -c;
+                    if (MODE == 3) {
+                        v = x[vb] / c;
+                    } else {
+                        v = c * x[vb] + s;
+                        if (MODE >= 1) v = f[vb] - v;
+                        if (MODE == 1) acc += (double)v * (double)v;
+                        if (MODE == 2) v = v / c;
                     }
                 }
                 y[vb] = v;
@@ -381,10 +403,44 @@ __global__ __launch_bounds__(NT) void k_apply(LevelDev L, int op, const T* __res
             }
         }
     }
-    if (RES && partials) {
+    if (MODE == 1 && partials) {
         const double s = block_sum<NT>(acc, sm);
         if (threadIdx.x == 0) partials[blockIdx.x] = s;
     }
+}
+
+// Per-block sums of x*y over owned interior points (faces, interior edge
+// points, interior vertices): each unknown once.
+template <class T>
+__global__ __launch_bounds__(NT) void k_dot(LevelDev L, const T* __restrict__ x, const T* __restrict__ y,
+                                            int gf, double* partials) {
+    __shared__ double sm[NT / 64 + 1];
+    double acc = 0.0;
+    if ((int)blockIdx.x < gf) {
+        FACE_ALL_LOOP(L, gf)
+        (void)fi;
+        if (interior) acc += (double)x[p] * (double)y[p];
+        }
+    } else {
+        const int n = L.n;
+        const int64_t ne = (int64_t)L.n_iedges * (n - 2);
+        for (int64_t t = (int64_t)(blockIdx.x - gf) * NT + threadIdx.x; t < ne + L.n_iverts;
+             t += (int64_t)(gridDim.x - gf) * NT) {
+            int64_t q;
+            if (t < ne) q = edge_main(L, L.iedges[t / (n - 2)]) + (t % (n - 2)) + 1;
+            else q = vert_off(L, L.iverts[t - ne]);
+            acc += (double)x[q] * (double)y[q];
+        }
+    }
+    const double s = block_sum<NT>(acc, sm);
+    if (threadIdx.x == 0) partials[blockIdx.x] = s;
+}
+
+template <class T>
+__global__ __launch_bounds__(NT) void k_axpby(int64_t n, T alpha, const T* __restrict__ x, T beta,
+                                              const T* __restrict__ y, T* __restrict__ z) {
+    for (int64_t t = blockIdx.x * (int64_t)NT + threadIdx.x; t < n; t += (int64_t)gridDim.x * NT)
+        z[t] = alpha * x[t] + beta * y[t];
 }
 
 // Sum partials[0, count) in a fixed order; optional square root.
@@ -659,7 +715,8 @@ __global__ __launch_bounds__(GS_NT) void k_face_gs_fused(LevelDev L, const T* __
 // updated at once from the values before the stage; every update writes
 // its copies.  Odd points next to a vertex of two edges of one face read
 // each other in stage B, so stage B leaves those ghost-row copies alone and
-// stage A (which reads none of them) refreshes them.
+// stage A (which reads none of them) refreshes them; stage = 2 only
+// refreshes them.
 template <class T>
 __global__ __launch_bounds__(NT) void k_low_gs(LevelDev L, int op, T* __restrict__ u,
                                                const T* __restrict__ f, const T* __restrict__ kap,
@@ -673,7 +730,7 @@ __global__ __launch_bounds__(NT) void k_low_gs(LevelDev L, int op, T* __restrict
             const EdgeInfo& ei = L.edges[e];
             const int64_t m = edge_main(L, e);
             if ((k & 1) != stage) {
-                if (stage == 0 && (k == 1 || k == n - 2)) {
+                if (stage != 1 && (k & 1) && (k == 1 || k == n - 2)) {
                     const T v = u[m + k];
                     for (int end = 0; end < 2; ++end) {
                         if (k != (end == 0 ? 1 : n - 2)) continue;
@@ -1149,7 +1206,7 @@ template <class T>
 static hipError_t apply_t(const hhg_mesh* M, int level, int op, const T* x, T* y, hipStream_t s) {
     const LevelDev L = M->dev(level);
     const int gf = face_grid(L), gl = grid_for(low_items(L), MAX_LOW_BLOCKS);
-    k_apply<T, false><<<gf + gl, NT, 0, s>>>(L, op, x, nullptr, y, kap_of<T>(M, level), gf, nullptr);
+    k_apply<T, 0><<<gf + gl, NT, 0, s>>>(L, op, x, nullptr, y, kap_of<T>(M, level), gf, nullptr);
     return hipGetLastError();
 }
 
@@ -1164,7 +1221,7 @@ static hipError_t residual_t(const hhg_mesh* M, int level, int op, const T* u, c
                              double* norm, hipStream_t s) {
     const LevelDev L = M->dev(level);
     const int gf = face_grid(L), gl = grid_for(low_items(L), MAX_LOW_BLOCKS);
-    k_apply<T, true><<<gf + gl, NT, 0, s>>>(L, op, u, f, r, kap_of<T>(M, level), gf,
+    k_apply<T, 1><<<gf + gl, NT, 0, s>>>(L, op, u, f, r, kap_of<T>(M, level), gf,
                                             norm ? M->partials : nullptr);
     if (norm) k_reduce_final<<<1, 1024, 0, s>>>(M->partials, gf + gl, norm, 1);
     return hipGetLastError();
@@ -1350,6 +1407,54 @@ hipError_t launch_f64_to_f32(const double* src, float* dst, int64_t n, hipStream
 
 hipError_t launch_add_f32_to_f64(double* u, const float* e, int64_t n, hipStream_t s) {
     k_add_f32_to_f64<<<grid_for(n, 4096), NT, 0, s>>>(u, e, n);
+    return hipGetLastError();
+}
+
+template <class T>
+static hipError_t jacobi_t(const hhg_mesh* M, int level, int op, const T* u, const T* f, T* rho,
+                           hipStream_t s) {
+    const LevelDev L = M->dev(level);
+    const int gf = face_grid(L), gl = grid_for(low_items(L), MAX_LOW_BLOCKS);
+    if (f) k_apply<T, 2><<<gf + gl, NT, 0, s>>>(L, op, u, f, rho, kap_of<T>(M, level), gf, nullptr);
+    else k_apply<T, 3><<<gf + gl, NT, 0, s>>>(L, op, u, nullptr, rho, kap_of<T>(M, level), gf, nullptr);
+    return hipGetLastError();
+}
+
+hipError_t launch_jacobi(const hhg_mesh* M, int level, int op, int dtype, const void* u, const void* f,
+                         void* rho, hipStream_t s) {
+    if (dtype == DT_F64) return jacobi_t<double>(M, level, op, (const double*)u, (const double*)f, (double*)rho, s);
+    return jacobi_t<float>(M, level, op, (const float*)u, (const float*)f, (float*)rho, s);
+}
+
+hipError_t launch_dot(const hhg_mesh* M, int level, int dtype, const void* x, const void* y, double* out,
+                      hipStream_t s) {
+    const LevelDev L = M->dev(level);
+    const int gf = face_grid(L);
+    const int gl = grid_for((int64_t)L.n_iedges * (L.n - 2) + L.n_iverts, MAX_LOW_BLOCKS);
+    if (dtype == DT_F64) k_dot<double><<<gf + gl, NT, 0, s>>>(L, (const double*)x, (const double*)y, gf, M->partials);
+    else k_dot<float><<<gf + gl, NT, 0, s>>>(L, (const float*)x, (const float*)y, gf, M->partials);
+    k_reduce_final<<<1, 1024, 0, s>>>(M->partials, gf + gl, out, 0);
+    return hipGetLastError();
+}
+
+hipError_t launch_axpby(int64_t n, int dtype, double alpha, const void* x, double beta, const void* y,
+                        void* z, hipStream_t s) {
+    const int g = grid_for(n, 4096);
+    if (dtype == DT_F64)
+        k_axpby<double><<<g, NT, 0, s>>>(n, alpha, (const double*)x, beta, (const double*)y, (double*)z);
+    else
+        k_axpby<float><<<g, NT, 0, s>>>(n, (float)alpha, (const float*)x, (float)beta, (const float*)y, (float*)z);
+    return hipGetLastError();
+}
+
+hipError_t launch_low_gs(const hhg_mesh* M, int level, int op, int dtype, void* u, const void* f,
+                         int stage, hipStream_t s) {
+    const LevelDev L = M->dev(level);
+    const int gl = grid_for((int64_t)L.n_iedges * (L.n - 2) + L.n_iverts, MAX_LOW_BLOCKS);
+    if (dtype == DT_F64)
+        k_low_gs<double><<<gl, NT, 0, s>>>(L, op, (double*)u, (const double*)f, M->kap64[level], stage);
+    else
+        k_low_gs<float><<<gl, NT, 0, s>>>(L, op, (float*)u, (const float*)f, M->kap32[level], stage);
     return hipGetLastError();
 }
 

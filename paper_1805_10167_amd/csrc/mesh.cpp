@@ -307,6 +307,14 @@ void MeshData::build_level(int level) {
         for (int tj = 0; tj * GS_TJ <= n - 1; ++tj)
             if (ti * GS_TI + tj * GS_TJ <= n - 1) H.gs_tiles.push_back(make_int2(ti, tj));
 
+    // learned-smoother output tiles that contain interior points
+    H.net_tiles.clear();
+    for (int ti = 0; ti * NET_TI <= n - 3; ++ti)
+        for (int tj = 0; tj * NET_TJ <= n - 3; ++tj) {
+            int imin = std::max(ti * NET_TI, 1), jmin = std::max(tj * NET_TJ, 1);
+            if (imin + jmin <= n - 2) H.net_tiles.push_back(make_int2(ti, tj));
+        }
+
     // ghost table
     std::vector<std::tuple<int, int64_t, int64_t>> ent;
     auto cls_of = [&](const Owner& o) {
