@@ -1,7 +1,7 @@
 """Benchmark of the HHG P1 multigrid hot path on one MI355X.
 
-Workload (N = 1): Poisson -Laplace u = f with P1 elements on the jittered
-64-face annulus r in [0.55, 1], refinement level 10 (1025 points per
+Headline workload (N = 1): Poisson -Laplace u = f with P1 elements on the
+jittered 64-face annulus r in [0.55, 1], refinement level 10 (1025 points per
 macro-edge, 33,538,048 interior unknowns), constant coefficient, uniform
 [-1, 1] right-hand side (seed 1), homogeneous Dirichlet boundary, FP64,
 V(3,3) cycles with the staged multicolour Gauss-Seidel smoother to a relative
@@ -12,8 +12,18 @@ residual, restriction, coarse CG, prolongation, ghost-copy refresh, norms).
 value = whole-job smoother throughput: finest-level interior unknowns times
 the finest-level sweeps the solve performs, divided by the solve's wall time.
 The roofline entry is the finest-level face smoother, timed live with HIP
-events on the launch stream; the mixed-precision solve of the same problem is
-reported beside it.
+events on the launch stream.
+
+Reported beside it (untimed by the step contract, each from its own runs):
+  * the mixed-precision refinement solve of the same problem;
+  * the variable-coefficient problem on the same mesh at level 10, k = exp(g)
+    with g a Gaussian random field: the learned face smoother trained on the
+    GPU at level 7 on 256 coefficient fields, its acceptance against
+    Gauss-Seidel on 8 held-out fields, convergence factors, time to 1e-8 of
+    plain FP64, mixed precision with Gauss-Seidel and with the network, and
+    the live-timed kernels of that path;
+  * plain FP64 against mixed precision on the 128-face annulus at level 11
+    (268,369,920 unknowns) with the final difference of the two solutions.
 """
 import argparse
 import json
@@ -29,6 +39,11 @@ if ROOT not in sys.path:
 
 METRIC = "smoother GDoF/s, % HBM peak; time-to-1e-8 rel. residual plain vs MP/learned"
 HBM_PEAK_GBS = 8000.0
+BF16_PEAK_TFLOPS = 2500.0
+
+
+def log(msg):
+    print("bench: " + msg, file=sys.stderr, flush=True)
 
 
 def face_interior_dofs(F, n):
@@ -58,6 +73,209 @@ def cpu_baseline(level, rtol, nu):
                                                      nu, nu, dt)}
 
 
+def timed_solve(P, g, u, f, mode, op, rtol, nu, max_iters=100):
+    import torch
+    u.zero_()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    rc, st, hist = P.hhg_solve(g.h, u, f, mode=mode, op=op, rtol=rtol, nu1=nu, nu2=nu,
+                               max_iters=max_iters)
+    torch.cuda.synchronize()
+    return (time.perf_counter() - t0) * 1e3, rc, st, hist
+
+
+def face_sweep_rate(P, g, L, launches_ms, bytes_per_dof):
+    """GB/s and GDoF/s of the finest face smoother from hhg_timing."""
+    launches, kern_ms = launches_ms
+    n = 2 ** L + 1
+    nface = face_interior_dofs(g.F, n)
+    avg = kern_ms * 1e-3 / max(launches, 1)
+    return {"launches": launches, "avg_launch_ms": round(avg * 1e3, 5),
+            "gdofs": round(nface / avg / 1e9, 3),
+            "gbs": round(nface * bytes_per_dof / avg / 1e9, 2),
+            "hbm_frac": round(nface * bytes_per_dof / avg / 1e9 / HBM_PEAK_GBS, 4)}
+
+
+def learned_section(args, P, hi, torch):
+    """Variable-coefficient workload: training, acceptance, solves, kernels."""
+    import numpy as np
+
+    from paper_1805_10167_amd import train
+    out = {"workload": "variable-k P1 diffusion, 64-face annulus, level %d, k = exp(g), GRF "
+                       "corr. length 0.1, sigma 1, 512 Fourier features" % args.level}
+    D = P.HHG_OP_DIFFUSION
+    feats = P.HHG_FEAT_F64 | P.HHG_FEAT_MP | P.HHG_FEAT_VARK | P.HHG_FEAT_NET
+    vxy, tri = hi.mesh_by_name("annulus64")
+
+    # training at the coarser level on noise pairs
+    Lt = args.train_level
+    t0 = time.perf_counter()
+    gt = P.Mesh(vxy, tri, Lt, 2, feats)
+    _, nt_all = gt.n_dofs(Lt)
+    xy_t = gt.coords(Lt)
+    kaps = [torch.exp(hi.grf_eval_device(xy_t, s)) for s in range(args.train_fields)]
+    pairs = train.noise_pairs(gt, kaps, lambda s, j: hi.uniform_vector_device(
+        nt_all, 5000 + 100 * s + j), per_field=args.pairs_per_field)
+    torch.cuda.synchronize()
+    t_data = time.perf_counter() - t0
+    w_init = train.jacobi_init()
+    P.hhg_net_set_weights(gt.h, w_init)
+    tr = train.Trainer(pairs, lr=args.lr, batch=4, seed=0)
+    sub = np.random.default_rng(1).choice(len(pairs), min(256, len(pairs)), replace=False)
+    loss0 = tr.mean_loss(sub)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    losses = tr.train(args.train_steps)
+    torch.cuda.synchronize()
+    t_train = time.perf_counter() - t1
+    loss1 = tr.mean_loss(sub)
+    w_net = tr.weights()
+    log("trained %d steps in %.1f s: loss %.4f -> %.4f" % (args.train_steps, t_train, loss0, loss1))
+    out["train"] = {"level": Lt, "fields": args.train_fields, "pairs": len(pairs),
+                    "pair_kind": "noise", "steps": args.train_steps, "batch": 4, "lr": args.lr,
+                    "precision": "bf16 forward (MFMA), fp32 master weights",
+                    "loss_jacobi_init": round(loss0, 5), "loss_trained": round(loss1, 5),
+                    "loss_last100": round(float(np.mean(losses[-100:])), 5),
+                    "data_s": round(t_data, 2), "train_s": round(t_train, 2),
+                    "ms_per_step": round(t_train * 1e3 / args.train_steps, 3)}
+    if args.cycle_pair_check:
+        ncf = min(32, args.train_fields)
+        cp = train.capture_pairs(gt, kaps[:ncf], [hi.uniform_rhs(nt_all, 1000 + s)
+                                                  for s in range(ncf)], cycles=8)
+        P.hhg_net_set_weights(gt.h, w_init)
+        trc = train.Trainer(cp, lr=args.lr, batch=4, seed=0)
+        trc.train(500)
+        w_cyc = trc.weights()
+        del cp, trc
+    del pairs, tr, kaps, gt
+    torch.cuda.empty_cache()
+
+    # evaluation at the benchmark level
+    L = args.level
+    g = P.Mesh(vxy, tri, L, 2, feats)
+    _, n_all = g.n_dofs(L)
+    xy = g.coords(L)
+    seeds = list(range(10000, 10000 + args.eval_fields))
+    ek = [torch.exp(hi.grf_eval_device(xy, s)) for s in seeds]
+    ef = [hi.uniform_rhs(n_all, 1000 + s) for s in seeds]
+    dec = train.accept(g, ek, ef, w_net)
+    rho_init, _ = train.evaluate(g, ek, ef, w_init)
+    out.update({"accepted": dec["accepted"], "guard_tripped": dec["guard_tripped"],
+                "rho_gs_mean": round(dec["rho_gs_mean"], 5),
+                "rho_net_mean": round(dec["rho_net_mean"], 5),
+                "rho_jacobi_init_mean": round(float(rho_init.mean()), 5),
+                "rho_gs": [round(x, 5) for x in dec["rho_gs"]],
+                "rho_net": [round(x, 5) for x in dec["rho_net"]],
+                "eval_fields": len(seeds)})
+    log("acceptance: GS %.4f net %.4f init %.4f accepted %s" % (
+        dec["rho_gs_mean"], dec["rho_net_mean"], rho_init.mean(), dec["accepted"]))
+    if args.cycle_pair_check:
+        d2 = train.accept(g, ek[:2], ef[:2], w_cyc)
+        out["cycle_pair_network"] = {"fields": ncf, "steps": 500, "guard_tripped":
+                                     d2["guard_tripped"], "accepted": d2["accepted"]}
+
+    # time to 1e-8 on the first held-out field
+    P.hhg_set_coefficient(g.h, ek[0])
+    f = g.from_canonical(L, ef[0])
+    u = g.field(L)
+    t2t, its = {}, {}
+    for name, mode in (("plain_fp64", P.HHG_MODE_PLAIN_FP64), ("mp_gs", P.HHG_MODE_MP_IR)):
+        ms = []
+        for _ in range(args.mp_runs):
+            t, rc, st, _ = timed_solve(P, g, u, f, mode, D, 1e-8, 3)
+            assert rc == 0, st
+            ms.append(t)
+        t2t[name], its[name] = round(statistics.median(ms), 3), st["iters"]
+    P.hhg_net_set_weights(g.h, w_net)
+    P.hhg_net_set_options(g.h, P.HHG_BF16, 1)        # the network regardless of the decision
+    ms = []
+    for _ in range(args.mp_runs):
+        t, rc, st, _ = timed_solve(P, g, u, f, P.HHG_MODE_LEARNED, D, 1e-8, 3)
+        ms.append(t)
+    t2t["mp_net"], its["mp_net"] = round(statistics.median(ms), 3), st["iters"]
+    out["mp_net_guard_fallback"] = st["fallback"]
+    P.hhg_net_set_options(g.h, P.HHG_BF16, int(dec["accepted"]))
+    t, rc, st, _ = timed_solve(P, g, u, f, P.HHG_MODE_LEARNED, D, 1e-8, 3)
+    t2t["learned_mode"], its["learned_mode"] = round(t, 3), st["iters"]
+    out["learned_mode_smoother"] = "net" if st["smoother_used"] == P.HHG_SMOOTH_NET else "gs"
+    out["time_to_tol_ms"], out["iterations"] = t2t, its
+
+    # kernels of the path, live: variable-k FP64 face smoother, FP32 net step
+    P.hhg_timing_read(g.h, reset=True)
+    P.hhg_timing_enable(g.h, 1)
+    for _ in range(20):
+        P.hhg_smooth(g.h, L, D, P.HHG_SMOOTH_GS, P.HHG_F64, u, f, 1, 0)
+    P.hhg_timing_enable(g.h, 0)
+    out["vark_face_smoother_fp64"] = face_sweep_rate(P, g, L, P.hhg_timing_read(g.h), 32.0)
+    u32, f32 = g.field(L, P.HHG_F32), g.from_canonical(L, ef[0], P.HHG_F32)
+    rho = g.field(L, P.HHG_F32)
+    n_int = g.n_dofs(L)[0]
+    nface = face_interior_dofs(g.F, 2 ** L + 1)
+
+    def event_ms(fn, reps=20):
+        fn()
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record()
+        for _ in range(reps):
+            fn()
+        b.record()
+        b.synchronize()
+        return a.elapsed_time(b) / reps
+
+    sweep_ms = event_ms(lambda: P.hhg_smooth(g.h, L, D, P.HHG_SMOOTH_NET, P.HHG_F32, u32, f32, 1, 0))
+    jac_ms = event_ms(lambda: P.hhg_jacobi(g.h, L, D, P.HHG_F32, u32, f32, rho))
+    fwd_ms = event_ms(lambda: P.hhg_net_forward(g.h, L, rho, u32))
+    flops = 448.0 * nface
+    out["net_step_fp32"] = {
+        "sweep_ms": round(sweep_ms, 4), "sweep_gdofs": round(n_int / sweep_ms / 1e6, 3),
+        "sweep_hbm_frac_vs_16B": round(n_int * 16.0 / sweep_ms / 1e6 / HBM_PEAK_GBS, 4),
+        "jacobi_ms": round(jac_ms, 4), "forward_ms": round(fwd_ms, 4),
+        "forward_tflops": round(flops / fwd_ms / 1e9, 3),
+        "mfma_frac_of_bf16_peak": round(flops / fwd_ms / 1e9 / BF16_PEAK_TFLOPS, 6),
+        "note": "events around whole calls on torch's stream (the library's launch stream)"}
+    del g, ek, u, f, u32, f32, rho
+    torch.cuda.empty_cache()
+    return out
+
+
+def large_mp_section(args, P, hi, torch):
+    """Plain FP64 against mixed precision on the 128-face annulus."""
+    L = args.large_level
+    vxy, tri = hi.mesh_by_name("annulus128")
+    t0 = time.perf_counter()
+    g = P.Mesh(vxy, tri, L, 2, P.HHG_FEAT_F64 | P.HHG_FEAT_MP)
+    n_int, n_all = g.n_dofs(L)
+    f = g.from_canonical(L, hi.uniform_rhs(n_all, 1))
+    log("large mesh level %d: %d unknowns, setup %.1f s" % (L, n_int, time.perf_counter() - t0))
+    u, ref = g.field(L), g.field(L)
+    out = {"workload": "Poisson P1, 128-face annulus, level %d, uniform RHS seed 1" % L,
+           "interior_dofs": n_int}
+    res = {}
+    for name, mode in (("plain_fp64", P.HHG_MODE_PLAIN_FP64), ("mp_ir", P.HHG_MODE_MP_IR)):
+        ms = []
+        for _ in range(max(1, args.mp_runs)):
+            t, rc, st, _ = timed_solve(P, g, u, f, mode, P.HHG_OP_LAPLACE, 1e-8, 3)
+            assert rc == 0, st
+            ms.append(t)
+        res[name] = (round(statistics.median(ms), 3), st["iters"], st["rel_res"])
+        if name == "plain_fp64":
+            ref.copy_(u)
+    out["time_to_tol_ms"] = {k: v[0] for k, v in res.items()}
+    out["iterations"] = {k: v[1] for k, v in res.items()}
+    out["final_rel_res"] = {k: v[2] for k, v in res.items()}
+    # u (MP) against a plain solve to 1e-12
+    _, rc, st, _ = timed_solve(P, g, ref, f, P.HHG_MODE_PLAIN_FP64, P.HHG_OP_LAPLACE, 1e-12, 3)
+    d = torch.zeros(2, dtype=torch.float64, device="cuda")
+    P.hhg_axpby(g.h, L, P.HHG_F64, 1.0, u, -1.0, ref, u)
+    P.hhg_dot(g.h, L, P.HHG_F64, u, u, d[0:1])
+    P.hhg_dot(g.h, L, P.HHG_F64, ref, ref, d[1:2])
+    dd = d.cpu().numpy()
+    out["mp_rel_err_vs_fp64_1e-12"] = float(math.sqrt(dd[0] / dd[1]))
+    del g, u, ref, f
+    torch.cuda.empty_cache()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -67,15 +285,24 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-level", type=int, default=9)
     ap.add_argument("--mp-runs", type=int, default=3)
+    ap.add_argument("--no-learned", action="store_true")
+    ap.add_argument("--train-level", type=int, default=7)
+    ap.add_argument("--train-fields", type=int, default=256)
+    ap.add_argument("--pairs-per-field", type=int, default=8)
+    ap.add_argument("--train-steps", type=int, default=2000)
+    ap.add_argument("--lr", type=float, default=3e-3)
+    ap.add_argument("--eval-fields", type=int, default=8)
+    ap.add_argument("--cycle-pair-check", type=int, default=1)
+    ap.add_argument("--no-large", action="store_true")
+    ap.add_argument("--large-level", type=int, default=11)
     ap.add_argument("--copy-calibration", type=int, default=0,
                     help="bytes of a plain device copy run after the benchmark (counter scale)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py measures one GPU only: the method's multi-GPU sharding is not part "
-              "of this build (see the design notes); run with --gpus 1", file=sys.stderr)
+        print("bench.py measures one GPU: sharding the macro-faces over several GPUs is "
+              "designed but not implemented; run with --gpus 1", file=sys.stderr)
         sys.exit(2)
 
-    import numpy as np
     import torch
 
     import hhg_inputs as hi
@@ -84,7 +311,7 @@ def main():
     torch.cuda.set_device(0)
     L, nu, rtol = args.level, 3, 1e-8
     vxy, tri = hi.mesh_by_name("annulus64")
-    print("bench: setting up annulus64 level %d" % L, file=sys.stderr, flush=True)
+    log("setting up annulus64 level %d" % L)
     g = P.Mesh(vxy, tri, L, 2, P.HHG_FEAT_F64 | P.HHG_FEAT_MP)
     n_int, n_all = g.n_dofs(L)
     n = 2 ** L + 1
@@ -114,8 +341,7 @@ def main():
     wall = time.perf_counter() - t0
     P.hhg_timing_enable(g.h, 0)
     launches, kern_ms = P.hhg_timing_read(g.h, reset=True)
-    print("bench: %d solves, iters %s, %d face-smoother launches" % (args.steps, iters, launches),
-          file=sys.stderr, flush=True)
+    log("%d solves, iters %s, %d face-smoother launches" % (args.steps, iters, launches))
 
     ms_per_step = wall * 1e3 / args.steps
     sweeps = 2 * nu * statistics.mean(iters)
@@ -143,6 +369,7 @@ def main():
         for _ in range(3):
             dst.copy_(src)
         torch.cuda.synchronize()
+        del src, dst
 
     from paper_1805_10167_amd.profiling import traffic_for
     traffic = traffic_for(os.path.join(ROOT, "profiles", "face_smoother_annulus64_l10.txt"))
@@ -169,9 +396,16 @@ def main():
         out["time_to_tol_ms"]["mp_ir"] = round(statistics.median(mp_times), 3)
         out["iterations"]["mp_ir"] = mp_iters[0]
         out["mp_final_rel_res"] = mp_res[0]
+    del g, u, f
+    torch.cuda.empty_cache()
+    if not args.no_learned:
+        log("learned smoother: training and acceptance")
+        out["learned"] = learned_section(args, P, hi, torch)
+    if not args.no_large:
+        log("plain vs mixed precision on the 128-face annulus")
+        out["mp_large"] = large_mp_section(args, P, hi, torch)
     if not args.no_cpu_baseline:
-        print("bench: timing the CPU oracle at level %d" % args.cpu_level, file=sys.stderr,
-              flush=True)
+        log("timing the CPU oracle at level %d" % args.cpu_level)
         out["cpu_baseline"] = cpu_baseline(args.cpu_level, rtol, nu)
     print(json.dumps(out), flush=True)
 

@@ -80,6 +80,16 @@ def uniform_vector(n, seed, lo=-1.0, hi=1.0):
     return np.random.default_rng(seed).uniform(lo, hi, n)
 
 
+def uniform_vector_device(n, seed, lo=-1.0, hi=1.0, device="cuda"):
+    """n i.i.d. U[lo, hi] FP64 values drawn on the device by torch's seeded
+    generator (for large training sets; reproducible on one device type)."""
+    import torch
+    gen = torch.Generator(device=device)
+    gen.manual_seed(seed)
+    x = torch.rand(n, generator=gen, dtype=torch.float64, device=device)
+    return lo + (hi - lo) * x
+
+
 def grf_draws(seed, m=512, corr_len=0.1):
     """Random draws of a random-Fourier-feature Gaussian random field.
 
@@ -102,6 +112,22 @@ def grf_eval(xy, seed, m=512, corr_len=0.1, sigma=1.0, chunk=1 << 16):
     for s in range(0, len(xy), chunk):
         arg = xy[s:s + chunk] @ omega.T + phi
         out[s:s + chunk] = scale * np.cos(arg).sum(axis=1)
+    return out
+
+
+def grf_eval_device(xy, seed, m=512, corr_len=0.1, sigma=1.0, chunk=1 << 20, device="cuda"):
+    """grf_eval on the GPU (torch, FP64) for large point sets: the same draws
+    and formula, summed in another order (differences at rounding level)."""
+    import torch
+    omega, phi = grf_draws(seed, m, corr_len)
+    om = torch.tensor(omega.T.copy(), dtype=torch.float64, device=device)
+    ph = torch.tensor(phi, dtype=torch.float64, device=device)
+    xy = torch.as_tensor(xy, dtype=torch.float64).to(device)
+    out = torch.empty(len(xy), dtype=torch.float64, device=device)
+    scale = sigma * math.sqrt(2.0 / m)
+    for s in range(0, len(xy), chunk):
+        arg = xy[s:s + chunk] @ om + ph
+        out[s:s + chunk] = scale * torch.cos(arg).sum(dim=1)
     return out
 
 

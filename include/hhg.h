@@ -266,6 +266,37 @@ int hhg_axpby(const hhg_mesh* mesh, int32_t level, int32_t dtype, double alpha,
               const void* x, double beta, const void* y, void* z, void* stream);
 
 /*
+ * Full-weighting restriction fc = R r from `level` to level - 1 (sec. 4.3:
+ * the transpose of linear interpolation, weight 1 at the coincident point and
+ * 1/2 at each of its six fine neighbours), 0 at coarse Dirichlet points,
+ * every copy of fc written.  r must carry consistent copies (every library
+ * call leaves its outputs so).  2 <= level <= max_level; fc is a field of
+ * level - 1 and must not alias r.
+ */
+int hhg_restrict(const hhg_mesh* mesh, int32_t level, int32_t dtype,
+                 const void* r, void* fc, void* stream);
+
+/*
+ * u += P uc on `level`: linear interpolation of the level - 1 field uc
+ * (sec. 4.3: coarse points are copied, new points on a coarse edge take
+ * the mean of its two ends), added on interior points; Dirichlet entries of
+ * u are left alone and every copy of u is refreshed.  2 <= level <=
+ * max_level.
+ */
+int hhg_prolong_add(const hhg_mesh* mesh, int32_t level, int32_t dtype,
+                    const void* uc, void* u, void* stream);
+
+/*
+ * Whole-field precision change dst = (dst_dtype) src on `level` (FP64 to
+ * FP32 rounds to nearest even; FP32 to FP64 is exact), the conversion the
+ * mixed-precision refinement loop applies to residuals and corrections
+ * (sec. 5: FP32 inner cycles under FP64 accuracy).  Only F64 <-> F32;
+ * src and dst must not overlap.
+ */
+int hhg_convert(const hhg_mesh* mesh, int32_t level, int32_t src_dtype,
+                const void* src, int32_t dst_dtype, void* dst, void* stream);
+
+/*
  * Learned face smoother (not part of the paper; a smoother variant layered
  * on the method).  N(rho) = HexConv(16->1)(ReLU(HexConv(1->16)(rho))) with
  * 7-tap kernels over the offsets C, E, W, N, S, SE, NW of face-local (i, j),

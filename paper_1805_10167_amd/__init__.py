@@ -26,6 +26,7 @@ class Mesh:
         self._destroy = lib().hhg_destroy_mesh   # kept alive for interpreter exit
         self.L = max_level
         self.lc = coarse_level
+        self.F = len(tri)
         self.features = features
         self.device = device
         nbytes = hhg_workspace_bytes(self.h, features)

@@ -59,6 +59,9 @@ _SIGS = {
     "hhg_jacobi": (_c.c_int, [_vp, _i32, _i32, _i32, _vp, _vp, _vp, _vp]),
     "hhg_dot": (_c.c_int, [_vp, _i32, _i32, _vp, _vp, _vp, _vp]),
     "hhg_axpby": (_c.c_int, [_vp, _i32, _i32, _c.c_double, _vp, _c.c_double, _vp, _vp, _vp]),
+    "hhg_convert": (_c.c_int, [_vp, _i32, _i32, _vp, _i32, _vp, _vp]),
+    "hhg_restrict": (_c.c_int, [_vp, _i32, _i32, _vp, _vp, _vp]),
+    "hhg_prolong_add": (_c.c_int, [_vp, _i32, _i32, _vp, _vp, _vp]),
     "hhg_net_set_weights": (_c.c_int, [_vp, _vp, _i32, _vp]),
     "hhg_net_get_weights": (_c.c_int, [_vp, _vp, _i32, _vp]),
     "hhg_net_set_options": (_c.c_int, [_vp, _i32, _i32]),
@@ -227,6 +230,18 @@ def hhg_dot(h, level, dtype, x, y, out, stream=None):
 def hhg_axpby(h, level, dtype, alpha, x, beta, y, z, stream=None):
     _check(lib().hhg_axpby(h, level, dtype, alpha, _ptr(x), beta, _ptr(y), _ptr(z),
                            _stream(stream)))
+
+
+def hhg_restrict(h, level, dtype, r, fc, stream=None):
+    _check(lib().hhg_restrict(h, level, dtype, _ptr(r), _ptr(fc), _stream(stream)))
+
+
+def hhg_prolong_add(h, level, dtype, uc, u, stream=None):
+    _check(lib().hhg_prolong_add(h, level, dtype, _ptr(uc), _ptr(u), _stream(stream)))
+
+
+def hhg_convert(h, level, src_dtype, src, dst_dtype, dst, stream=None):
+    _check(lib().hhg_convert(h, level, src_dtype, _ptr(src), dst_dtype, _ptr(dst), _stream(stream)))
 
 
 def hhg_net_set_weights(h, w, stream=None):

@@ -651,6 +651,40 @@ int hhg_axpby(const hhg_mesh* M, int32_t level, int32_t dtype, double alpha, con
     return HHG_OK;
 }
 
+int hhg_restrict(const hhg_mesh* M, int32_t level, int32_t dtype, const void* r, void* fc, void* stream) {
+    int rc = check_common(M, level, dtype);
+    if (rc) return rc;
+    if (level < 2) return fail(HHG_EINVAL, "restriction needs level >= 2");
+    if (!r || !fc || r == fc) return fail(HHG_EINVAL, "bad buffers");
+    HIP_CHECK(launch_restrict(M, level, dtype, r, fc, nullptr, (hipStream_t)stream), "restrict");
+    return HHG_OK;
+}
+
+int hhg_prolong_add(const hhg_mesh* M, int32_t level, int32_t dtype, const void* uc, void* u, void* stream) {
+    int rc = check_common(M, level, dtype);
+    if (rc) return rc;
+    if (level < 2) return fail(HHG_EINVAL, "prolongation needs level >= 2");
+    if (!uc || !u || uc == u) return fail(HHG_EINVAL, "bad buffers");
+    HIP_CHECK(launch_prolong_add(M, level, dtype, uc, u, (hipStream_t)stream), "prolong");
+    return HHG_OK;
+}
+
+int hhg_convert(const hhg_mesh* M, int32_t level, int32_t src_dtype, const void* src, int32_t dst_dtype,
+                void* dst, void* stream) {
+    int rc = check_common(M, level, src_dtype);
+    if (rc) return rc;
+    if (!src || !dst) return fail(HHG_EINVAL, "null buffer");
+    const int64_t n = M->m.lv[level].total;
+    hipStream_t s = (hipStream_t)stream;
+    if (src_dtype == HHG_F64 && dst_dtype == HHG_F32)
+        HIP_CHECK(launch_f64_to_f32((const double*)src, (float*)dst, n, s), "convert");
+    else if (src_dtype == HHG_F32 && dst_dtype == HHG_F64)
+        HIP_CHECK(launch_f32_to_f64((const float*)src, (double*)dst, n, s), "convert");
+    else
+        return fail(HHG_EINVAL, "only F64 <-> F32 conversions");
+    return HHG_OK;
+}
+
 static int check_net(const hhg_mesh* M) {
     if (!M) return fail(HHG_EINVAL, "null mesh");
     if (!M->bound) return fail(HHG_ENOMEM, "no workspace bound");

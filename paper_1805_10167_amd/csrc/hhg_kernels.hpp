@@ -45,6 +45,7 @@ hipError_t launch_inject(const hhg_mesh* M, int level, int dtype, const void* kf
                          hipStream_t s);
 // Elementwise conversions over whole fields.
 hipError_t launch_f64_to_f32(const double* src, float* dst, int64_t n, hipStream_t s);
+hipError_t launch_f32_to_f64(const float* src, double* dst, int64_t n, hipStream_t s);
 hipError_t launch_add_f32_to_f64(double* u, const float* e, int64_t n, hipStream_t s);
 
 // One Gauss-Seidel stage on edges and vertices (0: A, 1: B), copies written.

@@ -1153,6 +1153,12 @@ __global__ __launch_bounds__(NT) void k_f64_to_f32(const double* __restrict__ s,
         d[t] = (float)s[t];
 }
 
+__global__ __launch_bounds__(NT) void k_f32_to_f64(const float* __restrict__ s, double* __restrict__ d,
+                                                   int64_t n) {
+    for (int64_t t = blockIdx.x * (int64_t)NT + threadIdx.x; t < n; t += (int64_t)gridDim.x * NT)
+        d[t] = (double)s[t];
+}
+
 __global__ __launch_bounds__(NT) void k_add_f32_to_f64(double* __restrict__ u, const float* __restrict__ e,
                                                        int64_t n) {
     for (int64_t t = blockIdx.x * (int64_t)NT + threadIdx.x; t < n; t += (int64_t)gridDim.x * NT)
@@ -1307,7 +1313,7 @@ template <class T>
 static hipError_t restrict_t(const hhg_mesh* M, int level, const T* r, T* fc, T* uc, hipStream_t s) {
     const LevelDev Lf = M->dev(level), Lc = M->dev(level - 1);
     const int gf = face_grid(Lc), gl = gf + grid_for(low_items(Lc), MAX_LOW_BLOCKS);
-    const int gz = grid_for(Lc.total, 2048);
+    const int gz = uc ? grid_for(Lc.total, 2048) : 0;
     k_restrict<T><<<gl + gz, NT, 0, s>>>(Lf, Lc, r, fc, uc, Lc.total, gf, gl);
     return hipGetLastError();
 }
@@ -1402,6 +1408,11 @@ hipError_t launch_inject(const hhg_mesh* M, int level, int dtype, const void* kf
 
 hipError_t launch_f64_to_f32(const double* src, float* dst, int64_t n, hipStream_t s) {
     k_f64_to_f32<<<grid_for(n, 4096), NT, 0, s>>>(src, dst, n);
+    return hipGetLastError();
+}
+
+hipError_t launch_f32_to_f64(const float* src, double* dst, int64_t n, hipStream_t s) {
+    k_f32_to_f64<<<grid_for(n, 4096), NT, 0, s>>>(src, dst, n);
     return hipGetLastError();
 }
 
