@@ -5,9 +5,9 @@ TEST INFRASTRUCTURE ONLY (see the package docstring).
 The paper (sec. 4.3) names the ingredients: pointwise smoothers that use the
 diagonal, Gauss-Seidel needing a global update order (sec. 2.4) realised as a
 multicolour Gauss-Seidel (sec. 3.2), interpolation and restriction as
-non-square matrix-vector products, Krylov solvers (PCG) on the coarse grid,
-and multigrid as a solver.  It fixes none of the parameters; the readings
-used here are:
+non-square matrix-vector products, Krylov or direct solvers on the coarse
+grid, and multigrid as a solver.  It fixes none of the parameters; the
+readings used here are:
 
   * smoother stages, each updated simultaneously: A = interior macro-vertices
     and even-k edge points, B = odd-k edge points, then face colours
@@ -18,13 +18,16 @@ used here are:
     coincident point, 1/2 at each neighbour);
   * residual, correction and coarse right-hand side are zero at Dirichlet
     points;
-  * coarse solve: CG with Jacobi preconditioner from zero, stopping when
-    |r| <= 1e-14 |b| or after 4 N iterations;
+  * coarse solve: direct (the exact solution of the coarse interior system,
+    by a sparse LU factorisation) by default; the Krylov alternative is CG
+    with Jacobi preconditioner from zero, stopping when |r| <= 1e-14 |b| or
+    after 4 N iterations;
   * solve loop: relative residual |f - A u| / |f - A u0| over interior points
     after every cycle.
 """
 import numpy as np
 import scipy.sparse as sp
+import scipy.sparse.linalg as spla
 
 from .assemble import assemble, inject
 from .mesh import Level
@@ -129,12 +132,16 @@ class Hierarchy:
     """All levels lc..L of one macro mesh with their operators.
 
     op: "laplace" (k = 1) or "diffusion" (nodal k at the finest level,
-    injected to coarser levels)."""
+    injected to coarser levels).  coarse: "direct" or "pcg" (sec. 4.3 allows
+    either on the coarse grid)."""
 
-    def __init__(self, mesh, L, lc=2, kappa_fine=None):
+    def __init__(self, mesh, L, lc=2, kappa_fine=None, coarse="direct"):
         self.mesh = mesh
         self.L = L
         self.lc = lc
+        if coarse not in ("direct", "pcg"):
+            raise ValueError(coarse)
+        self.coarse = coarse
         self.levels = {l: Level(mesh, l) for l in range(lc, L + 1)}
         self.kappa = {}
         if kappa_fine is not None:
@@ -157,6 +164,7 @@ class Hierarchy:
         lvc = self.levels[lc]
         ic = lvc.interior
         self.A_coarse = self.A[lc][ic][:, ic].tocsr()
+        self._lu = spla.splu(self.A_coarse.tocsc()) if coarse == "direct" else None
 
     # ---- Alg. 3 semantics: y = A x on interior rows, 0 on Dirichlet rows
     def apply(self, l, x, op="A"):
@@ -196,10 +204,15 @@ class Hierarchy:
         return u
 
     def coarse_solve(self, u, f):
-        """u += CG(A_int, (f - A u)_int) on the coarsest level."""
+        """u += A_int^-1 (f - A u)_int on the coarsest level (exactly, or by
+        PCG); returns the PCG iterations (0 for the direct solve)."""
         lvc = self.levels[self.lc]
         r = self.residual(self.lc, u, f)
-        x, it = pcg_jacobi(self.A_coarse, r[lvc.interior])
+        b = r[lvc.interior]
+        if self._lu is not None:
+            x, it = self._lu.solve(b), 0
+        else:
+            x, it = pcg_jacobi(self.A_coarse, b)
         u[lvc.interior] += x
         return it
 

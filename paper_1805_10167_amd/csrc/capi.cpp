@@ -65,6 +65,13 @@ void carve(hhg_mesh* M, uint32_t feat, Carver& c) {
     C.cols = (const int32_t*)c.take(sizeof(int32_t) * NW);
     C.vals = (double*)c.take(sizeof(double) * NW);                  // Laplace
     M->coarse_vals_diff = (double*)c.take(sizeof(double) * NW);     // diffusion
+    M->coarse_inv[0] = M->coarse_inv[1] = nullptr;
+    M->inv_ok[0] = M->inv_ok[1] = false;
+    if (m.Nc > 0 && m.Nc <= COARSE_DENSE_MAXN) {
+        const size_t NN = (size_t)m.Nc * m.Nc;
+        M->coarse_inv[0] = (double*)c.take(sizeof(double) * NN);
+        if (feat & HHG_FEAT_VARK) M->coarse_inv[1] = (double*)c.take(sizeof(double) * NN);
+    }
     C.vec = (double*)c.take(sizeof(double) * 5 * (size_t)m.Nc);
     M->n_partials = 8192 + 1024;
     M->partials = (double*)c.take(sizeof(double) * M->n_partials);
@@ -459,6 +466,7 @@ int hhg_set_coefficient(hhg_mesh* M, const double* k_canon, void* stream) {
             HIP_CHECK(launch_f64_to_f32(M->kap64[l], M->kap32[l], M->m.lv[l].total, s), "coefficient f32");
     M->kappa_set = true;
     HIP_CHECK(launch_coarse_extract(M, OP_DIFFUSION, M->coarse_vals_diff, s), "coarse operator");
+    M->inv_ok[1] = false;
     return HHG_OK;
 }
 

@@ -26,6 +26,7 @@ constexpr int GS_TJ = 24;
 // learned-smoother tile: NET_TI x NET_TJ output points
 constexpr int NET_TI = 60;
 constexpr int NET_TJ = 12;
+constexpr int COARSE_DENSE_MAXN = 2048;   // coarse systems solved with a stored inverse
 constexpr int NET_NW = 224;     // weights: W1[16][7] then W2[16][7]
 
 inline int64_t pad_up(int64_t x, int64_t p) { return (x + p - 1) / p * p; }

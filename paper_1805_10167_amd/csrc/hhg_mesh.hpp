@@ -92,6 +92,10 @@ struct hhg_mesh {
     int32_t* d_iverts = nullptr;
     hhg::CoarseDev coarse{};              // vals: Laplace operator
     double* coarse_vals_diff = nullptr;   // diffusion operator
+    // explicit inverses of the coarse interior operator (Laplace, diffusion),
+    // rebuilt on the GPU before the first coarse solve after a change
+    double* coarse_inv[2] = {nullptr, nullptr};
+    mutable bool inv_ok[2] = {false, false};
     // fields per level (index = level); finest-level u, f come from the caller
     void* u64[hhg::MAXLEVEL + 1] = {};
     void* f64[hhg::MAXLEVEL + 1] = {};

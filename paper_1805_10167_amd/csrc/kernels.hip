@@ -1067,17 +1067,16 @@ __device__ __forceinline__ void block_sum2(double& a, double& b, double* sm) {
 // Register-resident Jacobi-PCG for coarse systems with N <= CG_RPT * 1024
 // rows and at most CG_W stencil entries per row.  Each thread owns rows
 // tid + k * blockDim.x; only the search direction is shared (LDS).  Same
-// recurrences and stopping rule as k_coarse_pcg.
+// recurrences and stopping rule as k_coarse_pcg.  rhs(a) gives b[a]; out(a,
+// x) receives the solution row by row (not called when b = 0).
 constexpr int CG_RPT = 2;
 constexpr int CG_W = 8;
 constexpr int CG_MAXN = CG_RPT * 1024;
+static_assert(CG_MAXN == COARSE_DENSE_MAXN, "coarse inverse size bound");
 
-template <class T>
-__global__ __launch_bounds__(1024) void k_coarse_pcg_reg(CoarseDev C, const double* __restrict__ vals,
-                                                         const T* __restrict__ rf, T* __restrict__ uf,
-                                                         double tol, int maxit) {
-    __shared__ double ps[CG_MAXN];
-    __shared__ double sm[2 * (1024 / 64) + 2];
+template <class Rhs, class Out>
+__device__ __forceinline__ void pcg_reg_core(const CoarseDev& C, const double* __restrict__ vals, Rhs rhs,
+                                             Out out, double tol, int maxit, double* ps, double* sm) {
     const int N = C.N, W = C.W, nt = blockDim.x, tid = threadIdx.x;
     double x[CG_RPT], r[CG_RPT], z[CG_RPT], p[CG_RPT], dinv[CG_RPT], av[CG_RPT][CG_W];
     int ac[CG_RPT][CG_W];
@@ -1087,7 +1086,7 @@ __global__ __launch_bounds__(1024) void k_coarse_pcg_reg(CoarseDev C, const doub
         const int a = tid + k * nt;
         const bool own = a < N;
         x[k] = 0.0;
-        r[k] = own ? (double)rf[C.owner[a]] : 0.0;
+        r[k] = own ? rhs(a) : 0.0;
         dinv[k] = own ? 1.0 / vals[(int64_t)a * W] : 0.0;
 #pragma unroll
         for (int w = 0; w < CG_W; ++w) {
@@ -1143,7 +1142,80 @@ __global__ __launch_bounds__(1024) void k_coarse_pcg_reg(CoarseDev C, const doub
 #pragma unroll
     for (int k = 0; k < CG_RPT; ++k) {
         const int a = tid + k * nt;
-        if (a < N) uf[C.owner[a]] += (T)x[k];
+        if (a < N) out(a, x[k]);
+    }
+}
+
+template <class T>
+__global__ __launch_bounds__(1024) void k_coarse_pcg_reg(CoarseDev C, const double* __restrict__ vals,
+                                                         const T* __restrict__ rf, T* __restrict__ uf,
+                                                         double tol, int maxit) {
+    __shared__ double ps[CG_MAXN];
+    __shared__ double sm[2 * (1024 / 64) + 2];
+    pcg_reg_core(C, vals, [&](int a) { return (double)rf[C.owner[a]]; },
+                 [&](int a, double x) { uf[C.owner[a]] += (T)x; }, tol, maxit, ps, sm);
+}
+
+// Row j of the coarse inverse (block j): PCG on A x = e_j; inv[j N + a] =
+// x[a] = (A^-1)[a][j].
+__global__ __launch_bounds__(1024) void k_coarse_inverse(CoarseDev C, const double* __restrict__ vals,
+                                                         double* __restrict__ inv, double tol, int maxit) {
+    __shared__ double ps[CG_MAXN];
+    __shared__ double sm[2 * (1024 / 64) + 2];
+    const int j = blockIdx.x;
+    double* row = inv + (int64_t)j * C.N;
+    pcg_reg_core(C, vals, [&](int a) { return a == j ? 1.0 : 0.0; },
+                 [&](int a, double x) { row[a] = x; }, tol, maxit, ps, sm);
+}
+
+// Direct coarse solve with the stored inverse, in two launches: x = A^-1 b,
+// then one refinement step x += A^-1 (b - A x) and u[owner] += x, with b
+// read from the residual field.  The refinement makes the result exact to
+// rounding although the inverse comes from an iterative solve.  One wave
+// per row: it reads the row of the (symmetric) inverse coalesced, multiplies
+// with the vector held in LDS and reduces in a fixed order.
+constexpr int CD_NT = 256;
+
+__device__ __forceinline__ double coarse_row_dot(const double* __restrict__ row, const double* v, int N) {
+    double s = 0.0;
+    for (int j = threadIdx.x & 63; j < N; j += 64) s += row[j] * v[j];
+    return wave_sum(s);
+}
+
+template <class T>
+__global__ __launch_bounds__(CD_NT) void k_coarse_dense1(CoarseDev C, const double* __restrict__ inv,
+                                                         const T* __restrict__ rf, double* __restrict__ xbuf) {
+    __shared__ double bs[CG_MAXN];
+    const int N = C.N;
+    for (int a = threadIdx.x; a < N; a += CD_NT) bs[a] = (double)rf[C.owner[a]];
+    __syncthreads();
+    const int nw = gridDim.x * (CD_NT / 64);
+    for (int a = blockIdx.x * (CD_NT / 64) + (threadIdx.x >> 6); a < N; a += nw) {
+        const double s = coarse_row_dot(inv + (int64_t)a * N, bs, N);
+        if ((threadIdx.x & 63) == 0) xbuf[a] = s;
+    }
+}
+
+template <class T>
+__global__ __launch_bounds__(CD_NT) void k_coarse_dense2(CoarseDev C, const double* __restrict__ vals,
+                                                         const double* __restrict__ inv,
+                                                         const T* __restrict__ rf,
+                                                         const double* __restrict__ xbuf, T* __restrict__ uf) {
+    __shared__ double rs[CG_MAXN];
+    const int N = C.N, W = C.W;
+    for (int a = threadIdx.x; a < N; a += CD_NT) {
+        double s = (double)rf[C.owner[a]];
+        for (int w = 0; w < W; ++w) {
+            const int c = C.cols[(int64_t)a * W + w];
+            if (c >= 0) s -= vals[(int64_t)a * W + w] * xbuf[c];
+        }
+        rs[a] = s;
+    }
+    __syncthreads();
+    const int nw = gridDim.x * (CD_NT / 64);
+    for (int a = blockIdx.x * (CD_NT / 64) + (threadIdx.x >> 6); a < N; a += nw) {
+        const double s = coarse_row_dot(inv + (int64_t)a * N, rs, N);
+        if ((threadIdx.x & 63) == 0) uf[C.owner[a]] += (T)(xbuf[a] + s);
     }
 }
 
@@ -1360,7 +1432,19 @@ static hipError_t coarse_t(const hhg_mesh* M, int op, T* u, const T* f, const do
     hipError_t e = residual_t<T>(M, lc, op, u, f, r, nullptr, s);
     if (e != hipSuccess) return e;
     const int N = M->coarse.N;
-    if (N <= CG_MAXN && M->coarse.W <= CG_W) {
+    const int which = vals == M->coarse.vals ? 0 : 1;
+    double* inv = M->coarse_inv[which];
+    if (N > 0 && inv && N <= CG_MAXN && M->coarse.W <= CG_W) {
+        int nt = (N + CG_RPT - 1) / CG_RPT;
+        nt = (nt + 63) / 64 * 64;
+        if (!M->inv_ok[which]) {
+            k_coarse_inverse<<<N, nt, 0, s>>>(M->coarse, vals, inv, 1e-14, 4 * N);
+            M->inv_ok[which] = true;
+        }
+        const int nb = std::min((N + CD_NT / 64 - 1) / (CD_NT / 64), 512);
+        k_coarse_dense1<T><<<nb, CD_NT, 0, s>>>(M->coarse, inv, r, M->coarse.vec);
+        k_coarse_dense2<T><<<nb, CD_NT, 0, s>>>(M->coarse, vals, inv, r, M->coarse.vec, u);
+    } else if (N <= CG_MAXN && M->coarse.W <= CG_W) {
         int nt = (N + CG_RPT - 1) / CG_RPT;
         nt = (nt + 63) / 64 * 64;
         k_coarse_pcg_reg<T><<<1, nt, 0, s>>>(M->coarse, vals, r, u, 1e-14, 4 * N);

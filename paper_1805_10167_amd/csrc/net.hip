@@ -32,17 +32,18 @@ __constant__ int c_dj[7] = {0, 0, 0, 1, -1, -1, 1};
 
 typedef short short4v __attribute__((ext_vector_type(4)));
 typedef float float4v __attribute__((ext_vector_type(4)));
+typedef float float2v __attribute__((ext_vector_type(2)));
+typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
+typedef __bf16 bf16x4 __attribute__((ext_vector_type(4)));
 
-// Round to nearest even BF16 (bit pattern), finite inputs.
-__device__ __forceinline__ short to_bf16(float x) {
-    uint32_t b = __float_as_uint(x);
-    b += 0x7FFFu + ((b >> 16) & 1u);
-    return (short)(b >> 16);
+// Round to nearest even BF16 (the hardware conversion).
+__device__ __forceinline__ short4v to_bf16x4(float a, float b, float c, float d) {
+    const bf16x2 lo = __builtin_convertvector((float2v){a, b}, bf16x2);
+    const bf16x2 hi = __builtin_convertvector((float2v){c, d}, bf16x2);
+    const bf16x4 v = {lo[0], lo[1], hi[0], hi[1]};
+    return __builtin_bit_cast(short4v, v);
 }
-__device__ __forceinline__ float from_bf16(short s) {
-    return __uint_as_float(((uint32_t)(uint16_t)s) << 16);
-}
-__device__ __forceinline__ float bf16_round(float x) { return from_bf16(to_bf16(x)); }
+__device__ __forceinline__ float bf16_round(float x) { return (float)(__bf16)x; }
 
 __device__ __forceinline__ int nrow_start(int n, int j) {
     const auto S = [](int N) { const int q = N >> 4, t = N & 15; return 8 * q * (q + 1) + t * (q + 1); };
@@ -56,54 +57,61 @@ __device__ __forceinline__ int64_t nedge_ghost(const LevelDev& L, int e, int s) 
     return L.edge_base + (int64_t)e * L.edge_stride + L.ghost_off + (int64_t)s * L.ghost_stride;
 }
 
-// rho over the tile grown by 2 (zero outside the triangle)
-template <class T>
-__device__ __forceinline__ void net_load_rho(const LevelDev& L, int64_t fb, int i0, int j0,
-                                             const T* __restrict__ rho, float (*rs)[NRW]) {
-    const int n = L.n;
-    for (int idx = threadIdx.x; idx < NRR * NRW; idx += NET_NT) {
-        const int r = idx / NRW, c = idx - r * NRW;
-        const int j = j0 - 2 + r, i = i0 - 2 + c;
-        float v = 0.f;
-        if (j >= 0 && j < n && i >= 0 && i <= n - 1 - j) v = (float)rho[fb + nrow_start(n, j) + i];
-        rs[r][c] = v;
-    }
-}
+// z_t over the tile grown by 1: MFMA (BF16) or FP32 arithmetic.  Each wave
+// takes groups of 16 hidden pixels; two groups per trip give the scheduler
+// independent MFMA chains to interleave.
+constexpr int NGRP = (NPX + 15) / 16;
+constexpr int NWV = NET_NT / 64;
+constexpr int GPW = (NGRP + NWV - 1) / NWV;
 
-// z_t over the tile grown by 1: MFMA (BF16) or FP32 arithmetic.
 template <bool MFMA>
 __device__ __forceinline__ void net_hidden(int n, int i0, int j0, const float* __restrict__ W,
                                            float (*rs)[NRW], float (*zs)[NPX]) {
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     if (MFMA) {
         const int q4 = lane >> 4, l16 = lane & 15;
-        short4v w1op, w2op;
+        float a1[4], a2[4];
+#pragma unroll
         for (int e = 0; e < 4; ++e) {
             const int t = 4 * q4 + e;
-            w1op[e] = t < 7 ? to_bf16(W[l16 * 7 + t]) : (short)0;           // A[c = l16][k = t]
-            w2op[e] = l16 < 7 ? to_bf16(W[112 + t * 7 + l16]) : (short)0;    // B[k = c = t][n = tap l16]
+            a1[e] = t < 7 ? W[l16 * 7 + t] : 0.f;            // A[c = l16][k = t]
+            a2[e] = l16 < 7 ? W[112 + t * 7 + l16] : 0.f;     // B[k = c = t][n = tap l16]
         }
-        for (int g = wv; g * 16 < NPX; g += NET_NT / 64) {
+        const short4v w1op = to_bf16x4(a1[0], a1[1], a1[2], a1[3]);
+        const short4v w2op = to_bf16x4(a2[0], a2[1], a2[2], a2[3]);
+        int di[4], dj[4];
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+            const int t = 4 * q4 + e;
+            di[e] = t < 7 ? c_di[t] : 0;
+            dj[e] = t < 7 ? c_dj[t] : 0;
+        }
+#pragma unroll 2
+        for (int it = 0; it < GPW; ++it) {
+            const int g = wv + NWV * it;
+            if (g >= NGRP) break;
             const int px = g * 16 + l16;
-            const int rr = px / NZ, cc = px - rr * NZ;
-            short4v bop;
+            const int pxc = px < NPX ? px : NPX - 1;
+            const int rr = pxc / NZ, cc = pxc - rr * NZ;
+            float v[4];
+#pragma unroll
             for (int e = 0; e < 4; ++e) {
-                const int t = 4 * q4 + e;
-                float v = 0.f;
-                if (t < 7 && px < NPX) v = rs[rr + 1 + c_dj[t]][cc + 1 + c_di[t]];
-                bop[e] = to_bf16(v);
+                const float x = rs[rr + 1 + dj[e]][cc + 1 + di[e]];
+                v[e] = (4 * q4 + e < 7) ? x : 0.f;
             }
             float4v acc = {0.f, 0.f, 0.f, 0.f};
-            acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(w1op, bop, acc, 0, 0, 0);
+            acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(w1op, to_bf16x4(v[0], v[1], v[2], v[3]),
+                                                            acc, 0, 0, 0);
             // lane holds a for channels 4 q4 + e of pixel l16: ReLU on interior
             const int j = j0 - 1 + rr, i = i0 - 1 + cc;
             const bool inner = px < NPX && j >= 1 && i >= 1 && i + j <= n - 2;
-            short4v hop;
-            for (int e = 0; e < 4; ++e) hop[e] = to_bf16(inner ? fmaxf(acc[e], 0.f) : 0.f);
+            const short4v hop = to_bf16x4(inner ? fmaxf(acc[0], 0.f) : 0.f, inner ? fmaxf(acc[1], 0.f) : 0.f,
+                                          inner ? fmaxf(acc[2], 0.f) : 0.f, inner ? fmaxf(acc[3], 0.f) : 0.f);
             float4v z = {0.f, 0.f, 0.f, 0.f};
             z = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(hop, w2op, z, 0, 0, 0);
             // lane holds z for tap l16 of pixels 4 q4 + e
             if (l16 < 7)
+#pragma unroll
                 for (int e = 0; e < 4; ++e) {
                     const int p2 = g * 16 + 4 * q4 + e;
                     if (p2 < NPX) zs[l16][p2] = z[e];
@@ -130,7 +138,12 @@ __device__ __forceinline__ void net_hidden(int n, int i0, int j0, const float* _
 
 // out = N(rho) on face-interior points (mode 0: write out, whose other
 // entries the caller has zeroed; mode 1: u += N(rho) in place).  Both write
-// the near-edge-row copies of what they change.
+// the near-edge-row copies of what they change.  All global loads of a
+// thread are issued together: rho for the LDS tile, then (mode 1) the
+// outputs' old values, which arrive while the MFMA phase runs.
+constexpr int NLD = (NRR * NRW + NET_NT - 1) / NET_NT;
+constexpr int NOUT = (NET_TI * NET_TJ + NET_NT - 1) / NET_NT;
+
 template <class T, bool MFMA>
 __global__ __launch_bounds__(NET_NT) void k_net_forward(LevelDev L, const T* __restrict__ rho,
                                                         T* __restrict__ y, const float* __restrict__ W,
@@ -143,25 +156,53 @@ __global__ __launch_bounds__(NET_NT) void k_net_forward(LevelDev L, const T* __r
     const int i0 = tl.x * NET_TI, j0 = tl.y * NET_TJ;
     const FaceInfo& fi = L.faces[face];
     const int64_t fb = nface_base(L, face);
-    net_load_rho<T>(L, fb, i0, j0, rho, rs);
+    float v[NLD];
+#pragma unroll
+    for (int k = 0; k < NLD; ++k) {
+        const int idx = threadIdx.x + k * NET_NT;
+        const int r = idx / NRW, c = idx - r * NRW;
+        const int j = j0 - 2 + r, i = i0 - 2 + c;
+        v[k] = 0.f;
+        if (idx < NRR * NRW && j >= 0 && j < n && i >= 0 && i <= n - 1 - j)
+            v[k] = (float)rho[fb + nrow_start(n, j) + i];
+    }
+    int64_t po[NOUT];
+    float yo[NOUT];
+#pragma unroll
+    for (int k = 0; k < NOUT; ++k) {
+        const int idx = threadIdx.x + k * NET_NT;
+        const int rr = idx / NET_TI, cc = idx - rr * NET_TI;
+        const int j = j0 + rr, i = i0 + cc;
+        const bool ok = idx < NET_TI * NET_TJ && j >= 1 && i >= 1 && i + j <= n - 2;
+        po[k] = ok ? fb + nrow_start(n, j) + i : -1;
+        yo[k] = 0.f;
+        if (ok && mode == 1) yo[k] = (float)y[po[k]];
+    }
+#pragma unroll
+    for (int k = 0; k < NLD; ++k) {
+        const int idx = threadIdx.x + k * NET_NT;
+        if (idx < NRR * NRW) rs[idx / NRW][idx % NRW] = v[k];
+    }
     __syncthreads();
     net_hidden<MFMA>(n, i0, j0, W, rs, zs);
     __syncthreads();
-    for (int idx = threadIdx.x; idx < NET_TI * NET_TJ; idx += NET_NT) {
+#pragma unroll
+    for (int k = 0; k < NOUT; ++k) {
+        if (po[k] < 0) continue;
+        const int idx = threadIdx.x + k * NET_NT;
         const int rr = idx / NET_TI, cc = idx - rr * NET_TI;
         const int j = j0 + rr, i = i0 + cc;
-        if (!(j >= 1 && i >= 1 && i + j <= n - 2)) continue;
         float o = 0.f;
+#pragma unroll
         for (int t = 0; t < 7; ++t) o += zs[t][(rr + 1 + c_dj[t]) * NZ + (cc + 1 + c_di[t])];
-        const int64_t p = fb + nrow_start(n, j) + i;
-        const T v = mode == 1 ? (T)((float)y[p] + o) : (T)o;
-        y[p] = v;
+        const T val = (T)(yo[k] + o);
+        y[po[k]] = val;
         if (j == 1 && i <= n - 2 && !fi.bside[0])
-            y[nedge_ghost(L, fi.edge[0], fi.slot[0]) + (fi.rev[0] ? n - 2 - i : i)] = v;
+            y[nedge_ghost(L, fi.edge[0], fi.slot[0]) + (fi.rev[0] ? n - 2 - i : i)] = val;
         if (i == 1 && j <= n - 2 && !fi.bside[1])
-            y[nedge_ghost(L, fi.edge[1], fi.slot[1]) + (fi.rev[1] ? n - 2 - j : j)] = v;
+            y[nedge_ghost(L, fi.edge[1], fi.slot[1]) + (fi.rev[1] ? n - 2 - j : j)] = val;
         if (i + j == n - 2 && !fi.bside[2])
-            y[nedge_ghost(L, fi.edge[2], fi.slot[2]) + (fi.rev[2] ? n - 2 - j : j)] = v;
+            y[nedge_ghost(L, fi.edge[2], fi.slot[2]) + (fi.rev[2] ? n - 2 - j : j)] = val;
     }
 }
 

@@ -170,7 +170,7 @@ def test_vcycle_matches_dense_error_propagation(ann3c1, nu):
         e0[ii] = rng.standard_normal(len(ii))
         u = e0.copy()
         ann4.vcycle(l, u, np.zeros(lv.n_all), *nu)   # exact solution is 0
-        assert np.abs(u[ii] - E @ e0[ii]).max() < 1e-10 * np.abs(e0).max()
+        assert np.abs(u[ii] - E @ e0[ii]).max() < 1e-12 * np.abs(e0).max()
     if nu[0] == nu[1]:
         A = ann4.A[l].toarray()[np.ix_(ii, ii)]
         AE = A @ E
@@ -186,6 +186,24 @@ def test_pcg_matches_direct_solve(ann4):
     assert np.linalg.norm(b - A @ x) <= 1e-14 * np.linalg.norm(b)
     assert it < 4 * len(b)
     assert pcg_jacobi(A, np.zeros(len(b)))[1] == 0
+
+
+def test_coarse_solve_direct_and_pcg(ann4):
+    """The direct coarse solve is the exact solution; the PCG alternative
+    agrees within its stopping tolerance."""
+    lvc = ann4.levels[ann4.lc]
+    ic = lvc.interior
+    rng = np.random.default_rng(4)
+    f = np.zeros(lvc.n_all)
+    f[ic] = rng.standard_normal(len(ic))
+    u = np.zeros(lvc.n_all)
+    assert ann4.coarse_solve(u, f) == 0
+    xd = np.linalg.solve(ann4.A_coarse.toarray(), f[ic])
+    assert np.abs(u[ic] - xd).max() <= 1e-13 * np.abs(xd).max()
+    Hp = Hierarchy(ann4.mesh, ann4.lc + 1, ann4.lc, coarse="pcg")
+    up = np.zeros(lvc.n_all)
+    assert Hp.coarse_solve(up, f) > 0
+    assert np.abs(up[ic] - xd).max() <= 1e-11 * np.abs(xd).max()
 
 
 def test_solve_matches_sparse_direct():
