@@ -232,9 +232,11 @@ int hhg_vcycle(const hhg_mesh* mesh, int32_t level, int32_t op,
  * V-cycle on the correction, FP64 coarse CG); learned smoother inside the
  * mixed-precision loop with Gauss-Seidel fallback: the learned smoother runs
  * only if a network is loaded and marked accepted, and a learned cycle that
- * does not lower the residual (or makes it non-finite) is undone and the
- * solve goes on with Gauss-Seidel (stats->fallback = 1; the undone cycle
- * counts in stats->iters).  Returns HHG_ENOTCONV if
+ * does not lower the residual (or makes it non-finite) is undone (the
+ * previous iterate is kept) and the solve goes on with Gauss-Seidel
+ * (stats->fallback = 1; the undone cycle counts in stats->iters).  The
+ * mixed-precision modes alternate the iterate between u and a workspace
+ * field and copy it back to u before returning.  Returns HHG_ENOTCONV if
  * max_iters is reached or the residual stops decreasing; stats are filled in
  * every case.
  */

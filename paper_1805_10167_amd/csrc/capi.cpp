@@ -109,9 +109,7 @@ void carve(hhg_mesh* M, uint32_t feat, Carver& c) {
         if (feat & HHG_FEAT_MP) M->a32[l] = fld(l, 4);
     }
     M->net_w = M->net_m = M->net_v = M->net_partials = nullptr;
-    M->u_backup = nullptr;
     if (feat & HHG_FEAT_NET) {
-        M->u_backup = (double*)fld(m.L, 8);
         M->net_w = (float*)c.take(sizeof(float) * NET_NW);
         M->net_m = (float*)c.take(sizeof(float) * NET_NW);
         M->net_v = (float*)c.take(sizeof(float) * NET_NW);
@@ -550,13 +548,30 @@ int hhg_solve(hhg_mesh* M, const hhg_solve_opts* o, void* u, const void* f, hhg_
         return fail(HHG_EINVAL, "FP32 coefficient missing");
     hipStream_t s = (hipStream_t)stream;
     double* dnorm = M->dscalars;
-    double* r64 = (double*)M->r64[L];
-    auto norm_now = [&](double* out) -> int {
-        HIP_CHECK(launch_residual(M, L, o->op, HHG_F64, u, f, r64, dnorm, s), "residual");
+    const int64_t nL = M->m.lv[L].total;
+    const bool mp = o->mode != HHG_MODE_PLAIN_FP64;
+    // Plain: u in place, norm-only residuals.  Mixed precision: the fused
+    // outer step writes u + e into the other FP64 buffer (ping-pong with the
+    // level's FP64 scratch field) together with the FP32 residual, which is
+    // the next cycle's right-hand side.
+    double* cur = (double*)u;
+    double* alt = (double*)M->r64[L];
+    float* r32 = (float*)M->f32[L];
+    float* e32 = (float*)M->u32[L];
+    auto first_norm = [&](double* out) -> int {
+        if (mp) HIP_CHECK(launch_mp_step(M, L, o->op, cur, nullptr, (const double*)f, nullptr, r32, dnorm, s),
+                          "residual");
+        else HIP_CHECK(launch_residual(M, L, o->op, HHG_F64, cur, f, nullptr, dnorm, s), "residual");
         return read_scalar(dnorm, out, s);
     };
+    auto finish = [&](int status) -> int {
+        if (cur != (double*)u)
+            HIP_CHECK(hipMemcpyAsync(u, cur, sizeof(double) * nL, hipMemcpyDeviceToDevice, s), "copy back");
+        st->ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+        return status;
+    };
     double r0 = 0.0;
-    if ((rc = norm_now(&r0))) return rc;
+    if ((rc = first_norm(&r0))) return rc;
     st->res0 = r0;
     // the learned smoother runs only when a network is loaded and accepted
     int smoother = HHG_SMOOTH_GS;
@@ -569,44 +584,36 @@ int hhg_solve(hhg_mesh* M, const hhg_solve_opts* o, void* u, const void* f, hhg_
     if (r0 == 0.0) {
         st->converged = 1;
         st->rel_res = 0.0;
-        st->ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
-        return HHG_OK;
+        return finish(HHG_OK);
     }
     double prev = r0;
     int rising = 0;
     int status = HHG_ENOTCONV;
-    const int64_t nL = M->m.lv[L].total;
     for (int it = 0; it < o->max_iters; ++it) {
-        const bool learned = smoother == HHG_SMOOTH_NET;
-        if (learned)
-            HIP_CHECK(hipMemcpyAsync(M->u_backup, u, sizeof(double) * nL, hipMemcpyDeviceToDevice, s),
-                      "backup");
-        if (o->mode == HHG_MODE_PLAIN_FP64) {
-            rc = vcycle_rec(M, L, o->op, HHG_SMOOTH_GS, HHG_F64, u, f, o->nu1, o->nu2, s);
-        } else {
-            // mixed precision: FP32 V-cycle on A e = r, FP64 residual and update
-            float* r32 = (float*)M->f32[L];
-            float* e32 = (float*)M->u32[L];
-            HIP_CHECK(launch_f64_to_f32(r64, r32, nL, s), "downcast");
-            HIP_CHECK(launch_fill(e32, nL, HHG_F32, 0.0, s), "fill");
-            rc = vcycle_rec(M, L, o->op, smoother, HHG_F32, e32, r32, o->nu1, o->nu2, s);
-            if (!rc) HIP_CHECK(launch_add_f32_to_f64((double*)u, e32, nL, s), "update");
-        }
-        if (rc) return rc;
         double rn = 0.0;
-        if ((rc = norm_now(&rn))) return rc;
-        st->iters = it + 1;
-        // learned smoother guard: a cycle that does not reduce the residual
-        // (or leaves it non-finite) is undone and the rest of the solve
-        // runs Gauss-Seidel
-        if (learned && !(rn <= prev)) {
-            HIP_CHECK(hipMemcpyAsync(u, M->u_backup, sizeof(double) * nL, hipMemcpyDeviceToDevice, s),
-                      "restore");
-            if ((rc = norm_now(&rn))) return rc;     // also refreshes r64
-            smoother = HHG_SMOOTH_GS;
-            st->fallback = 1;
-            st->smoother_used = HHG_SMOOTH_GS;
+        const bool learned = smoother == HHG_SMOOTH_NET;
+        if (!mp) {
+            if ((rc = vcycle_rec(M, L, o->op, HHG_SMOOTH_GS, HHG_F64, u, f, o->nu1, o->nu2, s))) return rc;
+            HIP_CHECK(launch_residual(M, L, o->op, HHG_F64, u, f, nullptr, dnorm, s), "residual");
+            if ((rc = read_scalar(dnorm, &rn, s))) return rc;
+        } else {
+            HIP_CHECK(launch_fill(e32, nL, HHG_F32, 0.0, s), "fill");
+            if ((rc = vcycle_rec(M, L, o->op, smoother, HHG_F32, e32, r32, o->nu1, o->nu2, s))) return rc;
+            HIP_CHECK(launch_mp_step(M, L, o->op, cur, e32, (const double*)f, alt, r32, dnorm, s), "update");
+            if ((rc = read_scalar(dnorm, &rn, s))) return rc;
+            if (learned && !(rn <= prev)) {
+                // learned smoother guard: the cycle did not lower the residual
+                // (or made it non-finite): keep the previous iterate, rebuild
+                // its residual and go on with Gauss-Seidel
+                if ((rc = first_norm(&rn))) return rc;
+                smoother = HHG_SMOOTH_GS;
+                st->fallback = 1;
+                st->smoother_used = HHG_SMOOTH_GS;
+            } else {
+                std::swap(cur, alt);
+            }
         }
+        st->iters = it + 1;
         st->rel_res = rn / r0;
         if (o->res_history && it + 1 < o->history_capacity) o->res_history[it + 1] = rn;
         if (!std::isfinite(rn)) {
@@ -626,8 +633,7 @@ int hhg_solve(hhg_mesh* M, const hhg_solve_opts* o, void* u, const void* f, hhg_
         prev = rn;
     }
     if (status == HHG_ENOTCONV && g_err.empty()) g_err = "iteration cap reached";
-    st->ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
-    return status;
+    return finish(status);
 }
 
 int hhg_jacobi(const hhg_mesh* M, int32_t level, int32_t op, int32_t dtype, const void* u,

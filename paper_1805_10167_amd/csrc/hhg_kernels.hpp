@@ -26,6 +26,10 @@ hipError_t launch_residual(const hhg_mesh* M, int level, int op, int dtype, cons
 hipError_t launch_gs_sweep(const hhg_mesh* M, int level, int op, int dtype, void* x, void* y,
                            const void* f, int backward, hipStream_t s);
 // fc (level-1) = P^T r (level) from r with its copies; uc (level-1) = 0.
+// Mixed-precision outer step (see k_mp_step): e == nullptr for the first
+// residual; xo receives x + e otherwise.
+hipError_t launch_mp_step(const hhg_mesh* M, int level, int op, const double* x, const float* e,
+                          const double* f, double* xo, float* r, double* norm, hipStream_t s);
 hipError_t launch_restrict(const hhg_mesh* M, int level, int dtype, const void* r, void* fc,
                            void* uc, hipStream_t s);
 // u (level) += P uc (level-1) on interior points, copies included.

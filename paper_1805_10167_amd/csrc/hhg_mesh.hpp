@@ -113,7 +113,6 @@ struct hhg_mesh {
     float* net_m = nullptr;
     float* net_v = nullptr;
     float* net_partials = nullptr;
-    double* u_backup = nullptr;      // finest-level iterate before a learned cycle
     bool net_loaded = false;
     bool net_accepted = false;
     bool net_mfma = true;         // BF16 MFMA forward (false: FP32, for tests)

@@ -329,7 +329,7 @@ __device__ __forceinline__ T vertex_apply(int op, const LevelDev& L, const Verte
 // Point operator of every interior row, with all copies of the result:
 //   MODE 0: y = A x              MODE 1: y = f - A x (+ per-block sums of y^2)
 //   MODE 2: y = (f - A x) / a_pp MODE 3: y = x / a_pp
-// and 0 on Dirichlet rows.
+// and 0 on Dirichlet rows; MODE 4 only sums (f - A x)^2 and writes nothing.
 template <class T, int MODE>
 __global__ __launch_bounds__(NT) void k_apply(LevelDev L, int op, const T* __restrict__ x,
                                               const T* __restrict__ f, T* __restrict__ y,
@@ -349,9 +349,10 @@ __global__ __launch_bounds__(NT) void k_apply(LevelDev L, int op, const T* __res
             v = w.c * x[p] + w.e * x[p + 1] + w.w * x[p - 1] + w.n * x[p + up] + w.s * x[p - dn] +
                 w.se * x[p - dn + 1] + w.nw * x[p + up - 1];
             if (MODE >= 1) v = f[p] - v;
-            if (MODE == 1) acc += (double)v * (double)v;
+            if (MODE == 1 || MODE == 4) acc += (double)v * (double)v;
             if (MODE == 2) v = v / w.c;
         }
+        if (MODE == 4) continue;
         y[p] = v;
         push_face_near(L, y, fi, i, j, v);
         }
@@ -371,10 +372,11 @@ __global__ __launch_bounds__(NT) void k_apply(LevelDev L, int op, const T* __res
                         v = w.c * x[m + k] + w.al * x[m + k - 1] + w.ah * x[m + k + 1] + w.l0 * x[g0 + k - 1] +
                             w.h0 * x[g0 + k] + w.l1 * x[g1 + k - 1] + w.h1 * x[g1 + k];
                         if (MODE >= 1) v = f[m + k] - v;
-                        if (MODE == 1) acc += (double)v * (double)v;
+                        if (MODE == 1 || MODE == 4) acc += (double)v * (double)v;
                         if (MODE == 2) v = v / w.c;
                     }
                 }
+                if (MODE == 4) continue;
                 y[m + k] = v;
                 push_edge(L, y, ei, k, v, true);
             } else {
@@ -394,19 +396,102 @@ __global__ __launch_bounds__(NT) void k_apply(LevelDev L, int op, const T* __res
                     } else {
                         v = c * x[vb] + s;
                         if (MODE >= 1) v = f[vb] - v;
-                        if (MODE == 1) acc += (double)v * (double)v;
+                        if (MODE == 1 || MODE == 4) acc += (double)v * (double)v;
                         if (MODE == 2) v = v / c;
                     }
                 }
+                if (MODE == 4) continue;
                 y[vb] = v;
                 push_vertex(L, y, vi, v);
             }
         }
     }
-    if (MODE == 1 && partials) {
+    if ((MODE == 1 || MODE == 4) && partials) {
         const double s = block_sum<NT>(acc, sm);
         if (threadIdx.x == 0) partials[blockIdx.x] = s;
     }
+}
+
+// Outer step of mixed-precision refinement on FP64 x, FP32 correction e and
+// FP64 f.  With UPD: v = x + e is the new iterate, written to xo with all
+// copies (Dirichlet entries keep x); without: v = x and xo is untouched.
+// The residual f - A v is formed in FP64, its squares summed per block in
+// FP64 for the norm, and it is stored rounded to FP32 in r with all copies
+// (0 on Dirichlet rows): the right-hand side of the next FP32 cycle.
+template <bool UPD>
+__global__ __launch_bounds__(NT) void k_mp_step(LevelDev L, int op, const double* __restrict__ x,
+                                                const float* __restrict__ e, const double* __restrict__ f,
+                                                double* __restrict__ xo, float* __restrict__ r,
+                                                const double* __restrict__ kap, int gf, double* partials) {
+    __shared__ double sm[NT / 64 + 1];
+    double acc = 0.0;
+    auto V = [&](int64_t q) -> double { return UPD ? x[q] + (double)e[q] : x[q]; };
+    if ((int)blockIdx.x < gf) {
+        FACE_ALL_LOOP(L, gf)
+        if (!interior) continue;
+        const int64_t up = row_start(n, j + 1) - row_start(n, j);
+        const int64_t dn = row_start(n, j) - row_start(n, j - 1);
+        const W7<double> w = face_weights<double>(op, fi, L.inv4l, kap, p, up, dn);
+        const double v0 = V(p);
+        const double v = f[p] - (w.c * v0 + w.e * V(p + 1) + w.w * V(p - 1) + w.n * V(p + up) +
+                                 w.s * V(p - dn) + w.se * V(p - dn + 1) + w.nw * V(p + up - 1));
+        acc += v * v;
+        r[p] = (float)v;
+        push_face_near(L, r, fi, i, j, (float)v);
+        if (UPD) {
+            xo[p] = v0;
+            push_face_near(L, xo, fi, i, j, v0);
+        }
+        }
+    } else {
+        LOW_LOOP(L, gf) {
+            if (t < ne_) {
+                const int ed = (int)(t / (nl_ - 2)), k = (int)(t % (nl_ - 2)) + 1;
+                const EdgeInfo& ei = L.edges[ed];
+                const int64_t m = edge_main(L, ed);
+                double v = 0.0, v0 = x[m + k];
+                if (!ei.boundary) {
+                    v0 = V(m + k);
+                    const int64_t g0 = edge_ghost(L, ed, 0), g1 = edge_ghost(L, ed, 1);
+                    const WE<double> w = edge_weights<double>(op, ei, L.inv4l, kap, m, g0, g1, k);
+                    v = f[m + k] - (w.c * v0 + w.al * V(m + k - 1) + w.ah * V(m + k + 1) +
+                                    w.l0 * V(g0 + k - 1) + w.h0 * V(g0 + k) + w.l1 * V(g1 + k - 1) +
+                                    w.h1 * V(g1 + k));
+                    acc += v * v;
+                }
+                r[m + k] = (float)v;
+                push_edge(L, r, ei, k, (float)v, true);
+                if (UPD) {
+                    xo[m + k] = v0;
+                    push_edge(L, xo, ei, k, v0, true);
+                }
+            } else {
+                const int vv = (int)(t - ne_);
+                const VertexInfo& vi = L.verts[vv];
+                const int64_t vb = vert_off(L, vv);
+                double v = 0.0, v0 = x[vb];
+                if (!vi.boundary) {
+                    v0 = V(vb);
+                    double sn = 0.0, c = 0.0;
+                    for (int q = 0; q < vi.deg; ++q) {
+                        const double wq = vertex_weight<double>(op, vi, L.inv4l, kap, vb, q);
+                        sn += wq * V(vb + 1 + q);
+                        c += wq;
+                    }
+                    v = f[vb] - (-c * v0 + sn);
+                    acc += v * v;
+                }
+                r[vb] = (float)v;
+                push_vertex(L, r, vi, (float)v);
+                if (UPD) {
+                    xo[vb] = v0;
+                    push_vertex(L, xo, vi, v0);
+                }
+            }
+        }
+    }
+    const double sum = block_sum<NT>(acc, sm);
+    if (threadIdx.x == 0) partials[blockIdx.x] = sum;
 }
 
 // Per-block sums of x*y over owned interior points (faces, interior edge
@@ -1299,9 +1384,24 @@ static hipError_t residual_t(const hhg_mesh* M, int level, int op, const T* u, c
                              double* norm, hipStream_t s) {
     const LevelDev L = M->dev(level);
     const int gf = face_grid(L), gl = grid_for(low_items(L), MAX_LOW_BLOCKS);
-    k_apply<T, 1><<<gf + gl, NT, 0, s>>>(L, op, u, f, r, kap_of<T>(M, level), gf,
-                                            norm ? M->partials : nullptr);
+    if (r)
+        k_apply<T, 1><<<gf + gl, NT, 0, s>>>(L, op, u, f, r, kap_of<T>(M, level), gf,
+                                                norm ? M->partials : nullptr);
+    else
+        k_apply<T, 4><<<gf + gl, NT, 0, s>>>(L, op, u, f, r, kap_of<T>(M, level), gf, M->partials);
     if (norm) k_reduce_final<<<1, 1024, 0, s>>>(M->partials, gf + gl, norm, 1);
+    return hipGetLastError();
+}
+
+hipError_t launch_mp_step(const hhg_mesh* M, int level, int op, const double* x, const float* e,
+                          const double* f, double* xo, float* r, double* norm, hipStream_t s) {
+    const LevelDev L = M->dev(level);
+    const int gf = face_grid(L), gl = grid_for(low_items(L), MAX_LOW_BLOCKS);
+    if (e)
+        k_mp_step<true><<<gf + gl, NT, 0, s>>>(L, op, x, e, f, xo, r, M->kap64[level], gf, M->partials);
+    else
+        k_mp_step<false><<<gf + gl, NT, 0, s>>>(L, op, x, e, f, xo, r, M->kap64[level], gf, M->partials);
+    k_reduce_final<<<1, 1024, 0, s>>>(M->partials, gf + gl, norm, 1);
     return hipGetLastError();
 }
 
