@@ -236,9 +236,15 @@ int vcycle_rec(const hhg_mesh* M, int level, int op, int smoother, int dt, void*
     HIP_CHECK(launch_restrict(M, level, dt, r, fc, uc, s), "restrict");
     rc = vcycle_rec(M, level - 1, op, smoother, dt, uc, fc, nu1, nu2, s);
     if (rc) return rc;
-    HIP_CHECK(launch_prolong_add(M, level, dt, uc, cur, s), "prolong");
     void* fin = nullptr;
-    rc = smooth_pp(M, level, op, smoother, dt, cur, other, f, nu2, 1, s, &fin);
+    if (smoother == HHG_SMOOTH_GS && nu2 > 0) {
+        // prolongation folded into the first post-smoothing sweep: cur -> other
+        HIP_CHECK(launch_gs_sweep_prolong(M, level, op, dt, cur, other, f, uc, s), "prolong + smooth");
+        rc = smooth_pp(M, level, op, smoother, dt, other, cur, f, nu2 - 1, 1, s, &fin);
+    } else {
+        HIP_CHECK(launch_prolong_add(M, level, dt, uc, cur, s), "prolong");
+        rc = smooth_pp(M, level, op, smoother, dt, cur, other, f, nu2, 1, s, &fin);
+    }
     if (rc) return rc;
     if (fin != u) return copy_field(M, level, dt, u, fin, s);
     return HHG_OK;

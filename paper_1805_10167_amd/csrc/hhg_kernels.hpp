@@ -30,6 +30,10 @@ hipError_t launch_gs_sweep(const hhg_mesh* M, int level, int op, int dtype, void
 // residual; xo receives x + e otherwise.
 hipError_t launch_mp_step(const hhg_mesh* M, int level, int op, const double* x, const float* e,
                           const double* f, double* xo, float* r, double* norm, hipStream_t s);
+// Backward sweep that starts from x + P uc (uc: correction of level - 1):
+// prolongation and the first post-smoothing sweep in the same launches.
+hipError_t launch_gs_sweep_prolong(const hhg_mesh* M, int level, int op, int dtype, void* x, void* y,
+                                   const void* f, const void* uc, hipStream_t s);
 hipError_t launch_restrict(const hhg_mesh* M, int level, int dtype, const void* r, void* fc,
                            void* uc, hipStream_t s);
 // u (level) += P uc (level-1) on interior points, copies included.

@@ -538,6 +538,56 @@ __global__ __launch_bounds__(1024) void k_reduce_final(const double* __restrict_
     if (threadIdx.x == 0) *out = do_sqrt ? sqrt(s) : s;
 }
 
+// Linear interpolation of coarse face values at fine face point (i, j):
+// coincident points copy, midpoints of coarse micro-edges average the two
+// ends (horizontal, vertical, and the diagonal from (I+1, J) to (I, J+1)).
+template <class T>
+__device__ __forceinline__ T prol_face(const T* __restrict__ uc, int64_t cb, int nc, int i, int j) {
+    const int I = i >> 1, J = j >> 1;
+    if (!(i & 1) && !(j & 1)) return uc[cb + row_start(nc, J) + I];
+    if ((i & 1) && !(j & 1)) return (T)0.5 * (uc[cb + row_start(nc, J) + I] + uc[cb + row_start(nc, J) + I + 1]);
+    if (!(i & 1) && (j & 1)) return (T)0.5 * (uc[cb + row_start(nc, J) + I] + uc[cb + row_start(nc, J + 1) + I]);
+    return (T)0.5 * (uc[cb + row_start(nc, J) + I + 1] + uc[cb + row_start(nc, J + 1) + I]);
+}
+
+// Dirichlet status of face point (i, j) (ring points on boundary sides or
+// at boundary vertices).
+__device__ __forceinline__ bool face_dirichlet(const FaceInfo& fi, int n, int i, int j) {
+    if (i >= 1 && j >= 1 && i + j <= n - 2) return false;
+    if (j == 0 && i == 0) return fi.bvtx[0];
+    if (j == 0 && i == n - 1) return fi.bvtx[1];
+    if (i == 0 && j == n - 1) return fi.bvtx[2];
+    if (j == 0) return fi.bside[0];
+    if (i == 0) return fi.bside[1];
+    return fi.bside[2];
+}
+
+// Prolongation of one entry of the edge and vertex blocks (edge main
+// k = 0..n-1, vertex value and ghost slots): the value to add, 0 at
+// Dirichlet points and padding.
+template <class T>
+__device__ __forceinline__ T prol_low(const LevelDev& Lf, const LevelDev& Lc, const T* __restrict__ uc,
+                                      int64_t t) {
+    const int n = Lf.n;
+    const int64_t ne = (int64_t)Lf.E * n;
+    if (t < ne) {
+        const int e = (int)(t / n), k = (int)(t % n);
+        const EdgeInfo& ei = Lf.edges[e];
+        if (ei.boundary) return (T)0;
+        const int64_t mc = edge_main(Lc, e);
+        if (k == 0) return Lf.verts[ei.a].boundary ? (T)0 : uc[mc];
+        if (k == n - 1) return Lf.verts[ei.b].boundary ? (T)0 : uc[mc + Lc.n - 1];
+        return (k & 1) ? (T)0.5 * (uc[mc + (k >> 1)] + uc[mc + (k >> 1) + 1]) : uc[mc + (k >> 1)];
+    }
+    const int64_t tv = t - ne;
+    const int v = (int)(tv / Lf.vert_stride), slot = (int)(tv % Lf.vert_stride);
+    const VertexInfo& vi = Lf.verts[v];
+    if (vi.boundary || slot > vi.deg) return (T)0;
+    const int64_t vc = vert_off(Lc, v);
+    const T cv = uc[vc];
+    return slot == 0 ? cv : (T)0.5 * (cv + uc[vc + slot]);
+}
+
 // Fused multicolour face smoother.  A tile of GS_TI x GS_TJ points plus a
 // halo of GS_H points sits in LDS; colour stage s (of ncol) is applied on
 // the tile grown by ncol - 1 - s points, so every stage sees exactly the
@@ -580,9 +630,19 @@ __device__ __forceinline__ T gs_point(const FaceInfo& fi, const W7<T>& w, T invc
 
 // Tile rows into registers: wave w takes LDS rows w + GS_NW q, lane l columns
 // l, l + 64, l + 128.  The caller stores them to LDS after issuing f loads.
-template <class T, bool VARK>
+// Coarse correction added while a tile is loaded (the first sweep after
+// the prolongation): uc is the coarse field, cb its face base, nc its n.
+template <class T>
+struct ProlTile {
+    const T* uc;
+    int64_t cb;
+    int nc;
+};
+
+template <class T, bool VARK, bool PROL>
 __device__ __forceinline__ void gs_load_u(int n, int i0, int j0, int64_t fb, const T* __restrict__ uin,
-                                          const T* __restrict__ kap, T (*ur)[3], T (*kr)[3]) {
+                                          const T* __restrict__ kap, T (*ur)[3], T (*kr)[3],
+                                          const FaceInfo& fi, const ProlTile<T>& pt) {
     const int wv = wave_id(), lane = threadIdx.x & 63;
 #pragma unroll
     for (int q = 0; q < GS_RPW; ++q) {
@@ -592,7 +652,9 @@ __device__ __forceinline__ void gs_load_u(int n, int i0, int j0, int64_t fb, con
         for (int c = 0; c < 3; ++c) {
             const int i = i0 + lane + 64 * c;
             const bool in = r < GS_R && j >= 0 && j < n && i >= 0 && i <= n - 1 - j;
-            ur[q][c] = in ? uin[rb + i] : (T)0;
+            T v = in ? uin[rb + i] : (T)0;
+            if (PROL && in && !face_dirichlet(fi, n, i, j)) v += prol_face<T>(pt.uc, pt.cb, pt.nc, i, j);
+            ur[q][c] = v;
             if (VARK) kr[q][c] = in ? kap[rb + i] : (T)0;
         }
     }
@@ -620,14 +682,14 @@ __device__ __forceinline__ void gs_store_u(T (*us)[GS_W], T (*ks)[GS_W], T (*ur)
 // per row; the row, the colour offset and the bounds are wave-uniform.
 constexpr int GS_IT3 = (GS_TJ + 4 + GS_NW - 1) / GS_NW;
 
-template <class T, bool VARK>
+template <class T, bool VARK, bool PROL>
 __device__ __forceinline__ void gs_tile3(const LevelDev& L, const FaceInfo& fi, int n, int i0, int j0,
                                          int64_t fb, const T* __restrict__ uin, const T* __restrict__ f,
                                          const T* __restrict__ kap, int backward, T (*us)[GS_W],
-                                         T (*ks)[GS_W]) {
+                                         T (*ks)[GS_W], const ProlTile<T>& pt) {
     const int wv = wave_id(), lane = threadIdx.x & 63;
     T ur[GS_RPW][3], kr[VARK ? GS_RPW : 1][3], fr[3][GS_IT3];
-    gs_load_u<T, VARK>(n, i0, j0, fb, uin, kap, ur, kr);
+    gs_load_u<T, VARK, PROL>(n, i0, j0, fb, uin, kap, ur, kr, fi, pt);
 #pragma unroll
     for (int s = 0; s < 3; ++s) {
         const int c = backward ? 2 - s : s, h = 2 - s;
@@ -684,14 +746,14 @@ __device__ __forceinline__ bool gs_decode2(int idx, int rule, int c, int h, int 
     return r < hi_j && tx < hi_i;
 }
 
-template <class T, bool VARK>
+template <class T, bool VARK, bool PROL>
 __device__ __forceinline__ void gs_tile2(const LevelDev& L, const FaceInfo& fi, int n, int i0, int j0,
                                          int64_t fb, const T* __restrict__ uin, const T* __restrict__ f,
                                          const T* __restrict__ kap, int backward, T (*us)[GS_W],
-                                         T (*ks)[GS_W]) {
+                                         T (*ks)[GS_W], const ProlTile<T>& pt) {
     const int rule = fi.colour_rule;
     T ur[GS_RPW][3], kr[VARK ? GS_RPW : 1][3], fr[2][GS_IT2];
-    gs_load_u<T, VARK>(n, i0, j0, fb, uin, kap, ur, kr);
+    gs_load_u<T, VARK, PROL>(n, i0, j0, fb, uin, kap, ur, kr, fi, pt);
 #pragma unroll
     for (int s = 0; s < 2; ++s) {
         const int c = backward ? 1 - s : s, h = 1 - s;
@@ -725,12 +787,15 @@ __device__ __forceinline__ void gs_tile2(const LevelDev& L, const FaceInfo& fi, 
 
 // NCOL selects the faces this launch handles (3: general faces, 2: faces
 // with a right angle); copies of edge and vertex blocks are done by the
-// extra blocks of the launch with with_copy = 1.
-template <class T, bool VARK, int NCOL>
+// extra blocks of the launch with with_copy = 1.  PROL: the sweep starts
+// from uin + P uc (the coarse correction of level Lc), which is then never
+// stored on its own: tiles add it as they load, copy blocks as they copy.
+template <class T, bool VARK, int NCOL, bool PROL>
 __global__ __launch_bounds__(GS_NT) void k_face_gs_fused(LevelDev L, const T* __restrict__ uin,
                                                          T* __restrict__ uout, const T* __restrict__ f,
                                                          const T* __restrict__ kap, int backward,
-                                                         int nblk_tiles, int with_copy) {
+                                                         int nblk_tiles, int with_copy, LevelDev Lc,
+                                                         const T* __restrict__ uc) {
     __shared__ T us[GS_R][GS_W];
     __shared__ T ks[VARK ? GS_R : 1][GS_W];
     const int G = gridDim.x;                              // multiple of 8
@@ -745,7 +810,9 @@ __global__ __launch_bounds__(GS_NT) void k_face_gs_fused(LevelDev L, const T* __
         for (int64_t t = (int64_t)cb * GS_NT + threadIdx.x; t < ne + nv; t += (int64_t)ncb * GS_NT) {
             const int64_t off = t < ne ? L.edge_base + (t / n) * L.edge_stride + (t % n)
                                        : L.vert_base + (t - ne);
-            uout[off] = uin[off];
+            T v = uin[off];
+            if (PROL) v += prol_low<T>(L, Lc, uc, t);
+            uout[off] = v;
         }
         return;
     }
@@ -755,10 +822,11 @@ __global__ __launch_bounds__(GS_NT) void k_face_gs_fused(LevelDev L, const T* __
     const int2 tl = L.gs_tiles[logical % L.n_gs_tiles];
     const int i0 = tl.x * GS_TI - GS_H, j0 = tl.y * GS_TJ - GS_H;   // LDS origin
     const int64_t fb = face_base(L, face);
+    const ProlTile<T> pt{uc, PROL ? face_base(Lc, face) : 0, Lc.n};
     if (NCOL == 3)
-        gs_tile3<T, VARK>(L, fi, n, i0, j0, fb, uin, f, kap, backward, us, VARK ? ks : nullptr);
+        gs_tile3<T, VARK, PROL>(L, fi, n, i0, j0, fb, uin, f, kap, backward, us, VARK ? ks : nullptr, pt);
     else
-        gs_tile2<T, VARK>(L, fi, n, i0, j0, fb, uin, f, kap, backward, us, VARK ? ks : nullptr);
+        gs_tile2<T, VARK, PROL>(L, fi, n, i0, j0, fb, uin, f, kap, backward, us, VARK ? ks : nullptr, pt);
     const int wv = wave_id(), lane = threadIdx.x & 63;
     // tile points (interior updated, ring copied) to uout
     for (int r = GS_H + wv; r < GS_H + GS_TJ; r += GS_NW) {
@@ -915,28 +983,10 @@ __global__ __launch_bounds__(NT) void k_prolong(LevelDev Lf, LevelDev Lc, const 
                                                 T* __restrict__ u, int gf) {
     if ((int)blockIdx.x < gf) {
         FACE_ALL_LOOP(Lf, gf)
-        bool dir;
-        if (interior) dir = false;
-        else if (j == 0 && i == 0) dir = fi.bvtx[0];
-        else if (j == 0 && i == n - 1) dir = fi.bvtx[1];
-        else if (i == 0 && j == n - 1) dir = fi.bvtx[2];
-        else if (j == 0) dir = fi.bside[0];
-        else if (i == 0) dir = fi.bside[1];
-        else dir = fi.bside[2];
+        (void)interior;
         T v = u[p];
-        if (!dir) {
-            const int nc_ = Lc.n;
-            const int64_t cb = face_base(Lc, face);
-            const int I = i >> 1, J = j >> 1;
-            T c;
-            if (!(i & 1) && !(j & 1)) c = uc[cb + row_start(nc_, J) + I];
-            else if ((i & 1) && !(j & 1))
-                c = (T)0.5 * (uc[cb + row_start(nc_, J) + I] + uc[cb + row_start(nc_, J) + I + 1]);
-            else if (!(i & 1) && (j & 1))
-                c = (T)0.5 * (uc[cb + row_start(nc_, J) + I] + uc[cb + row_start(nc_, J + 1) + I]);
-            else
-                c = (T)0.5 * (uc[cb + row_start(nc_, J) + I + 1] + uc[cb + row_start(nc_, J + 1) + I]);
-            v += c;
+        if (!face_dirichlet(fi, n, i, j)) {
+            v += prol_face<T>(uc, face_base(Lc, face), Lc.n, i, j);
             u[p] = v;
         }
         push_face_near(Lf, u, fi, i, j, v);
@@ -1440,26 +1490,34 @@ struct TimingScope {
 
 template <class T>
 static hipError_t gs_t(const hhg_mesh* M, int level, int op, T* x, T* y, const T* f, int backward,
-                       hipStream_t s) {
+                       hipStream_t s, const T* uc = nullptr) {
     const LevelDev L = M->dev(level);
     const T* kap = kap_of<T>(M, level);
     const int gl = grid_for((int64_t)L.n_iedges * (L.n - 2) + L.n_iverts, MAX_LOW_BLOCKS);
-    const bool timed = M->timing && level == M->m.L;
+    const bool timed = M->timing && level == M->m.L && !uc;
+    const LevelDev Lc = uc ? M->dev(level - 1) : L;
     const int ntile_blocks = L.F * L.n_gs_tiles;
     const int g = (ntile_blocks + GS_COPY_BLOCKS + 7) / 8 * 8;
     const int g2 = (ntile_blocks + 7) / 8 * 8;
     const bool has2 = M->m.nfaces2 > 0;
     auto faces = [&]() -> hipError_t {
         TimingScope ts(M, s, timed);
+#define HHG_FACE_LAUNCH(VK, PR)                                                                     \
+    do {                                                                                            \
+        k_face_gs_fused<T, VK, 3, PR><<<g, GS_NT, 0, s>>>(L, x, y, f, kap, backward, ntile_blocks, 1,  \
+                                                          Lc, uc);                                   \
+        if (has2)                                                                                   \
+            k_face_gs_fused<T, VK, 2, PR><<<g2, GS_NT, 0, s>>>(L, x, y, f, kap, backward,            \
+                                                               ntile_blocks, 0, Lc, uc);            \
+    } while (0)
         if (op == OP_DIFFUSION) {
-            k_face_gs_fused<T, true, 3><<<g, GS_NT, 0, s>>>(L, x, y, f, kap, backward, ntile_blocks, 1);
-            if (has2)
-                k_face_gs_fused<T, true, 2><<<g2, GS_NT, 0, s>>>(L, x, y, f, kap, backward, ntile_blocks, 0);
+            if (uc) HHG_FACE_LAUNCH(true, true);
+            else HHG_FACE_LAUNCH(true, false);
         } else {
-            k_face_gs_fused<T, false, 3><<<g, GS_NT, 0, s>>>(L, x, y, f, kap, backward, ntile_blocks, 1);
-            if (has2)
-                k_face_gs_fused<T, false, 2><<<g2, GS_NT, 0, s>>>(L, x, y, f, kap, backward, ntile_blocks, 0);
+            if (uc) HHG_FACE_LAUNCH(false, true);
+            else HHG_FACE_LAUNCH(false, false);
         }
+#undef HHG_FACE_LAUNCH
         return hipGetLastError();
     };
     hipError_t e;
@@ -1479,6 +1537,13 @@ hipError_t launch_gs_sweep(const hhg_mesh* M, int level, int op, int dtype, void
     if (dtype == DT_F64)
         return gs_t<double>(M, level, op, (double*)x, (double*)y, (const double*)f, backward, s);
     return gs_t<float>(M, level, op, (float*)x, (float*)y, (const float*)f, backward, s);
+}
+
+hipError_t launch_gs_sweep_prolong(const hhg_mesh* M, int level, int op, int dtype, void* x, void* y,
+                                   const void* f, const void* uc, hipStream_t s) {
+    if (dtype == DT_F64)
+        return gs_t<double>(M, level, op, (double*)x, (double*)y, (const double*)f, 1, s, (const double*)uc);
+    return gs_t<float>(M, level, op, (float*)x, (float*)y, (const float*)f, 1, s, (const float*)uc);
 }
 
 template <class T>
