@@ -81,3 +81,45 @@ def inject(lv_fine, lv_coarse, x_fine):
         m = I + J <= nc - 1
         out[locc[J[m], I[m]]] = x_fine[locf[2 * J[m], 2 * I[m]]]
     return out
+
+
+def rows_at(lv, points, x, kappa=None):
+    """(A x)[points] for the Neumann stiffness A, from the element matrices of
+    the micro-triangles incident to each point only (the same definition as
+    `assemble`, for levels too large to assemble).  kappa(xy) -> nodal k at
+    the given coordinates, or None for k = 1."""
+    n = lv.n
+    points = np.asarray(points, dtype=np.int64)
+    want = {int(p): k for k, p in enumerate(points)}
+    # every occurrence (face, i, j) of the wanted points
+    occ = []
+    for f, loc in enumerate(lv.loc):
+        J, I = np.nonzero(np.isin(loc, points))
+        for j, i in zip(J.tolist(), I.tolist()):
+            occ.append((f, i, j))
+    tris = set()
+    for f, i, j in occ:
+        loc = lv.loc[f]
+        for a, b in ((i, j), (i - 1, j), (i, j - 1)):           # up triangles
+            if a >= 0 and b >= 0 and a + b <= n - 2:
+                tris.add(tuple(sorted((loc[b, a], loc[b, a + 1], loc[b + 1, a]))) + (0,) +
+                         (loc[b, a], loc[b, a + 1], loc[b + 1, a]))
+        for a, b in ((i - 1, j - 1), (i - 1, j), (i, j - 1)):   # down triangles
+            if a >= 0 and b >= 0 and a + b <= n - 3:
+                tris.add(tuple(sorted((loc[b, a + 1], loc[b + 1, a + 1], loc[b + 1, a]))) + (1,) +
+                         (loc[b, a + 1], loc[b + 1, a + 1], loc[b + 1, a]))
+    T = np.array([t[4:] for t in tris], dtype=np.int64)
+    kap = None
+    if kappa is not None:
+        uniq = np.unique(T)
+        kv = np.zeros(lv.n_all)
+        kv[uniq] = kappa(lv.xy[uniq])
+        kap = kv
+    K, _ = element_matrices(lv.xy, T, kap)
+    out = np.zeros(len(points))
+    for t in range(len(T)):
+        for a in range(3):
+            k = want.get(int(T[t, a]))
+            if k is not None:
+                out[k] += K[t, a] @ x[T[t]]
+    return out

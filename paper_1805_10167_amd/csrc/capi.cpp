@@ -49,6 +49,7 @@ void carve(hhg_mesh* M, uint32_t feat, Carver& c) {
         H.d_row_off = (int32_t*)c.take(sizeof(int32_t) * H.row_off.size());
         H.d_tiles = (int2*)c.take(sizeof(int2) * (H.tiles.size() + 1));
         H.d_gs_tiles = (int2*)c.take(sizeof(int2) * (H.gs_tiles.size() + 1));
+        H.d_gs_tiles16 = (int2*)c.take(sizeof(int2) * (H.gs_tiles16.size() + 1));
         H.d_net_tiles = (int2*)c.take(sizeof(int2) * (H.net_tiles.size() + 1));
         H.d_gdst = (int64_t*)c.take(sizeof(int64_t) * (H.gdst.size() + 1));
         H.d_gsrc = (int64_t*)c.take(sizeof(int64_t) * (H.gsrc.size() + 1));
@@ -269,6 +270,7 @@ hhg::LevelDev hhg_mesh::dev(int level) const {
     L.vert_stride = (int32_t)H.vert_stride;
     L.ntiles = (int32_t)H.tiles.size();
     L.n_gs_tiles = (int32_t)H.gs_tiles.size();
+    L.n_gs_tiles16 = (int32_t)H.gs_tiles16.size();
     L.n_net_tiles = (int32_t)H.net_tiles.size();
     L.n_iedges = (int32_t)m.iedges.size();
     L.n_iverts = (int32_t)m.iverts.size();
@@ -286,6 +288,7 @@ hhg::LevelDev hhg_mesh::dev(int level) const {
     L.row_off = H.d_row_off;
     L.tiles = H.d_tiles;
     L.gs_tiles = H.d_gs_tiles;
+    L.gs_tiles16 = H.d_gs_tiles16;
     L.net_tiles = H.d_net_tiles;
     L.faces = d_faces;
     L.edges = d_edges;
@@ -365,6 +368,7 @@ int hhg_bind_workspace(hhg_mesh* M, uint32_t features, void* dptr, size_t bytes,
         HIP_CHECK(upload(H.d_row_off, H.row_off, s), "upload");
         HIP_CHECK(upload(H.d_tiles, H.tiles, s), "upload");
         HIP_CHECK(upload(H.d_gs_tiles, H.gs_tiles, s), "upload");
+        HIP_CHECK(upload(H.d_gs_tiles16, H.gs_tiles16, s), "upload");
         HIP_CHECK(upload(H.d_net_tiles, H.net_tiles, s), "upload");
         HIP_CHECK(upload(H.d_gdst, H.gdst, s), "upload");
         HIP_CHECK(upload(H.d_gsrc, H.gsrc, s), "upload");

@@ -23,6 +23,7 @@ constexpr int TILE_J = 4;
 constexpr int GS_H = 3;
 constexpr int GS_TI = 192 - 2 * GS_H;
 constexpr int GS_TJ = 24;
+constexpr int GS_TJ16 = 16;   // tile height of the variable-coefficient FP64 smoother
 // learned-smoother tile: NET_TI x NET_TJ output points
 constexpr int NET_TI = 60;
 constexpr int NET_TJ = 12;
@@ -99,7 +100,7 @@ struct LevelDev {
     int32_t level, n;
     int32_t F, E, V;
     int32_t ghost_off, ghost_stride, vert_stride;
-    int32_t ntiles, n_iedges, n_iverts, n_gs_tiles, n_net_tiles, pad1;
+    int32_t ntiles, n_iedges, n_iverts, n_gs_tiles, n_net_tiles, n_gs_tiles16;
     int64_t face_stride, edge_stride;
     int64_t face_base, edge_base, vert_base, total;
     int64_t gcls[G_NCLS + 1];
@@ -108,6 +109,7 @@ struct LevelDev {
     const int32_t* row_off;           // [n + 1] start of row j inside a face
     const int2* tiles;                // 64 x 4 tiles covering the whole face
     const int2* gs_tiles;             // smoother tiles covering the whole face
+    const int2* gs_tiles16;           // the same with GS_TJ16-row tiles
     const int2* net_tiles;            // learned-smoother tiles meeting the interior
     const FaceInfo* faces;
     const EdgeInfo* edges;
@@ -140,6 +142,7 @@ struct LevelHost {
     std::vector<int32_t> row_off;
     std::vector<int2> tiles;
     std::vector<int2> gs_tiles;
+    std::vector<int2> gs_tiles16;
     std::vector<int2> net_tiles;
     std::vector<int64_t> gdst, gsrc;
     int64_t gcls[G_NCLS + 1] = {0, 0, 0, 0, 0};
@@ -148,6 +151,7 @@ struct LevelHost {
     int32_t* d_row_off = nullptr;
     int2* d_tiles = nullptr;
     int2* d_gs_tiles = nullptr;
+    int2* d_gs_tiles16 = nullptr;
     int2* d_net_tiles = nullptr;
     int64_t* d_gdst = nullptr;
     int64_t* d_gsrc = nullptr;

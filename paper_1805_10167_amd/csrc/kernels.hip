@@ -598,11 +598,19 @@ __device__ __forceinline__ T prol_low(const LevelDev& Lf, const LevelDev& Lc, co
 // points and vertex blocks into uout and writes the near-edge rows into
 // uout's edge ghost rows, leaving uout a complete, consistent field.
 constexpr int GS_W = GS_TI + 2 * GS_H;          // 192 values per LDS row
-constexpr int GS_R = GS_TJ + 2 * GS_H;          // LDS rows
 constexpr int GS_NT = 512;                      // threads per block
 constexpr int GS_NW = GS_NT / 64;               // waves per block
-constexpr int GS_RPW = (GS_R + GS_NW - 1) / GS_NW;   // LDS rows loaded per wave
 constexpr int GS_COPY_BLOCKS = 32;
+
+// Shape of a tile of TJ updated rows: LDS rows, rows loaded per wave, and
+// the per-stage row (three colours) or slot (two colours) iterations.
+template <int TJ>
+struct GsTile {
+    static constexpr int R = TJ + 2 * GS_H;
+    static constexpr int RPW = (R + GS_NW - 1) / GS_NW;
+    static constexpr int IT3 = (TJ + 4 + GS_NW - 1) / GS_NW;
+    static constexpr int IT2 = ((TJ + 2) * (GS_W / 2) + GS_NT - 1) / GS_NT;
+};
 
 __device__ __forceinline__ int pmod(int a, int m) { return ((a % m) + m) % m; }
 
@@ -639,19 +647,19 @@ struct ProlTile {
     int nc;
 };
 
-template <class T, bool VARK, bool PROL>
+template <class T, bool VARK, bool PROL, int TJ>
 __device__ __forceinline__ void gs_load_u(int n, int i0, int j0, int64_t fb, const T* __restrict__ uin,
                                           const T* __restrict__ kap, T (*ur)[3], T (*kr)[3],
                                           const FaceInfo& fi, const ProlTile<T>& pt) {
     const int wv = wave_id(), lane = threadIdx.x & 63;
 #pragma unroll
-    for (int q = 0; q < GS_RPW; ++q) {
+    for (int q = 0; q < GsTile<TJ>::RPW; ++q) {
         const int r = wv + GS_NW * q, j = j0 + r;
         const int64_t rb = fb + row_start(n, j < 0 ? 0 : (j > n ? n : j));
 #pragma unroll
         for (int c = 0; c < 3; ++c) {
             const int i = i0 + lane + 64 * c;
-            const bool in = r < GS_R && j >= 0 && j < n && i >= 0 && i <= n - 1 - j;
+            const bool in = r < GsTile<TJ>::R && j >= 0 && j < n && i >= 0 && i <= n - 1 - j;
             T v = in ? uin[rb + i] : (T)0;
             if (PROL && in && !face_dirichlet(fi, n, i, j)) v += prol_face<T>(pt.uc, pt.cb, pt.nc, i, j);
             ur[q][c] = v;
@@ -660,13 +668,13 @@ __device__ __forceinline__ void gs_load_u(int n, int i0, int j0, int64_t fb, con
     }
 }
 
-template <class T, bool VARK>
+template <class T, bool VARK, int TJ>
 __device__ __forceinline__ void gs_store_u(T (*us)[GS_W], T (*ks)[GS_W], T (*ur)[3], T (*kr)[3]) {
     const int wv = wave_id(), lane = threadIdx.x & 63;
 #pragma unroll
-    for (int q = 0; q < GS_RPW; ++q) {
+    for (int q = 0; q < GsTile<TJ>::RPW; ++q) {
         const int r = wv + GS_NW * q;
-        if (r < GS_R) {
+        if (r < GsTile<TJ>::R) {
 #pragma unroll
             for (int c = 0; c < 3; ++c) {
                 us[r][lane + 64 * c] = ur[q][c];
@@ -680,38 +688,37 @@ __device__ __forceinline__ void gs_store_u(T (*us)[GS_W], T (*ks)[GS_W], T (*ur)
 // the stage region.  In a row the colour-c points are every third column and
 // lane l owns columns 3 l .. 3 l + 2, so each lane updates exactly one point
 // per row; the row, the colour offset and the bounds are wave-uniform.
-constexpr int GS_IT3 = (GS_TJ + 4 + GS_NW - 1) / GS_NW;
 
-template <class T, bool VARK, bool PROL>
+template <class T, bool VARK, bool PROL, int TJ>
 __device__ __forceinline__ void gs_tile3(const LevelDev& L, const FaceInfo& fi, int n, int i0, int j0,
                                          int64_t fb, const T* __restrict__ uin, const T* __restrict__ f,
                                          const T* __restrict__ kap, int backward, T (*us)[GS_W],
                                          T (*ks)[GS_W], const ProlTile<T>& pt) {
     const int wv = wave_id(), lane = threadIdx.x & 63;
-    T ur[GS_RPW][3], kr[VARK ? GS_RPW : 1][3], fr[3][GS_IT3];
-    gs_load_u<T, VARK, PROL>(n, i0, j0, fb, uin, kap, ur, kr, fi, pt);
+    T ur[GsTile<TJ>::RPW][3], kr[VARK ? GsTile<TJ>::RPW : 1][3], fr[3][GsTile<TJ>::IT3];
+    gs_load_u<T, VARK, PROL, TJ>(n, i0, j0, fb, uin, kap, ur, kr, fi, pt);
 #pragma unroll
     for (int s = 0; s < 3; ++s) {
         const int c = backward ? 2 - s : s, h = 2 - s;
-        const int lo = GS_H - h, hi_i = GS_H + GS_TI + h, hi_j = GS_H + GS_TJ + h;
+        const int lo = GS_H - h, hi_i = GS_H + GS_TI + h, hi_j = GS_H + TJ + h;
 #pragma unroll
-        for (int it = 0; it < GS_IT3; ++it) {
+        for (int it = 0; it < GsTile<TJ>::IT3; ++it) {
             const int r = lo + wv + GS_NW * it, j = j0 + r;
             const int tx = pmod(c + j - i0, 3) + 3 * lane, i = i0 + tx;
             const bool upd = r < hi_j && tx >= lo && tx < hi_i && j >= 1 && i >= 1 && i + j <= n - 2;
             fr[s][it] = upd ? f[fb + row_start(n, upd ? j : 0) + i] : (T)0;
         }
     }
-    gs_store_u<T, VARK>(us, ks, ur, kr);
+    gs_store_u<T, VARK, TJ>(us, ks, ur, kr);
     const W7<T> w = face_weights<T>(OP_LAPLACE, fi, L.inv4l, (const T*)nullptr, 0, 0, 0);
     const T invc = (T)1 / w.c;
     __syncthreads();
 #pragma unroll
     for (int s = 0; s < 3; ++s) {
         const int c = backward ? 2 - s : s, h = 2 - s;
-        const int lo = GS_H - h, hi_i = GS_H + GS_TI + h, hi_j = GS_H + GS_TJ + h;
+        const int lo = GS_H - h, hi_i = GS_H + GS_TI + h, hi_j = GS_H + TJ + h;
 #pragma unroll
-        for (int it = 0; it < GS_IT3; ++it) {
+        for (int it = 0; it < GsTile<TJ>::IT3; ++it) {
             const int r = lo + wv + GS_NW * it, j = j0 + r;
             if (r >= hi_j) break;
             int tx = pmod(c + j - i0, 3) + 3 * lane;
@@ -727,11 +734,11 @@ __device__ __forceinline__ void gs_tile3(const LevelDev& L, const FaceInfo& fi, 
 
 // Two colours (faces with an exact right angle): slots map densely onto the
 // colour-c points, every second column or every second row.
-constexpr int GS_IT2 = ((GS_TJ + 2) * (GS_W / 2) + GS_NT - 1) / GS_NT;
 
+template <int TJ>
 __device__ __forceinline__ bool gs_decode2(int idx, int rule, int c, int h, int i0, int j0, int& r,
                                            int& tx) {
-    const int lo = GS_H - h, hi_i = GS_H + GS_TI + h, hi_j = GS_H + GS_TJ + h;
+    const int lo = GS_H - h, hi_i = GS_H + GS_TI + h, hi_j = GS_H + TJ + h;
     if (rule == 3) {
         const int rr = idx / GS_W, m = idx - rr * GS_W;
         r = lo + pmod(c - (j0 + lo), 2) + 2 * rr;
@@ -746,27 +753,27 @@ __device__ __forceinline__ bool gs_decode2(int idx, int rule, int c, int h, int 
     return r < hi_j && tx < hi_i;
 }
 
-template <class T, bool VARK, bool PROL>
+template <class T, bool VARK, bool PROL, int TJ>
 __device__ __forceinline__ void gs_tile2(const LevelDev& L, const FaceInfo& fi, int n, int i0, int j0,
                                          int64_t fb, const T* __restrict__ uin, const T* __restrict__ f,
                                          const T* __restrict__ kap, int backward, T (*us)[GS_W],
                                          T (*ks)[GS_W], const ProlTile<T>& pt) {
     const int rule = fi.colour_rule;
-    T ur[GS_RPW][3], kr[VARK ? GS_RPW : 1][3], fr[2][GS_IT2];
-    gs_load_u<T, VARK, PROL>(n, i0, j0, fb, uin, kap, ur, kr, fi, pt);
+    T ur[GsTile<TJ>::RPW][3], kr[VARK ? GsTile<TJ>::RPW : 1][3], fr[2][GsTile<TJ>::IT2];
+    gs_load_u<T, VARK, PROL, TJ>(n, i0, j0, fb, uin, kap, ur, kr, fi, pt);
 #pragma unroll
     for (int s = 0; s < 2; ++s) {
         const int c = backward ? 1 - s : s, h = 1 - s;
 #pragma unroll
-        for (int it = 0; it < GS_IT2; ++it) {
+        for (int it = 0; it < GsTile<TJ>::IT2; ++it) {
             int r, tx;
-            const bool ok = gs_decode2(threadIdx.x + it * GS_NT, rule, c, h, i0, j0, r, tx);
+            const bool ok = gs_decode2<TJ>(threadIdx.x + it * GS_NT, rule, c, h, i0, j0, r, tx);
             const int j = j0 + r, i = i0 + tx;
             const bool upd = ok && j >= 1 && i >= 1 && i + j <= n - 2;
             fr[s][it] = upd ? f[fb + row_start(n, upd ? j : 0) + i] : (T)0;
         }
     }
-    gs_store_u<T, VARK>(us, ks, ur, kr);
+    gs_store_u<T, VARK, TJ>(us, ks, ur, kr);
     const W7<T> w = face_weights<T>(OP_LAPLACE, fi, L.inv4l, (const T*)nullptr, 0, 0, 0);
     const T invc = (T)1 / w.c;
     __syncthreads();
@@ -774,9 +781,9 @@ __device__ __forceinline__ void gs_tile2(const LevelDev& L, const FaceInfo& fi, 
     for (int s = 0; s < 2; ++s) {
         const int c = backward ? 1 - s : s, h = 1 - s;
 #pragma unroll
-        for (int it = 0; it < GS_IT2; ++it) {
+        for (int it = 0; it < GsTile<TJ>::IT2; ++it) {
             int r, tx;
-            const bool ok = gs_decode2(threadIdx.x + it * GS_NT, rule, c, h, i0, j0, r, tx);
+            const bool ok = gs_decode2<TJ>(threadIdx.x + it * GS_NT, rule, c, h, i0, j0, r, tx);
             const int j = j0 + r, i = i0 + tx;
             if (!(ok && j >= 1 && i >= 1 && i + j <= n - 2)) continue;
             us[r][tx] = gs_point<T, VARK>(fi, w, invc, fr[s][it], us, ks, r, tx);
@@ -790,14 +797,14 @@ __device__ __forceinline__ void gs_tile2(const LevelDev& L, const FaceInfo& fi, 
 // extra blocks of the launch with with_copy = 1.  PROL: the sweep starts
 // from uin + P uc (the coarse correction of level Lc), which is then never
 // stored on its own: tiles add it as they load, copy blocks as they copy.
-template <class T, bool VARK, int NCOL, bool PROL>
+template <class T, bool VARK, int NCOL, bool PROL, int TJ>
 __global__ __launch_bounds__(GS_NT) void k_face_gs_fused(LevelDev L, const T* __restrict__ uin,
                                                          T* __restrict__ uout, const T* __restrict__ f,
                                                          const T* __restrict__ kap, int backward,
                                                          int nblk_tiles, int with_copy, LevelDev Lc,
                                                          const T* __restrict__ uc) {
-    __shared__ T us[GS_R][GS_W];
-    __shared__ T ks[VARK ? GS_R : 1][GS_W];
+    __shared__ T us[GsTile<TJ>::R][GS_W];
+    __shared__ T ks[VARK ? GsTile<TJ>::R : 1][GS_W];
     const int G = gridDim.x;                              // multiple of 8
     const int b = blockIdx.x;
     const int logical = (b & 7) * (G >> 3) + (b >> 3);    // contiguous tiles per XCD
@@ -816,20 +823,21 @@ __global__ __launch_bounds__(GS_NT) void k_face_gs_fused(LevelDev L, const T* __
         }
         return;
     }
-    const int face = logical / L.n_gs_tiles;
+    const int face = logical / (TJ == GS_TJ16 ? L.n_gs_tiles16 : L.n_gs_tiles);
     const FaceInfo& fi = L.faces[face];
     if (fi.ncolours != NCOL) return;
-    const int2 tl = L.gs_tiles[logical % L.n_gs_tiles];
-    const int i0 = tl.x * GS_TI - GS_H, j0 = tl.y * GS_TJ - GS_H;   // LDS origin
+    const bool t16 = TJ == GS_TJ16;
+    const int2 tl = (t16 ? L.gs_tiles16 : L.gs_tiles)[logical % (t16 ? L.n_gs_tiles16 : L.n_gs_tiles)];
+    const int i0 = tl.x * GS_TI - GS_H, j0 = tl.y * TJ - GS_H;   // LDS origin
     const int64_t fb = face_base(L, face);
     const ProlTile<T> pt{uc, PROL ? face_base(Lc, face) : 0, Lc.n};
     if (NCOL == 3)
-        gs_tile3<T, VARK, PROL>(L, fi, n, i0, j0, fb, uin, f, kap, backward, us, VARK ? ks : nullptr, pt);
+        gs_tile3<T, VARK, PROL, TJ>(L, fi, n, i0, j0, fb, uin, f, kap, backward, us, VARK ? ks : nullptr, pt);
     else
-        gs_tile2<T, VARK, PROL>(L, fi, n, i0, j0, fb, uin, f, kap, backward, us, VARK ? ks : nullptr, pt);
+        gs_tile2<T, VARK, PROL, TJ>(L, fi, n, i0, j0, fb, uin, f, kap, backward, us, VARK ? ks : nullptr, pt);
     const int wv = wave_id(), lane = threadIdx.x & 63;
     // tile points (interior updated, ring copied) to uout
-    for (int r = GS_H + wv; r < GS_H + GS_TJ; r += GS_NW) {
+    for (int r = GS_H + wv; r < GS_H + TJ; r += GS_NW) {
         const int j = j0 + r;
         if (j >= n) break;
         const int64_t rb = fb + row_start(n, j);
@@ -848,15 +856,15 @@ __global__ __launch_bounds__(GS_NT) void k_face_gs_fused(LevelDev L, const T* __
         }
     }
     if (!fi.bside[1] && tl.x == 0) {            // (1, m)
-        for (int t = threadIdx.x; t < GS_TJ; t += GS_NT) {
-            const int m = tl.y * GS_TJ + t;
+        for (int t = threadIdx.x; t < TJ; t += GS_NT) {
+            const int m = tl.y * TJ + t;
             if (m <= n - 2)
                 uout[edge_ghost(L, fi.edge[1], fi.slot[1]) + (fi.rev[1] ? n - 2 - m : m)] = us[GS_H + t][1 - i0];
         }
     }
     if (!fi.bside[2]) {                         // (n-2-m, m)
-        for (int t = threadIdx.x; t < GS_TJ; t += GS_NT) {
-            const int m = tl.y * GS_TJ + t, i = n - 2 - m;
+        for (int t = threadIdx.x; t < TJ; t += GS_NT) {
+            const int m = tl.y * TJ + t, i = n - 2 - m;
             if (m <= n - 2 && i >= tl.x * GS_TI && i < tl.x * GS_TI + GS_TI)
                 uout[edge_ghost(L, fi.edge[2], fi.slot[2]) + (fi.rev[2] ? n - 2 - m : m)] = us[GS_H + t][i - i0];
         }
@@ -1496,26 +1504,30 @@ static hipError_t gs_t(const hhg_mesh* M, int level, int op, T* x, T* y, const T
     const int gl = grid_for((int64_t)L.n_iedges * (L.n - 2) + L.n_iverts, MAX_LOW_BLOCKS);
     const bool timed = M->timing && level == M->m.L && !uc;
     const LevelDev Lc = uc ? M->dev(level - 1) : L;
-    const int ntile_blocks = L.F * L.n_gs_tiles;
+    // the variable-coefficient FP64 tile (u and k in LDS) is 16 rows high so
+    // that two blocks fit on a CU; the others are 24 rows high
+    const bool t16 = op == OP_DIFFUSION && sizeof(T) == 8;
+    const int ntile_blocks = L.F * (t16 ? L.n_gs_tiles16 : L.n_gs_tiles);
     const int g = (ntile_blocks + GS_COPY_BLOCKS + 7) / 8 * 8;
     const int g2 = (ntile_blocks + 7) / 8 * 8;
     const bool has2 = M->m.nfaces2 > 0;
     auto faces = [&]() -> hipError_t {
         TimingScope ts(M, s, timed);
-#define HHG_FACE_LAUNCH(VK, PR)                                                                     \
+#define HHG_FACE_LAUNCH(VK, PR, TJ)                                                                 \
     do {                                                                                            \
-        k_face_gs_fused<T, VK, 3, PR><<<g, GS_NT, 0, s>>>(L, x, y, f, kap, backward, ntile_blocks, 1,  \
-                                                          Lc, uc);                                   \
+        k_face_gs_fused<T, VK, 3, PR, TJ><<<g, GS_NT, 0, s>>>(L, x, y, f, kap, backward, ntile_blocks, \
+                                                              1, Lc, uc);                            \
         if (has2)                                                                                   \
-            k_face_gs_fused<T, VK, 2, PR><<<g2, GS_NT, 0, s>>>(L, x, y, f, kap, backward,            \
-                                                               ntile_blocks, 0, Lc, uc);            \
+            k_face_gs_fused<T, VK, 2, PR, TJ><<<g2, GS_NT, 0, s>>>(L, x, y, f, kap, backward,        \
+                                                                   ntile_blocks, 0, Lc, uc);        \
     } while (0)
         if (op == OP_DIFFUSION) {
-            if (uc) HHG_FACE_LAUNCH(true, true);
-            else HHG_FACE_LAUNCH(true, false);
+            constexpr int TJV = sizeof(T) == 8 ? GS_TJ16 : GS_TJ;
+            if (uc) HHG_FACE_LAUNCH(true, true, TJV);
+            else HHG_FACE_LAUNCH(true, false, TJV);
         } else {
-            if (uc) HHG_FACE_LAUNCH(false, true);
-            else HHG_FACE_LAUNCH(false, false);
+            if (uc) HHG_FACE_LAUNCH(false, true, GS_TJ);
+            else HHG_FACE_LAUNCH(false, false, GS_TJ);
         }
 #undef HHG_FACE_LAUNCH
         return hipGetLastError();

@@ -306,6 +306,10 @@ void MeshData::build_level(int level) {
     for (int ti = 0; ti * GS_TI <= n - 1; ++ti)
         for (int tj = 0; tj * GS_TJ <= n - 1; ++tj)
             if (ti * GS_TI + tj * GS_TJ <= n - 1) H.gs_tiles.push_back(make_int2(ti, tj));
+    H.gs_tiles16.clear();
+    for (int ti = 0; ti * GS_TI <= n - 1; ++ti)
+        for (int tj = 0; tj * GS_TJ16 <= n - 1; ++tj)
+            if (ti * GS_TI + tj * GS_TJ16 <= n - 1) H.gs_tiles16.push_back(make_int2(ti, tj));
 
     // learned-smoother output tiles that contain interior points
     H.net_tiles.clear();

@@ -119,10 +119,27 @@ def test_smooth_parity(name, L, backward, sweeps):
                                        ("annulus64", 6, (2, 0)), ("annulus64", 7, (3, 3)),
                                        ("annulus128", 7, (1, 2))])
 def test_vcycle_parity(name, L, nu):
+    _vcycle_parity(name, L, nu, 2)
+
+
+@pytest.mark.parametrize("name,L,lc,coarse", [("annulus64", 6, 3, "direct"), ("square", 6, 3, "direct"),
+                                              ("annulus64", 5, 4, "pcg")])
+def test_vcycle_parity_other_coarse_levels(name, L, lc, coarse):
+    """The coarsest level is a parameter (sec. 4.3 fixes none).  Level 3 of
+    the annulus (1,920 coarse unknowns) still takes the stored inverse; level
+    4 (7,936) exceeds it and the library falls back to Jacobi-PCG, compared
+    with the oracle's PCG option."""
+    _vcycle_parity(name, L, (3, 3), lc, coarse)
+
+
+def _vcycle_parity(name, L, nu, lc, coarse="direct"):
     import paper_1805_10167_amd as P
-    log("vcycle %s L=%d nu=%s" % (name, L, nu))
-    g = mesh(name, L)
-    H = oracle_hierarchy(name, L, 2)
+    from oracle.mesh import MacroMesh
+    from oracle.mg import Hierarchy
+    log("vcycle %s L=%d nu=%s lc=%d" % (name, L, nu, lc))
+    g = mesh(name, L) if lc == 2 else gpu_mesh(name, L, lc, P.HHG_FEAT_F64 | P.HHG_FEAT_MP)
+    H = (oracle_hierarchy(name, L, lc) if coarse == "direct"
+         else Hierarchy(MacroMesh(*hi.mesh_by_name(name)), L, lc, coarse="pcg"))
     lv = H.levels[L]
     u, f = canon_vec(lv, 5), canon_vec(lv, 6)
     uf, ff = g.from_canonical(L, u), g.from_canonical(L, f)

@@ -151,3 +151,20 @@ def test_variable_k_brute_force_quadrature():
         kq = np.mean([0.5 * (kap[t[a]] + kap[t[b]]) for a, b in ((0, 1), (1, 2), (0, 2))])
         ref[np.ix_(t, t)] += kq * area * (G.T @ G)
     assert np.abs(A - ref).max() < 1e-12
+
+
+@pytest.mark.parametrize("variable_k", [False, True])
+def test_rows_at_equals_assembled_rows(variable_k):
+    """The sampled-row operator (for levels too large to assemble) equals the
+    rows of the globally assembled stiffness."""
+    from oracle.assemble import assemble, rows_at
+    m = MacroMesh(*hi.annulus(16))
+    lv = Level(m, 4)
+    rng = np.random.default_rng(0)
+    x = rng.standard_normal(lv.n_all)
+    pts = np.concatenate([np.arange(m.V), rng.choice(lv.n_all, 300, replace=False)])
+    pts = np.unique(pts)
+    kf = (lambda xy: np.exp(hi.grf_eval(xy, 3))) if variable_k else None
+    A = assemble(lv, None if kf is None else kf(lv.xy))["A"]
+    got = rows_at(lv, pts, x, kf)
+    assert np.abs(got - (A @ x)[pts]).max() <= 1e-13 * np.abs(A @ x).max()
