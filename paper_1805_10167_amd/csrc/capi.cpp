@@ -172,36 +172,43 @@ void* level_r(const hhg_mesh* M, int l, int dt) { return dt == HHG_F64 ? M->r64[
 
 void* level_alt(const hhg_mesh* M, int l, int dt) { return dt == HHG_F64 ? M->a64[l] : M->a32[l]; }
 
-// Learned-smoother sweep (FP32): Gauss-Seidel stages A and B on edges and
-// vertices, then u += N(D^-1 (f - A u)) on face interiors; the backward
-// sweep runs the face step first.  In place, rho in the level's r32 field.
-int net_sweep(const hhg_mesh* M, int level, int op, void* u, const void* f, int backward, hipStream_t s) {
+// Learned-smoother sweep (FP32), x -> y: Gauss-Seidel stages A and B on
+// edges and vertices (in place on x, then a refresh of the stage-B corner
+// copies), then the face step y = x + N(D^-1 (f - A x)) on face interiors
+// with the ring values of D^-1 (f - A x) from an edge/vertex pass; the
+// backward sweep runs the face step first and the stages on y after it.
+int net_sweep(const hhg_mesh* M, int level, int op, void* x_, void* y_, const void* f_, int backward,
+              hipStream_t s) {
+    float* x = (float*)x_;
+    float* y = (float*)y_;
+    const float* f = (const float*)f_;
     float* rho = (float*)M->r32[level];
     auto face_step = [&]() -> int {
-        HIP_CHECK(launch_jacobi(M, level, op, HHG_F32, u, f, rho, s), "net rho");
-        HIP_CHECK(launch_net_forward(M, level, rho, (float*)u, 1, M->net_mfma, s), "net step");
+        HIP_CHECK(launch_jacobi_low(M, level, op, x, f, rho, s), "net rho");
+        HIP_CHECK(launch_net_step(M, level, op, x, y, f, rho, M->net_mfma, s), "net step");
         return HHG_OK;
     };
     int rc;
-    if (backward && (rc = face_step())) return rc;
-    HIP_CHECK(launch_low_gs(M, level, op, HHG_F32, u, f, backward ? 1 : 0, s), "stage");
-    HIP_CHECK(launch_low_gs(M, level, op, HHG_F32, u, f, backward ? 0 : 1, s), "stage");
-    if (!backward) {
-        // stage B left the ghost-row corner copies to its successor
-        HIP_CHECK(launch_low_gs(M, level, op, HHG_F32, u, f, 2, s), "corner copies");
+    if (backward) {
         if ((rc = face_step())) return rc;
+        HIP_CHECK(launch_low_gs(M, level, op, HHG_F32, y, f, 1, s), "stage");
+        HIP_CHECK(launch_low_gs(M, level, op, HHG_F32, y, f, 0, s), "stage");
+        return HHG_OK;
     }
-    return HHG_OK;
+    HIP_CHECK(launch_low_gs(M, level, op, HHG_F32, x, f, 0, s), "stage");
+    HIP_CHECK(launch_low_gs(M, level, op, HHG_F32, x, f, 1, s), "stage");
+    // stage B left the ghost-row corner copies to its successor
+    HIP_CHECK(launch_low_gs(M, level, op, HHG_F32, x, f, 2, s), "corner copies");
+    return face_step();
 }
 
-// `sweeps` sweeps; Gauss-Seidel sweeps alternate between the buffers x and
-// y, learned sweeps stay in x.  *out receives the buffer with the result.
 int smooth_pp(const hhg_mesh* M, int level, int op, int smoother, int dt, void* x, void* y,
               const void* f, int sweeps, int backward, hipStream_t s, void** out) {
     for (int i = 0; i < sweeps; ++i) {
         if (smoother == HHG_SMOOTH_NET) {
-            int rc = net_sweep(M, level, op, x, f, backward, s);
+            int rc = net_sweep(M, level, op, x, y, f, backward, s);
             if (rc) return rc;
+            std::swap(x, y);
             continue;
         }
         HIP_CHECK(launch_gs_sweep(M, level, op, dt, x, y, f, backward, s), "smooth");

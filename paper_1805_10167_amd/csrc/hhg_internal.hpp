@@ -25,7 +25,7 @@ constexpr int GS_TI = 192 - 2 * GS_H;
 constexpr int GS_TJ = 24;
 constexpr int GS_TJ16 = 16;   // tile height of the variable-coefficient FP64 smoother
 // learned-smoother tile: NET_TI x NET_TJ output points
-constexpr int NET_TI = 60;
+constexpr int NET_TI = 58;
 constexpr int NET_TJ = 12;
 constexpr int COARSE_DENSE_MAXN = 2048;   // coarse systems solved with a stored inverse
 constexpr int NET_NW = 224;     // weights: W1[16][7] then W2[16][7]

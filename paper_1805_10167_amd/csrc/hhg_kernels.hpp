@@ -34,6 +34,13 @@ hipError_t launch_mp_step(const hhg_mesh* M, int level, int op, const double* x,
 // prolongation and the first post-smoothing sweep in the same launches.
 hipError_t launch_gs_sweep_prolong(const hhg_mesh* M, int level, int op, int dtype, void* x, void* y,
                                    const void* f, const void* uc, hipStream_t s);
+// Jacobi-scaled residual at edge and vertex points only (FP32), with their
+// copies (face rings included).
+hipError_t launch_jacobi_low(const hhg_mesh* M, int level, int op, const float* u, const float* f,
+                             float* rho, hipStream_t s);
+// Face step of the learned sweep, x -> y (see k_net_step).
+hipError_t launch_net_step(const hhg_mesh* M, int level, int op, const float* x, float* y, const float* f,
+                           const float* rho_ring, bool mfma, hipStream_t s);
 hipError_t launch_restrict(const hhg_mesh* M, int level, int dtype, const void* r, void* fc,
                            void* uc, hipStream_t s);
 // u (level) += P uc (level-1) on interior points, copies included.

@@ -1692,6 +1692,14 @@ static hipError_t jacobi_t(const hhg_mesh* M, int level, int op, const T* u, con
     return hipGetLastError();
 }
 
+hipError_t launch_jacobi_low(const hhg_mesh* M, int level, int op, const float* u, const float* f,
+                             float* rho, hipStream_t s) {
+    const LevelDev L = M->dev(level);
+    k_apply<float, 2><<<grid_for(low_items(L), MAX_LOW_BLOCKS), NT, 0, s>>>(L, op, u, f, rho, M->kap32[level], 0,
+                                                                             nullptr);
+    return hipGetLastError();
+}
+
 hipError_t launch_jacobi(const hhg_mesh* M, int level, int op, int dtype, const void* u, const void* f,
                          void* rho, hipStream_t s) {
     if (dtype == DT_F64) return jacobi_t<double>(M, level, op, (const double*)u, (const double*)f, (double*)rho, s);

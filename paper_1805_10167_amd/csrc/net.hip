@@ -16,6 +16,7 @@
 // k % 4; D[m][n] in lane n + 16 (m / 4) element m % 4.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cstdint>
 
 #include "hhg_kernels.hpp"
@@ -23,9 +24,15 @@
 namespace hhg {
 
 constexpr int NET_NT = 256;
+constexpr int NWV = NET_NT / 64;                      // waves per block
 constexpr int NZ = NET_TI + 2, NZR = NET_TJ + 2;      // hidden/z region (tile + 1)
 constexpr int NRW = NET_TI + 4, NRR = NET_TJ + 4;     // rho region (tile + 2)
-constexpr int NPX = NZ * NZR;                          // pixels of the hidden region
+constexpr int NXW = NET_TI + 6, NXR = NET_TJ + 6;     // x region of the fused step (tile + 3)
+// LDS rows of every region are 64 values: one per lane of a wave, so a wave
+// works on whole rows with wave-uniform row offsets.  The hidden row of 60
+// pixels is four MFMA groups of 16 (4 slots unused).
+constexpr int RW = 64;
+static_assert(NXW == RW, "x region row = one wave");
 
 __constant__ int c_di[7] = {0, 1, -1, 0, 0, 1, -1};
 __constant__ int c_dj[7] = {0, 0, 0, 1, -1, -1, 1};
@@ -38,10 +45,8 @@ typedef __bf16 bf16x4 __attribute__((ext_vector_type(4)));
 
 // Round to nearest even BF16 (the hardware conversion).
 __device__ __forceinline__ short4v to_bf16x4(float a, float b, float c, float d) {
-    const bf16x2 lo = __builtin_convertvector((float2v){a, b}, bf16x2);
-    const bf16x2 hi = __builtin_convertvector((float2v){c, d}, bf16x2);
-    const bf16x4 v = {lo[0], lo[1], hi[0], hi[1]};
-    return __builtin_bit_cast(short4v, v);
+    const float4v f = {a, b, c, d};
+    return __builtin_bit_cast(short4v, __builtin_convertvector(f, bf16x4));
 }
 __device__ __forceinline__ float bf16_round(float x) { return (float)(__bf16)x; }
 
@@ -57,152 +62,301 @@ __device__ __forceinline__ int64_t nedge_ghost(const LevelDev& L, int e, int s) 
     return L.edge_base + (int64_t)e * L.edge_stride + L.ghost_off + (int64_t)s * L.ghost_stride;
 }
 
-// z_t over the tile grown by 1: MFMA (BF16) or FP32 arithmetic.  Each wave
-// takes groups of 16 hidden pixels; two groups per trip give the scheduler
-// independent MFMA chains to interleave.
-constexpr int NGRP = (NPX + 15) / 16;
-constexpr int NWV = NET_NT / 64;
-constexpr int GPW = (NGRP + NWV - 1) / NWV;
-
+// z_t over the hidden region (tile grown by 1): MFMA (BF16) or FP32.
+// rs[r][c]: rho at (i0 - 2 + c, j0 - 2 + r); zs[t][r][c]: z_t at hidden
+// pixel (i0 - 1 + c, j0 - 1 + r).  A wave takes whole hidden rows; in an
+// MFMA group lane l16 is pixel 16 q + l16 of the row and lane group q4
+// holds taps (layer 1) or channels (layer 2) 4 q4 .. 4 q4 + 3.
 template <bool MFMA>
 __device__ __forceinline__ void net_hidden(int n, int i0, int j0, const float* __restrict__ W,
-                                           float (*rs)[NRW], float (*zs)[NPX]) {
+                                           float (*rs)[RW], float (*zs)[NZR][RW]) {
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     if (MFMA) {
         const int q4 = lane >> 4, l16 = lane & 15;
         float a1[4], a2[4];
+        int toff[4];
+        bool tval[4];
 #pragma unroll
         for (int e = 0; e < 4; ++e) {
             const int t = 4 * q4 + e;
             a1[e] = t < 7 ? W[l16 * 7 + t] : 0.f;            // A[c = l16][k = t]
             a2[e] = l16 < 7 ? W[112 + t * 7 + l16] : 0.f;     // B[k = c = t][n = tap l16]
+            tval[e] = t < 7;
+            toff[e] = t < 7 ? (1 + c_dj[t]) * RW + (1 + c_di[t]) : RW + 1;
         }
         const short4v w1op = to_bf16x4(a1[0], a1[1], a1[2], a1[3]);
         const short4v w2op = to_bf16x4(a2[0], a2[1], a2[2], a2[3]);
-        int di[4], dj[4];
-#pragma unroll
-        for (int e = 0; e < 4; ++e) {
-            const int t = 4 * q4 + e;
-            di[e] = t < 7 ? c_di[t] : 0;
-            dj[e] = t < 7 ? c_dj[t] : 0;
-        }
+        for (int row = wv; row < NZR; row += NWV) {
+            const int j = j0 - 1 + row;
 #pragma unroll 2
-        for (int it = 0; it < GPW; ++it) {
-            const int g = wv + NWV * it;
-            if (g >= NGRP) break;
-            const int px = g * 16 + l16;
-            const int pxc = px < NPX ? px : NPX - 1;
-            const int rr = pxc / NZ, cc = pxc - rr * NZ;
-            float v[4];
-#pragma unroll
-            for (int e = 0; e < 4; ++e) {
-                const float x = rs[rr + 1 + dj[e]][cc + 1 + di[e]];
-                v[e] = (4 * q4 + e < 7) ? x : 0.f;
-            }
-            float4v acc = {0.f, 0.f, 0.f, 0.f};
-            acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(w1op, to_bf16x4(v[0], v[1], v[2], v[3]),
-                                                            acc, 0, 0, 0);
-            // lane holds a for channels 4 q4 + e of pixel l16: ReLU on interior
-            const int j = j0 - 1 + rr, i = i0 - 1 + cc;
-            const bool inner = px < NPX && j >= 1 && i >= 1 && i + j <= n - 2;
-            const short4v hop = to_bf16x4(inner ? fmaxf(acc[0], 0.f) : 0.f, inner ? fmaxf(acc[1], 0.f) : 0.f,
-                                          inner ? fmaxf(acc[2], 0.f) : 0.f, inner ? fmaxf(acc[3], 0.f) : 0.f);
-            float4v z = {0.f, 0.f, 0.f, 0.f};
-            z = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(hop, w2op, z, 0, 0, 0);
-            // lane holds z for tap l16 of pixels 4 q4 + e
-            if (l16 < 7)
+            for (int q = 0; q < 4; ++q) {
+                const int cc = 16 * q + l16;
+                const float* base = &rs[row][cc];
+                // the hidden layer exists on interior pixels only: zero taps there
+                // give a = 0 exactly, so ReLU needs no mask afterwards
+                const int i = i0 - 1 + cc;
+                const bool inner = cc < NZ && j >= 1 && i >= 1 && i + j <= n - 2;
+                float v[4];
 #pragma unroll
                 for (int e = 0; e < 4; ++e) {
-                    const int p2 = g * 16 + 4 * q4 + e;
-                    if (p2 < NPX) zs[l16][p2] = z[e];
+                    const float xv = base[toff[e]];
+                    v[e] = (tval[e] && inner) ? xv : 0.f;
                 }
+                float4v acc = {0.f, 0.f, 0.f, 0.f};
+                acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(w1op, to_bf16x4(v[0], v[1], v[2], v[3]),
+                                                                acc, 0, 0, 0);
+                // lane holds a for channels 4 q4 + e of pixel cc
+                const short4v hop = to_bf16x4(fmaxf(acc[0], 0.f), fmaxf(acc[1], 0.f), fmaxf(acc[2], 0.f),
+                                              fmaxf(acc[3], 0.f));
+                float4v z = {0.f, 0.f, 0.f, 0.f};
+                z = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(hop, w2op, z, 0, 0, 0);
+                // lane holds z for tap l16 of pixels 16 q + 4 q4 + e
+                if (l16 < 7) {
+                    float* zr = &zs[l16][row][16 * q + 4 * q4];
+#pragma unroll
+                    for (int e = 0; e < 4; ++e) zr[e] = z[e];
+                }
+            }
         }
     } else {
-        for (int px = threadIdx.x; px < NPX; px += NET_NT) {
-            const int rr = px / NZ, cc = px - rr * NZ;
-            const int j = j0 - 1 + rr, i = i0 - 1 + cc;
-            const bool inner = j >= 1 && i >= 1 && i + j <= n - 2;
-            float rt[7];
-            for (int t = 0; t < 7; ++t) rt[t] = rs[rr + 1 + c_dj[t]][cc + 1 + c_di[t]];
+        for (int row = wv; row < NZR; row += NWV) {
+            const int cc = lane, j = j0 - 1 + row, i = i0 - 1 + cc;
+            const bool inner = cc < NZ && j >= 1 && i >= 1 && i + j <= n - 2;
             float z[7] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
-            for (int c = 0; c < 16; ++c) {
-                float a = 0.f;
-                for (int t = 0; t < 7; ++t) a += W[c * 7 + t] * rt[t];
-                const float h = inner ? fmaxf(a, 0.f) : 0.f;
-                for (int t = 0; t < 7; ++t) z[t] += W[112 + c * 7 + t] * h;
+            if (cc < NZ) {
+                float rt[7];
+                for (int t = 0; t < 7; ++t) rt[t] = rs[row + 1 + c_dj[t]][cc + 1 + c_di[t]];
+                for (int c = 0; c < 16; ++c) {
+                    float a = 0.f;
+                    for (int t = 0; t < 7; ++t) a += W[c * 7 + t] * rt[t];
+                    const float h = inner ? fmaxf(a, 0.f) : 0.f;
+                    for (int t = 0; t < 7; ++t) z[t] += W[112 + c * 7 + t] * h;
+                }
             }
-            for (int t = 0; t < 7; ++t) zs[t][px] = z[t];
+            for (int t = 0; t < 7; ++t) zs[t][row][cc] = z[t];
         }
     }
 }
 
+// out at output pixel (i0 + c, j0 + r) from the z planes.
+__device__ __forceinline__ float net_out(float (*zs)[NZR][RW], int r, int c) {
+    float o = 0.f;
+#pragma unroll
+    for (int t = 0; t < 7; ++t) o += zs[t][r + 1 + c_dj[t]][c + 1 + c_di[t]];
+    return o;
+}
+
 // out = N(rho) on face-interior points (mode 0: write out, whose other
 // entries the caller has zeroed; mode 1: u += N(rho) in place).  Both write
-// the near-edge-row copies of what they change.  All global loads of a
-// thread are issued together: rho for the LDS tile, then (mode 1) the
-// outputs' old values, which arrive while the MFMA phase runs.
-constexpr int NLD = (NRR * NRW + NET_NT - 1) / NET_NT;
-constexpr int NOUT = (NET_TI * NET_TJ + NET_NT - 1) / NET_NT;
+// the near-edge-row copies of what they change.  Waves take whole rows of
+// each region; a thread issues its global loads (rho, then the outputs' old
+// values) before any of them is used.
+constexpr int NLR = (NRR + NWV - 1) / NWV;      // rho rows per wave
+constexpr int NOR = (NET_TJ + NWV - 1) / NWV;   // output rows per wave
 
 template <class T, bool MFMA>
 __global__ __launch_bounds__(NET_NT) void k_net_forward(LevelDev L, const T* __restrict__ rho,
                                                         T* __restrict__ y, const float* __restrict__ W,
                                                         int mode) {
-    __shared__ float rs[NRR][NRW];
-    __shared__ float zs[7][NPX];
+    __shared__ float rs[NRR + 1][RW];
+    __shared__ float zs[7][NZR][RW];
     const int n = L.n;
-    const int face = blockIdx.x / L.n_net_tiles;
-    const int2 tl = L.net_tiles[blockIdx.x % L.n_net_tiles];
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int ntile = L.F * L.n_net_tiles;
+    for (int tile = blockIdx.x; tile < ntile; tile += gridDim.x) {
+    __syncthreads();                                   // LDS of the previous tile is free
+    const int face = tile / L.n_net_tiles;
+    const int2 tl = L.net_tiles[tile % L.n_net_tiles];
     const int i0 = tl.x * NET_TI, j0 = tl.y * NET_TJ;
     const FaceInfo& fi = L.faces[face];
     const int64_t fb = nface_base(L, face);
-    float v[NLD];
+    float v[NLR];
 #pragma unroll
-    for (int k = 0; k < NLD; ++k) {
-        const int idx = threadIdx.x + k * NET_NT;
-        const int r = idx / NRW, c = idx - r * NRW;
-        const int j = j0 - 2 + r, i = i0 - 2 + c;
-        v[k] = 0.f;
-        if (idx < NRR * NRW && j >= 0 && j < n && i >= 0 && i <= n - 1 - j)
-            v[k] = (float)rho[fb + nrow_start(n, j) + i];
+    for (int k = 0; k < NLR; ++k) {
+        const int r = wv + NWV * k, j = j0 - 2 + r, i = i0 - 2 + lane;
+        const bool in = r < NRR && lane < NRW && j >= 0 && j < n && i >= 0 && i <= n - 1 - j;
+        v[k] = in ? (float)rho[fb + nrow_start(n, in ? j : 0) + i] : 0.f;
     }
-    int64_t po[NOUT];
-    float yo[NOUT];
+    float yo[NOR];
 #pragma unroll
-    for (int k = 0; k < NOUT; ++k) {
-        const int idx = threadIdx.x + k * NET_NT;
-        const int rr = idx / NET_TI, cc = idx - rr * NET_TI;
-        const int j = j0 + rr, i = i0 + cc;
-        const bool ok = idx < NET_TI * NET_TJ && j >= 1 && i >= 1 && i + j <= n - 2;
-        po[k] = ok ? fb + nrow_start(n, j) + i : -1;
-        yo[k] = 0.f;
-        if (ok && mode == 1) yo[k] = (float)y[po[k]];
+    for (int k = 0; k < NOR; ++k) {
+        const int r = wv + NWV * k, j = j0 + r, i = i0 + lane;
+        const bool ok = r < NET_TJ && lane < NET_TI && j >= 1 && i >= 1 && i + j <= n - 2;
+        yo[k] = (ok && mode == 1) ? (float)y[fb + nrow_start(n, ok ? j : 0) + i] : 0.f;
     }
 #pragma unroll
-    for (int k = 0; k < NLD; ++k) {
-        const int idx = threadIdx.x + k * NET_NT;
-        if (idx < NRR * NRW) rs[idx / NRW][idx % NRW] = v[k];
+    for (int k = 0; k < NLR; ++k) {
+        const int r = wv + NWV * k;
+        if (r < NRR) rs[r][lane] = v[k];
     }
+    if (wv == 0) rs[NRR][lane] = 0.f;
     __syncthreads();
     net_hidden<MFMA>(n, i0, j0, W, rs, zs);
     __syncthreads();
 #pragma unroll
-    for (int k = 0; k < NOUT; ++k) {
-        if (po[k] < 0) continue;
-        const int idx = threadIdx.x + k * NET_NT;
-        const int rr = idx / NET_TI, cc = idx - rr * NET_TI;
-        const int j = j0 + rr, i = i0 + cc;
-        float o = 0.f;
-#pragma unroll
-        for (int t = 0; t < 7; ++t) o += zs[t][(rr + 1 + c_dj[t]) * NZ + (cc + 1 + c_di[t])];
-        const T val = (T)(yo[k] + o);
-        y[po[k]] = val;
+    for (int k = 0; k < NOR; ++k) {
+        const int r = wv + NWV * k, j = j0 + r, i = i0 + lane;
+        if (!(r < NET_TJ && lane < NET_TI && j >= 1 && i >= 1 && i + j <= n - 2)) continue;
+        const T val = (T)(yo[k] + net_out(zs, r, lane));
+        y[fb + nrow_start(n, j) + i] = val;
         if (j == 1 && i <= n - 2 && !fi.bside[0])
             y[nedge_ghost(L, fi.edge[0], fi.slot[0]) + (fi.rev[0] ? n - 2 - i : i)] = val;
         if (i == 1 && j <= n - 2 && !fi.bside[1])
             y[nedge_ghost(L, fi.edge[1], fi.slot[1]) + (fi.rev[1] ? n - 2 - j : j)] = val;
         if (i + j == n - 2 && !fi.bside[2])
             y[nedge_ghost(L, fi.edge[2], fi.slot[2]) + (fi.rev[2] ? n - 2 - j : j)] = val;
+    }
+    }
+}
+
+// Face step of the learned sweep in one pass, from x to y:
+//   rho = D^-1 (f - A x) on the tile grown by 2 (face-interior points from an
+//   LDS tile of x grown by 3; ring points from rho_ring, written beforehand
+//   by the edge/vertex Jacobi pass; 0 outside the triangle),
+//   y = x + N(rho) on the tile's face-interior points, with their near-row
+//   copies in y's ghost rows.
+// Extra blocks copy what the face step leaves unchanged from x to y: edge
+// and vertex blocks, face rings and the ghost-row corner entries, so y is a
+// complete field.  Reading x and writing y keeps the halo reads of
+// neighbouring tiles free of updated values.
+constexpr int NS_COPY_BLOCKS = 32;
+constexpr int NXL = (NXR + NWV - 1) / NWV;      // x rows per wave
+
+template <bool VARK>
+__device__ __forceinline__ float net_rho_point(const FaceInfo& fi, float (*xs)[RW], float (*ks)[RW],
+                                               int r, int c, float fv) {
+    const float uE = xs[r][c + 1], uW = xs[r][c - 1], uN = xs[r + 1][c], uS = xs[r - 1][c];
+    const float uSE = xs[r - 1][c + 1], uNW = xs[r + 1][c - 1], u0 = xs[r][c];
+    const float c0 = (float)fi.cot[0], c1 = (float)fi.cot[1], c2 = (float)fi.cot[2];
+    float we, ww, wn, ws, wse, wnw, wc;
+    if (!VARK) {
+        wc = (float)(2.0 * (fi.cot[0] + fi.cot[1] + fi.cot[2]));
+        we = ww = -c2;
+        wn = ws = -c1;
+        wse = wnw = -c0;
+    } else {
+        const float k0 = ks[r][c], kE = ks[r][c + 1], kW = ks[r][c - 1], kN = ks[r + 1][c];
+        const float kS = ks[r - 1][c], kSE = ks[r - 1][c + 1], kNW = ks[r + 1][c - 1];
+        const float third = 1.0f / 3.0f, h = 0.5f;
+        const float t1 = (k0 + kE + kN) * third, t2 = (kSE + kE + k0) * third;
+        const float t3 = (kW + k0 + kNW) * third, t4 = (kS + k0 + kW) * third;
+        const float t5 = (k0 + kN + kNW) * third, t6 = (kS + kSE + k0) * third;
+        we = -h * c2 * (t1 + t2);
+        ww = -h * c2 * (t3 + t4);
+        wn = -h * c1 * (t1 + t5);
+        ws = -h * c1 * (t6 + t4);
+        wse = -h * c0 * (t6 + t2);
+        wnw = -h * c0 * (t3 + t5);
+        wc = -(we + ww + wn + ws + wse + wnw);
+    }
+    const float ax = wc * u0 + we * uE + ww * uW + wn * uN + ws * uS + wse * uSE + wnw * uNW;
+    return (fv - ax) / wc;
+}
+
+template <bool VARK, bool MFMA>
+__global__ __launch_bounds__(NET_NT) void k_net_step(LevelDev L, const float* __restrict__ x,
+                                                     float* __restrict__ y, const float* __restrict__ f,
+                                                     const float* __restrict__ kap,
+                                                     const float* __restrict__ rho_ring,
+                                                     const float* __restrict__ W, int nblk_tiles) {
+    __shared__ float xs[NXR][RW];
+    __shared__ float ks[VARK ? NXR : 1][RW];
+    __shared__ float rs[NRR + 1][RW];
+    __shared__ float zs[7][NZR][RW];
+    const int n = L.n;
+    if ((int)blockIdx.x >= nblk_tiles) {
+        // copies x -> y: edge main (k = 0..n-1), vertex blocks, face rings,
+        // ghost-row corner entries
+        const int cb = blockIdx.x - nblk_tiles, ncb = gridDim.x - nblk_tiles;
+        const int64_t ne = (int64_t)L.E * n, nv = (int64_t)L.V * L.vert_stride;
+        const int64_t nr = (int64_t)L.F * 3 * (n - 1), ng = (int64_t)L.E * 4;
+        for (int64_t t = (int64_t)cb * NET_NT + threadIdx.x; t < ne + nv + nr + ng; t += (int64_t)ncb * NET_NT) {
+            int64_t off;
+            if (t < ne) {
+                off = L.edge_base + (t / n) * L.edge_stride + (t % n);
+            } else if (t < ne + nv) {
+                off = L.vert_base + (t - ne);
+            } else if (t < ne + nv + nr) {
+                const int64_t q = t - ne - nv;
+                const int face = (int)(q / (3 * (n - 1))), m = (int)(q % (3 * (n - 1)));
+                const int sd = m / (n - 1), tt = m % (n - 1);
+                int i, j;
+                if (sd == 0) { i = tt; j = 0; }
+                else if (sd == 1) { i = n - 1 - tt; j = tt; }
+                else { i = 0; j = n - 1 - tt; }
+                off = nface_base(L, face) + nrow_start(n, j) + i;
+            } else {
+                const int64_t q = t - ne - nv - nr;
+                const int e = (int)(q >> 2), sl = (int)((q >> 1) & 1), end = (int)(q & 1);
+                if (L.edges[e].boundary) continue;
+                off = nedge_ghost(L, e, sl) + (end ? n - 2 : 0);
+            }
+            y[off] = x[off];
+        }
+        return;
+    }
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int ntile = L.F * L.n_net_tiles;
+    for (int tile = blockIdx.x; tile < ntile; tile += nblk_tiles) {
+    __syncthreads();                                   // LDS of the previous tile is free
+    const int face = tile / L.n_net_tiles;
+    const int2 tl = L.net_tiles[tile % L.n_net_tiles];
+    const int i0 = tl.x * NET_TI, j0 = tl.y * NET_TJ;
+    const FaceInfo& fi = L.faces[face];
+    const int64_t fb = nface_base(L, face);
+    // x (and k) over the tile grown by 3: row r of wave wv + NWV k, column = lane
+    float xv[NXL], kv[VARK ? NXL : 1];
+#pragma unroll
+    for (int k = 0; k < NXL; ++k) {
+        const int r = wv + NWV * k, j = j0 - 3 + r, i = i0 - 3 + lane;
+        const bool in = r < NXR && j >= 0 && j < n && i >= 0 && i <= n - 1 - j;
+        const int64_t p = fb + nrow_start(n, in ? j : 0) + i;
+        xv[k] = in ? x[p] : 0.f;
+        if (VARK) kv[k] = in ? kap[p] : 0.f;
+    }
+    // f at the rho region's interior points, rho at its ring points
+    float fv[NLR];
+#pragma unroll
+    for (int k = 0; k < NLR; ++k) {
+        const int r = wv + NWV * k, j = j0 - 2 + r, i = i0 - 2 + lane;
+        const bool in = r < NRR && lane < NRW && j >= 0 && j < n && i >= 0 && i <= n - 1 - j;
+        const bool interior = in && j >= 1 && i >= 1 && i + j <= n - 2;
+        const int64_t p = fb + nrow_start(n, in ? j : 0) + i;
+        fv[k] = interior ? f[p] : (in ? rho_ring[p] : 0.f);
+    }
+#pragma unroll
+    for (int k = 0; k < NXL; ++k) {
+        const int r = wv + NWV * k;
+        if (r < NXR) {
+            xs[r][lane] = xv[k];
+            if (VARK) ks[r][lane] = kv[k];
+        }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < NLR; ++k) {
+        const int r = wv + NWV * k, j = j0 - 2 + r, i = i0 - 2 + lane;
+        if (r >= NRR) continue;
+        const bool interior = lane < NRW && j >= 1 && i >= 1 && i + j <= n - 2;
+        rs[r][lane] = interior ? net_rho_point<VARK>(fi, xs, VARK ? ks : nullptr, r + 1, lane + 1, fv[k]) : fv[k];
+    }
+    if (wv == 0) rs[NRR][lane] = 0.f;
+    __syncthreads();
+    net_hidden<MFMA>(n, i0, j0, W, rs, zs);
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < NOR; ++k) {
+        const int r = wv + NWV * k, j = j0 + r, i = i0 + lane;
+        if (!(r < NET_TJ && lane < NET_TI && j >= 1 && i >= 1 && i + j <= n - 2)) continue;
+        const float val = xs[r + 3][lane + 3] + net_out(zs, r, lane);
+        y[fb + nrow_start(n, j) + i] = val;
+        if (j == 1 && i <= n - 2 && !fi.bside[0])
+            y[nedge_ghost(L, fi.edge[0], fi.slot[0]) + (fi.rev[0] ? n - 2 - i : i)] = val;
+        if (i == 1 && j <= n - 2 && !fi.bside[1])
+            y[nedge_ghost(L, fi.edge[1], fi.slot[1]) + (fi.rev[1] ? n - 2 - j : j)] = val;
+        if (i + j == n - 2 && !fi.bside[2])
+            y[nedge_ghost(L, fi.edge[2], fi.slot[2]) + (fi.rev[2] ? n - 2 - j : j)] = val;
+    }
     }
 }
 
@@ -291,13 +445,33 @@ __global__ __launch_bounds__(256) void k_net_adam(float* __restrict__ W, float* 
     W[w] -= lr * mh / (sqrtf(vh) + eps);
 }
 
+// Workgroups that loop over the tiles (a few per CU): tiles are short-lived
+// work, so one workgroup per tile would be limited by wave launch.
+constexpr int NET_MAX_BLOCKS = 2048;
+
 hipError_t launch_net_forward(const hhg_mesh* M, int level, const float* rho, float* y, int mode,
                               bool mfma, hipStream_t s) {
     const LevelDev L = M->dev(level);
-    const int g = L.F * L.n_net_tiles;
+    const int g = std::min(L.F * L.n_net_tiles, NET_MAX_BLOCKS);
     if (g == 0) return hipSuccess;
     if (mfma) k_net_forward<float, true><<<g, NET_NT, 0, s>>>(L, rho, y, M->net_w, mode);
     else k_net_forward<float, false><<<g, NET_NT, 0, s>>>(L, rho, y, M->net_w, mode);
+    return hipGetLastError();
+}
+
+hipError_t launch_net_step(const hhg_mesh* M, int level, int op, const float* x, float* y, const float* f,
+                           const float* rho_ring, bool mfma, hipStream_t s) {
+    const LevelDev L = M->dev(level);
+    const int nt = std::min(L.F * L.n_net_tiles, NET_MAX_BLOCKS);
+    const int g = nt + NS_COPY_BLOCKS;
+    const float* kap = M->kap32[level];
+    if (op == OP_DIFFUSION) {
+        if (mfma) k_net_step<true, true><<<g, NET_NT, 0, s>>>(L, x, y, f, kap, rho_ring, M->net_w, nt);
+        else k_net_step<true, false><<<g, NET_NT, 0, s>>>(L, x, y, f, kap, rho_ring, M->net_w, nt);
+    } else {
+        if (mfma) k_net_step<false, true><<<g, NET_NT, 0, s>>>(L, x, y, f, kap, rho_ring, M->net_w, nt);
+        else k_net_step<false, false><<<g, NET_NT, 0, s>>>(L, x, y, f, kap, rho_ring, M->net_w, nt);
+    }
     return hipGetLastError();
 }
 
