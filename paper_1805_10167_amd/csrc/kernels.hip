@@ -541,13 +541,15 @@ __global__ __launch_bounds__(1024) void k_reduce_final(const double* __restrict_
 // Linear interpolation of coarse face values at fine face point (i, j):
 // coincident points copy, midpoints of coarse micro-edges average the two
 // ends (horizontal, vertical, and the diagonal from (I+1, J) to (I, J+1)).
+// Branch-free over the parities: the two ends are (I + (io & jo), J) and
+// (I + (io & !jo), J + jo); at a coincident point both are (I, J), and
+// 0.5 (x + x) = x exactly.
 template <class T>
 __device__ __forceinline__ T prol_face(const T* __restrict__ uc, int64_t cb, int nc, int i, int j) {
-    const int I = i >> 1, J = j >> 1;
-    if (!(i & 1) && !(j & 1)) return uc[cb + row_start(nc, J) + I];
-    if ((i & 1) && !(j & 1)) return (T)0.5 * (uc[cb + row_start(nc, J) + I] + uc[cb + row_start(nc, J) + I + 1]);
-    if (!(i & 1) && (j & 1)) return (T)0.5 * (uc[cb + row_start(nc, J) + I] + uc[cb + row_start(nc, J + 1) + I]);
-    return (T)0.5 * (uc[cb + row_start(nc, J) + I + 1] + uc[cb + row_start(nc, J + 1) + I]);
+    const int I = i >> 1, J = j >> 1, io = i & 1, jo = j & 1;
+    const T a = uc[cb + row_start(nc, J) + I + (io & jo)];
+    const T b = uc[cb + row_start(nc, J + jo) + I + (io & (jo ^ 1))];
+    return (T)0.5 * (a + b);
 }
 
 // Dirichlet status of face point (i, j) (ring points on boundary sides or

@@ -445,14 +445,11 @@ __global__ __launch_bounds__(256) void k_net_adam(float* __restrict__ W, float* 
     W[w] -= lr * mh / (sqrtf(vh) + eps);
 }
 
-// Workgroups that loop over the tiles (a few per CU): tiles are short-lived
-// work, so one workgroup per tile would be limited by wave launch.
-constexpr int NET_MAX_BLOCKS = 2048;
 
 hipError_t launch_net_forward(const hhg_mesh* M, int level, const float* rho, float* y, int mode,
                               bool mfma, hipStream_t s) {
     const LevelDev L = M->dev(level);
-    const int g = std::min(L.F * L.n_net_tiles, NET_MAX_BLOCKS);
+    const int g = L.F * L.n_net_tiles;
     if (g == 0) return hipSuccess;
     if (mfma) k_net_forward<float, true><<<g, NET_NT, 0, s>>>(L, rho, y, M->net_w, mode);
     else k_net_forward<float, false><<<g, NET_NT, 0, s>>>(L, rho, y, M->net_w, mode);
@@ -462,7 +459,7 @@ hipError_t launch_net_forward(const hhg_mesh* M, int level, const float* rho, fl
 hipError_t launch_net_step(const hhg_mesh* M, int level, int op, const float* x, float* y, const float* f,
                            const float* rho_ring, bool mfma, hipStream_t s) {
     const LevelDev L = M->dev(level);
-    const int nt = std::min(L.F * L.n_net_tiles, NET_MAX_BLOCKS);
+    const int nt = L.F * L.n_net_tiles;
     const int g = nt + NS_COPY_BLOCKS;
     const float* kap = M->kap32[level];
     if (op == OP_DIFFUSION) {

@@ -2,6 +2,8 @@
 
     python -m paper_1805_10167_amd.profiling summarize \
         --stats DIR --fetch DIR --write DIR --kernel NAME --out FILE --cmd "..."
+    python -m paper_1805_10167_amd.profiling counters \
+        --stats DIR --pmc DIR [DIR ...] --kernel NAME --out FILE --cmd "..."
 
 reads the kernel-trace CSV of one run (average duration per kernel and grid
 size) and the counter CSVs of two --pmc runs (FETCH_SIZE, WRITE_SIZE, KiB
@@ -110,19 +112,64 @@ def traffic_for(path):
     return None
 
 
+def counter_table(pmc_dir):
+    """(kernel name, grid) -> {counter name: [values per dispatch]}."""
+    out = defaultdict(lambda: defaultdict(list))
+    for r in _csv(pmc_dir, "counter_collection.csv"):
+        out[(r["Kernel_Name"], int(r["Grid_Size"]))][r["Counter_Name"]].append(float(r["Counter_Value"]))
+    return out
+
+
+def counters_summary(stats_dir, pmc_dirs, kernel, cmd, out):
+    """Average duration and counters of the largest-grid dispatches of
+    `kernel`; MFMA operation counters (units of 512 flops) are turned into
+    achieved matrix-core TFLOP/s."""
+    dur = kernel_durations(stats_dir)
+    kd = _largest(dur, kernel)
+    avg_ns = sum(dur[kd]) / len(dur[kd])
+    vals = {}
+    for d in pmc_dirs:
+        tab = counter_table(d)
+        kk = _largest(tab, kernel)
+        for name, v in tab[kk].items():
+            vals[name] = sum(v) / len(v)
+    lines = ["# rocprofv3 counters: %s (grid %d)" % (kd[0], kd[1]), "",
+             "command: " + cmd, "kernel source hash: " + source_hash(), "",
+             "average duration: %.2f us over %d dispatches" % (avg_ns / 1e3, len(dur[kd])), "",
+             "counters (average per dispatch):"]
+    for name in sorted(vals):
+        lines.append("  %-34s %.4g" % (name, vals[name]))
+    mops = [v for n, v in vals.items() if n.startswith("SQ_INSTS_VALU_MFMA_MOPS_")]
+    rec = {"kernel": kd[0], "grid": kd[1], "avg_duration_us": avg_ns / 1e3, "counters": vals,
+           "command": cmd, "source_hash": source_hash()}
+    if mops:
+        flops = 512.0 * sum(mops)
+        rec["mfma_flops"] = flops
+        rec["mfma_tflops"] = flops / avg_ns / 1e3
+        lines += ["", "matrix-core work: %.4g flop per dispatch (MOPS x 512) -> %.2f TFLOP/s achieved"
+                  % (flops, rec["mfma_tflops"])]
+    lines += ["", "json: " + json.dumps(rec)]
+    with open(out, "w") as fh:
+        fh.write("\n".join(lines) + "\n")
+
+
 def main():
     ap = argparse.ArgumentParser()
-    ap.add_argument("mode", choices=["summarize"])
+    ap.add_argument("mode", choices=["summarize", "counters"])
     ap.add_argument("--stats", required=True)
-    ap.add_argument("--fetch", required=True)
-    ap.add_argument("--write", required=True)
+    ap.add_argument("--fetch")
+    ap.add_argument("--write")
+    ap.add_argument("--pmc", nargs="*", default=[])
     ap.add_argument("--kernel", required=True)
-    ap.add_argument("--copy-bytes", type=int, required=True)
+    ap.add_argument("--copy-bytes", type=int, default=0)
     ap.add_argument("--cmd", default="")
     ap.add_argument("--out", required=True)
     a = ap.parse_args()
-    s = summarize(a.stats, a.fetch, a.write, a.kernel, a.copy_bytes, a.cmd)
-    write_summary(s, a.out)
+    if a.mode == "summarize":
+        s = summarize(a.stats, a.fetch, a.write, a.kernel, a.copy_bytes, a.cmd)
+        write_summary(s, a.out)
+    else:
+        counters_summary(a.stats, a.pmc, a.kernel, a.cmd, a.out)
     print(open(a.out).read())
 
 
