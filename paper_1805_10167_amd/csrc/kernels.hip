@@ -881,13 +881,9 @@ __global__ __launch_bounds__(GS_NT) void k_face_gs_fused(LevelDev L, const T* __
 // stage A (which reads none of them) refreshes them; stage = 2 only
 // refreshes them.
 template <class T>
-__global__ __launch_bounds__(NT) void k_low_gs(LevelDev L, int op, T* __restrict__ u,
-                                               const T* __restrict__ f, const T* __restrict__ kap,
-                                               int stage) {
+__device__ __forceinline__ void low_gs_item(const LevelDev& L, int op, T* __restrict__ u, const T* __restrict__ f,
+                                            const T* __restrict__ kap, int stage, int64_t t, int64_t ne) {
     const int n = L.n;
-    const int64_t ne = (int64_t)L.n_iedges * (n - 2);
-    const int64_t nv = stage == 0 ? L.n_iverts : 0;
-    for (int64_t t = blockIdx.x * (int64_t)NT + threadIdx.x; t < ne + nv; t += (int64_t)gridDim.x * NT) {
         if (t < ne) {
             const int e = L.iedges[t / (n - 2)], k = (int)(t % (n - 2)) + 1;
             const EdgeInfo& ei = L.edges[e];
@@ -904,7 +900,7 @@ __global__ __launch_bounds__(NT) void k_low_gs(LevelDev L, int op, T* __restrict
                         }
                     }
                 }
-                continue;
+                return;
             }
             const int64_t g0 = edge_ghost(L, e, 0), g1 = edge_ghost(L, e, 1);
             const WE<T> w = edge_weights<T>(op, ei, L.inv4l, kap, m, g0, g1, k);
@@ -928,7 +924,17 @@ __global__ __launch_bounds__(NT) void k_low_gs(LevelDev L, int op, T* __restrict
             u[vb] = v;
             push_vertex(L, u, vi, v);
         }
-    }
+}
+
+template <class T>
+__global__ __launch_bounds__(NT) void k_low_gs(LevelDev L, int op, T* __restrict__ u,
+                                               const T* __restrict__ f, const T* __restrict__ kap,
+                                               int stage) {
+    const int n = L.n;
+    const int64_t ne = (int64_t)L.n_iedges * (n - 2);
+    const int64_t nv = stage == 0 ? L.n_iverts : 0;
+    for (int64_t t = blockIdx.x * (int64_t)NT + threadIdx.x; t < ne + nv; t += (int64_t)gridDim.x * NT)
+        low_gs_item<T>(L, op, u, f, kap, stage, t, ne);
 }
 
 // Restriction, the transpose of linear interpolation: a coarse point gets
@@ -1322,9 +1328,18 @@ __global__ __launch_bounds__(1024) void k_coarse_inverse(CoarseDev C, const doub
 constexpr int CD_NT = 256;
 
 __device__ __forceinline__ double coarse_row_dot(const double* __restrict__ row, const double* v, int N) {
-    double s = 0.0;
-    for (int j = threadIdx.x & 63; j < N; j += 64) s += row[j] * v[j];
-    return wave_sum(s);
+    // four independent partial sums keep four loads per lane in flight
+    const int l = threadIdx.x & 63;
+    double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
+    int j = l;
+    for (; j + 192 < N; j += 256) {
+        s0 += row[j] * v[j];
+        s1 += row[j + 64] * v[j + 64];
+        s2 += row[j + 128] * v[j + 128];
+        s3 += row[j + 192] * v[j + 192];
+    }
+    for (; j < N; j += 64) s0 += row[j] * v[j];
+    return wave_sum((s0 + s1) + (s2 + s3));
 }
 
 template <class T>
