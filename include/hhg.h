@@ -141,8 +141,9 @@ int hhg_workspace_bytes(const hhg_mesh* mesh, uint32_t features, size_t* bytes);
 
 /*
  * Bind a caller-owned device buffer of at least hhg_workspace_bytes(features)
- * bytes (256-byte aligned) and upload the tables into it on `stream`.  The
- * buffer must stay alive and unused by the caller while the mesh uses it.
+ * bytes (256-byte aligned), clear it to zero and upload the tables into it on
+ * `stream` (synchronised before returning).  The buffer must stay alive and
+ * unused by the caller while the mesh uses it.
  * Errors: HHG_ENOMEM if bytes is too small, HHG_EHIP on a failed upload.
  */
 int hhg_bind_workspace(hhg_mesh* mesh, uint32_t features, void* dptr,
@@ -216,7 +217,10 @@ int hhg_smooth(const hhg_mesh* mesh, int32_t level, int32_t op,
  * One V(nu1, nu2) cycle from `level` down to the coarse level (sec. 4.3):
  * nu1 forward sweeps, residual and restriction (transpose of linear
  * interpolation), recursion with zero initial guess, linear prolongation and
- * correction, nu2 backward sweeps; Jacobi-PCG on the coarse level.  Uses the
+ * correction, nu2 backward sweeps.  The coarse level is solved directly
+ * through a stored inverse (built on the GPU by Jacobi-PCG columns the first
+ * time it is needed) when it has at most 2048 interior unknowns, else by
+ * Jacobi-PCG to a relative residual of 1e-14.  Uses the
  * bound workspace for coarse fields (HHG_FEAT_F64 for dtype F64, HHG_FEAT_MP
  * for F32).
  */

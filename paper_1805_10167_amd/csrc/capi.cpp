@@ -48,8 +48,9 @@ void carve(hhg_mesh* M, uint32_t feat, Carver& c) {
         LevelHost& H = m.lv[l];
         H.d_row_off = (int32_t*)c.take(sizeof(int32_t) * H.row_off.size());
         H.d_tiles = (int2*)c.take(sizeof(int2) * (H.tiles.size() + 1));
-        H.d_gs_tiles = (int2*)c.take(sizeof(int2) * (H.gs_tiles.size() + 1));
-        H.d_gs_tiles16 = (int2*)c.take(sizeof(int2) * (H.gs_tiles16.size() + 1));
+        for (int e = 0; e < 2; ++e)
+            for (int t = 0; t < 2; ++t)
+                H.d_gs_tl[e][t] = (int2*)c.take(sizeof(int2) * (H.gs_tl[e][t].size() + 1));
         H.d_net_tiles = (int2*)c.take(sizeof(int2) * (H.net_tiles.size() + 1));
         H.d_gdst = (int64_t*)c.take(sizeof(int64_t) * (H.gdst.size() + 1));
         H.d_gsrc = (int64_t*)c.take(sizeof(int64_t) * (H.gsrc.size() + 1));
@@ -234,13 +235,20 @@ int vcycle_rec(const hhg_mesh* M, int level, int op, int smoother, int dt, void*
     }
     void* alt = level_alt(M, level, dt);
     void* cur = nullptr;
-    int rc = smooth_pp(M, level, op, smoother, dt, u, alt, f, nu1, 0, s, &cur);
+    // with Gauss-Seidel the last pre-smoothing sweep also forms the residual
+    const bool sweep_res = smoother == HHG_SMOOTH_GS && nu1 > 0;
+    int rc = smooth_pp(M, level, op, smoother, dt, u, alt, f, sweep_res ? nu1 - 1 : nu1, 0, s, &cur);
     if (rc) return rc;
     void* other = cur == u ? alt : u;
     void* r = level_r(M, level, dt);
     void* uc = level_u(M, level - 1, dt);
     void* fc = level_f(M, level - 1, dt);
-    HIP_CHECK(launch_residual(M, level, op, dt, cur, f, r, nullptr, s), "residual");
+    if (sweep_res) {
+        HIP_CHECK(launch_gs_sweep_residual(M, level, op, dt, cur, other, f, r, s), "smooth + residual");
+        std::swap(cur, other);
+    } else {
+        HIP_CHECK(launch_residual(M, level, op, dt, cur, f, r, nullptr, s), "residual");
+    }
     HIP_CHECK(launch_restrict(M, level, dt, r, fc, uc, s), "restrict");
     rc = vcycle_rec(M, level - 1, op, smoother, dt, uc, fc, nu1, nu2, s);
     if (rc) return rc;
@@ -276,8 +284,11 @@ hhg::LevelDev hhg_mesh::dev(int level) const {
     L.ghost_stride = H.ghost_stride;
     L.vert_stride = (int32_t)H.vert_stride;
     L.ntiles = (int32_t)H.tiles.size();
-    L.n_gs_tiles = (int32_t)H.gs_tiles.size();
-    L.n_gs_tiles16 = (int32_t)H.gs_tiles16.size();
+    for (int e = 0; e < 2; ++e)
+        for (int t = 0; t < 2; ++t) {
+            L.n_gs_tl[e][t] = (int32_t)H.gs_tl[e][t].size();
+            L.gs_tl[e][t] = H.d_gs_tl[e][t];
+        }
     L.n_net_tiles = (int32_t)H.net_tiles.size();
     L.n_iedges = (int32_t)m.iedges.size();
     L.n_iverts = (int32_t)m.iverts.size();
@@ -294,8 +305,6 @@ hhg::LevelDev hhg_mesh::dev(int level) const {
     L.inv4l = std::ldexp(1.0, -2 * level);
     L.row_off = H.d_row_off;
     L.tiles = H.d_tiles;
-    L.gs_tiles = H.d_gs_tiles;
-    L.gs_tiles16 = H.d_gs_tiles16;
     L.net_tiles = H.d_net_tiles;
     L.faces = d_faces;
     L.edges = d_edges;
@@ -362,6 +371,9 @@ int hhg_bind_workspace(hhg_mesh* M, uint32_t features, void* dptr, size_t bytes,
     if (bytes < need) return fail(HHG_ENOMEM, "workspace too small: need " + std::to_string(need));
     if ((uintptr_t)dptr % 256) return fail(HHG_EINVAL, "workspace must be 256-byte aligned");
     hipStream_t s = (hipStream_t)stream;
+    // zero once, so that entries no kernel writes (row and block padding)
+    // hold zeros in every workspace field, whatever the memory held before
+    HIP_CHECK(hipMemsetAsync(dptr, 0, need, s), "workspace clear");
     Carver c(dptr);
     carve(M, features, c);
     MeshData& m = M->m;
@@ -374,8 +386,8 @@ int hhg_bind_workspace(hhg_mesh* M, uint32_t features, void* dptr, size_t bytes,
         LevelHost& H = m.lv[l];
         HIP_CHECK(upload(H.d_row_off, H.row_off, s), "upload");
         HIP_CHECK(upload(H.d_tiles, H.tiles, s), "upload");
-        HIP_CHECK(upload(H.d_gs_tiles, H.gs_tiles, s), "upload");
-        HIP_CHECK(upload(H.d_gs_tiles16, H.gs_tiles16, s), "upload");
+        for (int e = 0; e < 2; ++e)
+            for (int t = 0; t < 2; ++t) HIP_CHECK(upload(H.d_gs_tl[e][t], H.gs_tl[e][t], s), "upload");
         HIP_CHECK(upload(H.d_net_tiles, H.net_tiles, s), "upload");
         HIP_CHECK(upload(H.d_gdst, H.gdst, s), "upload");
         HIP_CHECK(upload(H.d_gsrc, H.gsrc, s), "upload");

@@ -17,13 +17,16 @@ constexpr int MAXLEVEL = 12;
 constexpr int PAD = 16;         // row/segment padding in elements
 constexpr int TILE_I = 64;      // generic face tile: 64 (i) x 4 (j) points
 constexpr int TILE_J = 4;
-// fused smoother tile: GS_TI x GS_TJ updated points plus a halo of GS_H on
-// every side, so that an LDS row holds GS_TI + 2 GS_H = 192 values (three
-// per lane of a wave)
+// fused smoother tile: TI x TJ updated points plus a halo of H on every
+// side, so that an LDS row holds TI + 2 H = GS_W values (three per lane of a
+// wave); H = GS_H for the sweep, GS_HE for the sweep that also forms the
+// residual
+constexpr int GS_W = 192;
 constexpr int GS_H = 3;
-constexpr int GS_TI = 192 - 2 * GS_H;
+constexpr int GS_HE = 4;
 constexpr int GS_TJ = 24;
 constexpr int GS_TJ16 = 16;   // tile height of the variable-coefficient FP64 smoother
+constexpr int gs_tile_width(int halo) { return GS_W - 2 * halo; }
 // learned-smoother tile: NET_TI x NET_TJ output points
 constexpr int NET_TI = 58;
 constexpr int NET_TJ = 12;
@@ -100,7 +103,8 @@ struct LevelDev {
     int32_t level, n;
     int32_t F, E, V;
     int32_t ghost_off, ghost_stride, vert_stride;
-    int32_t ntiles, n_iedges, n_iverts, n_gs_tiles, n_net_tiles, n_gs_tiles16;
+    int32_t ntiles, n_iedges, n_iverts, n_net_tiles;
+    int32_t n_gs_tl[2][2];           // smoother tiles per face, [halo GS_HE][GS_TJ16 rows]
     int64_t face_stride, edge_stride;
     int64_t face_base, edge_base, vert_base, total;
     int64_t gcls[G_NCLS + 1];
@@ -108,8 +112,7 @@ struct LevelDev {
     double inv4l;                     // 1 / 4^level: micro/macro area ratio
     const int32_t* row_off;           // [n + 1] start of row j inside a face
     const int2* tiles;                // 64 x 4 tiles covering the whole face
-    const int2* gs_tiles;             // smoother tiles covering the whole face
-    const int2* gs_tiles16;           // the same with GS_TJ16-row tiles
+    const int2* gs_tl[2][2];          // smoother tiles covering the whole face
     const int2* net_tiles;            // learned-smoother tiles meeting the interior
     const FaceInfo* faces;
     const EdgeInfo* edges;
@@ -141,8 +144,7 @@ struct LevelHost {
     int32_t ghost_off = 0, ghost_stride = 0;
     std::vector<int32_t> row_off;
     std::vector<int2> tiles;
-    std::vector<int2> gs_tiles;
-    std::vector<int2> gs_tiles16;
+    std::vector<int2> gs_tl[2][2];    // [halo GS_HE][GS_TJ16 rows]
     std::vector<int2> net_tiles;
     std::vector<int64_t> gdst, gsrc;
     int64_t gcls[G_NCLS + 1] = {0, 0, 0, 0, 0};
@@ -150,8 +152,7 @@ struct LevelHost {
     // device copies (inside the bound workspace)
     int32_t* d_row_off = nullptr;
     int2* d_tiles = nullptr;
-    int2* d_gs_tiles = nullptr;
-    int2* d_gs_tiles16 = nullptr;
+    int2* d_gs_tl[2][2] = {{nullptr, nullptr}, {nullptr, nullptr}};
     int2* d_net_tiles = nullptr;
     int64_t* d_gdst = nullptr;
     int64_t* d_gsrc = nullptr;

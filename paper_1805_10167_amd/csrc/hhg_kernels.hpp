@@ -25,11 +25,14 @@ hipError_t launch_residual(const hhg_mesh* M, int level, int op, int dtype, cons
 // (x is used as scratch; y receives the complete result).
 hipError_t launch_gs_sweep(const hhg_mesh* M, int level, int op, int dtype, void* x, void* y,
                            const void* f, int backward, hipStream_t s);
-// fc (level-1) = P^T r (level) from r with its copies; uc (level-1) = 0.
 // Mixed-precision outer step (see k_mp_step): e == nullptr for the first
 // residual; xo receives x + e otherwise.
 hipError_t launch_mp_step(const hhg_mesh* M, int level, int op, const double* x, const float* e,
                           const double* f, double* xo, float* r, double* norm, hipStream_t s);
+// Forward sweep x -> y that also forms r = f - A y with all its copies (the
+// last pre-smoothing sweep before the restriction).
+hipError_t launch_gs_sweep_residual(const hhg_mesh* M, int level, int op, int dtype, void* x, void* y,
+                                    const void* f, void* r, hipStream_t s);
 // Backward sweep that starts from x + P uc (uc: correction of level - 1):
 // prolongation and the first post-smoothing sweep in the same launches.
 hipError_t launch_gs_sweep_prolong(const hhg_mesh* M, int level, int op, int dtype, void* x, void* y,
@@ -41,6 +44,7 @@ hipError_t launch_jacobi_low(const hhg_mesh* M, int level, int op, const float* 
 // Face step of the learned sweep, x -> y (see k_net_step).
 hipError_t launch_net_step(const hhg_mesh* M, int level, int op, const float* x, float* y, const float* f,
                            const float* rho_ring, bool mfma, hipStream_t s);
+// fc (level-1) = P^T r (level) from r with its copies; uc (level-1) = 0.
 hipError_t launch_restrict(const hhg_mesh* M, int level, int dtype, const void* r, void* fc,
                            void* uc, hipStream_t s);
 // u (level) += P uc (level-1) on interior points, copies included.
@@ -49,7 +53,8 @@ hipError_t launch_prolong_add(const hhg_mesh* M, int level, int dtype, const voi
 hipError_t launch_fill(void* x, int64_t n, int dtype, double v, hipStream_t s);
 // ELL values of the coarse operator for `op` into `vals`.
 hipError_t launch_coarse_extract(const hhg_mesh* M, int op, double* vals, hipStream_t s);
-// u += PCG(A_int, (f - A u)_int) on the coarse level, ghosts refreshed.
+// u += A_int^-1 (f - A u)_int on the coarse level (stored inverse and one
+// refinement step, or Jacobi-PCG), ghosts refreshed.
 hipError_t launch_coarse_solve(const hhg_mesh* M, int op, int dtype, void* u, const void* f,
                                const double* vals, hipStream_t s);
 // Canonical <-> layout conversion (to_canon = 1: field -> canonical).

@@ -590,32 +590,60 @@ __device__ __forceinline__ T prol_low(const LevelDev& Lf, const LevelDev& Lc, co
     return slot == 0 ? cv : (T)0.5 * (cv + uc[vc + slot]);
 }
 
-// Fused multicolour face smoother.  A tile of GS_TI x GS_TJ points plus a
-// halo of GS_H points sits in LDS; colour stage s (of ncol) is applied on
-// the tile grown by ncol - 1 - s points, so every stage sees exactly the
-// values that separate colour passes over the whole face would give it, and
-// u, f are read once and u written once per sweep.  Tiles would otherwise
-// read halo points a neighbour tile has already overwritten, so the sweep
-// reads uin and writes uout; the same launch copies the face rings, edge
-// points and vertex blocks into uout and writes the near-edge rows into
-// uout's edge ghost rows, leaving uout a complete, consistent field.
-constexpr int GS_W = GS_TI + 2 * GS_H;          // 192 values per LDS row
+// Fused multicolour face smoother.  A tile of TI x TJ points plus a halo of
+// H points sits in LDS (TI + 2 H = GS_W values per row); colour stage s (of
+// ncol) is applied on the tile grown by ncol - 1 - s points, so every stage
+// sees exactly the values that separate colour passes over the whole face
+// would give it, and u, f are read once and u written once per sweep.  Tiles
+// would otherwise read halo points a neighbour tile has already overwritten,
+// so the sweep reads uin and writes uout; the same launch copies the face
+// rings, edge points and vertex blocks into uout and writes the near-edge
+// rows into uout's edge ghost rows, leaving uout a complete, consistent
+// field.  The residual variant (H = GS_HE) grows every stage by one more
+// point, so that after the last colour the values one point beyond the tile
+// are final too; it then forms f - A u at the tile's interior points from LDS
+// and stores it as well (one more write stream instead of a separate pass
+// that reads u and f again).
 constexpr int GS_NT = 512;                      // threads per block
 constexpr int GS_NW = GS_NT / 64;               // waves per block
 constexpr int GS_COPY_BLOCKS = 32;
 
-// Shape of a tile of TJ updated rows: LDS rows, rows loaded per wave, and
-// the per-stage row (three colours) or slot (two colours) iterations.
-template <int TJ>
+// Shape of a tile of TJ updated rows with halo H: tile width, LDS rows, rows
+// loaded per wave, and the per-stage row (three colours) or slot (two
+// colours) iterations; stages grow by at most H - 1 (three colours) or
+// H - 2 (two colours) points.
+template <int TJ, int H>
 struct GsTile {
-    static constexpr int R = TJ + 2 * GS_H;
+    static constexpr int TI = GS_W - 2 * H;
+    static constexpr int R = TJ + 2 * H;
     static constexpr int RPW = (R + GS_NW - 1) / GS_NW;
-    static constexpr int IT3 = (TJ + 4 + GS_NW - 1) / GS_NW;
-    static constexpr int IT2 = ((TJ + 2) * (GS_W / 2) + GS_NT - 1) / GS_NT;
+    static constexpr int IT3 = (TJ + 2 * (H - 1) + GS_NW - 1) / GS_NW;
+    static constexpr int IT2 = ((TJ + 2 * (H - 2)) * (GS_W / 2) + GS_NT - 1) / GS_NT;
 };
 
 __device__ __forceinline__ int pmod(int a, int m) { return ((a % m) + m) % m; }
 
+// Variable-coefficient weights of the point at LDS position (r, tx), from the
+// coefficient tile: the same arithmetic as face_weights.
+template <class T>
+__device__ __forceinline__ W7<T> gs_weights_lds(const FaceInfo& fi, T (*ks)[GS_W], int r, int tx) {
+    const T c0 = (T)fi.cot[0], c1 = (T)fi.cot[1], c2 = (T)fi.cot[2];
+    const T k0 = ks[r][tx], kE = ks[r][tx + 1], kW = ks[r][tx - 1], kN = ks[r + 1][tx];
+    const T kS = ks[r - 1][tx], kSE = ks[r - 1][tx + 1], kNW = ks[r + 1][tx - 1];
+    const T third = (T)(1.0 / 3.0), hf = (T)0.5;
+    const T t1 = (k0 + kE + kN) * third, t2 = (kSE + kE + k0) * third;
+    const T t3 = (kW + k0 + kNW) * third, t4 = (kS + k0 + kW) * third;
+    const T t5 = (k0 + kN + kNW) * third, t6 = (kS + kSE + k0) * third;
+    W7<T> w;
+    w.e = -hf * c2 * (t1 + t2);
+    w.w = -hf * c2 * (t3 + t4);
+    w.n = -hf * c1 * (t1 + t5);
+    w.s = -hf * c1 * (t6 + t4);
+    w.se = -hf * c0 * (t6 + t2);
+    w.nw = -hf * c0 * (t3 + t5);
+    w.c = -(w.e + w.w + w.n + w.s + w.se + w.nw);
+    return w;
+}
 
 // Stage update of one face point at LDS position (r, tx).
 template <class T, bool VARK>
@@ -624,18 +652,18 @@ __device__ __forceinline__ T gs_point(const FaceInfo& fi, const W7<T>& w, T invc
     const T uE = us[r][tx + 1], uW = us[r][tx - 1], uN = us[r + 1][tx], uS = us[r - 1][tx];
     const T uSE = us[r - 1][tx + 1], uNW = us[r + 1][tx - 1];
     if (!VARK) return (fv - (w.e * (uE + uW) + w.n * (uN + uS) + w.se * (uSE + uNW))) * invc;
-    const T c0 = (T)fi.cot[0], c1 = (T)fi.cot[1], c2 = (T)fi.cot[2];
-    const T k0 = ks[r][tx], kE = ks[r][tx + 1], kW = ks[r][tx - 1], kN = ks[r + 1][tx];
-    const T kS = ks[r - 1][tx], kSE = ks[r - 1][tx + 1], kNW = ks[r + 1][tx - 1];
-    const T third = (T)(1.0 / 3.0), hf = (T)0.5;
-    const T t1 = (k0 + kE + kN) * third, t2 = (kSE + kE + k0) * third;
-    const T t3 = (kW + k0 + kNW) * third, t4 = (kS + k0 + kW) * third;
-    const T t5 = (k0 + kN + kNW) * third, t6 = (kS + kSE + k0) * third;
-    const T we = -hf * c2 * (t1 + t2), ww = -hf * c2 * (t3 + t4);
-    const T wn = -hf * c1 * (t1 + t5), ws = -hf * c1 * (t6 + t4);
-    const T wse = -hf * c0 * (t6 + t2), wnw = -hf * c0 * (t3 + t5);
-    const T wc = -(we + ww + wn + ws + wse + wnw);
-    return (fv - (we * uE + ww * uW + wn * uN + ws * uS + wse * uSE + wnw * uNW)) / wc;
+    const W7<T> v = gs_weights_lds<T>(fi, ks, r, tx);
+    return (fv - (v.e * uE + v.w * uW + v.n * uN + v.s * uS + v.se * uSE + v.nw * uNW)) / v.c;
+}
+
+// Residual f - A u of the point at LDS position (r, tx), in the order of the
+// residual kernel's point formula.
+template <class T, bool VARK>
+__device__ __forceinline__ T gs_resid(const FaceInfo& fi, const W7<T>& wl, T fv, T (*us)[GS_W],
+                                      T (*ks)[GS_W], int r, int tx) {
+    const W7<T> w = VARK ? gs_weights_lds<T>(fi, ks, r, tx) : wl;
+    return fv - (w.c * us[r][tx] + w.e * us[r][tx + 1] + w.w * us[r][tx - 1] + w.n * us[r + 1][tx] +
+                 w.s * us[r - 1][tx] + w.se * us[r - 1][tx + 1] + w.nw * us[r + 1][tx - 1]);
 }
 
 // Tile rows into registers: wave w takes LDS rows w + GS_NW q, lane l columns
@@ -649,19 +677,19 @@ struct ProlTile {
     int nc;
 };
 
-template <class T, bool VARK, bool PROL, int TJ>
+template <class T, bool VARK, bool PROL, int TJ, int H>
 __device__ __forceinline__ void gs_load_u(int n, int i0, int j0, int64_t fb, const T* __restrict__ uin,
                                           const T* __restrict__ kap, T (*ur)[3], T (*kr)[3],
                                           const FaceInfo& fi, const ProlTile<T>& pt) {
     const int wv = wave_id(), lane = threadIdx.x & 63;
 #pragma unroll
-    for (int q = 0; q < GsTile<TJ>::RPW; ++q) {
+    for (int q = 0; q < GsTile<TJ, H>::RPW; ++q) {
         const int r = wv + GS_NW * q, j = j0 + r;
         const int64_t rb = fb + row_start(n, j < 0 ? 0 : (j > n ? n : j));
 #pragma unroll
         for (int c = 0; c < 3; ++c) {
             const int i = i0 + lane + 64 * c;
-            const bool in = r < GsTile<TJ>::R && j >= 0 && j < n && i >= 0 && i <= n - 1 - j;
+            const bool in = r < GsTile<TJ, H>::R && j >= 0 && j < n && i >= 0 && i <= n - 1 - j;
             T v = in ? uin[rb + i] : (T)0;
             if (PROL && in && !face_dirichlet(fi, n, i, j)) v += prol_face<T>(pt.uc, pt.cb, pt.nc, i, j);
             ur[q][c] = v;
@@ -670,13 +698,13 @@ __device__ __forceinline__ void gs_load_u(int n, int i0, int j0, int64_t fb, con
     }
 }
 
-template <class T, bool VARK, int TJ>
+template <class T, bool VARK, int TJ, int H>
 __device__ __forceinline__ void gs_store_u(T (*us)[GS_W], T (*ks)[GS_W], T (*ur)[3], T (*kr)[3]) {
     const int wv = wave_id(), lane = threadIdx.x & 63;
 #pragma unroll
-    for (int q = 0; q < GsTile<TJ>::RPW; ++q) {
+    for (int q = 0; q < GsTile<TJ, H>::RPW; ++q) {
         const int r = wv + GS_NW * q;
-        if (r < GsTile<TJ>::R) {
+        if (r < GsTile<TJ, H>::R) {
 #pragma unroll
             for (int c = 0; c < 3; ++c) {
                 us[r][lane + 64 * c] = ur[q][c];
@@ -690,57 +718,96 @@ __device__ __forceinline__ void gs_store_u(T (*us)[GS_W], T (*ks)[GS_W], T (*ur)
 // the stage region.  In a row the colour-c points are every third column and
 // lane l owns columns 3 l .. 3 l + 2, so each lane updates exactly one point
 // per row; the row, the colour offset and the bounds are wave-uniform.
+// `out` stores the tile's u once the stages are done; with the residual
+// (H = GS_HE) the residuals then replace the interior tile values in LDS.
 
-template <class T, bool VARK, bool PROL, int TJ>
+template <class T, bool VARK, bool PROL, int TJ, int H, class Out>
 __device__ __forceinline__ void gs_tile3(const LevelDev& L, const FaceInfo& fi, int n, int i0, int j0,
                                          int64_t fb, const T* __restrict__ uin, const T* __restrict__ f,
                                          const T* __restrict__ kap, int backward, T (*us)[GS_W],
-                                         T (*ks)[GS_W], const ProlTile<T>& pt) {
+                                         T (*ks)[GS_W], const ProlTile<T>& pt, Out out) {
+    using G = GsTile<TJ, H>;
     const int wv = wave_id(), lane = threadIdx.x & 63;
-    T ur[GsTile<TJ>::RPW][3], kr[VARK ? GsTile<TJ>::RPW : 1][3], fr[3][GsTile<TJ>::IT3];
-    gs_load_u<T, VARK, PROL, TJ>(n, i0, j0, fb, uin, kap, ur, kr, fi, pt);
+    T ur[G::RPW][3], kr[VARK ? G::RPW : 1][3], fr[3][G::IT3];
+    gs_load_u<T, VARK, PROL, TJ, H>(n, i0, j0, fb, uin, kap, ur, kr, fi, pt);
 #pragma unroll
     for (int s = 0; s < 3; ++s) {
-        const int c = backward ? 2 - s : s, h = 2 - s;
-        const int lo = GS_H - h, hi_i = GS_H + GS_TI + h, hi_j = GS_H + TJ + h;
+        const int c = backward ? 2 - s : s, h = H - 1 - s;
+        const int lo = H - h, hi_i = H + G::TI + h, hi_j = H + TJ + h;
 #pragma unroll
-        for (int it = 0; it < GsTile<TJ>::IT3; ++it) {
+        for (int it = 0; it < G::IT3; ++it) {
             const int r = lo + wv + GS_NW * it, j = j0 + r;
             const int tx = pmod(c + j - i0, 3) + 3 * lane, i = i0 + tx;
             const bool upd = r < hi_j && tx >= lo && tx < hi_i && j >= 1 && i >= 1 && i + j <= n - 2;
             fr[s][it] = upd ? f[fb + row_start(n, upd ? j : 0) + i] : (T)0;
         }
     }
-    gs_store_u<T, VARK, TJ>(us, ks, ur, kr);
+    gs_store_u<T, VARK, TJ, H>(us, ks, ur, kr);
     const W7<T> w = face_weights<T>(OP_LAPLACE, fi, L.inv4l, (const T*)nullptr, 0, 0, 0);
     const T invc = (T)1 / w.c;
     __syncthreads();
 #pragma unroll
     for (int s = 0; s < 3; ++s) {
-        const int c = backward ? 2 - s : s, h = 2 - s;
-        const int lo = GS_H - h, hi_i = GS_H + GS_TI + h, hi_j = GS_H + TJ + h;
+        const int c = backward ? 2 - s : s, h = H - 1 - s;
+        const int lo = H - h, hi_i = H + G::TI + h, hi_j = H + TJ + h;
 #pragma unroll
-        for (int it = 0; it < GsTile<TJ>::IT3; ++it) {
+        for (int it = 0; it < G::IT3; ++it) {
             const int r = lo + wv + GS_NW * it, j = j0 + r;
             if (r >= hi_j) break;
             int tx = pmod(c + j - i0, 3) + 3 * lane;
             const int i = i0 + tx;
             const bool upd = tx >= lo && tx < hi_i && j >= 1 && i >= 1 && i + j <= n - 2;
-            tx = upd ? tx : GS_H;     // keep the neighbour reads inside the tile
+            tx = upd ? tx : H;        // keep the neighbour reads inside the tile
             const T val = gs_point<T, VARK>(fi, w, invc, fr[s][it], us, ks, r, tx);
             if (upd) us[r][tx] = val;
         }
         __syncthreads();
     }
+    if (H != GS_HE) {
+        out();
+        return;
+    }
+    // residual at the interior tile points, each found in the stage of its colour
+    T res[3][G::IT3];
+#pragma unroll
+    for (int s = 0; s < 3; ++s) {
+        const int c = backward ? 2 - s : s, lo = 1 + s;
+#pragma unroll
+        for (int it = 0; it < G::IT3; ++it) {
+            const int r = lo + wv + GS_NW * it, j = j0 + r;
+            res[s][it] = (T)0;
+            if (r < H || r >= H + TJ) continue;
+            int tx = pmod(c + j - i0, 3) + 3 * lane;
+            const int i = i0 + tx;
+            const bool in = tx >= H && tx < H + G::TI && j >= 1 && i >= 1 && i + j <= n - 2;
+            tx = in ? tx : H;
+            const T v = gs_resid<T, VARK>(fi, w, fr[s][it], us, ks, r, tx);
+            res[s][it] = in ? v : (T)0;
+        }
+    }
+    out();
+    __syncthreads();
+#pragma unroll
+    for (int s = 0; s < 3; ++s) {
+        const int c = backward ? 2 - s : s, lo = 1 + s;
+#pragma unroll
+        for (int it = 0; it < G::IT3; ++it) {
+            const int r = lo + wv + GS_NW * it, j = j0 + r;
+            if (r < H || r >= H + TJ) continue;
+            const int tx = pmod(c + j - i0, 3) + 3 * lane, i = i0 + tx;
+            if (tx >= H && tx < H + G::TI && j >= 1 && i >= 1 && i + j <= n - 2) us[r][tx] = res[s][it];
+        }
+    }
+    __syncthreads();
 }
 
 // Two colours (faces with an exact right angle): slots map densely onto the
 // colour-c points, every second column or every second row.
 
-template <int TJ>
+template <int TJ, int H>
 __device__ __forceinline__ bool gs_decode2(int idx, int rule, int c, int h, int i0, int j0, int& r,
                                            int& tx) {
-    const int lo = GS_H - h, hi_i = GS_H + GS_TI + h, hi_j = GS_H + TJ + h;
+    const int lo = H - h, hi_i = H + GsTile<TJ, H>::TI + h, hi_j = H + TJ + h;
     if (rule == 3) {
         const int rr = idx / GS_W, m = idx - rr * GS_W;
         r = lo + pmod(c - (j0 + lo), 2) + 2 * rr;
@@ -755,42 +822,64 @@ __device__ __forceinline__ bool gs_decode2(int idx, int rule, int c, int h, int 
     return r < hi_j && tx < hi_i;
 }
 
-template <class T, bool VARK, bool PROL, int TJ>
+template <class T, bool VARK, bool PROL, int TJ, int H, class Out>
 __device__ __forceinline__ void gs_tile2(const LevelDev& L, const FaceInfo& fi, int n, int i0, int j0,
                                          int64_t fb, const T* __restrict__ uin, const T* __restrict__ f,
                                          const T* __restrict__ kap, int backward, T (*us)[GS_W],
-                                         T (*ks)[GS_W], const ProlTile<T>& pt) {
+                                         T (*ks)[GS_W], const ProlTile<T>& pt, Out out,
+                                         T* __restrict__ rout) {
+    using G = GsTile<TJ, H>;
     const int rule = fi.colour_rule;
-    T ur[GsTile<TJ>::RPW][3], kr[VARK ? GsTile<TJ>::RPW : 1][3], fr[2][GsTile<TJ>::IT2];
-    gs_load_u<T, VARK, PROL, TJ>(n, i0, j0, fb, uin, kap, ur, kr, fi, pt);
+    T ur[G::RPW][3], kr[VARK ? G::RPW : 1][3], fr[2][G::IT2];
+    gs_load_u<T, VARK, PROL, TJ, H>(n, i0, j0, fb, uin, kap, ur, kr, fi, pt);
 #pragma unroll
     for (int s = 0; s < 2; ++s) {
-        const int c = backward ? 1 - s : s, h = 1 - s;
+        const int c = backward ? 1 - s : s, h = H - 2 - s;
 #pragma unroll
-        for (int it = 0; it < GsTile<TJ>::IT2; ++it) {
+        for (int it = 0; it < G::IT2; ++it) {
             int r, tx;
-            const bool ok = gs_decode2<TJ>(threadIdx.x + it * GS_NT, rule, c, h, i0, j0, r, tx);
+            const bool ok = gs_decode2<TJ, H>(threadIdx.x + it * GS_NT, rule, c, h, i0, j0, r, tx);
             const int j = j0 + r, i = i0 + tx;
             const bool upd = ok && j >= 1 && i >= 1 && i + j <= n - 2;
             fr[s][it] = upd ? f[fb + row_start(n, upd ? j : 0) + i] : (T)0;
         }
     }
-    gs_store_u<T, VARK, TJ>(us, ks, ur, kr);
+    gs_store_u<T, VARK, TJ, H>(us, ks, ur, kr);
     const W7<T> w = face_weights<T>(OP_LAPLACE, fi, L.inv4l, (const T*)nullptr, 0, 0, 0);
     const T invc = (T)1 / w.c;
     __syncthreads();
 #pragma unroll
     for (int s = 0; s < 2; ++s) {
-        const int c = backward ? 1 - s : s, h = 1 - s;
+        const int c = backward ? 1 - s : s, h = H - 2 - s;
 #pragma unroll
-        for (int it = 0; it < GsTile<TJ>::IT2; ++it) {
+        for (int it = 0; it < G::IT2; ++it) {
             int r, tx;
-            const bool ok = gs_decode2<TJ>(threadIdx.x + it * GS_NT, rule, c, h, i0, j0, r, tx);
+            const bool ok = gs_decode2<TJ, H>(threadIdx.x + it * GS_NT, rule, c, h, i0, j0, r, tx);
             const int j = j0 + r, i = i0 + tx;
             if (!(ok && j >= 1 && i >= 1 && i + j <= n - 2)) continue;
             us[r][tx] = gs_point<T, VARK>(fi, w, invc, fr[s][it], us, ks, r, tx);
         }
         __syncthreads();
+    }
+    out();
+    if (H != GS_HE) return;
+    // residuals straight from the final LDS values to rout with their
+    // ghost-row copies (faces with a right angle are few, so this path keeps
+    // registers low rather than staging through LDS)
+#pragma unroll
+    for (int s = 0; s < 2; ++s) {
+        const int c = backward ? 1 - s : s, h = H - 2 - s;
+#pragma unroll
+        for (int it = 0; it < G::IT2; ++it) {
+            int r, tx;
+            const bool ok = gs_decode2<TJ, H>(threadIdx.x + it * GS_NT, rule, c, h, i0, j0, r, tx);
+            const int j = j0 + r, i = i0 + tx;
+            if (!(ok && r >= H && r < H + TJ && tx >= H && tx < H + G::TI && j >= 1 && i >= 1 && i + j <= n - 2))
+                continue;
+            const T v = gs_resid<T, VARK>(fi, w, fr[s][it], us, ks, r, tx);
+            rout[fb + row_start(n, j) + i] = v;
+            push_face_near(L, rout, fi, i, j, v);
+        }
     }
 }
 
@@ -799,14 +888,22 @@ __device__ __forceinline__ void gs_tile2(const LevelDev& L, const FaceInfo& fi, 
 // extra blocks of the launch with with_copy = 1.  PROL: the sweep starts
 // from uin + P uc (the coarse correction of level Lc), which is then never
 // stored on its own: tiles add it as they load, copy blocks as they copy.
-template <class T, bool VARK, int NCOL, bool PROL, int TJ>
+// RES: the residual variant; rout receives f - A uout at the interior face
+// points and their copies in the edge ghost rows (the edge and vertex
+// residuals and the remaining copies are left to an edge/vertex pass).
+// Three-colour tiles stage the residuals through LDS for row-wise stores;
+// two-colour tiles store them point by point.
+template <class T, bool VARK, int NCOL, bool PROL, int TJ, bool RES>
 __global__ __launch_bounds__(GS_NT) void k_face_gs_fused(LevelDev L, const T* __restrict__ uin,
                                                          T* __restrict__ uout, const T* __restrict__ f,
                                                          const T* __restrict__ kap, int backward,
                                                          int nblk_tiles, int with_copy, LevelDev Lc,
-                                                         const T* __restrict__ uc) {
-    __shared__ T us[GsTile<TJ>::R][GS_W];
-    __shared__ T ks[VARK ? GsTile<TJ>::R : 1][GS_W];
+                                                         const T* __restrict__ uc, T* __restrict__ rout) {
+    constexpr int H = RES ? GS_HE : GS_H;
+    constexpr int TI = GsTile<TJ, H>::TI;
+    constexpr int T16 = TJ == GS_TJ16 ? 1 : 0;
+    __shared__ T us[GsTile<TJ, H>::R][GS_W];
+    __shared__ T ks[VARK ? GsTile<TJ, H>::R : 1][GS_W];
     const int G = gridDim.x;                              // multiple of 8
     const int b = blockIdx.x;
     const int logical = (b & 7) * (G >> 3) + (b >> 3);    // contiguous tiles per XCD
@@ -825,50 +922,89 @@ __global__ __launch_bounds__(GS_NT) void k_face_gs_fused(LevelDev L, const T* __
         }
         return;
     }
-    const int face = logical / (TJ == GS_TJ16 ? L.n_gs_tiles16 : L.n_gs_tiles);
+    const int ntl = L.n_gs_tl[RES ? 1 : 0][T16];
+    const int face = logical / ntl;
     const FaceInfo& fi = L.faces[face];
     if (fi.ncolours != NCOL) return;
-    const bool t16 = TJ == GS_TJ16;
-    const int2 tl = (t16 ? L.gs_tiles16 : L.gs_tiles)[logical % (t16 ? L.n_gs_tiles16 : L.n_gs_tiles)];
-    const int i0 = tl.x * GS_TI - GS_H, j0 = tl.y * TJ - GS_H;   // LDS origin
+    const int2 tl = L.gs_tl[RES ? 1 : 0][T16][logical % ntl];
+    const int i0 = tl.x * TI - H, j0 = tl.y * TJ - H;   // LDS origin
     const int64_t fb = face_base(L, face);
     const ProlTile<T> pt{uc, PROL ? face_base(Lc, face) : 0, Lc.n};
-    if (NCOL == 3)
-        gs_tile3<T, VARK, PROL, TJ>(L, fi, n, i0, j0, fb, uin, f, kap, backward, us, VARK ? ks : nullptr, pt);
-    else
-        gs_tile2<T, VARK, PROL, TJ>(L, fi, n, i0, j0, fb, uin, f, kap, backward, us, VARK ? ks : nullptr, pt);
     const int wv = wave_id(), lane = threadIdx.x & 63;
-    // tile points (interior updated, ring copied) to uout
-    for (int r = GS_H + wv; r < GS_H + TJ; r += GS_NW) {
+    auto out = [&]() {
+        // tile points (interior updated, ring copied) to uout
+        for (int r = H + wv; r < H + TJ; r += GS_NW) {
+            const int j = j0 + r;
+            if (j >= n) break;
+            const int64_t rb = fb + row_start(n, j);
+#pragma unroll
+            for (int c = 0; c < 3; ++c) {
+                const int tx = lane + 64 * c, i = i0 + tx;
+                if (tx >= H && tx < H + TI && i <= n - 1 - j) uout[rb + i] = us[r][tx];
+            }
+        }
+        // near-edge rows into the edge ghost rows of uout (edge order)
+        if (!fi.bside[0] && tl.y == 0) {            // (m, 1)
+            for (int t = threadIdx.x; t < TI; t += GS_NT) {
+                const int m = tl.x * TI + t;
+                if (m <= n - 2)
+                    uout[edge_ghost(L, fi.edge[0], fi.slot[0]) + (fi.rev[0] ? n - 2 - m : m)] = us[1 - j0][H + t];
+            }
+        }
+        if (!fi.bside[1] && tl.x == 0) {            // (1, m)
+            for (int t = threadIdx.x; t < TJ; t += GS_NT) {
+                const int m = tl.y * TJ + t;
+                if (m <= n - 2)
+                    uout[edge_ghost(L, fi.edge[1], fi.slot[1]) + (fi.rev[1] ? n - 2 - m : m)] = us[H + t][1 - i0];
+            }
+        }
+        if (!fi.bside[2]) {                         // (n-2-m, m)
+            for (int t = threadIdx.x; t < TJ; t += GS_NT) {
+                const int m = tl.y * TJ + t, i = n - 2 - m;
+                if (m <= n - 2 && i >= tl.x * TI && i < tl.x * TI + TI)
+                    uout[edge_ghost(L, fi.edge[2], fi.slot[2]) + (fi.rev[2] ? n - 2 - m : m)] = us[H + t][i - i0];
+            }
+        }
+    };
+    if (NCOL == 3)
+        gs_tile3<T, VARK, PROL, TJ, H>(L, fi, n, i0, j0, fb, uin, f, kap, backward, us, VARK ? ks : nullptr, pt,
+                                       out);
+    else
+        gs_tile2<T, VARK, PROL, TJ, H>(L, fi, n, i0, j0, fb, uin, f, kap, backward, us, VARK ? ks : nullptr, pt,
+                                       out, rout);
+    if (!RES || NCOL == 2) return;
+    // interior residuals (now in LDS) to rout, with the ghost-row copies of
+    // the near-edge ones: rows 1 .. n-3 hold interior points
+    for (int r = H + wv; r < H + TJ; r += GS_NW) {
         const int j = j0 + r;
-        if (j >= n) break;
+        if (j > n - 3) break;
+        if (j < 1) continue;
         const int64_t rb = fb + row_start(n, j);
 #pragma unroll
         for (int c = 0; c < 3; ++c) {
             const int tx = lane + 64 * c, i = i0 + tx;
-            if (tx >= GS_H && tx < GS_H + GS_TI && i <= n - 1 - j) uout[rb + i] = us[r][tx];
+            if (tx >= H && tx < H + TI && i >= 1 && i + j <= n - 2) rout[rb + i] = us[r][tx];
         }
     }
-    // near-edge rows into the edge ghost rows of uout (edge order)
-    if (!fi.bside[0] && tl.y == 0) {            // (m, 1)
-        for (int t = threadIdx.x; t < GS_TI; t += GS_NT) {
-            const int m = tl.x * GS_TI + t;
-            if (m <= n - 2)
-                uout[edge_ghost(L, fi.edge[0], fi.slot[0]) + (fi.rev[0] ? n - 2 - m : m)] = us[1 - j0][GS_H + t];
+    if (!fi.bside[0] && tl.y == 0) {                // (m, 1)
+        for (int t = threadIdx.x; t < TI; t += GS_NT) {
+            const int m = tl.x * TI + t;
+            if (m >= 1 && m <= n - 3)
+                rout[edge_ghost(L, fi.edge[0], fi.slot[0]) + (fi.rev[0] ? n - 2 - m : m)] = us[1 - j0][H + t];
         }
     }
-    if (!fi.bside[1] && tl.x == 0) {            // (1, m)
+    if (!fi.bside[1] && tl.x == 0) {                // (1, m)
         for (int t = threadIdx.x; t < TJ; t += GS_NT) {
             const int m = tl.y * TJ + t;
-            if (m <= n - 2)
-                uout[edge_ghost(L, fi.edge[1], fi.slot[1]) + (fi.rev[1] ? n - 2 - m : m)] = us[GS_H + t][1 - i0];
+            if (m >= 1 && m <= n - 3)
+                rout[edge_ghost(L, fi.edge[1], fi.slot[1]) + (fi.rev[1] ? n - 2 - m : m)] = us[H + t][1 - i0];
         }
     }
-    if (!fi.bside[2]) {                         // (n-2-m, m)
+    if (!fi.bside[2]) {                             // (n-2-m, m)
         for (int t = threadIdx.x; t < TJ; t += GS_NT) {
             const int m = tl.y * TJ + t, i = n - 2 - m;
-            if (m <= n - 2 && i >= tl.x * GS_TI && i < tl.x * GS_TI + GS_TI)
-                uout[edge_ghost(L, fi.edge[2], fi.slot[2]) + (fi.rev[2] ? n - 2 - m : m)] = us[GS_H + t][i - i0];
+            if (m >= 1 && m <= n - 3 && i >= tl.x * TI && i < tl.x * TI + TI)
+                rout[edge_ghost(L, fi.edge[2], fi.slot[2]) + (fi.rev[2] ? n - 2 - m : m)] = us[H + t][i - i0];
         }
     }
 }
@@ -1515,36 +1651,39 @@ struct TimingScope {
 
 template <class T>
 static hipError_t gs_t(const hhg_mesh* M, int level, int op, T* x, T* y, const T* f, int backward,
-                       hipStream_t s, const T* uc = nullptr) {
+                       hipStream_t s, const T* uc = nullptr, T* rout = nullptr) {
     const LevelDev L = M->dev(level);
     const T* kap = kap_of<T>(M, level);
     const int gl = grid_for((int64_t)L.n_iedges * (L.n - 2) + L.n_iverts, MAX_LOW_BLOCKS);
-    const bool timed = M->timing && level == M->m.L && !uc;
+    const bool res = rout != nullptr;
+    const bool timed = M->timing && level == M->m.L && !uc && !res;
     const LevelDev Lc = uc ? M->dev(level - 1) : L;
     // the variable-coefficient FP64 tile (u and k in LDS) is 16 rows high so
     // that two blocks fit on a CU; the others are 24 rows high
     const bool t16 = op == OP_DIFFUSION && sizeof(T) == 8;
-    const int ntile_blocks = L.F * (t16 ? L.n_gs_tiles16 : L.n_gs_tiles);
+    const int ntile_blocks = L.F * L.n_gs_tl[res ? 1 : 0][t16 ? 1 : 0];
     const int g = (ntile_blocks + GS_COPY_BLOCKS + 7) / 8 * 8;
     const int g2 = (ntile_blocks + 7) / 8 * 8;
     const bool has2 = M->m.nfaces2 > 0;
     auto faces = [&]() -> hipError_t {
         TimingScope ts(M, s, timed);
-#define HHG_FACE_LAUNCH(VK, PR, TJ)                                                                 \
+#define HHG_FACE_LAUNCH(VK, PR, TJ, RS)                                                             \
     do {                                                                                            \
-        k_face_gs_fused<T, VK, 3, PR, TJ><<<g, GS_NT, 0, s>>>(L, x, y, f, kap, backward, ntile_blocks, \
-                                                              1, Lc, uc);                            \
+        k_face_gs_fused<T, VK, 3, PR, TJ, RS><<<g, GS_NT, 0, s>>>(L, x, y, f, kap, backward,         \
+                                                                  ntile_blocks, 1, Lc, uc, rout);   \
         if (has2)                                                                                   \
-            k_face_gs_fused<T, VK, 2, PR, TJ><<<g2, GS_NT, 0, s>>>(L, x, y, f, kap, backward,        \
-                                                                   ntile_blocks, 0, Lc, uc);        \
+            k_face_gs_fused<T, VK, 2, PR, TJ, RS><<<g2, GS_NT, 0, s>>>(L, x, y, f, kap, backward,    \
+                                                                       ntile_blocks, 0, Lc, uc, rout); \
     } while (0)
         if (op == OP_DIFFUSION) {
             constexpr int TJV = sizeof(T) == 8 ? GS_TJ16 : GS_TJ;
-            if (uc) HHG_FACE_LAUNCH(true, true, TJV);
-            else HHG_FACE_LAUNCH(true, false, TJV);
+            if (uc) HHG_FACE_LAUNCH(true, true, TJV, false);
+            else if (res) HHG_FACE_LAUNCH(true, false, TJV, true);
+            else HHG_FACE_LAUNCH(true, false, TJV, false);
         } else {
-            if (uc) HHG_FACE_LAUNCH(false, true, GS_TJ);
-            else HHG_FACE_LAUNCH(false, false, GS_TJ);
+            if (uc) HHG_FACE_LAUNCH(false, true, GS_TJ, false);
+            else if (res) HHG_FACE_LAUNCH(false, false, GS_TJ, true);
+            else HHG_FACE_LAUNCH(false, false, GS_TJ, false);
         }
 #undef HHG_FACE_LAUNCH
         return hipGetLastError();
@@ -1553,7 +1692,11 @@ static hipError_t gs_t(const hhg_mesh* M, int level, int op, T* x, T* y, const T
     if (!backward) {
         k_low_gs<T><<<gl, NT, 0, s>>>(L, op, x, f, kap, 0);
         k_low_gs<T><<<gl, NT, 0, s>>>(L, op, x, f, kap, 1);
-        return faces();
+        if ((e = faces()) != hipSuccess || !res) return e;
+        // residual of the edge and vertex points (all copies) from the swept y
+        k_apply<T, 1><<<grid_for(low_items(L), MAX_LOW_BLOCKS), NT, 0, s>>>(L, op, y, f, rout, kap, 0,
+                                                                            nullptr);
+        return hipGetLastError();
     }
     if ((e = faces()) != hipSuccess) return e;
     k_low_gs<T><<<gl, NT, 0, s>>>(L, op, y, f, kap, 1);
@@ -1566,6 +1709,13 @@ hipError_t launch_gs_sweep(const hhg_mesh* M, int level, int op, int dtype, void
     if (dtype == DT_F64)
         return gs_t<double>(M, level, op, (double*)x, (double*)y, (const double*)f, backward, s);
     return gs_t<float>(M, level, op, (float*)x, (float*)y, (const float*)f, backward, s);
+}
+
+hipError_t launch_gs_sweep_residual(const hhg_mesh* M, int level, int op, int dtype, void* x, void* y,
+                                    const void* f, void* r, hipStream_t s) {
+    if (dtype == DT_F64)
+        return gs_t<double>(M, level, op, (double*)x, (double*)y, (const double*)f, 0, s, nullptr, (double*)r);
+    return gs_t<float>(M, level, op, (float*)x, (float*)y, (const float*)f, 0, s, nullptr, (float*)r);
 }
 
 hipError_t launch_gs_sweep_prolong(const hhg_mesh* M, int level, int op, int dtype, void* x, void* y,

@@ -302,14 +302,15 @@ void MeshData::build_level(int level) {
 
     // smoother tiles over the whole face triangle (ring included), column by
     // column so that consecutive tiles are vertical neighbours
-    H.gs_tiles.clear();
-    for (int ti = 0; ti * GS_TI <= n - 1; ++ti)
-        for (int tj = 0; tj * GS_TJ <= n - 1; ++tj)
-            if (ti * GS_TI + tj * GS_TJ <= n - 1) H.gs_tiles.push_back(make_int2(ti, tj));
-    H.gs_tiles16.clear();
-    for (int ti = 0; ti * GS_TI <= n - 1; ++ti)
-        for (int tj = 0; tj * GS_TJ16 <= n - 1; ++tj)
-            if (ti * GS_TI + tj * GS_TJ16 <= n - 1) H.gs_tiles16.push_back(make_int2(ti, tj));
+    for (int e = 0; e < 2; ++e)
+        for (int t = 0; t < 2; ++t) {
+            const int ti_w = gs_tile_width(e ? GS_HE : GS_H), tj_h = t ? GS_TJ16 : GS_TJ;
+            std::vector<int2>& tl = H.gs_tl[e][t];
+            tl.clear();
+            for (int ti = 0; ti * ti_w <= n - 1; ++ti)
+                for (int tj = 0; tj * tj_h <= n - 1; ++tj)
+                    if (ti * ti_w + tj * tj_h <= n - 1) tl.push_back(make_int2(ti, tj));
+        }
 
     // learned-smoother output tiles that contain interior points
     H.net_tiles.clear();
