@@ -76,6 +76,7 @@ void carve(hhg_mesh* M, uint32_t feat, Carver& c) {
     }
     C.vec = (double*)c.take(sizeof(double) * 5 * (size_t)m.Nc);
     M->n_partials = 8192 + 1024;
+    for (int l = 1; l <= m.L; ++l) M->n_partials = std::max(M->n_partials, sweep_norm_partials(M, l));
     M->partials = (double*)c.take(sizeof(double) * M->n_partials);
     M->dscalars = (double*)c.take(sizeof(double) * 64);
     for (int l = 0; l <= MAXLEVEL; ++l) {
@@ -225,12 +226,17 @@ int copy_field(const hhg_mesh* M, int level, int dt, void* dst, const void* src,
     return HHG_OK;
 }
 
+// One V-cycle on `level`.  norm != nullptr: also |f - A u|_2 of the result
+// into the device double *norm, formed by the last post-smoothing sweep when
+// there is one besides the sweep that carries the prolongation, else by a
+// residual pass.
 int vcycle_rec(const hhg_mesh* M, int level, int op, int smoother, int dt, void* u, const void* f,
-               int nu1, int nu2, hipStream_t s) {
+               int nu1, int nu2, hipStream_t s, double* norm = nullptr) {
     const int lc = M->m.lc;
     const double* vals = op == HHG_OP_DIFFUSION ? M->coarse_vals_diff : M->coarse.vals;
     if (level == lc) {
         HIP_CHECK(launch_coarse_solve(M, op, dt, u, f, vals, s), "coarse solve");
+        if (norm) HIP_CHECK(launch_residual(M, level, op, dt, u, f, nullptr, norm, s), "residual norm");
         return HHG_OK;
     }
     void* alt = level_alt(M, level, dt);
@@ -256,13 +262,22 @@ int vcycle_rec(const hhg_mesh* M, int level, int op, int smoother, int dt, void*
     if (smoother == HHG_SMOOTH_GS && nu2 > 0) {
         // prolongation folded into the first post-smoothing sweep: cur -> other
         HIP_CHECK(launch_gs_sweep_prolong(M, level, op, dt, cur, other, f, uc, s), "prolong + smooth");
-        rc = smooth_pp(M, level, op, smoother, dt, other, cur, f, nu2 - 1, 1, s, &fin);
+        const bool sweep_norm = norm && nu2 >= 2;
+        rc = smooth_pp(M, level, op, smoother, dt, other, cur, f, sweep_norm ? nu2 - 2 : nu2 - 1, 1, s, &fin);
+        if (rc) return rc;
+        if (sweep_norm) {
+            void* y = fin == other ? cur : other;
+            HIP_CHECK(launch_gs_sweep_norm(M, level, op, dt, fin, y, f, norm, s), "smooth + norm");
+            fin = y;
+            norm = nullptr;
+        }
     } else {
         HIP_CHECK(launch_prolong_add(M, level, dt, uc, cur, s), "prolong");
         rc = smooth_pp(M, level, op, smoother, dt, cur, other, f, nu2, 1, s, &fin);
+        if (rc) return rc;
     }
-    if (rc) return rc;
-    if (fin != u) return copy_field(M, level, dt, u, fin, s);
+    if (fin != u && (rc = copy_field(M, level, dt, u, fin, s))) return rc;
+    if (norm) HIP_CHECK(launch_residual(M, level, op, dt, u, f, nullptr, norm, s), "residual norm");
     return HHG_OK;
 }
 
@@ -622,8 +637,8 @@ int hhg_solve(hhg_mesh* M, const hhg_solve_opts* o, void* u, const void* f, hhg_
         double rn = 0.0;
         const bool learned = smoother == HHG_SMOOTH_NET;
         if (!mp) {
-            if ((rc = vcycle_rec(M, L, o->op, HHG_SMOOTH_GS, HHG_F64, u, f, o->nu1, o->nu2, s))) return rc;
-            HIP_CHECK(launch_residual(M, L, o->op, HHG_F64, u, f, nullptr, dnorm, s), "residual");
+            if ((rc = vcycle_rec(M, L, o->op, HHG_SMOOTH_GS, HHG_F64, u, f, o->nu1, o->nu2, s, dnorm)))
+                return rc;
             if ((rc = read_scalar(dnorm, &rn, s))) return rc;
         } else {
             HIP_CHECK(launch_fill(e32, nL, HHG_F32, 0.0, s), "fill");

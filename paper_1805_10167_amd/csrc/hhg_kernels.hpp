@@ -33,6 +33,13 @@ hipError_t launch_mp_step(const hhg_mesh* M, int level, int op, const double* x,
 // last pre-smoothing sweep before the restriction).
 hipError_t launch_gs_sweep_residual(const hhg_mesh* M, int level, int op, int dtype, void* x, void* y,
                                     const void* f, void* r, hipStream_t s);
+// Backward sweep x -> y that also writes |f - A y|_2 over interior points to
+// the device double *norm (fixed-order sums: face-core points per tile, then
+// the points on and next to the macro-edges).
+hipError_t launch_gs_sweep_norm(const hhg_mesh* M, int level, int op, int dtype, void* x, void* y,
+                                const void* f, double* norm, hipStream_t s);
+// Reduction slots the norm sweep of `level` needs (host data only).
+int64_t sweep_norm_partials(const hhg_mesh* M, int level);
 // Backward sweep that starts from x + P uc (uc: correction of level - 1):
 // prolongation and the first post-smoothing sweep in the same launches.
 hipError_t launch_gs_sweep_prolong(const hhg_mesh* M, int level, int op, int dtype, void* x, void* y,

@@ -14,6 +14,8 @@
 // the nodal k at T's corners (computed on the fly, sec. 1.1).
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+
 #include <cstdint>
 
 #include "hhg_kernels.hpp"
@@ -721,11 +723,12 @@ __device__ __forceinline__ void gs_store_u(T (*us)[GS_W], T (*ks)[GS_W], T (*ur)
 // `out` stores the tile's u once the stages are done; with the residual
 // (H = GS_HE) the residuals then replace the interior tile values in LDS.
 
-template <class T, bool VARK, bool PROL, int TJ, int H, class Out>
+template <class T, bool VARK, bool PROL, int TJ, int RES, class Out>
 __device__ __forceinline__ void gs_tile3(const LevelDev& L, const FaceInfo& fi, int n, int i0, int j0,
                                          int64_t fb, const T* __restrict__ uin, const T* __restrict__ f,
                                          const T* __restrict__ kap, int backward, T (*us)[GS_W],
-                                         T (*ks)[GS_W], const ProlTile<T>& pt, Out out) {
+                                         T (*ks)[GS_W], const ProlTile<T>& pt, Out out, double& acc) {
+    constexpr int H = RES ? GS_HE : GS_H;
     using G = GsTile<TJ, H>;
     const int wv = wave_id(), lane = threadIdx.x & 63;
     T ur[G::RPW][3], kr[VARK ? G::RPW : 1][3], fr[3][G::IT3];
@@ -763,7 +766,28 @@ __device__ __forceinline__ void gs_tile3(const LevelDev& L, const FaceInfo& fi, 
         }
         __syncthreads();
     }
-    if (H != GS_HE) {
+    if (RES == 0) {
+        out();
+        return;
+    }
+    if (RES == 2) {
+        // squared residuals of the tile's core points (no neighbour on a
+        // macro-edge, whose values the later edge stages still change)
+#pragma unroll
+        for (int s = 0; s < 3; ++s) {
+            const int c = backward ? 2 - s : s, lo = 1 + s;
+#pragma unroll
+            for (int it = 0; it < G::IT3; ++it) {
+                const int r = lo + wv + GS_NW * it, j = j0 + r;
+                if (r < H || r >= H + TJ) continue;
+                int tx = pmod(c + j - i0, 3) + 3 * lane;
+                const int i = i0 + tx;
+                const bool core = tx >= H && tx < H + G::TI && j >= 2 && i >= 2 && i + j <= n - 3;
+                tx = core ? tx : H;
+                const double v = (double)gs_resid<T, VARK>(fi, w, fr[s][it], us, ks, r, tx);
+                acc += core ? v * v : 0.0;
+            }
+        }
         out();
         return;
     }
@@ -822,12 +846,13 @@ __device__ __forceinline__ bool gs_decode2(int idx, int rule, int c, int h, int 
     return r < hi_j && tx < hi_i;
 }
 
-template <class T, bool VARK, bool PROL, int TJ, int H, class Out>
+template <class T, bool VARK, bool PROL, int TJ, int RES, class Out>
 __device__ __forceinline__ void gs_tile2(const LevelDev& L, const FaceInfo& fi, int n, int i0, int j0,
                                          int64_t fb, const T* __restrict__ uin, const T* __restrict__ f,
                                          const T* __restrict__ kap, int backward, T (*us)[GS_W],
                                          T (*ks)[GS_W], const ProlTile<T>& pt, Out out,
-                                         T* __restrict__ rout) {
+                                         T* __restrict__ rout, double& acc) {
+    constexpr int H = RES ? GS_HE : GS_H;
     using G = GsTile<TJ, H>;
     const int rule = fi.colour_rule;
     T ur[G::RPW][3], kr[VARK ? G::RPW : 1][3], fr[2][G::IT2];
@@ -862,7 +887,25 @@ __device__ __forceinline__ void gs_tile2(const LevelDev& L, const FaceInfo& fi, 
         __syncthreads();
     }
     out();
-    if (H != GS_HE) return;
+    if (RES == 0) return;
+    if (RES == 2) {
+#pragma unroll
+        for (int s = 0; s < 2; ++s) {
+            const int c = backward ? 1 - s : s, h = H - 2 - s;
+#pragma unroll
+            for (int it = 0; it < G::IT2; ++it) {
+                int r, tx;
+                const bool ok = gs_decode2<TJ, H>(threadIdx.x + it * GS_NT, rule, c, h, i0, j0, r, tx);
+                const int j = j0 + r, i = i0 + tx;
+                if (!(ok && r >= H && r < H + TJ && tx >= H && tx < H + G::TI && j >= 2 && i >= 2 &&
+                      i + j <= n - 3))
+                    continue;
+                const double v = (double)gs_resid<T, VARK>(fi, w, fr[s][it], us, ks, r, tx);
+                acc += v * v;
+            }
+        }
+        return;
+    }
     // residuals straight from the final LDS values to rout with their
     // ghost-row copies (faces with a right angle are few, so this path keeps
     // registers low rather than staging through LDS)
@@ -892,23 +935,29 @@ __device__ __forceinline__ void gs_tile2(const LevelDev& L, const FaceInfo& fi, 
 // points and their copies in the edge ghost rows (the edge and vertex
 // residuals and the remaining copies are left to an edge/vertex pass).
 // Three-colour tiles stage the residuals through LDS for row-wise stores;
-// two-colour tiles store them point by point.
-template <class T, bool VARK, int NCOL, bool PROL, int TJ, bool RES>
+// two-colour tiles store them point by point.  RES = 2 (backward sweeps):
+// every block writes partials[blockIdx.x], the sum of the squared residuals
+// of its tile's core points (0 for blocks without a tile); the points next
+// to or on the macro-edges are left to a pass after the edge stages.
+template <class T, bool VARK, int NCOL, bool PROL, int TJ, int RES>
 __global__ __launch_bounds__(GS_NT) void k_face_gs_fused(LevelDev L, const T* __restrict__ uin,
                                                          T* __restrict__ uout, const T* __restrict__ f,
                                                          const T* __restrict__ kap, int backward,
                                                          int nblk_tiles, int with_copy, LevelDev Lc,
-                                                         const T* __restrict__ uc, T* __restrict__ rout) {
+                                                         const T* __restrict__ uc, T* __restrict__ rout,
+                                                         double* __restrict__ partials) {
     constexpr int H = RES ? GS_HE : GS_H;
     constexpr int TI = GsTile<TJ, H>::TI;
     constexpr int T16 = TJ == GS_TJ16 ? 1 : 0;
     __shared__ T us[GsTile<TJ, H>::R][GS_W];
     __shared__ T ks[VARK ? GsTile<TJ, H>::R : 1][GS_W];
+    __shared__ double sm[RES == 2 ? GS_NW + 1 : 1];
     const int G = gridDim.x;                              // multiple of 8
     const int b = blockIdx.x;
     const int logical = (b & 7) * (G >> 3) + (b >> 3);    // contiguous tiles per XCD
     const int n = L.n;
     if (logical >= nblk_tiles) {
+        if (RES == 2 && threadIdx.x == 0) partials[b] = 0.0;
         if (!with_copy) return;
         // edge points (k = 0..n-1) and vertex blocks
         const int cb = logical - nblk_tiles, ncb = G - nblk_tiles;
@@ -925,7 +974,10 @@ __global__ __launch_bounds__(GS_NT) void k_face_gs_fused(LevelDev L, const T* __
     const int ntl = L.n_gs_tl[RES ? 1 : 0][T16];
     const int face = logical / ntl;
     const FaceInfo& fi = L.faces[face];
-    if (fi.ncolours != NCOL) return;
+    if (fi.ncolours != NCOL) {
+        if (RES == 2 && threadIdx.x == 0) partials[b] = 0.0;
+        return;
+    }
     const int2 tl = L.gs_tl[RES ? 1 : 0][T16][logical % ntl];
     const int i0 = tl.x * TI - H, j0 = tl.y * TJ - H;   // LDS origin
     const int64_t fb = face_base(L, face);
@@ -966,13 +1018,19 @@ __global__ __launch_bounds__(GS_NT) void k_face_gs_fused(LevelDev L, const T* __
             }
         }
     };
+    double acc = 0.0;
     if (NCOL == 3)
-        gs_tile3<T, VARK, PROL, TJ, H>(L, fi, n, i0, j0, fb, uin, f, kap, backward, us, VARK ? ks : nullptr, pt,
-                                       out);
+        gs_tile3<T, VARK, PROL, TJ, RES>(L, fi, n, i0, j0, fb, uin, f, kap, backward, us, VARK ? ks : nullptr,
+                                         pt, out, acc);
     else
-        gs_tile2<T, VARK, PROL, TJ, H>(L, fi, n, i0, j0, fb, uin, f, kap, backward, us, VARK ? ks : nullptr, pt,
-                                       out, rout);
-    if (!RES || NCOL == 2) return;
+        gs_tile2<T, VARK, PROL, TJ, RES>(L, fi, n, i0, j0, fb, uin, f, kap, backward, us, VARK ? ks : nullptr,
+                                         pt, out, rout, acc);
+    if (RES == 2) {
+        const double t = block_sum<GS_NT>(acc, sm);
+        if (threadIdx.x == 0) partials[b] = t;
+        return;
+    }
+    if (RES != 1 || NCOL == 2) return;
     // interior residuals (now in LDS) to rout, with the ghost-row copies of
     // the near-edge ones: rows 1 .. n-3 hold interior points
     for (int r = H + wv; r < H + TJ; r += GS_NW) {
@@ -1007,6 +1065,65 @@ __global__ __launch_bounds__(GS_NT) void k_face_gs_fused(LevelDev L, const T* __
                 rout[edge_ghost(L, fi.edge[2], fi.slot[2]) + (fi.rev[2] ? n - 2 - m : m)] = us[H + t][i - i0];
         }
     }
+}
+
+// Squared residuals, one partial sum per block, of the points a backward
+// sweep's face stage leaves out of its sum: the interior face points on the
+// first row along each side (j = 1, i = 1, i + j = n - 2), enumerated per
+// face as the row j = 1, the column i = 1 from j = 2, and the diagonal from
+// j = 2 to n - 4; then the interior edge points and interior vertices.  Each
+// interior unknown is in exactly one of the two sums.
+template <class T>
+__global__ __launch_bounds__(NT) void k_resnorm_rim(LevelDev L, int op, const T* __restrict__ x,
+                                                    const T* __restrict__ f, const T* __restrict__ kap,
+                                                    double* __restrict__ partials) {
+    __shared__ double sm[NT / 64 + 1];
+    const int n = L.n;
+    const int64_t pf = n >= 5 ? 3 * (int64_t)n - 12 : 0;   // rim points per face
+    const int64_t nfp = (int64_t)L.F * pf, ne = (int64_t)L.E * (n - 2);
+    double acc = 0.0;
+    for (int64_t t = blockIdx.x * (int64_t)NT + threadIdx.x; t < nfp + ne + L.V; t += (int64_t)gridDim.x * NT) {
+        T v = (T)0;
+        if (t < nfp) {
+            const int face = (int)(t / pf), q = (int)(t - face * pf);
+            int i, j;
+            if (q < n - 3) {
+                i = q + 1;
+                j = 1;
+            } else if (q < 2 * n - 7) {
+                i = 1;
+                j = q - (n - 3) + 2;
+            } else {
+                j = q - (2 * n - 7) + 2;
+                i = n - 2 - j;
+            }
+            const FaceInfo& fi = L.faces[face];
+            const int64_t p = face_base(L, face) + row_start(n, j) + i;
+            const int64_t up = row_start(n, j + 1) - row_start(n, j);
+            const int64_t dn = row_start(n, j) - row_start(n, j - 1);
+            const W7<T> w = face_weights<T>(op, fi, L.inv4l, kap, p, up, dn);
+            v = f[p] - (w.c * x[p] + w.e * x[p + 1] + w.w * x[p - 1] + w.n * x[p + up] + w.s * x[p - dn] +
+                        w.se * x[p - dn + 1] + w.nw * x[p + up - 1]);
+        } else if (t < nfp + ne) {
+            const int64_t te = t - nfp;
+            const int e = (int)(te / (n - 2)), k = (int)(te % (n - 2)) + 1;
+            const EdgeInfo& ei = L.edges[e];
+            if (!ei.boundary) {
+                const int64_t m = edge_main(L, e);
+                v = f[m + k] - edge_apply<T>(op, L, ei, x, kap, m, edge_ghost(L, e, 0), edge_ghost(L, e, 1), k);
+            }
+        } else {
+            const int vv = (int)(t - nfp - ne);
+            const VertexInfo& vi = L.verts[vv];
+            if (!vi.boundary) {
+                const int64_t vb = vert_off(L, vv);
+                v = f[vb] - vertex_apply<T>(op, L, vi, x, kap, vb);
+            }
+        }
+        acc += (double)v * (double)v;
+    }
+    const double s = block_sum<NT>(acc, sm);
+    if (threadIdx.x == 0) partials[blockIdx.x] = s;
 }
 
 // Stage A (stage = 0): interior vertices and even-k points of interior
@@ -1651,39 +1768,48 @@ struct TimingScope {
 
 template <class T>
 static hipError_t gs_t(const hhg_mesh* M, int level, int op, T* x, T* y, const T* f, int backward,
-                       hipStream_t s, const T* uc = nullptr, T* rout = nullptr) {
+                       hipStream_t s, const T* uc = nullptr, T* rout = nullptr, double* norm = nullptr) {
     const LevelDev L = M->dev(level);
     const T* kap = kap_of<T>(M, level);
     const int gl = grid_for((int64_t)L.n_iedges * (L.n - 2) + L.n_iverts, MAX_LOW_BLOCKS);
-    const bool res = rout != nullptr;
-    const bool timed = M->timing && level == M->m.L && !uc && !res;
+    // 0: sweep; 1: forward sweep that also writes the residual; 2: backward
+    // sweep that also forms the residual norm
+    const int res = rout ? 1 : (norm ? 2 : 0);
+    const bool timed = M->timing && level == M->m.L && !uc && res == 0;
     const LevelDev Lc = uc ? M->dev(level - 1) : L;
     // the variable-coefficient FP64 tile (u and k in LDS) is 16 rows high so
     // that two blocks fit on a CU; the others are 24 rows high
     const bool t16 = op == OP_DIFFUSION && sizeof(T) == 8;
     const int ntile_blocks = L.F * L.n_gs_tl[res ? 1 : 0][t16 ? 1 : 0];
     const int g = (ntile_blocks + GS_COPY_BLOCKS + 7) / 8 * 8;
-    const int g2 = (ntile_blocks + 7) / 8 * 8;
     const bool has2 = M->m.nfaces2 > 0;
+    const int g2 = has2 ? (ntile_blocks + 7) / 8 * 8 : 0;
+    const int64_t nrim = (int64_t)L.F * (L.n >= 5 ? 3 * (int64_t)L.n - 12 : 0) + low_items(L);
+    const int grim = grid_for(nrim, MAX_LOW_BLOCKS);
+    double* part = M->partials;
+    if (res == 2 && (int64_t)g + g2 + grim > M->n_partials) return hipErrorInvalidValue;
     auto faces = [&]() -> hipError_t {
         TimingScope ts(M, s, timed);
 #define HHG_FACE_LAUNCH(VK, PR, TJ, RS)                                                             \
     do {                                                                                            \
         k_face_gs_fused<T, VK, 3, PR, TJ, RS><<<g, GS_NT, 0, s>>>(L, x, y, f, kap, backward,         \
-                                                                  ntile_blocks, 1, Lc, uc, rout);   \
+                                                                  ntile_blocks, 1, Lc, uc, rout, part); \
         if (has2)                                                                                   \
             k_face_gs_fused<T, VK, 2, PR, TJ, RS><<<g2, GS_NT, 0, s>>>(L, x, y, f, kap, backward,    \
-                                                                       ntile_blocks, 0, Lc, uc, rout); \
+                                                                       ntile_blocks, 0, Lc, uc, rout, \
+                                                                       part + g);                    \
     } while (0)
         if (op == OP_DIFFUSION) {
             constexpr int TJV = sizeof(T) == 8 ? GS_TJ16 : GS_TJ;
-            if (uc) HHG_FACE_LAUNCH(true, true, TJV, false);
-            else if (res) HHG_FACE_LAUNCH(true, false, TJV, true);
-            else HHG_FACE_LAUNCH(true, false, TJV, false);
+            if (uc) HHG_FACE_LAUNCH(true, true, TJV, 0);
+            else if (res == 1) HHG_FACE_LAUNCH(true, false, TJV, 1);
+            else if (res == 2) HHG_FACE_LAUNCH(true, false, TJV, 2);
+            else HHG_FACE_LAUNCH(true, false, TJV, 0);
         } else {
-            if (uc) HHG_FACE_LAUNCH(false, true, GS_TJ, false);
-            else if (res) HHG_FACE_LAUNCH(false, false, GS_TJ, true);
-            else HHG_FACE_LAUNCH(false, false, GS_TJ, false);
+            if (uc) HHG_FACE_LAUNCH(false, true, GS_TJ, 0);
+            else if (res == 1) HHG_FACE_LAUNCH(false, false, GS_TJ, 1);
+            else if (res == 2) HHG_FACE_LAUNCH(false, false, GS_TJ, 2);
+            else HHG_FACE_LAUNCH(false, false, GS_TJ, 0);
         }
 #undef HHG_FACE_LAUNCH
         return hipGetLastError();
@@ -1692,7 +1818,7 @@ static hipError_t gs_t(const hhg_mesh* M, int level, int op, T* x, T* y, const T
     if (!backward) {
         k_low_gs<T><<<gl, NT, 0, s>>>(L, op, x, f, kap, 0);
         k_low_gs<T><<<gl, NT, 0, s>>>(L, op, x, f, kap, 1);
-        if ((e = faces()) != hipSuccess || !res) return e;
+        if ((e = faces()) != hipSuccess || res != 1) return e;
         // residual of the edge and vertex points (all copies) from the swept y
         k_apply<T, 1><<<grid_for(low_items(L), MAX_LOW_BLOCKS), NT, 0, s>>>(L, op, y, f, rout, kap, 0,
                                                                             nullptr);
@@ -1701,7 +1827,26 @@ static hipError_t gs_t(const hhg_mesh* M, int level, int op, T* x, T* y, const T
     if ((e = faces()) != hipSuccess) return e;
     k_low_gs<T><<<gl, NT, 0, s>>>(L, op, y, f, kap, 1);
     k_low_gs<T><<<gl, NT, 0, s>>>(L, op, y, f, kap, 0);
+    if (res == 2) {
+        // the rest of the residual norm, now that the edge stages are done
+        k_resnorm_rim<T><<<grim, NT, 0, s>>>(L, op, y, f, kap, part + g + g2);
+        k_reduce_final<<<1, 1024, 0, s>>>(part, g + g2 + grim, norm, 1);
+    }
     return hipGetLastError();
+}
+
+int64_t sweep_norm_partials(const hhg_mesh* M, int level) {
+    const LevelHost& H = M->m.lv[level];
+    const int n = H.n;
+    const int64_t nrim = (int64_t)M->m.F * (n >= 5 ? 3 * (int64_t)n - 12 : 0) + (int64_t)M->m.E * (n - 2) + M->m.V;
+    int64_t most = 0;
+    for (int t = 0; t < 2; ++t) {
+        const int64_t tiles = (int64_t)M->m.F * (int64_t)H.gs_tl[1][t].size();
+        const int64_t g = (tiles + GS_COPY_BLOCKS + 7) / 8 * 8;
+        const int64_t g2 = M->m.nfaces2 > 0 ? (tiles + 7) / 8 * 8 : 0;
+        most = std::max(most, g + g2 + grid_for(nrim, MAX_LOW_BLOCKS));
+    }
+    return most;
 }
 
 hipError_t launch_gs_sweep(const hhg_mesh* M, int level, int op, int dtype, void* x, void* y,
@@ -1716,6 +1861,13 @@ hipError_t launch_gs_sweep_residual(const hhg_mesh* M, int level, int op, int dt
     if (dtype == DT_F64)
         return gs_t<double>(M, level, op, (double*)x, (double*)y, (const double*)f, 0, s, nullptr, (double*)r);
     return gs_t<float>(M, level, op, (float*)x, (float*)y, (const float*)f, 0, s, nullptr, (float*)r);
+}
+
+hipError_t launch_gs_sweep_norm(const hhg_mesh* M, int level, int op, int dtype, void* x, void* y,
+                                const void* f, double* norm, hipStream_t s) {
+    if (dtype == DT_F64)
+        return gs_t<double>(M, level, op, (double*)x, (double*)y, (const double*)f, 1, s, nullptr, nullptr, norm);
+    return gs_t<float>(M, level, op, (float*)x, (float*)y, (const float*)f, 1, s, nullptr, nullptr, norm);
 }
 
 hipError_t launch_gs_sweep_prolong(const hhg_mesh* M, int level, int op, int dtype, void* x, void* y,

@@ -111,3 +111,27 @@ def test_argument_errors():
         log("case %d: %s" % (k, P.hhg_last_error()))
         assert e.value.code in (P.HHG_EINVAL, P.HHG_ENOMEM)
     assert torch.equal(x, torch.zeros_like(x))
+
+
+@pytest.mark.parametrize("case", ["square_L2_lc1", "annulus_L3_lc2", "one_face_L5"])
+def test_solve_history_small_levels(case):
+    """Residual histories of small-level solves equal the oracle's: the
+    norm-forming sweep at n = 5 has no face-core points, and on one face all
+    edges are Dirichlet."""
+    import paper_1805_10167_amd as P
+    if case == "square_L2_lc1":
+        (vxy, tri), L, lc = hi.unit_square(), 2, 1
+    elif case == "annulus_L3_lc2":
+        (vxy, tri), L, lc = hi.annulus(16), 3, 2
+    else:
+        (vxy, tri), L, lc = one_face(), 5, 2
+    g, H = meshes(vxy, tri, L, lc)
+    lv = H.levels[L]
+    f = hi.uniform_rhs(lv.n_all, 3)
+    uf, ff = g.field(L), g.from_canonical(L, f)
+    rc, st, hist = P.hhg_solve(g.h, uf, ff, rtol=1e-10, max_iters=60)
+    uo, ho = H.solve(np.zeros(lv.n_all), f, 1e-10, 3, 3)
+    log("%s: iters %d (oracle %d)" % (case, st["iters"], len(ho) - 1))
+    assert rc == 0 and st["iters"] == len(ho) - 1
+    assert rel_err(hist, ho) <= 1e-10
+    assert rel_err(to_np(g.to_canonical(L, uf)), uo) <= F64_TOL

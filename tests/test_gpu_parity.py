@@ -152,7 +152,9 @@ def _vcycle_parity(name, L, nu, lc, coarse="direct"):
 
 
 @pytest.mark.parametrize("name,L,nu,rtol", [("annulus64", 6, (3, 3), 1e-8),
-                                            ("square", 6, (2, 2), 1e-10)])
+                                            ("square", 6, (2, 2), 1e-10),
+                                            ("square", 5, (1, 1), 1e-8),
+                                            ("annulus64", 5, (1, 2), 1e-9)])
 def test_solve_parity(name, L, nu, rtol):
     import paper_1805_10167_amd as P
     log("solve %s L=%d" % (name, L))

@@ -92,6 +92,7 @@ def test_diffusion_solves_plain_and_mixed():
     uf, ff = g.from_canonical(L, np.zeros(lv.n_all)), g.from_canonical(L, f)
     rc, st, hist = P.hhg_solve(g.h, uf, ff, op=P.HHG_OP_DIFFUSION, rtol=1e-8)
     assert rc == 0 and st["iters"] == len(ho) - 1
+    assert rel_err(hist, ho) <= 1e-10
     assert rel_err(to_np(g.to_canonical(L, uf)), uo) <= F64_TOL
     uref, _ = H.solve(np.zeros(lv.n_all), f, 1e-12)
     uf.zero_()
