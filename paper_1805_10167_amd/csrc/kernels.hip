@@ -682,7 +682,7 @@ struct ProlTile {
 template <class T, bool VARK, bool PROL, int TJ, int H>
 __device__ __forceinline__ void gs_load_u(int n, int i0, int j0, int64_t fb, const T* __restrict__ uin,
                                           const T* __restrict__ kap, T (*ur)[3], T (*kr)[3],
-                                          const FaceInfo& fi, const ProlTile<T>& pt) {
+                                          const FaceInfo& fi, const ProlTile<T>& pt, T (*us)[GS_W]) {
     const int wv = wave_id(), lane = threadIdx.x & 63;
 #pragma unroll
     for (int q = 0; q < GsTile<TJ, H>::RPW; ++q) {
@@ -692,12 +692,39 @@ __device__ __forceinline__ void gs_load_u(int n, int i0, int j0, int64_t fb, con
         for (int c = 0; c < 3; ++c) {
             const int i = i0 + lane + 64 * c;
             const bool in = r < GsTile<TJ, H>::R && j >= 0 && j < n && i >= 0 && i <= n - 1 - j;
-            T v = in ? uin[rb + i] : (T)0;
-            if (PROL && in && !face_dirichlet(fi, n, i, j)) v += prol_face<T>(pt.uc, pt.cb, pt.nc, i, j);
-            ur[q][c] = v;
+            ur[q][c] = in ? uin[rb + i] : (T)0;
             if (VARK) kr[q][c] = in ? kap[rb + i] : (T)0;
         }
     }
+    if (!PROL) return;
+    // The coarse values the tile interpolates, staged in LDS (the u tile's
+    // space is free until the tile is stored): coarse rows and columns from
+    // half the tile origin, one more each for the odd fine rows and columns.
+    constexpr int CW = GS_W / 2 + 2, CH = GsTile<TJ, H>::R / 2 + 2;
+    static_assert(CW * CH <= GsTile<TJ, H>::R * GS_W, "coarse tile must fit the u tile");
+    T* cs = &us[0][0];
+    const int nc = pt.nc, Ilo = (i0 < 0 ? 0 : i0) >> 1, Jlo = (j0 < 0 ? 0 : j0) >> 1;
+    for (int t = threadIdx.x; t < CW * CH; t += GS_NT) {
+        const int J = Jlo + t / CW, I = Ilo + t % CW;
+        cs[t] = (J <= nc - 1 && I <= nc - 1 - J) ? pt.uc[pt.cb + row_start(nc, J) + I] : (T)0;
+    }
+    __syncthreads();
+    // linear interpolation as in prol_face, from LDS
+#pragma unroll
+    for (int q = 0; q < GsTile<TJ, H>::RPW; ++q) {
+        const int r = wv + GS_NW * q, j = j0 + r;
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            const int i = i0 + lane + 64 * c;
+            const bool in = r < GsTile<TJ, H>::R && j >= 0 && j < n && i >= 0 && i <= n - 1 - j;
+            if (!in || face_dirichlet(fi, n, i, j)) continue;
+            const int I = (i >> 1) - Ilo, J = (j >> 1) - Jlo, io = i & 1, jo = j & 1;
+            const T a = cs[J * CW + I + (io & jo)];
+            const T b = cs[(J + jo) * CW + I + (io & (jo ^ 1))];
+            ur[q][c] += (T)0.5 * (a + b);
+        }
+    }
+    __syncthreads();
 }
 
 template <class T, bool VARK, int TJ, int H>
@@ -732,7 +759,7 @@ __device__ __forceinline__ void gs_tile3(const LevelDev& L, const FaceInfo& fi, 
     using G = GsTile<TJ, H>;
     const int wv = wave_id(), lane = threadIdx.x & 63;
     T ur[G::RPW][3], kr[VARK ? G::RPW : 1][3], fr[3][G::IT3];
-    gs_load_u<T, VARK, PROL, TJ, H>(n, i0, j0, fb, uin, kap, ur, kr, fi, pt);
+    gs_load_u<T, VARK, PROL, TJ, H>(n, i0, j0, fb, uin, kap, ur, kr, fi, pt, us);
 #pragma unroll
     for (int s = 0; s < 3; ++s) {
         const int c = backward ? 2 - s : s, h = H - 1 - s;
@@ -856,7 +883,7 @@ __device__ __forceinline__ void gs_tile2(const LevelDev& L, const FaceInfo& fi, 
     using G = GsTile<TJ, H>;
     const int rule = fi.colour_rule;
     T ur[G::RPW][3], kr[VARK ? G::RPW : 1][3], fr[2][G::IT2];
-    gs_load_u<T, VARK, PROL, TJ, H>(n, i0, j0, fb, uin, kap, ur, kr, fi, pt);
+    gs_load_u<T, VARK, PROL, TJ, H>(n, i0, j0, fb, uin, kap, ur, kr, fi, pt, us);
 #pragma unroll
     for (int s = 0; s < 2; ++s) {
         const int c = backward ? 1 - s : s, h = H - 2 - s;
