@@ -1164,46 +1164,52 @@ template <class T>
 __device__ __forceinline__ void low_gs_item(const LevelDev& L, int op, T* __restrict__ u, const T* __restrict__ f,
                                             const T* __restrict__ kap, int stage, int64_t t, int64_t ne) {
     const int n = L.n;
-        if (t < ne) {
-            const int e = L.iedges[t / (n - 2)], k = (int)(t % (n - 2)) + 1;
-            const EdgeInfo& ei = L.edges[e];
-            const int64_t m = edge_main(L, e);
-            if ((k & 1) != stage) {
-                if (stage != 1 && (k & 1) && (k == 1 || k == n - 2)) {
-                    const T v = u[m + k];
-                    for (int end = 0; end < 2; ++end) {
-                        if (k != (end == 0 ? 1 : n - 2)) continue;
-                        for (int s = 0; s < ei.nf; ++s) {
-                            const int e2 = ei.cg_edge[s][end];
-                            if (e2 >= 0)
-                                u[edge_ghost(L, e2, ei.cg_slot[s][end]) + (ei.cg_first[s][end] ? 0 : n - 2)] = v;
-                        }
+    if (t < ne) {
+        // every edge, Dirichlet ones skipped: the values' addresses need only
+        // the edge id, so they load together with the edge's metadata
+        const int e = (int)(t / (n - 2)), k = (int)(t % (n - 2)) + 1;
+        const EdgeInfo& ei = L.edges[e];
+        const int64_t m = edge_main(L, e);
+        if ((k & 1) != stage) {
+            if (stage != 1 && (k & 1) && (k == 1 || k == n - 2)) {
+                const T v = u[m + k];
+                if (ei.boundary) return;
+                for (int end = 0; end < 2; ++end) {
+                    if (k != (end == 0 ? 1 : n - 2)) continue;
+                    for (int s = 0; s < ei.nf; ++s) {
+                        const int e2 = ei.cg_edge[s][end];
+                        if (e2 >= 0)
+                            u[edge_ghost(L, e2, ei.cg_slot[s][end]) + (ei.cg_first[s][end] ? 0 : n - 2)] = v;
                     }
                 }
-                return;
             }
-            const int64_t g0 = edge_ghost(L, e, 0), g1 = edge_ghost(L, e, 1);
-            const WE<T> w = edge_weights<T>(op, ei, L.inv4l, kap, m, g0, g1, k);
-            const T off = w.al * u[m + k - 1] + w.ah * u[m + k + 1] + w.l0 * u[g0 + k - 1] +
-                          w.h0 * u[g0 + k] + w.l1 * u[g1 + k - 1] + w.h1 * u[g1 + k];
-            const T v = (f[m + k] - off) / w.c;
-            u[m + k] = v;
-            push_edge(L, u, ei, k, v, false);
-        } else {
-            const int vv = L.iverts[t - ne];
-            const VertexInfo& vi = L.verts[vv];
-            const int64_t vb = vert_off(L, vv);
-            T s = (T)0, c = (T)0;
-            for (int q = 0; q < vi.deg; ++q) {
-                const T wq = vertex_weight<T>(op, vi, L.inv4l, kap, vb, q);
-                s += wq * u[vb + 1 + q];
-                c += wq;
-            }
-            c = (op == OP_MASS) ? c : -c;
-            const T v = (f[vb] - s) / c;
-            u[vb] = v;
-            push_vertex(L, u, vi, v);
+            return;
         }
+        const int64_t g0 = edge_ghost(L, e, 0), g1 = edge_ghost(L, e, 1);
+        const T um = u[m + k - 1], up = u[m + k + 1], a0 = u[g0 + k - 1], b0 = u[g0 + k];
+        const T a1 = u[g1 + k - 1], b1 = u[g1 + k], fv = f[m + k];
+        if (ei.boundary) return;
+        const WE<T> w = edge_weights<T>(op, ei, L.inv4l, kap, m, g0, g1, k);
+        const T off = w.al * um + w.ah * up + w.l0 * a0 + w.h0 * b0 + w.l1 * a1 + w.h1 * b1;
+        const T v = (fv - off) / w.c;
+        u[m + k] = v;
+        push_edge(L, u, ei, k, v, false);
+    } else {
+        const int vv = (int)(t - ne);
+        const VertexInfo& vi = L.verts[vv];
+        if (vi.boundary) return;
+        const int64_t vb = vert_off(L, vv);
+        T s = (T)0, c = (T)0;
+        for (int q = 0; q < vi.deg; ++q) {
+            const T wq = vertex_weight<T>(op, vi, L.inv4l, kap, vb, q);
+            s += wq * u[vb + 1 + q];
+            c += wq;
+        }
+        c = (op == OP_MASS) ? c : -c;
+        const T v = (f[vb] - s) / c;
+        u[vb] = v;
+        push_vertex(L, u, vi, v);
+    }
 }
 
 template <class T>
@@ -1211,8 +1217,8 @@ __global__ __launch_bounds__(NT) void k_low_gs(LevelDev L, int op, T* __restrict
                                                const T* __restrict__ f, const T* __restrict__ kap,
                                                int stage) {
     const int n = L.n;
-    const int64_t ne = (int64_t)L.n_iedges * (n - 2);
-    const int64_t nv = stage == 0 ? L.n_iverts : 0;
+    const int64_t ne = (int64_t)L.E * (n - 2);
+    const int64_t nv = stage == 0 ? L.V : 0;
     for (int64_t t = blockIdx.x * (int64_t)NT + threadIdx.x; t < ne + nv; t += (int64_t)gridDim.x * NT)
         low_gs_item<T>(L, op, u, f, kap, stage, t, ne);
 }
@@ -1798,7 +1804,7 @@ static hipError_t gs_t(const hhg_mesh* M, int level, int op, T* x, T* y, const T
                        hipStream_t s, const T* uc = nullptr, T* rout = nullptr, double* norm = nullptr) {
     const LevelDev L = M->dev(level);
     const T* kap = kap_of<T>(M, level);
-    const int gl = grid_for((int64_t)L.n_iedges * (L.n - 2) + L.n_iverts, MAX_LOW_BLOCKS);
+    const int gl = grid_for((int64_t)L.E * (L.n - 2) + L.V, MAX_LOW_BLOCKS);
     // 0: sweep; 1: forward sweep that also writes the residual; 2: backward
     // sweep that also forms the residual norm
     const int res = rout ? 1 : (norm ? 2 : 0);
@@ -2076,7 +2082,7 @@ hipError_t launch_axpby(int64_t n, int dtype, double alpha, const void* x, doubl
 hipError_t launch_low_gs(const hhg_mesh* M, int level, int op, int dtype, void* u, const void* f,
                          int stage, hipStream_t s) {
     const LevelDev L = M->dev(level);
-    const int gl = grid_for((int64_t)L.n_iedges * (L.n - 2) + L.n_iverts, MAX_LOW_BLOCKS);
+    const int gl = grid_for((int64_t)L.E * (L.n - 2) + L.V, MAX_LOW_BLOCKS);
     if (dtype == DT_F64)
         k_low_gs<double><<<gl, NT, 0, s>>>(L, op, (double*)u, (const double*)f, M->kap64[level], stage);
     else
