@@ -75,6 +75,67 @@ def cpu_baseline(level, rtol, nu):
                                                      nu, nu, dt)}
 
 
+def kernel_section(P, hi, torch, g, L, reps=10):
+    """Per-call GDoF/s and fraction of the HBM peak at the finest level, for
+    the calls the V-cycle is made of, in FP64 and FP32.  Each figure brackets
+    a whole library call with events on torch's stream (the stream the call
+    launches on), so a sweep includes its edge/vertex stages.  Bytes are the
+    algorithmic ones per interior unknown: every field read once and written
+    once (residual + restriction: read u, f, write a quarter-size f_c;
+    prolongation + add: read a quarter-size u_c, read and write u)."""
+    n_int, n_all = g.n_dofs(L)
+    _, n_all_c = g.n_dofs(L - 1)
+    stream = torch.cuda.current_stream()
+
+    def ms_of(fn):
+        for _ in range(2):
+            fn()
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record(stream)
+        for _ in range(reps):
+            fn()
+        b.record(stream)
+        b.synchronize()
+        return a.elapsed_time(b) / reps
+
+    out = {"level": L, "interior_dofs": n_int, "reps": reps}
+    lap, gs = P.HHG_OP_LAPLACE, P.HHG_SMOOTH_GS
+    for dt, name, w in ((P.HHG_F64, "f64", 8), (P.HHG_F32, "f32", 4)):
+        x = g.from_canonical(L, hi.uniform_vector(n_all, 21), dt)
+        f = g.from_canonical(L, hi.uniform_rhs(n_all, 1), dt)
+        r = g.field(L, dt)
+        fc = g.field(L - 1, dt)
+        uc = g.from_canonical(L - 1, hi.uniform_vector(n_all_c, 22), dt)
+        norm = torch.zeros(1, dtype=torch.float64, device="cuda")
+        calls = [
+            ("apply", 2.0, lambda: P.hhg_apply(g.h, L, lap, dt, x, r, stream=stream)),
+            # two sweeps per call: the result lands back in x, so no copy
+            ("gs_sweep", 3.0, lambda: P.hhg_smooth(g.h, L, lap, gs, dt, x, f, 2, 0, stream=stream)),
+            ("residual_restrict", 2.25, lambda: (P.hhg_residual(g.h, L, lap, dt, x, f, r, stream=stream),
+                                                 P.hhg_restrict(g.h, L, dt, r, fc, stream=stream))),
+            ("prolong_add", 2.25, lambda: P.hhg_prolong_add(g.h, L, dt, uc, x, stream=stream)),
+            ("residual_norm", 2.0, lambda: P.hhg_residual(g.h, L, lap, dt, x, f, None, norm, stream=stream)),
+        ]
+        res = {}
+        for key, words, fn in calls:
+            ms = ms_of(fn) / (2 if key == "gs_sweep" else 1)
+            nbytes = words * w * n_int
+            res[key] = {"ms": round(ms, 4), "gdofs": round(n_int / (ms * 1e-3) / 1e9, 2),
+                        "alg_bytes_per_dof": words * w,
+                        "hbm_frac": round(nbytes / (ms * 1e-3) / (HBM_PEAK_GBS * 1e9), 4)}
+        out[name] = res
+        del x, f, r, fc, uc
+    # a plain device copy of the same size as one field: the practical ceiling
+    src = torch.empty(n_all, dtype=torch.float64, device="cuda")
+    dst = torch.empty_like(src)
+    ms = ms_of(lambda: dst.copy_(src))
+    out["stream_copy"] = {"bytes": 2 * src.numel() * 8, "ms": round(ms, 4),
+                          "gbs": round(2 * src.numel() * 8 / (ms * 1e-3) / 1e9, 1),
+                          "hbm_frac": round(2 * src.numel() * 8 / (ms * 1e-3) / (HBM_PEAK_GBS * 1e9), 4)}
+    del src, dst
+    return out
+
+
 def timed_solve(P, g, u, f, mode, op, rtol, nu, max_iters=100):
     import torch
     u.zero_()
@@ -297,6 +358,7 @@ def main():
     ap.add_argument("--eval-fields", type=int, default=8)
     ap.add_argument("--cycle-pair-check", type=int, default=1)
     ap.add_argument("--no-large", action="store_true")
+    ap.add_argument("--no-kernels", action="store_true")
     ap.add_argument("--large-level", type=int, default=11)
     ap.add_argument("--copy-calibration", type=int, default=0,
                     help="bytes of a plain device copy run after the benchmark (counter scale)")
@@ -400,6 +462,9 @@ def main():
         out["time_to_tol_ms"]["mp_ir"] = round(statistics.median(mp_times), 3)
         out["iterations"]["mp_ir"] = mp_iters[0]
         out["mp_final_rel_res"] = mp_res[0]
+    if not args.no_kernels:
+        log("per-call kernel rates at level %d" % L)
+        out["kernels"] = kernel_section(P, hi, torch, g, L)
     del g, u, f
     torch.cuda.empty_cache()
     if not args.no_learned:

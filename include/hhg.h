@@ -194,7 +194,8 @@ int hhg_apply(const hhg_mesh* mesh, int32_t level, int32_t op, int32_t dtype,
 /*
  * r = f - A u on interior points (0 on Dirichlet points) into field r, and
  * optionally |r|_2 over interior points (each unknown once, sec. 4.1 Alg. 2)
- * into the device double *norm (NULL to skip).
+ * into the device double *norm (NULL to skip).  With r == NULL only the norm
+ * is formed (norm must then be given).
  */
 int hhg_residual(const hhg_mesh* mesh, int32_t level, int32_t op, int32_t dtype,
                  const void* u, const void* f, void* r, double* norm,

@@ -75,8 +75,9 @@ void carve(hhg_mesh* M, uint32_t feat, Carver& c) {
         if (feat & HHG_FEAT_VARK) M->coarse_inv[1] = (double*)c.take(sizeof(double) * NN);
     }
     C.vec = (double*)c.take(sizeof(double) * 5 * (size_t)m.Nc);
-    M->n_partials = 8192 + 1024;
-    for (int l = 1; l <= m.L; ++l) M->n_partials = std::max(M->n_partials, sweep_norm_partials(M, l));
+    M->n_partials = 1024;
+    for (int l = 1; l <= m.L; ++l)
+        M->n_partials = std::max({M->n_partials, sweep_norm_partials(M, l), face_loop_partials(M, l)});
     M->partials = (double*)c.take(sizeof(double) * M->n_partials);
     M->dscalars = (double*)c.take(sizeof(double) * 64);
     for (int l = 0; l <= MAXLEVEL; ++l) {
@@ -528,7 +529,7 @@ int hhg_residual(const hhg_mesh* M, int32_t level, int32_t op, int32_t dtype, co
     if (rc) return rc;
     if ((rc = check_op(M, op, dtype))) return rc;
     if (op == HHG_OP_MASS) return fail(HHG_EINVAL, "residual needs a stiffness operator");
-    if (!u || !f || !r) return fail(HHG_EINVAL, "null buffer");
+    if (!u || !f || (!r && !norm)) return fail(HHG_EINVAL, "null buffer");
     HIP_CHECK(launch_residual(M, level, op, dtype, u, f, r, norm, (hipStream_t)stream), "residual");
     return HHG_OK;
 }

@@ -40,6 +40,9 @@ hipError_t launch_gs_sweep_norm(const hhg_mesh* M, int level, int op, int dtype,
                                 const void* f, double* norm, hipStream_t s);
 // Reduction slots the norm sweep of `level` needs (host data only).
 int64_t sweep_norm_partials(const hhg_mesh* M, int level);
+// Reduction slots the face-loop kernels (residual norm, dots, the mixed-
+// precision outer step) need on `level` (host data only).
+int64_t face_loop_partials(const hhg_mesh* M, int level);
 // Backward sweep that starts from x + P uc (uc: correction of level - 1):
 // prolongation and the first post-smoothing sweep in the same launches.
 hipError_t launch_gs_sweep_prolong(const hhg_mesh* M, int level, int op, int dtype, void* x, void* y,

@@ -328,6 +328,61 @@ __device__ __forceinline__ T vertex_apply(int op, const LevelDev& L, const Verte
     return c * x[vb] + s;
 }
 
+// Point operator at edge/vertex item t (edge points first, ne of them, then
+// vertices), with all copies of the result; see k_apply for the modes.
+template <class T, int MODE>
+__device__ __forceinline__ void apply_low_item(const LevelDev& L, int op, const T* __restrict__ x,
+                                               const T* __restrict__ f, T* __restrict__ y,
+                                               const T* __restrict__ kap, int64_t t, int64_t ne, double& acc) {
+    const int n = L.n;
+    T v = (T)0;
+    if (t < ne) {
+        const int e = (int)(t / (n - 2)), k = (int)(t % (n - 2)) + 1;
+        const EdgeInfo& ei = L.edges[e];
+        const int64_t m = edge_main(L, e);
+        if (!ei.boundary) {
+            const int64_t g0 = edge_ghost(L, e, 0), g1 = edge_ghost(L, e, 1);
+            const WE<T> w = edge_weights<T>(op, ei, L.inv4l, kap, m, g0, g1, k);
+            if (MODE == 3) {
+                v = x[m + k] / w.c;
+            } else {
+                v = w.c * x[m + k] + w.al * x[m + k - 1] + w.ah * x[m + k + 1] + w.l0 * x[g0 + k - 1] +
+                    w.h0 * x[g0 + k] + w.l1 * x[g1 + k - 1] + w.h1 * x[g1 + k];
+                if (MODE >= 1) v = f[m + k] - v;
+                if (MODE == 1 || MODE == 4) acc += (double)v * (double)v;
+                if (MODE == 2) v = v / w.c;
+            }
+        }
+        if (MODE == 4) return;
+        y[m + k] = v;
+        push_edge(L, y, ei, k, v, true);
+    } else {
+        const int vv = (int)(t - ne);
+        const VertexInfo& vi = L.verts[vv];
+        const int64_t vb = vert_off(L, vv);
+        if (!vi.boundary) {
+            T s = (T)0, c = (T)0;
+            for (int q = 0; q < vi.deg; ++q) {
+                const T wq = vertex_weight<T>(op, vi, L.inv4l, kap, vb, q);
+                s += wq * x[vb + 1 + q];
+                c += wq;
+            }
+            c = (op == OP_MASS) ? c : -c;
+            if (MODE == 3) {
+                v = x[vb] / c;
+            } else {
+                v = c * x[vb] + s;
+                if (MODE >= 1) v = f[vb] - v;
+                if (MODE == 1 || MODE == 4) acc += (double)v * (double)v;
+                if (MODE == 2) v = v / c;
+            }
+        }
+        if (MODE == 4) return;
+        y[vb] = v;
+        push_vertex(L, y, vi, v);
+    }
+}
+
 // Point operator of every interior row, with all copies of the result:
 //   MODE 0: y = A x              MODE 1: y = f - A x (+ per-block sums of y^2)
 //   MODE 2: y = (f - A x) / a_pp MODE 3: y = x / a_pp
@@ -359,54 +414,7 @@ __global__ __launch_bounds__(NT) void k_apply(LevelDev L, int op, const T* __res
         push_face_near(L, y, fi, i, j, v);
         }
     } else {
-        LOW_LOOP(L, gf) {
-            T v = (T)0;
-            if (t < ne_) {
-                const int e = (int)(t / (nl_ - 2)), k = (int)(t % (nl_ - 2)) + 1;
-                const EdgeInfo& ei = L.edges[e];
-                const int64_t m = edge_main(L, e);
-                if (!ei.boundary) {
-                    const int64_t g0 = edge_ghost(L, e, 0), g1 = edge_ghost(L, e, 1);
-                    const WE<T> w = edge_weights<T>(op, ei, L.inv4l, kap, m, g0, g1, k);
-                    if (MODE == 3) {
-                        v = x[m + k] / w.c;
-                    } else {
-                        v = w.c * x[m + k] + w.al * x[m + k - 1] + w.ah * x[m + k + 1] + w.l0 * x[g0 + k - 1] +
-                            w.h0 * x[g0 + k] + w.l1 * x[g1 + k - 1] + w.h1 * x[g1 + k];
-                        if (MODE >= 1) v = f[m + k] - v;
-                        if (MODE == 1 || MODE == 4) acc += (double)v * (double)v;
-                        if (MODE == 2) v = v / w.c;
-                    }
-                }
-                if (MODE == 4) continue;
-                y[m + k] = v;
-                push_edge(L, y, ei, k, v, true);
-            } else {
-                const int vv = (int)(t - ne_);
-                const VertexInfo& vi = L.verts[vv];
-                const int64_t vb = vert_off(L, vv);
-                if (!vi.boundary) {
-                    T s = (T)0, c = (T)0;
-                    for (int q = 0; q < vi.deg; ++q) {
-                        const T wq = vertex_weight<T>(op, vi, L.inv4l, kap, vb, q);
-                        s += wq * x[vb + 1 + q];
-                        c += wq;
-                    }
-                    c = (op == OP_MASS) ? c : -c;
-                    if (MODE == 3) {
-                        v = x[vb] / c;
-                    } else {
-                        v = c * x[vb] + s;
-                        if (MODE >= 1) v = f[vb] - v;
-                        if (MODE == 1 || MODE == 4) acc += (double)v * (double)v;
-                        if (MODE == 2) v = v / c;
-                    }
-                }
-                if (MODE == 4) continue;
-                y[vb] = v;
-                push_vertex(L, y, vi, v);
-            }
-        }
+        LOW_LOOP(L, gf) { apply_low_item<T, MODE>(L, op, x, f, y, kap, t, ne_, acc); }
     }
     if ((MODE == 1 || MODE == 4) && partials) {
         const double s = block_sum<NT>(acc, sm);
@@ -1094,6 +1102,112 @@ __global__ __launch_bounds__(GS_NT) void k_face_gs_fused(LevelDev L, const T* __
     }
 }
 
+// The point operator of k_apply with the face points taken from LDS tiles:
+// the smoother's TI x TJ tiles, each loaded with a one-point halo in one
+// round of independent row loads (f of the block's points into registers
+// alongside), then every interior point formed from LDS.  The blocks from gt
+// on take the edge and vertex points.  Modes and outputs as k_apply; for the
+// norm modes every block writes partials[blockIdx.x] (0 without work).
+template <class T, bool VARK, int MODE, int TJ>
+__global__ __launch_bounds__(GS_NT) void k_apply_tiled(LevelDev L, int op, const T* __restrict__ x,
+                                                       const T* __restrict__ f, T* __restrict__ y,
+                                                       const T* __restrict__ kap, int nblk_tiles, int gt,
+                                                       double* __restrict__ partials) {
+    constexpr int TI = GsTile<TJ, GS_H>::TI, RA = TJ + 2, TL = TJ == GS_TJ16 ? 1 : 0;
+    constexpr int RPW = (RA + GS_NW - 1) / GS_NW, KR = TJ / GS_NW;
+    static_assert(TJ % GS_NW == 0, "tile rows must split evenly over the waves");
+    static_assert(TI + 2 <= GS_W, "tile with halo must fit an LDS row");
+    constexpr bool NORM = MODE == 1 || MODE == 4;
+    __shared__ T xs[RA][GS_W];
+    __shared__ T ks[VARK ? RA : 1][GS_W];
+    __shared__ double sm[GS_NW + 1];
+    const int b = blockIdx.x, n = L.n;
+    const int wv = wave_id(), lane = threadIdx.x & 63;
+    double acc = 0.0;
+    if (b >= gt) {
+        const int64_t ne = (int64_t)L.E * (n - 2);
+        for (int64_t t = (int64_t)(b - gt) * GS_NT + threadIdx.x; t < ne + L.V;
+             t += (int64_t)(gridDim.x - gt) * GS_NT)
+            apply_low_item<T, MODE>(L, op, x, f, y, kap, t, ne, acc);
+    } else {
+        const int logical = (b & 7) * (gt >> 3) + (b >> 3);   // contiguous tiles per XCD
+        if (logical < nblk_tiles) {
+            const int ntl = L.n_gs_tl[0][TL];
+            const int face = logical / ntl;
+            const FaceInfo& fi = L.faces[face];
+            const int2 tl = L.gs_tl[0][TL][logical % ntl];
+            const int i0 = tl.x * TI - 1, j0 = tl.y * TJ - 1;   // LDS origin
+            const int64_t fb = face_base(L, face);
+            // all loads first (tile into registers, then f), LDS stores after,
+            // so that the loads are in flight together
+            T xr[RPW][3], kr[VARK ? RPW : 1][3];
+#pragma unroll
+            for (int q = 0; q < RPW; ++q) {
+                const int r = wv + GS_NW * q, j = j0 + r;
+                const int64_t rb = fb + row_start(n, j < 0 ? 0 : (j > n ? n : j));
+#pragma unroll
+                for (int c = 0; c < 3; ++c) {
+                    const int tx = lane + 64 * c, i = i0 + tx;
+                    const bool in = r < RA && tx < TI + 2 && j >= 0 && j < n && i >= 0 && i <= n - 1 - j;
+                    xr[q][c] = in ? x[rb + i] : (T)0;
+                    if (VARK) kr[q][c] = in ? kap[rb + i] : (T)0;
+                }
+            }
+            T fr[KR][3];
+#pragma unroll
+            for (int k = 0; k < KR; ++k) {
+                const int r = 1 + wv + GS_NW * k, j = j0 + r;
+#pragma unroll
+                for (int c = 0; c < 3; ++c) {
+                    const int tx = lane + 64 * c, i = i0 + tx;
+                    const bool pt = MODE >= 1 && MODE != 3 && tx >= 1 && tx <= TI && j >= 1 && i >= 1 &&
+                                    i + j <= n - 2;
+                    fr[k][c] = pt ? f[fb + row_start(n, pt ? j : 0) + i] : (T)0;
+                }
+            }
+#pragma unroll
+            for (int q = 0; q < RPW; ++q) {
+                const int r = wv + GS_NW * q;
+                if (r >= RA) continue;
+#pragma unroll
+                for (int c = 0; c < 3; ++c) {
+                    xs[r][lane + 64 * c] = xr[q][c];
+                    if (VARK) ks[r][lane + 64 * c] = kr[q][c];
+                }
+            }
+            const W7<T> wf = face_weights<T>(VARK ? OP_LAPLACE : op, fi, L.inv4l, (const T*)nullptr, 0, 0, 0);
+            __syncthreads();
+#pragma unroll
+            for (int k = 0; k < KR; ++k) {
+                const int r = 1 + wv + GS_NW * k, j = j0 + r;
+#pragma unroll
+                for (int c = 0; c < 3; ++c) {
+                    const int tx = lane + 64 * c, i = i0 + tx;
+                    if (!(tx >= 1 && tx <= TI && j >= 1 && i >= 1 && i + j <= n - 2)) continue;
+                    const W7<T> w = VARK ? gs_weights_lds<T>(fi, ks, r, tx) : wf;
+                    T v;
+                    if (MODE == 3) {
+                        v = xs[r][tx] / w.c;
+                    } else {
+                        v = w.c * xs[r][tx] + w.e * xs[r][tx + 1] + w.w * xs[r][tx - 1] + w.n * xs[r + 1][tx] +
+                            w.s * xs[r - 1][tx] + w.se * xs[r - 1][tx + 1] + w.nw * xs[r + 1][tx - 1];
+                        if (MODE >= 1) v = fr[k][c] - v;
+                        if (NORM) acc += (double)v * (double)v;
+                        if (MODE == 2) v = v / w.c;
+                    }
+                    if (MODE == 4) continue;
+                    y[fb + row_start(n, j) + i] = v;
+                    push_face_near(L, y, fi, i, j, v);
+                }
+            }
+        }
+    }
+    if (NORM && partials) {
+        const double t = block_sum<GS_NT>(acc, sm);
+        if (threadIdx.x == 0) partials[b] = t;
+    }
+}
+
 // Squared residuals, one partial sum per block, of the points a backward
 // sweep's face stage leaves out of its sum: the interior face points on the
 // first row along each side (j = 1, i = 1, i + j = n - 2), enumerated per
@@ -1726,11 +1840,43 @@ hipError_t launch_sync(const hhg_mesh* M, int level, int dtype, void* x, int mas
     return hipGetLastError();
 }
 
+// Grid of the tiled point operator: tile blocks (a multiple of 8, for the
+// XCD-contiguous order) followed by edge/vertex blocks.
+struct TiledGrid {
+    int tiles, gt, gl;
+};
+static inline TiledGrid tiled_grid(int64_t F, int64_t ntl, int64_t low) {
+    TiledGrid g;
+    g.tiles = (int)(F * ntl);
+    g.gt = (g.tiles + 7) / 8 * 8;
+    int64_t gl = (low + GS_NT - 1) / GS_NT;
+    g.gl = (int)std::max<int64_t>(1, std::min<int64_t>(gl, MAX_LOW_BLOCKS / 2));
+    return g;
+}
+
+// Point operator (k_apply's modes) over a whole level; returns the number of
+// partial sums written (norm modes with partials).
+template <class T, int MODE>
+static int apply_tiled(const hhg_mesh* M, int level, int op, const T* x, const T* f, T* y,
+                       double* partials, hipStream_t s) {
+    const LevelDev L = M->dev(level);
+    const T* kap = kap_of<T>(M, level);
+    const bool vk = op == OP_DIFFUSION;
+    const int tl = vk && sizeof(T) == 8 ? 1 : 0;
+    const TiledGrid g = tiled_grid(L.F, L.n_gs_tl[0][tl], low_items(L));
+    const int grid = g.gt + g.gl;
+    if (vk && sizeof(T) == 8)
+        k_apply_tiled<T, true, MODE, GS_TJ16><<<grid, GS_NT, 0, s>>>(L, op, x, f, y, kap, g.tiles, g.gt, partials);
+    else if (vk)
+        k_apply_tiled<T, true, MODE, GS_TJ><<<grid, GS_NT, 0, s>>>(L, op, x, f, y, kap, g.tiles, g.gt, partials);
+    else
+        k_apply_tiled<T, false, MODE, GS_TJ><<<grid, GS_NT, 0, s>>>(L, op, x, f, y, kap, g.tiles, g.gt, partials);
+    return grid;
+}
+
 template <class T>
 static hipError_t apply_t(const hhg_mesh* M, int level, int op, const T* x, T* y, hipStream_t s) {
-    const LevelDev L = M->dev(level);
-    const int gf = face_grid(L), gl = grid_for(low_items(L), MAX_LOW_BLOCKS);
-    k_apply<T, 0><<<gf + gl, NT, 0, s>>>(L, op, x, nullptr, y, kap_of<T>(M, level), gf, nullptr);
+    apply_tiled<T, 0>(M, level, op, x, nullptr, y, nullptr, s);
     return hipGetLastError();
 }
 
@@ -1743,14 +1889,9 @@ hipError_t launch_apply(const hhg_mesh* M, int level, int op, int dtype, const v
 template <class T>
 static hipError_t residual_t(const hhg_mesh* M, int level, int op, const T* u, const T* f, T* r,
                              double* norm, hipStream_t s) {
-    const LevelDev L = M->dev(level);
-    const int gf = face_grid(L), gl = grid_for(low_items(L), MAX_LOW_BLOCKS);
-    if (r)
-        k_apply<T, 1><<<gf + gl, NT, 0, s>>>(L, op, u, f, r, kap_of<T>(M, level), gf,
-                                                norm ? M->partials : nullptr);
-    else
-        k_apply<T, 4><<<gf + gl, NT, 0, s>>>(L, op, u, f, r, kap_of<T>(M, level), gf, M->partials);
-    if (norm) k_reduce_final<<<1, 1024, 0, s>>>(M->partials, gf + gl, norm, 1);
+    const int np = r ? apply_tiled<T, 1>(M, level, op, u, f, r, norm ? M->partials : nullptr, s)
+                     : apply_tiled<T, 4>(M, level, op, u, f, r, M->partials, s);
+    if (norm) k_reduce_final<<<1, 1024, 0, s>>>(M->partials, np, norm, 1);
     return hipGetLastError();
 }
 
@@ -1866,6 +2007,20 @@ static hipError_t gs_t(const hhg_mesh* M, int level, int op, T* x, T* y, const T
         k_reduce_final<<<1, 1024, 0, s>>>(part, g + g2 + grim, norm, 1);
     }
     return hipGetLastError();
+}
+
+int64_t face_loop_partials(const hhg_mesh* M, int level) {
+    const LevelHost& H = M->m.lv[level];
+    int64_t g = (int64_t)M->m.F * (int64_t)H.tiles.size();
+    g = std::max<int64_t>(1, std::min<int64_t>(g, MAX_FACE_BLOCKS));
+    const int n = H.n;
+    const int64_t low = (int64_t)M->m.E * (n - 2) + M->m.V;
+    int64_t most = g + grid_for(low, MAX_LOW_BLOCKS);
+    for (int t = 0; t < 2; ++t) {
+        const TiledGrid tg = tiled_grid(M->m.F, (int64_t)H.gs_tl[0][t].size(), low);
+        most = std::max<int64_t>(most, (int64_t)tg.gt + tg.gl);
+    }
+    return most;
 }
 
 int64_t sweep_norm_partials(const hhg_mesh* M, int level) {
@@ -2037,10 +2192,8 @@ hipError_t launch_add_f32_to_f64(double* u, const float* e, int64_t n, hipStream
 template <class T>
 static hipError_t jacobi_t(const hhg_mesh* M, int level, int op, const T* u, const T* f, T* rho,
                            hipStream_t s) {
-    const LevelDev L = M->dev(level);
-    const int gf = face_grid(L), gl = grid_for(low_items(L), MAX_LOW_BLOCKS);
-    if (f) k_apply<T, 2><<<gf + gl, NT, 0, s>>>(L, op, u, f, rho, kap_of<T>(M, level), gf, nullptr);
-    else k_apply<T, 3><<<gf + gl, NT, 0, s>>>(L, op, u, nullptr, rho, kap_of<T>(M, level), gf, nullptr);
+    if (f) apply_tiled<T, 2>(M, level, op, u, f, rho, nullptr, s);
+    else apply_tiled<T, 3>(M, level, op, u, nullptr, rho, nullptr, s);
     return hipGetLastError();
 }
 

@@ -91,6 +91,10 @@ def test_residual_and_norm(name, L):
     ro = H.residual(L, u, f)
     assert rel_err(to_np(g.to_canonical(L, r)), ro) <= F64_TOL
     assert abs(nrm.item() - np.linalg.norm(ro)) <= F64_TOL * np.linalg.norm(ro)
+    # norm only: no residual field
+    nrm2 = torch.zeros(1, dtype=torch.float64, device="cuda")
+    P.hhg_residual(g.h, L, P.HHG_OP_LAPLACE, P.HHG_F64, uf, ff, None, nrm2)
+    assert abs(nrm2.item() - np.linalg.norm(ro)) <= F64_TOL * np.linalg.norm(ro)
 
 
 @pytest.mark.parametrize("name,L", CASES + [("annulus64", 7), ("square", 7)])
