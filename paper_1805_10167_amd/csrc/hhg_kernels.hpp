@@ -25,7 +25,7 @@ hipError_t launch_residual(const hhg_mesh* M, int level, int op, int dtype, cons
 // (x is used as scratch; y receives the complete result).
 hipError_t launch_gs_sweep(const hhg_mesh* M, int level, int op, int dtype, void* x, void* y,
                            const void* f, int backward, hipStream_t s);
-// Mixed-precision outer step (see k_mp_step): e == nullptr for the first
+// Mixed-precision outer step (see k_mp_step_tiled): e == nullptr for the first
 // residual; xo receives x + e otherwise.
 hipError_t launch_mp_step(const hhg_mesh* M, int level, int op, const double* x, const float* e,
                           const double* f, double* xo, float* r, double* norm, hipStream_t s);

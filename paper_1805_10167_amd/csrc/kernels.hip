@@ -422,86 +422,58 @@ __global__ __launch_bounds__(NT) void k_apply(LevelDev L, int op, const T* __res
     }
 }
 
-// Outer step of mixed-precision refinement on FP64 x, FP32 correction e and
-// FP64 f.  With UPD: v = x + e is the new iterate, written to xo with all
-// copies (Dirichlet entries keep x); without: v = x and xo is untouched.
-// The residual f - A v is formed in FP64, its squares summed per block in
-// FP64 for the norm, and it is stored rounded to FP32 in r with all copies
-// (0 on Dirichlet rows): the right-hand side of the next FP32 cycle.
+// Mixed-precision outer step at edge/vertex item t (see k_mp_step_tiled).
 template <bool UPD>
-__global__ __launch_bounds__(NT) void k_mp_step(LevelDev L, int op, const double* __restrict__ x,
-                                                const float* __restrict__ e, const double* __restrict__ f,
-                                                double* __restrict__ xo, float* __restrict__ r,
-                                                const double* __restrict__ kap, int gf, double* partials) {
-    __shared__ double sm[NT / 64 + 1];
-    double acc = 0.0;
+__device__ __forceinline__ void mp_low_item(const LevelDev& L, int op, const double* __restrict__ x,
+                                            const float* __restrict__ e, const double* __restrict__ f,
+                                            double* __restrict__ xo, float* __restrict__ r,
+                                            const double* __restrict__ kap, int64_t t, int64_t ne_,
+                                            double& acc) {
+    const int nl_ = L.n;
     auto V = [&](int64_t q) -> double { return UPD ? x[q] + (double)e[q] : x[q]; };
-    if ((int)blockIdx.x < gf) {
-        FACE_ALL_LOOP(L, gf)
-        if (!interior) continue;
-        const int64_t up = row_start(n, j + 1) - row_start(n, j);
-        const int64_t dn = row_start(n, j) - row_start(n, j - 1);
-        const W7<double> w = face_weights<double>(op, fi, L.inv4l, kap, p, up, dn);
-        const double v0 = V(p);
-        const double v = f[p] - (w.c * v0 + w.e * V(p + 1) + w.w * V(p - 1) + w.n * V(p + up) +
-                                 w.s * V(p - dn) + w.se * V(p - dn + 1) + w.nw * V(p + up - 1));
-        acc += v * v;
-        r[p] = (float)v;
-        push_face_near(L, r, fi, i, j, (float)v);
-        if (UPD) {
-            xo[p] = v0;
-            push_face_near(L, xo, fi, i, j, v0);
+    if (t < ne_) {
+        const int ed = (int)(t / (nl_ - 2)), k = (int)(t % (nl_ - 2)) + 1;
+        const EdgeInfo& ei = L.edges[ed];
+        const int64_t m = edge_main(L, ed);
+        double v = 0.0, v0 = x[m + k];
+        if (!ei.boundary) {
+            v0 = V(m + k);
+            const int64_t g0 = edge_ghost(L, ed, 0), g1 = edge_ghost(L, ed, 1);
+            const WE<double> w = edge_weights<double>(op, ei, L.inv4l, kap, m, g0, g1, k);
+            v = f[m + k] - (w.c * v0 + w.al * V(m + k - 1) + w.ah * V(m + k + 1) +
+                            w.l0 * V(g0 + k - 1) + w.h0 * V(g0 + k) + w.l1 * V(g1 + k - 1) +
+                            w.h1 * V(g1 + k));
+            acc += v * v;
         }
+        r[m + k] = (float)v;
+        push_edge(L, r, ei, k, (float)v, true);
+        if (UPD) {
+            xo[m + k] = v0;
+            push_edge(L, xo, ei, k, v0, true);
         }
     } else {
-        LOW_LOOP(L, gf) {
-            if (t < ne_) {
-                const int ed = (int)(t / (nl_ - 2)), k = (int)(t % (nl_ - 2)) + 1;
-                const EdgeInfo& ei = L.edges[ed];
-                const int64_t m = edge_main(L, ed);
-                double v = 0.0, v0 = x[m + k];
-                if (!ei.boundary) {
-                    v0 = V(m + k);
-                    const int64_t g0 = edge_ghost(L, ed, 0), g1 = edge_ghost(L, ed, 1);
-                    const WE<double> w = edge_weights<double>(op, ei, L.inv4l, kap, m, g0, g1, k);
-                    v = f[m + k] - (w.c * v0 + w.al * V(m + k - 1) + w.ah * V(m + k + 1) +
-                                    w.l0 * V(g0 + k - 1) + w.h0 * V(g0 + k) + w.l1 * V(g1 + k - 1) +
-                                    w.h1 * V(g1 + k));
-                    acc += v * v;
-                }
-                r[m + k] = (float)v;
-                push_edge(L, r, ei, k, (float)v, true);
-                if (UPD) {
-                    xo[m + k] = v0;
-                    push_edge(L, xo, ei, k, v0, true);
-                }
-            } else {
-                const int vv = (int)(t - ne_);
-                const VertexInfo& vi = L.verts[vv];
-                const int64_t vb = vert_off(L, vv);
-                double v = 0.0, v0 = x[vb];
-                if (!vi.boundary) {
-                    v0 = V(vb);
-                    double sn = 0.0, c = 0.0;
-                    for (int q = 0; q < vi.deg; ++q) {
-                        const double wq = vertex_weight<double>(op, vi, L.inv4l, kap, vb, q);
-                        sn += wq * V(vb + 1 + q);
-                        c += wq;
-                    }
-                    v = f[vb] - (-c * v0 + sn);
-                    acc += v * v;
-                }
-                r[vb] = (float)v;
-                push_vertex(L, r, vi, (float)v);
-                if (UPD) {
-                    xo[vb] = v0;
-                    push_vertex(L, xo, vi, v0);
-                }
+        const int vv = (int)(t - ne_);
+        const VertexInfo& vi = L.verts[vv];
+        const int64_t vb = vert_off(L, vv);
+        double v = 0.0, v0 = x[vb];
+        if (!vi.boundary) {
+            v0 = V(vb);
+            double sn = 0.0, c = 0.0;
+            for (int q = 0; q < vi.deg; ++q) {
+                const double wq = vertex_weight<double>(op, vi, L.inv4l, kap, vb, q);
+                sn += wq * V(vb + 1 + q);
+                c += wq;
             }
+            v = f[vb] - (-c * v0 + sn);
+            acc += v * v;
+        }
+        r[vb] = (float)v;
+        push_vertex(L, r, vi, (float)v);
+        if (UPD) {
+            xo[vb] = v0;
+            push_vertex(L, xo, vi, v0);
         }
     }
-    const double sum = block_sum<NT>(acc, sm);
-    if (threadIdx.x == 0) partials[blockIdx.x] = sum;
 }
 
 // Per-block sums of x*y over owned interior points (faces, interior edge
@@ -712,9 +684,18 @@ __device__ __forceinline__ void gs_load_u(int n, int i0, int j0, int64_t fb, con
     static_assert(CW * CH <= GsTile<TJ, H>::R * GS_W, "coarse tile must fit the u tile");
     T* cs = &us[0][0];
     const int nc = pt.nc, Ilo = (i0 < 0 ? 0 : i0) >> 1, Jlo = (j0 < 0 ? 0 : j0) >> 1;
-    for (int t = threadIdx.x; t < CW * CH; t += GS_NT) {
+    constexpr int NCS = (CW * CH + GS_NT - 1) / GS_NT;
+    T cr[NCS];                                   // loads first, LDS stores after
+#pragma unroll
+    for (int q = 0; q < NCS; ++q) {
+        const int t = threadIdx.x + q * GS_NT;
         const int J = Jlo + t / CW, I = Ilo + t % CW;
-        cs[t] = (J <= nc - 1 && I <= nc - 1 - J) ? pt.uc[pt.cb + row_start(nc, J) + I] : (T)0;
+        cr[q] = (t < CW * CH && J <= nc - 1 && I <= nc - 1 - J) ? pt.uc[pt.cb + row_start(nc, J) + I] : (T)0;
+    }
+#pragma unroll
+    for (int q = 0; q < NCS; ++q) {
+        const int t = threadIdx.x + q * GS_NT;
+        if (t < CW * CH) cs[t] = cr[q];
     }
     __syncthreads();
     // linear interpolation as in prol_face, from LDS
@@ -1206,6 +1187,109 @@ __global__ __launch_bounds__(GS_NT) void k_apply_tiled(LevelDev L, int op, const
         const double t = block_sum<GS_NT>(acc, sm);
         if (threadIdx.x == 0) partials[b] = t;
     }
+}
+
+// Outer step of mixed-precision refinement on FP64 x, FP32 correction e and
+// FP64 f.  With UPD: v = x + e is the new iterate, written to xo with all
+// copies (Dirichlet entries keep x); without: v = x and xo is untouched.
+// The residual f - A v is formed in FP64, its squares summed per block in
+// FP64 for the norm, and it is stored rounded to FP32 in r with all copies
+// (0 on Dirichlet rows): the right-hand side of the next FP32 cycle.  Face
+// points come from LDS tiles as in k_apply_tiled (the tile holds v with a
+// one-point halo, loaded in one round of independent loads); the blocks from
+// gt on take edges and vertices; every block writes partials[blockIdx.x].
+template <bool UPD, bool VARK, int TJ>
+__global__ __launch_bounds__(GS_NT) void k_mp_step_tiled(LevelDev L, int op, const double* __restrict__ x,
+                                                         const float* __restrict__ e,
+                                                         const double* __restrict__ f,
+                                                         double* __restrict__ xo, float* __restrict__ r,
+                                                         const double* __restrict__ kap, int nblk_tiles, int gt,
+                                                         double* __restrict__ partials) {
+    constexpr int TI = GsTile<TJ, GS_H>::TI, RA = TJ + 2, TL = TJ == GS_TJ16 ? 1 : 0;
+    constexpr int RPW = (RA + GS_NW - 1) / GS_NW, KR = TJ / GS_NW;
+    static_assert(TJ % GS_NW == 0, "tile rows must split evenly over the waves");
+    __shared__ double vs[RA][GS_W];
+    __shared__ double ks[VARK ? RA : 1][GS_W];
+    __shared__ double sm[GS_NW + 1];
+    const int b = blockIdx.x, n = L.n;
+    const int wv = wave_id(), lane = threadIdx.x & 63;
+    double acc = 0.0;
+    if (b >= gt) {
+        const int64_t ne = (int64_t)L.E * (n - 2);
+        for (int64_t t = (int64_t)(b - gt) * GS_NT + threadIdx.x; t < ne + L.V;
+             t += (int64_t)(gridDim.x - gt) * GS_NT)
+            mp_low_item<UPD>(L, op, x, e, f, xo, r, kap, t, ne, acc);
+    } else {
+        const int logical = (b & 7) * (gt >> 3) + (b >> 3);
+        if (logical < nblk_tiles) {
+            const int ntl = L.n_gs_tl[0][TL];
+            const int face = logical / ntl;
+            const FaceInfo& fi = L.faces[face];
+            const int2 tl = L.gs_tl[0][TL][logical % ntl];
+            const int i0 = tl.x * TI - 1, j0 = tl.y * TJ - 1;
+            const int64_t fb = face_base(L, face);
+            double vr[RPW][3], kr[VARK ? RPW : 1][3], fr[KR][3];
+#pragma unroll
+            for (int q = 0; q < RPW; ++q) {
+                const int rr = wv + GS_NW * q, j = j0 + rr;
+                const int64_t rb = fb + row_start(n, j < 0 ? 0 : (j > n ? n : j));
+#pragma unroll
+                for (int c = 0; c < 3; ++c) {
+                    const int tx = lane + 64 * c, i = i0 + tx;
+                    const bool in = rr < RA && tx < TI + 2 && j >= 0 && j < n && i >= 0 && i <= n - 1 - j;
+                    vr[q][c] = in ? (UPD ? x[rb + i] + (double)e[rb + i] : x[rb + i]) : 0.0;
+                    if (VARK) kr[q][c] = in ? kap[rb + i] : 0.0;
+                }
+            }
+#pragma unroll
+            for (int k = 0; k < KR; ++k) {
+                const int rr = 1 + wv + GS_NW * k, j = j0 + rr;
+#pragma unroll
+                for (int c = 0; c < 3; ++c) {
+                    const int tx = lane + 64 * c, i = i0 + tx;
+                    const bool pt = tx >= 1 && tx <= TI && j >= 1 && i >= 1 && i + j <= n - 2;
+                    fr[k][c] = pt ? f[fb + row_start(n, pt ? j : 0) + i] : 0.0;
+                }
+            }
+#pragma unroll
+            for (int q = 0; q < RPW; ++q) {
+                const int rr = wv + GS_NW * q;
+                if (rr >= RA) continue;
+#pragma unroll
+                for (int c = 0; c < 3; ++c) {
+                    vs[rr][lane + 64 * c] = vr[q][c];
+                    if (VARK) ks[rr][lane + 64 * c] = kr[q][c];
+                }
+            }
+            const W7<double> wf = face_weights<double>(VARK ? OP_LAPLACE : op, fi, L.inv4l, (const double*)nullptr,
+                                                       0, 0, 0);
+            __syncthreads();
+#pragma unroll
+            for (int k = 0; k < KR; ++k) {
+                const int rr = 1 + wv + GS_NW * k, j = j0 + rr;
+#pragma unroll
+                for (int c = 0; c < 3; ++c) {
+                    const int tx = lane + 64 * c, i = i0 + tx;
+                    if (!(tx >= 1 && tx <= TI && j >= 1 && i >= 1 && i + j <= n - 2)) continue;
+                    const W7<double> w = VARK ? gs_weights_lds<double>(fi, ks, rr, tx) : wf;
+                    const double v0 = vs[rr][tx];
+                    const double v = fr[k][c] - (w.c * v0 + w.e * vs[rr][tx + 1] + w.w * vs[rr][tx - 1] +
+                                                 w.n * vs[rr + 1][tx] + w.s * vs[rr - 1][tx] +
+                                                 w.se * vs[rr - 1][tx + 1] + w.nw * vs[rr + 1][tx - 1]);
+                    acc += v * v;
+                    const int64_t p = fb + row_start(n, j) + i;
+                    r[p] = (float)v;
+                    push_face_near(L, r, fi, i, j, (float)v);
+                    if (UPD) {
+                        xo[p] = v0;
+                        push_face_near(L, xo, fi, i, j, v0);
+                    }
+                }
+            }
+        }
+    }
+    const double t = block_sum<GS_NT>(acc, sm);
+    if (threadIdx.x == 0) partials[b] = t;
 }
 
 // Squared residuals, one partial sum per block, of the points a backward
@@ -1898,12 +1982,23 @@ static hipError_t residual_t(const hhg_mesh* M, int level, int op, const T* u, c
 hipError_t launch_mp_step(const hhg_mesh* M, int level, int op, const double* x, const float* e,
                           const double* f, double* xo, float* r, double* norm, hipStream_t s) {
     const LevelDev L = M->dev(level);
-    const int gf = face_grid(L), gl = grid_for(low_items(L), MAX_LOW_BLOCKS);
-    if (e)
-        k_mp_step<true><<<gf + gl, NT, 0, s>>>(L, op, x, e, f, xo, r, M->kap64[level], gf, M->partials);
-    else
-        k_mp_step<false><<<gf + gl, NT, 0, s>>>(L, op, x, e, f, xo, r, M->kap64[level], gf, M->partials);
-    k_reduce_final<<<1, 1024, 0, s>>>(M->partials, gf + gl, norm, 1);
+    const bool vk = op == OP_DIFFUSION;
+    const TiledGrid g = tiled_grid(L.F, L.n_gs_tl[0][vk ? 1 : 0], low_items(L));
+    const int grid = g.gt + g.gl;
+    const double* kap = M->kap64[level];
+#define HHG_MP_LAUNCH(UP)                                                                              \
+    do {                                                                                               \
+        if (vk)                                                                                        \
+            k_mp_step_tiled<UP, true, GS_TJ16><<<grid, GS_NT, 0, s>>>(L, op, x, e, f, xo, r, kap, g.tiles, \
+                                                                     g.gt, M->partials);               \
+        else                                                                                           \
+            k_mp_step_tiled<UP, false, GS_TJ><<<grid, GS_NT, 0, s>>>(L, op, x, e, f, xo, r, kap, g.tiles, \
+                                                                     g.gt, M->partials);               \
+    } while (0)
+    if (e) HHG_MP_LAUNCH(true);
+    else HHG_MP_LAUNCH(false);
+#undef HHG_MP_LAUNCH
+    k_reduce_final<<<1, 1024, 0, s>>>(M->partials, grid, norm, 1);
     return hipGetLastError();
 }
 
