@@ -329,7 +329,7 @@ __device__ __forceinline__ T vertex_apply(int op, const LevelDev& L, const Verte
 }
 
 // Point operator at edge/vertex item t (edge points first, ne of them, then
-// vertices), with all copies of the result; see k_apply for the modes.
+// vertices), with all copies of the result; see k_apply_low for the modes.
 template <class T, int MODE>
 __device__ __forceinline__ void apply_low_item(const LevelDev& L, int op, const T* __restrict__ x,
                                                const T* __restrict__ f, T* __restrict__ y,
@@ -383,39 +383,18 @@ __device__ __forceinline__ void apply_low_item(const LevelDev& L, int op, const 
     }
 }
 
-// Point operator of every interior row, with all copies of the result:
+// Point operator of the edge and vertex points, with all copies of the
+// result (the face points are k_apply_tiled's):
 //   MODE 0: y = A x              MODE 1: y = f - A x (+ per-block sums of y^2)
 //   MODE 2: y = (f - A x) / a_pp MODE 3: y = x / a_pp
 // and 0 on Dirichlet rows; MODE 4 only sums (f - A x)^2 and writes nothing.
 template <class T, int MODE>
-__global__ __launch_bounds__(NT) void k_apply(LevelDev L, int op, const T* __restrict__ x,
-                                              const T* __restrict__ f, T* __restrict__ y,
-                                              const T* __restrict__ kap, int gf, double* partials) {
+__global__ __launch_bounds__(NT) void k_apply_low(LevelDev L, int op, const T* __restrict__ x,
+                                                  const T* __restrict__ f, T* __restrict__ y,
+                                                  const T* __restrict__ kap, double* partials) {
     __shared__ double sm[NT / 64 + 1];
     double acc = 0.0;
-    if ((int)blockIdx.x < gf) {
-        FACE_ALL_LOOP(L, gf)
-        if (!interior) continue;
-        const int64_t up = row_start(n, j + 1) - row_start(n, j);
-        const int64_t dn = row_start(n, j) - row_start(n, j - 1);
-        const W7<T> w = face_weights<T>(op, fi, L.inv4l, kap, p, up, dn);
-        T v;
-        if (MODE == 3) {
-            v = x[p] / w.c;
-        } else {
-            v = w.c * x[p] + w.e * x[p + 1] + w.w * x[p - 1] + w.n * x[p + up] + w.s * x[p - dn] +
-                w.se * x[p - dn + 1] + w.nw * x[p + up - 1];
-            if (MODE >= 1) v = f[p] - v;
-            if (MODE == 1 || MODE == 4) acc += (double)v * (double)v;
-            if (MODE == 2) v = v / w.c;
-        }
-        if (MODE == 4) continue;
-        y[p] = v;
-        push_face_near(L, y, fi, i, j, v);
-        }
-    } else {
-        LOW_LOOP(L, gf) { apply_low_item<T, MODE>(L, op, x, f, y, kap, t, ne_, acc); }
-    }
+    LOW_LOOP(L, 0) { apply_low_item<T, MODE>(L, op, x, f, y, kap, t, ne_, acc); }
     if ((MODE == 1 || MODE == 4) && partials) {
         const double s = block_sum<NT>(acc, sm);
         if (threadIdx.x == 0) partials[blockIdx.x] = s;
@@ -1083,11 +1062,11 @@ __global__ __launch_bounds__(GS_NT) void k_face_gs_fused(LevelDev L, const T* __
     }
 }
 
-// The point operator of k_apply with the face points taken from LDS tiles:
+// The point operator of k_apply_low extended to the face points, taken from LDS tiles:
 // the smoother's TI x TJ tiles, each loaded with a one-point halo in one
 // round of independent row loads (f of the block's points into registers
 // alongside), then every interior point formed from LDS.  The blocks from gt
-// on take the edge and vertex points.  Modes and outputs as k_apply; for the
+// on take the edge and vertex points.  Modes and outputs as k_apply_low; for the
 // norm modes every block writes partials[blockIdx.x] (0 without work).
 template <class T, bool VARK, int MODE, int TJ>
 __global__ __launch_bounds__(GS_NT) void k_apply_tiled(LevelDev L, int op, const T* __restrict__ x,
@@ -1938,7 +1917,7 @@ static inline TiledGrid tiled_grid(int64_t F, int64_t ntl, int64_t low) {
     return g;
 }
 
-// Point operator (k_apply's modes) over a whole level; returns the number of
+// Point operator (k_apply_low's modes) over a whole level; returns the number of
 // partial sums written (norm modes with partials).
 template <class T, int MODE>
 static int apply_tiled(const hhg_mesh* M, int level, int op, const T* x, const T* f, T* y,
@@ -2089,8 +2068,7 @@ static hipError_t gs_t(const hhg_mesh* M, int level, int op, T* x, T* y, const T
         k_low_gs<T><<<gl, NT, 0, s>>>(L, op, x, f, kap, 1);
         if ((e = faces()) != hipSuccess || res != 1) return e;
         // residual of the edge and vertex points (all copies) from the swept y
-        k_apply<T, 1><<<grid_for(low_items(L), MAX_LOW_BLOCKS), NT, 0, s>>>(L, op, y, f, rout, kap, 0,
-                                                                            nullptr);
+        k_apply_low<T, 1><<<grid_for(low_items(L), MAX_LOW_BLOCKS), NT, 0, s>>>(L, op, y, f, rout, kap, nullptr);
         return hipGetLastError();
     }
     if ((e = faces()) != hipSuccess) return e;
@@ -2295,8 +2273,8 @@ static hipError_t jacobi_t(const hhg_mesh* M, int level, int op, const T* u, con
 hipError_t launch_jacobi_low(const hhg_mesh* M, int level, int op, const float* u, const float* f,
                              float* rho, hipStream_t s) {
     const LevelDev L = M->dev(level);
-    k_apply<float, 2><<<grid_for(low_items(L), MAX_LOW_BLOCKS), NT, 0, s>>>(L, op, u, f, rho, M->kap32[level], 0,
-                                                                             nullptr);
+    k_apply_low<float, 2><<<grid_for(low_items(L), MAX_LOW_BLOCKS), NT, 0, s>>>(L, op, u, f, rho, M->kap32[level],
+                                                                                nullptr);
     return hipGetLastError();
 }
 
