@@ -244,7 +244,7 @@ def learned_section(args, P, hi, torch):
     t2t, its = {}, {}
     for name, mode in (("plain_fp64", P.HHG_MODE_PLAIN_FP64), ("mp_gs", P.HHG_MODE_MP_IR)):
         ms = []
-        for _ in range(args.mp_runs):
+        for _ in range(max(1, args.mp_runs)):
             t, rc, st, _ = timed_solve(P, g, u, f, mode, D, 1e-8, 3)
             assert rc == 0, st
             ms.append(t)
@@ -252,7 +252,7 @@ def learned_section(args, P, hi, torch):
     P.hhg_net_set_weights(g.h, w_net)
     P.hhg_net_set_options(g.h, P.HHG_BF16, 1)        # the network regardless of the decision
     ms = []
-    for _ in range(args.mp_runs):
+    for _ in range(max(1, args.mp_runs)):
         t, rc, st, _ = timed_solve(P, g, u, f, P.HHG_MODE_LEARNED, D, 1e-8, 3)
         ms.append(t)
     t2t["mp_net"], its["mp_net"] = round(statistics.median(ms), 3), st["iters"]
