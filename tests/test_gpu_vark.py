@@ -101,3 +101,50 @@ def test_diffusion_solves_plain_and_mixed():
     err = rel_err(to_np(g.to_canonical(L, uf)), uref)
     log("vark mp iters %d error vs oracle %.2e" % (st["iters"], err))
     assert err <= 1e-6
+
+
+@pytest.mark.parametrize("name,L", [("annulus64", 6), ("square", 5)])
+def test_diffusion_fp32_kernels(name, L):
+    """FP32 variable-coefficient kernels (LDS coefficient tiles) against the
+    FP64 oracle on FP32-representable inputs: apply, residual with and
+    without the field, Jacobi scaling with and without f, forward and
+    backward sweeps, and a V-cycle."""
+    import torch
+
+    import paper_1805_10167_amd as P
+    from oracle import net as onet
+    log("vark fp32 %s L=%d" % (name, L))
+    g, H = mesh_k(name, L)
+    lv = H.levels[L]
+    F32, D = P.HHG_F32, P.HHG_OP_DIFFUSION
+
+    def r32(v):
+        return v.astype(np.float32).astype(np.float64)
+
+    def back(x):
+        return to_np(g.to_canonical(L, x, F32))
+
+    u, f = r32(hi.uniform_vector(lv.n_all, 31)), r32(hi.uniform_vector(lv.n_all, 32))
+    uf, ff, y = g.from_canonical(L, u, F32), g.from_canonical(L, f, F32), g.field(L, F32)
+    P.hhg_apply(g.h, L, D, F32, uf, y)
+    assert rel_err(back(y), H.apply(L, u)) <= 2e-5
+    ro = H.residual(L, u, f)
+    nrm = torch.zeros(2, dtype=torch.float64, device="cuda")
+    P.hhg_residual(g.h, L, D, F32, uf, ff, y, nrm[0:1])
+    assert rel_err(back(y), ro) <= 2e-5
+    P.hhg_residual(g.h, L, D, F32, uf, ff, None, nrm[1:2])
+    ref = np.linalg.norm(ro)
+    assert abs(nrm[0].item() - ref) <= 2e-5 * ref and nrm[0].item() == nrm[1].item()
+    P.hhg_jacobi(g.h, L, D, F32, uf, ff, y)
+    assert rel_err(back(y), onet.jacobi_scale(H, L, ro)) <= 2e-5
+    P.hhg_jacobi(g.h, L, D, F32, uf, None, y)
+    assert rel_err(back(y), onet.jacobi_scale(H, L, u.copy())) <= 2e-5
+    for backward in (0, 1):
+        x = g.from_canonical(L, u, F32)
+        P.hhg_smooth(g.h, L, D, P.HHG_SMOOTH_GS, F32, x, ff, 2, backward)
+        assert rel_err(back(x), H.smooth(L, u.copy(), f, 2, bool(backward))) <= 2e-5
+    x = g.from_canonical(L, u, F32)
+    P.hhg_vcycle(g.h, L, D, P.HHG_SMOOTH_GS, F32, x, ff, 3, 3)
+    err = rel_err(back(x), H.vcycle(L, u.copy(), f, 3, 3))
+    log("fp32 vark V-cycle rel err %.2e" % err)
+    assert err <= 1e-4
