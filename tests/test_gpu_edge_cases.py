@@ -25,7 +25,16 @@ def meshes(vxy, tri, L, lc):
     return g, Hierarchy(MacroMesh(vxy, tri), L, lc)
 
 
-@pytest.mark.parametrize("case", ["one_face_L4", "square_lc1_L3", "annulus_lc_eq_L", "square_L1"])
+def fan16():
+    """16 triangles around the origin: a degree-16 interior macro-vertex (the
+    most the layout holds) where 16 interior macro-edges meet."""
+    t = 2 * np.pi * np.arange(16) / 16
+    vxy = np.vstack([[0.0, 0.0], np.c_[np.cos(t), np.sin(t)]])
+    tri = np.array([[0, 1 + k, 1 + (k + 1) % 16] for k in range(16)], dtype=np.int32)
+    return vxy, tri
+
+
+@pytest.mark.parametrize("case", ["one_face_L4", "square_lc1_L3", "annulus_lc_eq_L", "square_L1", "fan16_L5"])
 def test_vcycle_and_apply_degenerate_hierarchies(case):
     import paper_1805_10167_amd as P
     if case == "one_face_L4":
@@ -34,6 +43,8 @@ def test_vcycle_and_apply_degenerate_hierarchies(case):
         (vxy, tri), L, lc = hi.unit_square(), 3, 1
     elif case == "annulus_lc_eq_L":
         (vxy, tri), L, lc = hi.annulus(16), 3, 3
+    elif case == "fan16_L5":
+        (vxy, tri), L, lc = fan16(), 5, 2
     else:
         (vxy, tri), L, lc = hi.unit_square(), 1, 1
     log("degenerate hierarchy %s" % case)

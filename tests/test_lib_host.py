@@ -80,3 +80,22 @@ def test_unbound_mesh_rejects_compute_calls():
             P.hhg_workspace_bytes(h, 1 << 7)
     finally:
         P.hhg_destroy_mesh(h)
+
+
+def _fan(m):
+    """m triangles around the origin (all sharing vertex 0), counter-clockwise."""
+    import math
+    vxy = [[0.0, 0.0]] + [[math.cos(2 * math.pi * k / m), math.sin(2 * math.pi * k / m)] for k in range(m)]
+    tri = [[0, 1 + k, 1 + (k + 1) % m] for k in range(m)]
+    return vxy, tri
+
+
+def test_vertex_degree_limit():
+    """A macro-vertex may have up to 16 macro-edges: a 16-triangle fan sets
+    up, a 17-triangle fan is rejected with a clear message."""
+    h = P.hhg_setup_mesh(*_fan(16), 3, 2)
+    P.hhg_destroy_mesh(h)
+    with pytest.raises(P.HHGError) as e:
+        P.hhg_setup_mesh(*_fan(17), 3, 2)
+    assert e.value.code == P.HHG_EINVAL
+    assert "more than 16" in P.hhg_last_error()
