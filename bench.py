@@ -170,7 +170,17 @@ def learned_section(args, P, hi, torch):
     feats = P.HHG_FEAT_F64 | P.HHG_FEAT_MP | P.HHG_FEAT_VARK | P.HHG_FEAT_NET
     vxy, tri = hi.mesh_by_name("annulus64")
 
-    # training at the coarser level on noise pairs
+    # the benchmark-level mesh, for validation during training and evaluation
+    L = args.level
+    g = P.Mesh(vxy, tri, L, args.coarse_level, feats)
+    _, n_all = g.n_dofs(L)
+    xy = g.coords(L)
+    vseeds = list(range(20000, 20000 + args.val_fields))
+    vk = [torch.exp(hi.grf_eval_device(xy, s)) for s in vseeds]
+    vf = [hi.uniform_rhs(n_all, 1000 + s) for s in vseeds]
+
+    # training at the coarser level on noise pairs, the weights chosen by the
+    # convergence factor on the validation fields
     Lt = args.train_level
     t0 = time.perf_counter()
     gt = P.Mesh(vxy, tri, Lt, 2, feats)
@@ -188,17 +198,23 @@ def learned_section(args, P, hi, torch):
     loss0 = tr.mean_loss(sub)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
-    losses = tr.train(args.train_steps)
+    w_net, best_step, vhist, losses = train.train_early_stopping(
+        tr, args.train_steps, args.val_every, g, vk, vf)
     torch.cuda.synchronize()
     t_train = time.perf_counter() - t1
+    loss_last = tr.mean_loss(sub)
+    P.hhg_net_set_weights(gt.h, w_net)
     loss1 = tr.mean_loss(sub)
-    w_net = tr.weights()
-    log("trained %d steps in %.1f s: loss %.4f -> %.4f" % (args.train_steps, t_train, loss0, loss1))
+    log("trained %d steps in %.1f s (with validation), kept step %d: loss %.4f -> %.4f"
+        % (args.train_steps, t_train, best_step, loss0, loss1))
     out["train"] = {"level": Lt, "fields": args.train_fields, "pairs": len(pairs),
                     "pair_kind": "noise", "steps": args.train_steps, "batch": 4, "lr": args.lr,
                     "precision": "bf16 forward (MFMA), fp32 master weights",
-                    "loss_jacobi_init": round(loss0, 5), "loss_trained": round(loss1, 5),
-                    "loss_last100": round(float(np.mean(losses[-100:])), 5),
+                    "validation": {"fields": len(vseeds), "seeds": [vseeds[0], vseeds[-1]],
+                                   "every": args.val_every, "kept_step": best_step,
+                                   "factor": [[s, round(r, 5)] for s, r in vhist]},
+                    "loss_jacobi_init": round(loss0, 5), "loss_kept": round(loss1, 5),
+                    "loss_last_step": round(loss_last, 5),
                     "data_s": round(t_data, 2), "train_s": round(t_train, 2),
                     "ms_per_step": round(t_train * 1e3 / args.train_steps, 3)}
     if args.cycle_pair_check:
@@ -214,10 +230,6 @@ def learned_section(args, P, hi, torch):
     torch.cuda.empty_cache()
 
     # evaluation at the benchmark level
-    L = args.level
-    g = P.Mesh(vxy, tri, L, args.coarse_level, feats)
-    _, n_all = g.n_dofs(L)
-    xy = g.coords(L)
     seeds = list(range(10000, 10000 + args.eval_fields))
     ek = [torch.exp(hi.grf_eval_device(xy, s)) for s in seeds]
     ef = [hi.uniform_rhs(n_all, 1000 + s) for s in seeds]
@@ -353,7 +365,9 @@ def main():
     ap.add_argument("--train-level", type=int, default=7)
     ap.add_argument("--train-fields", type=int, default=256)
     ap.add_argument("--pairs-per-field", type=int, default=8)
-    ap.add_argument("--train-steps", type=int, default=2000)
+    ap.add_argument("--train-steps", type=int, default=1000)
+    ap.add_argument("--val-every", type=int, default=100)
+    ap.add_argument("--val-fields", type=int, default=2)
     ap.add_argument("--lr", type=float, default=3e-3)
     ap.add_argument("--eval-fields", type=int, default=8)
     ap.add_argument("--cycle-pair-check", type=int, default=1)

@@ -88,7 +88,7 @@ __device__ __forceinline__ void net_hidden(int n, int i0, int j0, const float* _
         const short4v w2op = to_bf16x4(a2[0], a2[1], a2[2], a2[3]);
         for (int row = wv; row < NZR; row += NWV) {
             const int j = j0 - 1 + row;
-#pragma unroll 2
+#pragma unroll
             for (int q = 0; q < 4; ++q) {
                 const int cc = 16 * q + l16;
                 const float* base = &rs[row][cc];

@@ -25,6 +25,13 @@ the energy-norm error left by one application of the network, relative to the
 error it was given; e^T A e = e^T r is taken once at capture.  A batch
 averages the losses of its pairs.
 
+Model selection.  The loss measures one application of the network, the
+acceptance a whole cycle; past a few hundred steps the first keeps falling
+while the second gets worse.  train_early_stopping therefore measures the
+convergence factor (below) on validation fields, whose seeds are disjoint
+from the training and the acceptance fields, at regular intervals, and keeps
+the weights with the smallest one.
+
 Acceptance.  The convergence factor of V(nu1, nu2) cycles inside the
 mixed-precision loop, (|r_last| / |r_first|)^(1 / (last - first)), with the
 network and with Gauss-Seidel on held-out coefficient fields; the network is
@@ -262,6 +269,34 @@ def evaluate(mesh, kappas, rhss, weights=None, precision=HHG_BF16, nu1=3, nu2=3)
         if weights is not None:
             hhg_net_set_options(mesh.h, precision, 0)
     return np.array(rho), np.array(fallback)
+
+
+def train_early_stopping(trainer, steps, every, mesh, kappas, rhss, precision=HHG_BF16, log=None):
+    """Model selection by the quantity the network is judged on (the
+    convergence factor of Q22): `steps` Adam steps in chunks of `every`;
+    after each chunk the mean convergence factor of the learned cycle on the
+    validation fields (kappas, rhss: seeds disjoint from the training and the
+    acceptance fields) is measured on `mesh`, which must not be the training
+    mesh, and the weights with the smallest factor are kept.  The one-step
+    energy loss goes on falling after this factor has turned, so training to
+    the loss plateau gives a worse smoother.  Returns (weights, step,
+    [(step, factor), ...], per-step losses); without a finite factor the
+    initial weights and step 0 come back."""
+    if mesh.h == trainer.h:
+        raise ValueError("validation needs a mesh of its own")
+    best_rho, best_step, best_w = float("inf"), 0, trainer.weights()
+    history, losses = [], []
+    for _ in range(max(1, steps // every)):
+        losses.append(trainer.train(every))
+        w = trainer.weights()
+        rho, fb = evaluate(mesh, kappas, rhss, w, precision)
+        r = float(rho.mean()) if np.all(np.isfinite(rho)) and not fb.any() else float("inf")
+        history.append((trainer.step, r))
+        if log:
+            log("step %d: validation factor %.5f" % (trainer.step, r))
+        if r < best_rho:
+            best_rho, best_step, best_w = r, trainer.step, w
+    return best_w, best_step, history, np.concatenate(losses)
 
 
 def accept(mesh, kappas, rhss, weights, precision=HHG_BF16, nu1=3, nu2=3):

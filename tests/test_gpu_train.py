@@ -194,3 +194,29 @@ def test_cycle_pair_training_is_rejected():
     dec = train.accept(g, hk, hr, tr.weights())
     log("cycle-pair network: guard tripped %d, accepted %s" % (dec["guard_tripped"], dec["accepted"]))
     assert dec["guard_tripped"] == 2 and not dec["accepted"]
+
+
+def test_early_stopping_keeps_the_best_factor():
+    """train_early_stopping keeps the weights of the chunk with the smallest
+    validation factor, which they reproduce exactly, and refuses to validate
+    on the training mesh."""
+    from paper_1805_10167_amd import train
+    L = 5
+    g, gv = make_mesh(L), make_mesh(L)
+    _, n_all = g.n_dofs(L)
+    kaps = [kappa_dev(g, L, s) for s in range(8)]
+    ps = train.noise_pairs(g, kaps, lambda s, j: hi.uniform_vector(n_all, 5000 + 100 * s + j), per_field=4)
+    import paper_1805_10167_amd as P
+    P.hhg_net_set_weights(g.h, train.jacobi_init())
+    tr = train.Trainer(ps, lr=3e-3, batch=4, seed=0)
+    vseeds = (20000, 20001)
+    vk = [kappa_dev(gv, L, s) for s in vseeds]
+    vf = [hi.uniform_rhs(n_all, 1000 + s) for s in vseeds]
+    w, step, hist, losses = train.train_early_stopping(tr, 400, 100, gv, vk, vf, log=log)
+    assert len(hist) == 4 and len(losses) == 400 and np.all(np.isfinite(losses))
+    best = min(r for _, r in hist)
+    assert np.isfinite(best) and step == next(s for s, r in hist if r == best)
+    rho, fb = train.evaluate(gv, vk, vf, w)
+    assert not fb.any() and float(rho.mean()) == best
+    with pytest.raises(ValueError):
+        train.train_early_stopping(tr, 100, 100, g, vk, vf)
