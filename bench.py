@@ -20,7 +20,8 @@ Reported beside it (untimed by the step contract, each from its own runs):
   * the mixed-precision refinement solve of the same problem;
   * the variable-coefficient problem on the same mesh at level 10, k = exp(g)
     with g a Gaussian random field: the learned face smoother trained on the
-    GPU at level 7 on 256 coefficient fields, its acceptance against
+    GPU at level 7 on 256 coefficient fields (weights kept by the convergence
+    factor on 2 validation fields), its acceptance against
     Gauss-Seidel on 8 held-out fields, convergence factors, time to 1e-8 of
     plain FP64, mixed precision with Gauss-Seidel and with the network, and
     the live-timed kernels of that path;
@@ -63,15 +64,17 @@ def cpu_baseline(level, rtol, nu):
     H = Hierarchy(MacroMesh(vxy, tri), level, 2)
     lv = H.levels[level]
     f = hi.uniform_rhs(lv.n_all, 1)
+    reps, iters = 2, 0
     t0 = time.perf_counter()
-    u, hist = H.solve(np.zeros(lv.n_all), f, rtol, nu, nu)
+    for _ in range(reps):
+        u, hist = H.solve(np.zeros(lv.n_all), f, rtol, nu, nu)
+        iters += len(hist) - 1
     dt = time.perf_counter() - t0
-    iters = len(hist) - 1
     work = lv.interior_count() * 2 * nu * iters
     return {"value": work / dt / 1e9, "unit": "GDoF/s", "cores": 1, "kind": "oracle",
-            "sample": "oracle plain solve to %g on the same 64-face annulus at level %d "
-                      "(%d interior unknowns, %d V(%d,%d) cycles, %.1f s; scipy sparse "
-                      "kernels, single-threaded)" % (rtol, level, lv.interior_count(), iters,
+            "sample": "%d oracle plain solves to %g on the same 64-face annulus at level %d "
+                      "(%d interior unknowns, %d V(%d,%d) cycles in all, %.1f s; scipy sparse "
+                      "kernels, single-threaded)" % (reps, rtol, level, lv.interior_count(), iters,
                                                      nu, nu, dt)}
 
 
