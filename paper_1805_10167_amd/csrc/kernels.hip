@@ -1662,7 +1662,7 @@ __device__ __forceinline__ void block_sum2(double& a, double& b, double* sm) {
     a = wave_sum(a);
     b = wave_sum(b);
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-    const int nw = (blockDim.x + 63) >> 6;
+    const unsigned nw = (blockDim.x + 63) >> 6;
     __syncthreads();
     if (lane == 0) { sm[w] = a; sm[NTH / 64 + w] = b; }
     __syncthreads();
