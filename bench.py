@@ -316,6 +316,46 @@ def learned_section(args, P, hi, torch):
     return out
 
 
+def square_section(P, hi, torch, levels=(3, 4, 5, 6, 7, 8), timed_level=6, reps=5):
+    """The manufactured case on the unit square: -Laplace u = f with
+    f = 2 pi^2 sin(pi x) sin(pi y) and u = 0 on the boundary, so that
+    u = sin(pi x) sin(pi y).  The right-hand side is b = M f_I (the library's
+    mass operator on the nodal interpolant), the solve plain FP64 V(2,2) to
+    1e-10 on coarse level 2.  Reports the solve time at one level and the
+    discretisation error against u at the nodes on several levels (it should
+    fall by 4 per level)."""
+    vxy, tri = hi.unit_square()
+    out = {"workload": "unit square, 2 macro-faces, manufactured sin(pi x) sin(pi y), "
+                       "V(2,2) to 1e-10, coarse level 2", "levels": {}}
+    prev = None
+    for L in levels:
+        g = P.Mesh(vxy, tri, L, 2, P.HHG_FEAT_F64)
+        n_int, _ = g.n_dofs(L)
+        xy = torch.tensor(g.coords(L), dtype=torch.float64, device="cuda")
+        s2 = torch.sin(math.pi * xy[:, 0]) * torch.sin(math.pi * xy[:, 1])
+        fI = g.from_canonical(L, 2.0 * math.pi ** 2 * s2)
+        b = g.field(L)
+        P.hhg_apply(g.h, L, P.HHG_OP_MASS, P.HHG_F64, fI, b)
+        u = g.field(L)
+        ms = []
+        for _ in range(reps if L == timed_level else 1):
+            t, rc, st, _ = timed_solve(P, g, u, b, P.HHG_MODE_PLAIN_FP64, P.HHG_OP_LAPLACE, 1e-10, 2)
+            assert rc == 0, st
+            ms.append(t)
+        err = (g.to_canonical(L, u) - s2).abs().max().item()
+        h = 1.0 / 2 ** L
+        rec = {"interior_dofs": n_int, "iterations": st["iters"], "max_error": err,
+               "rms_error": ((g.to_canonical(L, u) - s2) ** 2).sum().item() ** 0.5 * h}
+        if prev is not None:
+            rec["max_error_ratio"] = round(prev / err, 3)
+        if L == timed_level:
+            rec["time_to_tol_ms"] = round(statistics.median(ms), 3)
+        out["levels"][str(L)] = rec
+        prev = err
+        del g, u, b, fI, xy, s2
+    return out
+
+
 def large_mp_section(args, P, hi, torch):
     """Plain FP64 against mixed precision on the 128-face annulus."""
     L = args.large_level
@@ -376,6 +416,7 @@ def main():
     ap.add_argument("--cycle-pair-check", type=int, default=1)
     ap.add_argument("--no-large", action="store_true")
     ap.add_argument("--no-kernels", action="store_true")
+    ap.add_argument("--no-square", action="store_true")
     ap.add_argument("--large-level", type=int, default=11)
     ap.add_argument("--copy-calibration", type=int, default=0,
                     help="bytes of a plain device copy run after the benchmark (counter scale)")
@@ -490,6 +531,9 @@ def main():
     if not args.no_large:
         log("plain vs mixed precision on the 128-face annulus")
         out["mp_large"] = large_mp_section(args, P, hi, torch)
+    if not args.no_square:
+        log("manufactured solution on the unit square")
+        out["square"] = square_section(P, hi, torch)
     if not args.no_cpu_baseline:
         log("timing the CPU oracle at level %d" % args.cpu_level)
         out["cpu_baseline"] = cpu_baseline(args.cpu_level, rtol, nu)
