@@ -389,7 +389,12 @@ def large_mp_section(args, P, hi, torch):
     P.hhg_dot(g.h, L, P.HHG_F64, ref, ref, d[1:2])
     dd = d.cpu().numpy()
     out["mp_rel_err_vs_fp64_1e-12"] = float(math.sqrt(dd[0] / dd[1]))
-    del g, u, ref, f
+    del u, ref, f
+    torch.cuda.empty_cache()
+    if not args.no_kernels:
+        log("per-call kernel rates at level %d" % L)
+        out["kernels"] = kernel_section(P, hi, torch, g, L, reps=5)
+    del g
     torch.cuda.empty_cache()
     return out
 
