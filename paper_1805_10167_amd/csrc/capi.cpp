@@ -48,7 +48,7 @@ void carve(hhg_mesh* M, uint32_t feat, Carver& c) {
         LevelHost& H = m.lv[l];
         H.d_row_off = (int32_t*)c.take(sizeof(int32_t) * H.row_off.size());
         H.d_tiles = (int2*)c.take(sizeof(int2) * (H.tiles.size() + 1));
-        for (int e = 0; e < 2; ++e)
+        for (int e = 0; e < GS_NHALO; ++e)
             for (int t = 0; t < 2; ++t)
                 H.d_gs_tl[e][t] = (int2*)c.take(sizeof(int2) * (H.gs_tl[e][t].size() + 1));
         H.d_net_tiles = (int2*)c.take(sizeof(int2) * (H.net_tiles.size() + 1));
@@ -242,7 +242,7 @@ int vcycle_rec(const hhg_mesh* M, int level, int op, int smoother, int dt, void*
     }
     void* alt = level_alt(M, level, dt);
     void* cur = nullptr;
-    // with Gauss-Seidel the last pre-smoothing sweep also forms the residual
+    // with Gauss-Seidel the last pre-smoothing sweep also forms and restricts the residual
     const bool sweep_res = smoother == HHG_SMOOTH_GS && nu1 > 0;
     int rc = smooth_pp(M, level, op, smoother, dt, u, alt, f, sweep_res ? nu1 - 1 : nu1, 0, s, &cur);
     if (rc) return rc;
@@ -251,12 +251,13 @@ int vcycle_rec(const hhg_mesh* M, int level, int op, int smoother, int dt, void*
     void* uc = level_u(M, level - 1, dt);
     void* fc = level_f(M, level - 1, dt);
     if (sweep_res) {
-        HIP_CHECK(launch_gs_sweep_residual(M, level, op, dt, cur, other, f, r, s), "smooth + residual");
+        HIP_CHECK(launch_gs_sweep_restrict(M, level, op, dt, cur, other, f, r, fc, uc, s),
+                  "smooth + residual + restrict");
         std::swap(cur, other);
     } else {
         HIP_CHECK(launch_residual(M, level, op, dt, cur, f, r, nullptr, s), "residual");
+        HIP_CHECK(launch_restrict(M, level, dt, r, fc, uc, s), "restrict");
     }
-    HIP_CHECK(launch_restrict(M, level, dt, r, fc, uc, s), "restrict");
     rc = vcycle_rec(M, level - 1, op, smoother, dt, uc, fc, nu1, nu2, s);
     if (rc) return rc;
     void* fin = nullptr;
@@ -300,7 +301,7 @@ hhg::LevelDev hhg_mesh::dev(int level) const {
     L.ghost_stride = H.ghost_stride;
     L.vert_stride = (int32_t)H.vert_stride;
     L.ntiles = (int32_t)H.tiles.size();
-    for (int e = 0; e < 2; ++e)
+    for (int e = 0; e < GS_NHALO; ++e)
         for (int t = 0; t < 2; ++t) {
             L.n_gs_tl[e][t] = (int32_t)H.gs_tl[e][t].size();
             L.gs_tl[e][t] = H.d_gs_tl[e][t];
@@ -402,7 +403,7 @@ int hhg_bind_workspace(hhg_mesh* M, uint32_t features, void* dptr, size_t bytes,
         LevelHost& H = m.lv[l];
         HIP_CHECK(upload(H.d_row_off, H.row_off, s), "upload");
         HIP_CHECK(upload(H.d_tiles, H.tiles, s), "upload");
-        for (int e = 0; e < 2; ++e)
+        for (int e = 0; e < GS_NHALO; ++e)
             for (int t = 0; t < 2; ++t) HIP_CHECK(upload(H.d_gs_tl[e][t], H.gs_tl[e][t], s), "upload");
         HIP_CHECK(upload(H.d_net_tiles, H.net_tiles, s), "upload");
         HIP_CHECK(upload(H.d_gdst, H.gdst, s), "upload");

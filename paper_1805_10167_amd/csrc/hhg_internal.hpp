@@ -20,12 +20,17 @@ constexpr int TILE_J = 4;
 // fused smoother tile: TI x TJ updated points plus a halo of H on every
 // side, so that an LDS row holds TI + 2 H = GS_W values (three per lane of a
 // wave); H = GS_H for the sweep, GS_HE for the sweep that also forms the
-// residual
+// residual, GS_HR for the sweep that also restricts it (residuals one point
+// beyond the tile on its low-i and low-j sides)
 constexpr int GS_W = 192;
 constexpr int GS_H = 3;
 constexpr int GS_HE = 4;
+constexpr int GS_HR = 5;
+constexpr int GS_NHALO = 3;   // tile lists kept per level: halo GS_H, GS_HE, GS_HR
 constexpr int GS_TJ = 24;
 constexpr int GS_TJ16 = 16;   // tile height of the variable-coefficient FP64 smoother
+constexpr int GS_TJR = 22;    // tile height of the restricting sweep (GS_HR), so that its
+                              // tile has as many LDS rows as the residual sweep's
 constexpr int gs_tile_width(int halo) { return GS_W - 2 * halo; }
 // learned-smoother tile: NET_TI x NET_TJ output points
 constexpr int NET_TI = 58;
@@ -104,7 +109,7 @@ struct LevelDev {
     int32_t F, E, V;
     int32_t ghost_off, ghost_stride, vert_stride;
     int32_t ntiles, n_iedges, n_iverts, n_net_tiles;
-    int32_t n_gs_tl[2][2];           // smoother tiles per face, [halo GS_HE][GS_TJ16 rows]
+    int32_t n_gs_tl[GS_NHALO][2];    // smoother tiles per face, [halo][GS_TJ16 rows]
     int64_t face_stride, edge_stride;
     int64_t face_base, edge_base, vert_base, total;
     int64_t gcls[G_NCLS + 1];
@@ -112,7 +117,7 @@ struct LevelDev {
     double inv4l;                     // 1 / 4^level: micro/macro area ratio
     const int32_t* row_off;           // [n + 1] start of row j inside a face
     const int2* tiles;                // 64 x 4 tiles covering the whole face
-    const int2* gs_tl[2][2];          // smoother tiles covering the whole face
+    const int2* gs_tl[GS_NHALO][2];   // smoother tiles covering the whole face
     const int2* net_tiles;            // learned-smoother tiles meeting the interior
     const FaceInfo* faces;
     const EdgeInfo* edges;
@@ -144,7 +149,7 @@ struct LevelHost {
     int32_t ghost_off = 0, ghost_stride = 0;
     std::vector<int32_t> row_off;
     std::vector<int2> tiles;
-    std::vector<int2> gs_tl[2][2];    // [halo GS_HE][GS_TJ16 rows]
+    std::vector<int2> gs_tl[GS_NHALO][2];   // [halo][GS_TJ16 rows]
     std::vector<int2> net_tiles;
     std::vector<int64_t> gdst, gsrc;
     int64_t gcls[G_NCLS + 1] = {0, 0, 0, 0, 0};
@@ -152,7 +157,7 @@ struct LevelHost {
     // device copies (inside the bound workspace)
     int32_t* d_row_off = nullptr;
     int2* d_tiles = nullptr;
-    int2* d_gs_tl[2][2] = {{nullptr, nullptr}, {nullptr, nullptr}};
+    int2* d_gs_tl[GS_NHALO][2] = {};
     int2* d_net_tiles = nullptr;
     int64_t* d_gdst = nullptr;
     int64_t* d_gsrc = nullptr;

@@ -29,10 +29,11 @@ hipError_t launch_gs_sweep(const hhg_mesh* M, int level, int op, int dtype, void
 // residual; xo receives x + e otherwise.
 hipError_t launch_mp_step(const hhg_mesh* M, int level, int op, const double* x, const float* e,
                           const double* f, double* xo, float* r, double* norm, hipStream_t s);
-// Forward sweep x -> y that also forms r = f - A y with all its copies (the
-// last pre-smoothing sweep before the restriction).
-hipError_t launch_gs_sweep_residual(const hhg_mesh* M, int level, int op, int dtype, void* x, void* y,
-                                    const void* f, void* r, hipStream_t s);
+// Forward sweep x -> y followed by the restriction of r = f - A y:
+// fc (level-1) = P^T r, uc (level-1) = 0.  r is scratch: without two-colour
+// faces it receives only what the edge and vertex restriction reads.
+hipError_t launch_gs_sweep_restrict(const hhg_mesh* M, int level, int op, int dtype, void* x, void* y,
+                                    const void* f, void* r, void* fc, void* uc, hipStream_t s);
 // Backward sweep x -> y that also writes |f - A y|_2 over interior points to
 // the device double *norm (fixed-order sums: face-core points per tile, then
 // the points on and next to the macro-edges).

@@ -584,6 +584,11 @@ struct GsTile {
 
 __device__ __forceinline__ int pmod(int a, int m) { return ((a % m) + m) % m; }
 
+// Halo and tile list of the smoother variants: RES = 0 plain sweep, 1 with
+// the residual, 2 with the residual norm, 3 with the restricted residual.
+__host__ __device__ constexpr int gs_halo(int res) { return res == 3 ? GS_HR : (res ? GS_HE : GS_H); }
+__host__ __device__ constexpr int gs_list(int res) { return res == 3 ? 2 : (res ? 1 : 0); }
+
 // Variable-coefficient weights of the point at LDS position (r, tx), from the
 // coefficient tile: the same arithmetic as face_weights.
 template <class T>
@@ -717,13 +722,18 @@ __device__ __forceinline__ void gs_store_u(T (*us)[GS_W], T (*ks)[GS_W], T (*ur)
 // per row; the row, the colour offset and the bounds are wave-uniform.
 // `out` stores the tile's u once the stages are done; with the residual
 // (H = GS_HE) the residuals then replace the interior tile values in LDS.
+// With RES = 3 (H = GS_HR) they also replace the values one point beyond
+// the interior on the low-i and low-j sides, where the three stages have
+// left u final two points out.
 
 template <class T, bool VARK, bool PROL, int TJ, int RES, class Out>
 __device__ __forceinline__ void gs_tile3(const LevelDev& L, const FaceInfo& fi, int n, int i0, int j0,
                                          int64_t fb, const T* __restrict__ uin, const T* __restrict__ f,
                                          const T* __restrict__ kap, int backward, T (*us)[GS_W],
                                          T (*ks)[GS_W], const ProlTile<T>& pt, Out out, double& acc) {
-    constexpr int H = RES ? GS_HE : GS_H;
+    constexpr int H = gs_halo(RES);
+    // first LDS row and column of the residual region
+    constexpr int RL = RES == 3 ? H - 1 : H;
     using G = GsTile<TJ, H>;
     const int wv = wave_id(), lane = threadIdx.x & 63;
     T ur[G::RPW][3], kr[VARK ? G::RPW : 1][3], fr[3][G::IT3];
@@ -795,10 +805,10 @@ __device__ __forceinline__ void gs_tile3(const LevelDev& L, const FaceInfo& fi, 
         for (int it = 0; it < G::IT3; ++it) {
             const int r = lo + wv + GS_NW * it, j = j0 + r;
             res[s][it] = (T)0;
-            if (r < H || r >= H + TJ) continue;
+            if (r < RL || r >= H + TJ) continue;
             int tx = pmod(c + j - i0, 3) + 3 * lane;
             const int i = i0 + tx;
-            const bool in = tx >= H && tx < H + G::TI && j >= 1 && i >= 1 && i + j <= n - 2;
+            const bool in = tx >= RL && tx < H + G::TI && j >= 1 && i >= 1 && i + j <= n - 2;
             tx = in ? tx : H;
             const T v = gs_resid<T, VARK>(fi, w, fr[s][it], us, ks, r, tx);
             res[s][it] = in ? v : (T)0;
@@ -812,9 +822,9 @@ __device__ __forceinline__ void gs_tile3(const LevelDev& L, const FaceInfo& fi, 
 #pragma unroll
         for (int it = 0; it < G::IT3; ++it) {
             const int r = lo + wv + GS_NW * it, j = j0 + r;
-            if (r < H || r >= H + TJ) continue;
+            if (r < RL || r >= H + TJ) continue;
             const int tx = pmod(c + j - i0, 3) + 3 * lane, i = i0 + tx;
-            if (tx >= H && tx < H + G::TI && j >= 1 && i >= 1 && i + j <= n - 2) us[r][tx] = res[s][it];
+            if (tx >= RL && tx < H + G::TI && j >= 1 && i >= 1 && i + j <= n - 2) us[r][tx] = res[s][it];
         }
     }
     __syncthreads();
@@ -934,16 +944,28 @@ __device__ __forceinline__ void gs_tile2(const LevelDev& L, const FaceInfo& fi, 
 // every block writes partials[blockIdx.x], the sum of the squared residuals
 // of its tile's core points (0 for blocks without a tile); the points next
 // to or on the macro-edges are left to a pass after the edge stages.
+// RES = 3 (three colours only): the residual is restricted where it is
+// formed.  Every coarse interior face point of level Lc has its fine point
+// in exactly one tile interior (the tile origins and sizes are even), and
+// its fine neighbours lie in that interior or one point beyond it on the
+// low sides, where the residual is formed too; fcout receives the
+// restriction there, with the weights and summation order of k_restrict.
+// rout then receives only the ghost-row copies of the near-edge residuals,
+// which the edge restriction reads; the face residuals themselves are never
+// stored.
 template <class T, bool VARK, int NCOL, bool PROL, int TJ, int RES>
 __global__ __launch_bounds__(GS_NT) void k_face_gs_fused(LevelDev L, const T* __restrict__ uin,
                                                          T* __restrict__ uout, const T* __restrict__ f,
                                                          const T* __restrict__ kap, int backward,
                                                          int nblk_tiles, int with_copy, LevelDev Lc,
                                                          const T* __restrict__ uc, T* __restrict__ rout,
-                                                         double* __restrict__ partials) {
-    constexpr int H = RES ? GS_HE : GS_H;
+                                                         double* __restrict__ partials, T* __restrict__ fcout) {
+    static_assert(RES != 3 || NCOL == 3, "the restricting sweep is three-colour only");
+    constexpr int H = gs_halo(RES);
     constexpr int TI = GsTile<TJ, H>::TI;
     constexpr int T16 = TJ == GS_TJ16 ? 1 : 0;
+    static_assert(RES == 3 ? (TJ == GS_TJ16 || TJ == GS_TJR) : (TJ == GS_TJ16 || TJ == GS_TJ),
+                  "tile height must match the tile list");
     __shared__ T us[GsTile<TJ, H>::R][GS_W];
     __shared__ T ks[VARK ? GsTile<TJ, H>::R : 1][GS_W];
     __shared__ double sm[RES == 2 ? GS_NW + 1 : 1];
@@ -966,14 +988,14 @@ __global__ __launch_bounds__(GS_NT) void k_face_gs_fused(LevelDev L, const T* __
         }
         return;
     }
-    const int ntl = L.n_gs_tl[RES ? 1 : 0][T16];
+    const int ntl = L.n_gs_tl[gs_list(RES)][T16];
     const int face = logical / ntl;
     const FaceInfo& fi = L.faces[face];
     if (fi.ncolours != NCOL) {
         if (RES == 2 && threadIdx.x == 0) partials[b] = 0.0;
         return;
     }
-    const int2 tl = L.gs_tl[RES ? 1 : 0][T16][logical % ntl];
+    const int2 tl = L.gs_tl[gs_list(RES)][T16][logical % ntl];
     const int i0 = tl.x * TI - H, j0 = tl.y * TJ - H;   // LDS origin
     const int64_t fb = face_base(L, face);
     const ProlTile<T> pt{uc, PROL ? face_base(Lc, face) : 0, Lc.n};
@@ -1014,7 +1036,7 @@ __global__ __launch_bounds__(GS_NT) void k_face_gs_fused(LevelDev L, const T* __
         }
     };
     double acc = 0.0;
-    if (NCOL == 3)
+    if constexpr (NCOL == 3)
         gs_tile3<T, VARK, PROL, TJ, RES>(L, fi, n, i0, j0, fb, uin, f, kap, backward, us, VARK ? ks : nullptr,
                                          pt, out, acc);
     else
@@ -1025,10 +1047,25 @@ __global__ __launch_bounds__(GS_NT) void k_face_gs_fused(LevelDev L, const T* __
         if (threadIdx.x == 0) partials[b] = t;
         return;
     }
-    if (RES != 1 || NCOL == 2) return;
+    if ((RES != 1 && RES != 3) || NCOL == 2) return;
+    if (RES == 3) {
+        // coarse points whose fine point (2I, 2J) lies in the tile interior
+        static_assert(TI % 2 == 0 && TJ % 2 == 0, "tiles must start on coarse points");
+        constexpr int CI = TI / 2, CJ = TJ / 2;
+        const int nc = Lc.n, I0 = tl.x * CI, J0 = tl.y * CJ;
+        const int64_t cb = face_base(Lc, face);
+        for (int t = threadIdx.x; t < CI * CJ; t += GS_NT) {
+            const int jj = t / CI, ii = t - jj * CI, I = I0 + ii, J = J0 + jj;
+            if (I < 1 || J < 1 || I + J > nc - 2) continue;
+            const int r = H + 2 * jj, tx = H + 2 * ii;
+            const T nb = us[r][tx + 1] + us[r][tx - 1] + us[r + 1][tx] + us[r - 1][tx] + us[r - 1][tx + 1] +
+                         us[r + 1][tx - 1];
+            fcout[cb + row_start(nc, J) + I] = us[r][tx] + (T)0.5 * nb;
+        }
+    }
     // interior residuals (now in LDS) to rout, with the ghost-row copies of
     // the near-edge ones: rows 1 .. n-3 hold interior points
-    for (int r = H + wv; r < H + TJ; r += GS_NW) {
+    for (int r = H + wv; RES == 1 && r < H + TJ; r += GS_NW) {
         const int j = j0 + r;
         if (j > n - 3) break;
         if (j < 1) continue;
@@ -2016,21 +2053,24 @@ struct TimingScope {
 
 template <class T>
 static hipError_t gs_t(const hhg_mesh* M, int level, int op, T* x, T* y, const T* f, int backward,
-                       hipStream_t s, const T* uc = nullptr, T* rout = nullptr, double* norm = nullptr) {
+                       hipStream_t s, const T* uc = nullptr, T* rout = nullptr, double* norm = nullptr,
+                       T* fcout = nullptr) {
     const LevelDev L = M->dev(level);
     const T* kap = kap_of<T>(M, level);
     const int gl = grid_for((int64_t)L.E * (L.n - 2) + L.V, MAX_LOW_BLOCKS);
     // 0: sweep; 1: forward sweep that also writes the residual; 2: backward
-    // sweep that also forms the residual norm
-    const int res = rout ? 1 : (norm ? 2 : 0);
+    // sweep that also forms the residual norm; 3: forward sweep that also
+    // restricts the residual of the face points (three-colour faces only)
+    const int res = fcout ? 3 : (rout ? 1 : (norm ? 2 : 0));
+    const bool has2 = M->m.nfaces2 > 0;
+    if (res == 3 && (has2 || !rout)) return hipErrorInvalidValue;
     const bool timed = M->timing && level == M->m.L && !uc && res == 0;
-    const LevelDev Lc = uc ? M->dev(level - 1) : L;
+    const LevelDev Lc = (uc || fcout) ? M->dev(level - 1) : L;
     // the variable-coefficient FP64 tile (u and k in LDS) is 16 rows high so
     // that two blocks fit on a CU; the others are 24 rows high
     const bool t16 = op == OP_DIFFUSION && sizeof(T) == 8;
-    const int ntile_blocks = L.F * L.n_gs_tl[res ? 1 : 0][t16 ? 1 : 0];
+    const int ntile_blocks = L.F * L.n_gs_tl[gs_list(res)][t16 ? 1 : 0];
     const int g = (ntile_blocks + GS_COPY_BLOCKS + 7) / 8 * 8;
-    const bool has2 = M->m.nfaces2 > 0;
     const int g2 = has2 ? (ntile_blocks + 7) / 8 * 8 : 0;
     const int64_t nrim = (int64_t)L.F * (L.n >= 5 ? 3 * (int64_t)L.n - 12 : 0) + low_items(L);
     const int grim = grid_for(nrim, MAX_LOW_BLOCKS);
@@ -2041,32 +2081,39 @@ static hipError_t gs_t(const hhg_mesh* M, int level, int op, T* x, T* y, const T
 #define HHG_FACE_LAUNCH(VK, PR, TJ, RS)                                                             \
     do {                                                                                            \
         k_face_gs_fused<T, VK, 3, PR, TJ, RS><<<g, GS_NT, 0, s>>>(L, x, y, f, kap, backward,         \
-                                                                  ntile_blocks, 1, Lc, uc, rout, part); \
+                                                                  ntile_blocks, 1, Lc, uc, rout, part, \
+                                                                  nullptr);                          \
         if (has2)                                                                                   \
             k_face_gs_fused<T, VK, 2, PR, TJ, RS><<<g2, GS_NT, 0, s>>>(L, x, y, f, kap, backward,    \
                                                                        ntile_blocks, 0, Lc, uc, rout, \
-                                                                       part + g);                    \
+                                                                       part + g, nullptr);           \
     } while (0)
+#define HHG_FACE_LAUNCH_R(VK, TJ)                                                                   \
+    k_face_gs_fused<T, VK, 3, false, TJ, 3><<<g, GS_NT, 0, s>>>(L, x, y, f, kap, backward, ntile_blocks, 1, \
+                                                               Lc, uc, rout, part, fcout)
         if (op == OP_DIFFUSION) {
             constexpr int TJV = sizeof(T) == 8 ? GS_TJ16 : GS_TJ;
             if (uc) HHG_FACE_LAUNCH(true, true, TJV, 0);
+            else if (res == 3) HHG_FACE_LAUNCH_R(true, sizeof(T) == 8 ? GS_TJ16 : GS_TJR);
             else if (res == 1) HHG_FACE_LAUNCH(true, false, TJV, 1);
             else if (res == 2) HHG_FACE_LAUNCH(true, false, TJV, 2);
             else HHG_FACE_LAUNCH(true, false, TJV, 0);
         } else {
             if (uc) HHG_FACE_LAUNCH(false, true, GS_TJ, 0);
+            else if (res == 3) HHG_FACE_LAUNCH_R(false, GS_TJR);
             else if (res == 1) HHG_FACE_LAUNCH(false, false, GS_TJ, 1);
             else if (res == 2) HHG_FACE_LAUNCH(false, false, GS_TJ, 2);
             else HHG_FACE_LAUNCH(false, false, GS_TJ, 0);
         }
 #undef HHG_FACE_LAUNCH
+#undef HHG_FACE_LAUNCH_R
         return hipGetLastError();
     };
     hipError_t e;
     if (!backward) {
         k_low_gs<T><<<gl, NT, 0, s>>>(L, op, x, f, kap, 0);
         k_low_gs<T><<<gl, NT, 0, s>>>(L, op, x, f, kap, 1);
-        if ((e = faces()) != hipSuccess || res != 1) return e;
+        if ((e = faces()) != hipSuccess || (res != 1 && res != 3)) return e;
         // residual of the edge and vertex points (all copies) from the swept y
         k_apply_low<T, 1><<<grid_for(low_items(L), MAX_LOW_BLOCKS), NT, 0, s>>>(L, op, y, f, rout, kap, nullptr);
         return hipGetLastError();
@@ -2117,13 +2164,6 @@ hipError_t launch_gs_sweep(const hhg_mesh* M, int level, int op, int dtype, void
     return gs_t<float>(M, level, op, (float*)x, (float*)y, (const float*)f, backward, s);
 }
 
-hipError_t launch_gs_sweep_residual(const hhg_mesh* M, int level, int op, int dtype, void* x, void* y,
-                                    const void* f, void* r, hipStream_t s) {
-    if (dtype == DT_F64)
-        return gs_t<double>(M, level, op, (double*)x, (double*)y, (const double*)f, 0, s, nullptr, (double*)r);
-    return gs_t<float>(M, level, op, (float*)x, (float*)y, (const float*)f, 0, s, nullptr, (float*)r);
-}
-
 hipError_t launch_gs_sweep_norm(const hhg_mesh* M, int level, int op, int dtype, void* x, void* y,
                                 const void* f, double* norm, hipStream_t s) {
     if (dtype == DT_F64)
@@ -2138,10 +2178,13 @@ hipError_t launch_gs_sweep_prolong(const hhg_mesh* M, int level, int op, int dty
     return gs_t<float>(M, level, op, (float*)x, (float*)y, (const float*)f, 1, s, (const float*)uc);
 }
 
+// faces = false: the coarse face points are already done (by the restricting
+// sweep); only the edge and vertex points and the zeroing of uc remain.
 template <class T>
-static hipError_t restrict_t(const hhg_mesh* M, int level, const T* r, T* fc, T* uc, hipStream_t s) {
+static hipError_t restrict_t(const hhg_mesh* M, int level, const T* r, T* fc, T* uc, hipStream_t s,
+                             bool faces = true) {
     const LevelDev Lf = M->dev(level), Lc = M->dev(level - 1);
-    const int gf = face_grid(Lc), gl = gf + grid_for(low_items(Lc), MAX_LOW_BLOCKS);
+    const int gf = faces ? face_grid(Lc) : 0, gl = gf + grid_for(low_items(Lc), MAX_LOW_BLOCKS);
     const int gz = uc ? grid_for(Lc.total, 2048) : 0;
     k_restrict<T><<<gl + gz, NT, 0, s>>>(Lf, Lc, r, fc, uc, Lc.total, gf, gl);
     return hipGetLastError();
@@ -2151,6 +2194,27 @@ hipError_t launch_restrict(const hhg_mesh* M, int level, int dtype, const void* 
                            hipStream_t s) {
     if (dtype == DT_F64) return restrict_t<double>(M, level, (const double*)r, (double*)fc, (double*)uc, s);
     return restrict_t<float>(M, level, (const float*)r, (float*)fc, (float*)uc, s);
+}
+
+// The last pre-smoothing sweep with the restriction of its residual: on
+// meshes of three-colour faces the face points are restricted inside the
+// sweep; with two-colour faces the residual is stored and restricted after.
+template <class T>
+static hipError_t gs_restrict_t(const hhg_mesh* M, int level, int op, T* x, T* y, const T* f, T* r, T* fc,
+                                T* uc, hipStream_t s) {
+    const bool fused = M->m.nfaces2 == 0;
+    hipError_t e = gs_t<T>(M, level, op, x, y, f, 0, s, nullptr, r, nullptr, fused ? fc : nullptr);
+    if (e != hipSuccess) return e;
+    return restrict_t<T>(M, level, r, fc, uc, s, !fused);
+}
+
+hipError_t launch_gs_sweep_restrict(const hhg_mesh* M, int level, int op, int dtype, void* x, void* y,
+                                    const void* f, void* r, void* fc, void* uc, hipStream_t s) {
+    if (dtype == DT_F64)
+        return gs_restrict_t<double>(M, level, op, (double*)x, (double*)y, (const double*)f, (double*)r,
+                                     (double*)fc, (double*)uc, s);
+    return gs_restrict_t<float>(M, level, op, (float*)x, (float*)y, (const float*)f, (float*)r, (float*)fc,
+                                (float*)uc, s);
 }
 
 template <class T>

@@ -302,9 +302,10 @@ void MeshData::build_level(int level) {
 
     // smoother tiles over the whole face triangle (ring included), column by
     // column so that consecutive tiles are vertical neighbours
-    for (int e = 0; e < 2; ++e)
+    const int halos[GS_NHALO] = {GS_H, GS_HE, GS_HR};
+    for (int e = 0; e < GS_NHALO; ++e)
         for (int t = 0; t < 2; ++t) {
-            const int ti_w = gs_tile_width(e ? GS_HE : GS_H), tj_h = t ? GS_TJ16 : GS_TJ;
+            const int ti_w = gs_tile_width(halos[e]), tj_h = t ? GS_TJ16 : (e == 2 ? GS_TJR : GS_TJ);
             std::vector<int2>& tl = H.gs_tl[e][t];
             tl.clear();
             for (int ti = 0; ti * ti_w <= n - 1; ++ti)

@@ -155,6 +155,44 @@ def _vcycle_parity(name, L, nu, lc, coarse="direct"):
     assert np.array_equal(ug[lv.dirichlet], u[lv.dirichlet])
 
 
+_L8 = {}
+
+
+@pytest.mark.parametrize("op,dtype", [("laplace", "f64"), ("laplace", "f32"), ("diffusion", "f64")])
+def test_vcycle_parity_several_tile_columns(op, dtype):
+    """Level 8 of the 64-face annulus (257 points along a macro-edge).  The
+    smoother tiles (182 x 22 or 182 x 16 interior points in the sweep that
+    restricts its residual, 186 x 24 or 186 x 16 otherwise) span two columns
+    and up to seventeen rows per face with ragged last ones, so coarse points
+    next to every kind of tile border are restricted inside the sweep.  FP64
+    to 1e-12; FP32 on FP32-representable inputs within 1e-4, as at smaller
+    sizes.  The variable coefficient is the seeded random field of the
+    other variable-coefficient tests."""
+    import torch
+
+    import paper_1805_10167_amd as P
+    L = 8
+    log("vcycle several tile columns %s %s L=%d" % (op, dtype, L))
+    if op not in _L8:
+        ks = 7 if op == "diffusion" else None
+        H = oracle_hierarchy("annulus64", L, 2, ks)
+        g = gpu_mesh("annulus64", L, 2, P.HHG_FEAT_F64 | P.HHG_FEAT_MP | P.HHG_FEAT_VARK)
+        if ks is not None:
+            P.hhg_set_coefficient(g.h, torch.tensor(H.kappa[L], dtype=torch.float64, device="cuda"))
+        _L8[op] = (g, H)
+    g, H = _L8[op]
+    lv = H.levels[L]
+    dt = P.HHG_F64 if dtype == "f64" else P.HHG_F32
+    cast = (lambda x: x) if dtype == "f64" else (lambda x: x.astype(np.float32).astype(np.float64))
+    u, f = cast(canon_vec(lv, 5)), cast(canon_vec(lv, 6))
+    uf, ff = g.from_canonical(L, u, dt), g.from_canonical(L, f, dt)
+    opc = P.HHG_OP_LAPLACE if op == "laplace" else P.HHG_OP_DIFFUSION
+    P.hhg_vcycle(g.h, L, opc, P.HHG_SMOOTH_GS, dt, uf, ff, 3, 3)
+    err = rel_err(to_np(g.to_canonical(L, uf, dt)), H.vcycle(L, u.copy(), f, 3, 3))
+    log("  rel err %.2e" % err)
+    assert err <= (F64_TOL if dtype == "f64" else 1e-4)
+
+
 @pytest.mark.parametrize("name,L,nu,rtol", [("annulus64", 6, (3, 3), 1e-8),
                                             ("square", 6, (2, 2), 1e-10),
                                             ("square", 5, (1, 1), 1e-8),
