@@ -15,6 +15,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <cstddef>
 
 #include <cstdint>
 
@@ -193,6 +194,44 @@ __device__ __forceinline__ T vertex_weight(int op, const VertexInfo& vi, double 
     return (T)-0.5 * s;
 }
 
+// Vertex kernels read deg and boundary as one 8-byte load.
+static_assert(offsetof(VertexInfo, deg) == 0 && offsetof(VertexInfo, boundary) == 4 && alignof(VertexInfo) >= 8,
+              "deg and boundary must form an aligned pair");
+
+// s = sum_q w_q x[ring q] and c = sum_q w_q over the ring of a vertex, in
+// ring order (deg = vi.deg, read by the caller).  For the Laplacian the ring
+// values and weights are loaded four
+// at a time (indices clamped into the ring, so the loads need no branch):
+// the loads of a group are in flight together instead of one round trip per
+// neighbour.  The sums are formed in the same order as the plain loop.
+template <class T>
+__device__ __forceinline__ void vertex_ring_sums(int op, const VertexInfo& vi, int deg, double inv4l,
+                                                 const T* kap, const T* x, int64_t vb, T& s, T& c) {
+    if (op == OP_LAPLACE) {
+        for (int q0 = 0; q0 < deg; q0 += 4) {
+            T xq[4], wq[4];
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+                const int q = q0 + k < deg ? q0 + k : q0;
+                xq[k] = x[vb + 1 + q];
+                wq[k] = (T)(-0.5 * (vi.cA[q][0] + vi.cA[q][1]));
+            }
+#pragma unroll
+            for (int k = 0; k < 4; ++k)
+                if (q0 + k < deg) {
+                    s += wq[k] * xq[k];
+                    c += wq[k];
+                }
+        }
+        return;
+    }
+    for (int q = 0; q < deg; ++q) {
+        const T wq = vertex_weight<T>(op, vi, inv4l, kap, vb, q);
+        s += wq * x[vb + 1 + q];
+        c += wq;
+    }
+}
+
 // ------------------------------------------------------------------ kernels
 
 // Copy ghost entries [lo, hi) of the ghost table.
@@ -261,13 +300,32 @@ __device__ __forceinline__ void push_edge(const LevelDev& L, T* x, const EdgeInf
 }
 
 // Copies of a vertex value: edge end slots and face ring corners.
+// The targets are read four at a time (indices clamped into the lists), so
+// that a group's metadata loads are in flight together.
 template <class T>
 __device__ __forceinline__ void push_vertex(const LevelDev& L, T* x, const VertexInfo& vi, T val) {
-    const int n = L.n;
-    for (int q = 0; q < vi.deg; ++q) x[edge_main(L, vi.edge[q]) + (vi.at_a[q] ? 0 : n - 1)] = val;
-    for (int c = 0; c < vi.nfc; ++c) {
-        const int cr = vi.fc_corner[c];
-        x[face_base(L, vi.fc_face[c]) + row_start(n, cr == 2 ? n - 1 : 0) + (cr == 1 ? n - 1 : 0)] = val;
+    const int n = L.n, deg = vi.deg, nfc = vi.nfc;
+    for (int q0 = 0; q0 < deg; q0 += 4) {
+        int64_t a[4];
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            const int q = q0 + k < deg ? q0 + k : q0;
+            a[k] = edge_main(L, vi.edge[q]) + (vi.at_a[q] ? 0 : n - 1);
+        }
+#pragma unroll
+        for (int k = 0; k < 4; ++k)
+            if (q0 + k < deg) x[a[k]] = val;
+    }
+    for (int c0 = 0; c0 < nfc; c0 += 4) {
+        int64_t a[4];
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            const int c = c0 + k < nfc ? c0 + k : c0, cr = vi.fc_corner[c];
+            a[k] = face_base(L, vi.fc_face[c]) + row_start(n, cr == 2 ? n - 1 : 0) + (cr == 1 ? n - 1 : 0);
+        }
+#pragma unroll
+        for (int k = 0; k < 4; ++k)
+            if (c0 + k < nfc) x[a[k]] = val;
     }
 }
 
@@ -319,11 +377,7 @@ template <class T>
 __device__ __forceinline__ T vertex_apply(int op, const LevelDev& L, const VertexInfo& vi, const T* x,
                                           const T* kap, int64_t vb) {
     T s = (T)0, c = (T)0;
-    for (int q = 0; q < vi.deg; ++q) {
-        const T wq = vertex_weight<T>(op, vi, L.inv4l, kap, vb, q);
-        s += wq * x[vb + 1 + q];
-        c += wq;
-    }
+    vertex_ring_sums<T>(op, vi, vi.deg, L.inv4l, kap, x, vb, s, c);
     c = (op == OP_MASS) ? c : -c;
     return c * x[vb] + s;
 }
@@ -360,13 +414,10 @@ __device__ __forceinline__ void apply_low_item(const LevelDev& L, int op, const 
         const int vv = (int)(t - ne);
         const VertexInfo& vi = L.verts[vv];
         const int64_t vb = vert_off(L, vv);
-        if (!vi.boundary) {
+        const int2 db = *reinterpret_cast<const int2*>(&vi.deg);   // deg, boundary in one load
+        if (!db.y) {
             T s = (T)0, c = (T)0;
-            for (int q = 0; q < vi.deg; ++q) {
-                const T wq = vertex_weight<T>(op, vi, L.inv4l, kap, vb, q);
-                s += wq * x[vb + 1 + q];
-                c += wq;
-            }
+            vertex_ring_sums<T>(op, vi, db.x, L.inv4l, kap, x, vb, s, c);
             c = (op == OP_MASS) ? c : -c;
             if (MODE == 3) {
                 v = x[vb] / c;
@@ -1411,16 +1462,14 @@ __device__ __forceinline__ void low_gs_item(const LevelDev& L, int op, T* __rest
     } else {
         const int vv = (int)(t - ne);
         const VertexInfo& vi = L.verts[vv];
-        if (vi.boundary) return;
         const int64_t vb = vert_off(L, vv);
+        const int2 db = *reinterpret_cast<const int2*>(&vi.deg);   // deg, boundary in one load
+        const T fv = f[vb];
+        if (db.y) return;
         T s = (T)0, c = (T)0;
-        for (int q = 0; q < vi.deg; ++q) {
-            const T wq = vertex_weight<T>(op, vi, L.inv4l, kap, vb, q);
-            s += wq * u[vb + 1 + q];
-            c += wq;
-        }
+        vertex_ring_sums<T>(op, vi, db.x, L.inv4l, kap, u, vb, s, c);
         c = (op == OP_MASS) ? c : -c;
-        const T v = (f[vb] - s) / c;
+        const T v = (fv - s) / c;
         u[vb] = v;
         push_vertex(L, u, vi, v);
     }
