@@ -230,13 +230,14 @@ int copy_field(const hhg_mesh* M, int level, int dt, void* dst, const void* src,
 // One V-cycle on `level`.  norm != nullptr: also |f - A u|_2 of the result
 // into the device double *norm, formed by the last post-smoothing sweep when
 // there is one besides the sweep that carries the prolongation, else by a
-// residual pass.
+// residual pass.  u_zero: u is known to be 0 (the coarse corrections, which
+// the restriction zeroes).
 int vcycle_rec(const hhg_mesh* M, int level, int op, int smoother, int dt, void* u, const void* f,
-               int nu1, int nu2, hipStream_t s, double* norm = nullptr) {
+               int nu1, int nu2, hipStream_t s, double* norm = nullptr, bool u_zero = false) {
     const int lc = M->m.lc;
     const double* vals = op == HHG_OP_DIFFUSION ? M->coarse_vals_diff : M->coarse.vals;
     if (level == lc) {
-        HIP_CHECK(launch_coarse_solve(M, op, dt, u, f, vals, s), "coarse solve");
+        HIP_CHECK(launch_coarse_solve(M, op, dt, u, f, vals, s, u_zero), "coarse solve");
         if (norm) HIP_CHECK(launch_residual(M, level, op, dt, u, f, nullptr, norm, s), "residual norm");
         return HHG_OK;
     }
@@ -258,7 +259,7 @@ int vcycle_rec(const hhg_mesh* M, int level, int op, int smoother, int dt, void*
         HIP_CHECK(launch_residual(M, level, op, dt, cur, f, r, nullptr, s), "residual");
         HIP_CHECK(launch_restrict(M, level, dt, r, fc, uc, s), "restrict");
     }
-    rc = vcycle_rec(M, level - 1, op, smoother, dt, uc, fc, nu1, nu2, s);
+    rc = vcycle_rec(M, level - 1, op, smoother, dt, uc, fc, nu1, nu2, s, nullptr, true);
     if (rc) return rc;
     void* fin = nullptr;
     if (smoother == HHG_SMOOTH_GS && nu2 > 0) {

@@ -65,9 +65,10 @@ hipError_t launch_fill(void* x, int64_t n, int dtype, double v, hipStream_t s);
 // ELL values of the coarse operator for `op` into `vals`.
 hipError_t launch_coarse_extract(const hhg_mesh* M, int op, double* vals, hipStream_t s);
 // u += A_int^-1 (f - A u)_int on the coarse level (stored inverse and one
-// refinement step, or Jacobi-PCG), ghosts refreshed.
+// refinement step, or Jacobi-PCG), ghosts refreshed.  u_zero: the caller
+// guarantees u = 0 (then f is the residual and no residual pass runs).
 hipError_t launch_coarse_solve(const hhg_mesh* M, int op, int dtype, void* u, const void* f,
-                               const double* vals, hipStream_t s);
+                               const double* vals, hipStream_t s, bool u_zero = false);
 // Canonical <-> layout conversion (to_canon = 1: field -> canonical).
 hipError_t launch_canon(const hhg_mesh* M, int level, int dtype, const void* src, void* dst,
                         int to_canon, hipStream_t s);

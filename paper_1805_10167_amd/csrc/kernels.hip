@@ -276,27 +276,50 @@ __device__ __forceinline__ void side_point0(int side, int t, int n, int& i, int&
     else { i = n - 1 - t; j = t; }
 }
 
+// Copies of edge point k = 1 or n-2 in the first/last ghost-row entry of the
+// neighbouring edges of each adjacent face (the entries next to the shared
+// vertex).  Both faces' targets are read before either store, so their
+// metadata loads are in flight together.
+template <class T>
+__device__ __forceinline__ void push_corner_ghosts(const LevelDev& L, T* x, const EdgeInfo& ei, int k, T val) {
+    const int n = L.n, nf = ei.nf;
+    for (int end = 0; end < 2; ++end) {
+        if (k != (end == 0 ? 1 : n - 2)) continue;
+        int64_t a[2];
+        bool ok[2];
+#pragma unroll
+        for (int s = 0; s < 2; ++s) {
+            const int ss = s < nf ? s : 0, e2 = ei.cg_edge[ss][end];
+            ok[s] = s < nf && e2 >= 0;
+            a[s] = ok[s] ? edge_ghost(L, e2, ei.cg_slot[ss][end]) + (ei.cg_first[ss][end] ? 0 : n - 2) : 0;
+        }
+#pragma unroll
+        for (int s = 0; s < 2; ++s)
+            if (ok[s]) x[a[s]] = val;
+    }
+}
+
 // Copies of edge point k: face rings, the vertex ghost (k = 1 or n-2) and,
 // with `corners`, the first/last ghost-row entry of the neighbouring edges.
 template <class T>
 __device__ __forceinline__ void push_edge(const LevelDev& L, T* x, const EdgeInfo& ei, int k, T val,
                                           bool corners) {
-    const int n = L.n;
-    for (int s = 0; s < ei.nf; ++s) {
+    const int n = L.n, nf = ei.nf;
+    // both faces' targets first (the second clamped to the first when the
+    // edge has one face), so their metadata loads are in flight together
+    int64_t a[2];
+#pragma unroll
+    for (int s = 0; s < 2; ++s) {
+        const int ss = s < nf ? s : 0;
         int i, j;
-        side_point0(ei.side[s], ei.rev[s] ? n - 1 - k : k, n, i, j);
-        x[face_base(L, ei.face[s]) + row_start(n, j) + i] = val;
+        side_point0(ei.side[ss], ei.rev[ss] ? n - 1 - k : k, n, i, j);
+        a[s] = face_base(L, ei.face[ss]) + row_start(n, j) + i;
     }
+    x[a[0]] = val;
+    if (nf > 1) x[a[1]] = val;
     if (k == 1) x[vert_off(L, ei.a) + 1 + ei.vslot[0]] = val;
     if (k == n - 2) x[vert_off(L, ei.b) + 1 + ei.vslot[1]] = val;
-    if (!corners) return;
-    for (int end = 0; end < 2; ++end) {
-        if (k != (end == 0 ? 1 : n - 2)) continue;
-        for (int s = 0; s < ei.nf; ++s) {
-            const int e2 = ei.cg_edge[s][end];
-            if (e2 >= 0) x[edge_ghost(L, e2, ei.cg_slot[s][end]) + (ei.cg_first[s][end] ? 0 : n - 2)] = val;
-        }
-    }
+    if (corners) push_corner_ghosts(L, x, ei, k, val);
 }
 
 // Copies of a vertex value: edge end slots and face ring corners.
@@ -380,6 +403,27 @@ __device__ __forceinline__ T vertex_apply(int op, const LevelDev& L, const Verte
     vertex_ring_sums<T>(op, vi, vi.deg, L.inv4l, kap, x, vb, s, c);
     c = (op == OP_MASS) ? c : -c;
     return c * x[vb] + s;
+}
+
+// Residuals f - A x at edge point k of an interior edge e and at an interior
+// vertex, with the arithmetic of apply_low_item's residual mode.
+template <class T>
+__device__ __forceinline__ T edge_resid(int op, const LevelDev& L, const EdgeInfo& ei, int e, const T* x,
+                                        const T* f, const T* kap, int k) {
+    const int64_t m = edge_main(L, e), g0 = edge_ghost(L, e, 0), g1 = edge_ghost(L, e, 1);
+    const WE<T> w = edge_weights<T>(op, ei, L.inv4l, kap, m, g0, g1, k);
+    const T v = w.c * x[m + k] + w.al * x[m + k - 1] + w.ah * x[m + k + 1] + w.l0 * x[g0 + k - 1] +
+                w.h0 * x[g0 + k] + w.l1 * x[g1 + k - 1] + w.h1 * x[g1 + k];
+    return f[m + k] - v;
+}
+
+template <class T>
+__device__ __forceinline__ T vertex_resid(int op, const LevelDev& L, const VertexInfo& vi, int deg, const T* x,
+                                          const T* f, const T* kap, int64_t vb) {
+    T s = (T)0, c = (T)0;
+    vertex_ring_sums<T>(op, vi, deg, L.inv4l, kap, x, vb, s, c);
+    c = (op == OP_MASS) ? c : -c;
+    return f[vb] - (c * x[vb] + s);
 }
 
 // Point operator at edge/vertex item t (edge points first, ne of them, then
@@ -1439,14 +1483,7 @@ __device__ __forceinline__ void low_gs_item(const LevelDev& L, int op, T* __rest
             if (stage != 1 && (k & 1) && (k == 1 || k == n - 2)) {
                 const T v = u[m + k];
                 if (ei.boundary) return;
-                for (int end = 0; end < 2; ++end) {
-                    if (k != (end == 0 ? 1 : n - 2)) continue;
-                    for (int s = 0; s < ei.nf; ++s) {
-                        const int e2 = ei.cg_edge[s][end];
-                        if (e2 >= 0)
-                            u[edge_ghost(L, e2, ei.cg_slot[s][end]) + (ei.cg_first[s][end] ? 0 : n - 2)] = v;
-                    }
-                }
+                push_corner_ghosts(L, u, ei, k, v);
             }
             return;
         }
@@ -1526,9 +1563,85 @@ __global__ __launch_bounds__(NT) void k_restrict(LevelDev Lf, LevelDev Lc, const
                 const int64_t vc = vert_off(Lc, v);
                 if (vi.boundary) { fc[vc] = (T)0; continue; }
                 const int64_t vf = vert_off(Lf, v);
+                const int deg = vi.deg;
                 T nb = (T)0;
-                for (int q = 0; q < vi.deg; ++q) nb += r[vf + 1 + q];
+                for (int q0 = 0; q0 < deg; q0 += 4) {     // ring loads four at a time, summed in order
+                    T rq[4];
+#pragma unroll
+                    for (int k = 0; k < 4; ++k) rq[k] = r[vf + 1 + (q0 + k < deg ? q0 + k : q0)];
+#pragma unroll
+                    for (int k = 0; k < 4; ++k)
+                        if (q0 + k < deg) nb += rq[k];
+                }
                 fc[vc] = r[vf] + (T)0.5 * nb;
+            }
+        }
+    } else {
+        for (int64_t t = (int64_t)(blockIdx.x - gl) * NT + threadIdx.x; t < uc_n;
+             t += (int64_t)(gridDim.x - gl) * NT)
+            uc[t] = (T)0;
+    }
+}
+
+// Restriction of the coarse edge and vertex points straight from the swept
+// fine field x, after the sweep that restricts the face residuals (which
+// leaves the edge and vertex residuals unformed): the fine residuals these
+// points need (edge points k - 1, k, k + 1; a vertex and its ring, whose
+// members are the first points of the incident edges) are formed here, with
+// the arithmetic of k_apply_low's residual; the residuals of the face points
+// next to the edges come from r's ghost rows.  The weights and the order of
+// the sums are k_restrict's.  Blocks [gl, gridDim.x) zero the coarse
+// correction uc.
+template <class T>
+__global__ __launch_bounds__(NT) void k_restrict_low(LevelDev Lf, LevelDev Lc, int op, const T* __restrict__ x,
+                                                     const T* __restrict__ f, const T* __restrict__ kap,
+                                                     const T* __restrict__ r, T* __restrict__ fc,
+                                                     T* __restrict__ uc, int64_t uc_n, int gl) {
+    if ((int)blockIdx.x < gl) {
+        const int nc = Lc.n, n = Lf.n;
+        const int64_t ne = (int64_t)Lc.E * (nc - 2);
+        for (int64_t t = (int64_t)blockIdx.x * NT + threadIdx.x; t < ne + Lc.V; t += (int64_t)gl * NT) {
+            if (t < ne) {
+                const int e = (int)(t / (nc - 2)), K = (int)(t % (nc - 2)) + 1;
+                const int64_t mc = edge_main(Lc, e);
+                const EdgeInfo& ei = Lf.edges[e];
+                if (ei.boundary) {
+                    fc[mc + K] = (T)0;
+                    continue;
+                }
+                const int64_t g0 = edge_ghost(Lf, e, 0), g1 = edge_ghost(Lf, e, 1);
+                const int k = 2 * K;
+                const T rm = edge_resid<T>(op, Lf, ei, e, x, f, kap, k - 1);
+                const T rk = edge_resid<T>(op, Lf, ei, e, x, f, kap, k);
+                const T rp = edge_resid<T>(op, Lf, ei, e, x, f, kap, k + 1);
+                const T nb = rm + rp + r[g0 + k - 1] + r[g0 + k] + r[g1 + k - 1] + r[g1 + k];
+                fc[mc + K] = rk + (T)0.5 * nb;
+            } else {
+                const int v = (int)(t - ne);
+                const VertexInfo& vi = Lf.verts[v];
+                const int64_t vc = vert_off(Lc, v);
+                const int2 db = *reinterpret_cast<const int2*>(&vi.deg);   // deg, boundary in one load
+                if (db.y) {
+                    fc[vc] = (T)0;
+                    continue;
+                }
+                const int64_t vf = vert_off(Lf, v);
+                const int deg = db.x;
+                const T rv = vertex_resid<T>(op, Lf, vi, deg, x, f, kap, vf);
+                T nb = (T)0;
+                for (int q0 = 0; q0 < deg; q0 += 4) {     // ring members four at a time, summed in order
+                    T rq[4];
+#pragma unroll
+                    for (int j = 0; j < 4; ++j) {
+                        const int q = q0 + j < deg ? q0 + j : q0, e2 = vi.edge[q];
+                        const EdgeInfo& e2i = Lf.edges[e2];
+                        rq[j] = e2i.boundary ? (T)0 : edge_resid<T>(op, Lf, e2i, e2, x, f, kap, vi.at_a[q] ? 1 : n - 2);
+                    }
+#pragma unroll
+                    for (int j = 0; j < 4; ++j)
+                        if (q0 + j < deg) nb += rq[j];
+                }
+                fc[vc] = rv + (T)0.5 * nb;
             }
         }
     } else {
@@ -2162,7 +2275,7 @@ static hipError_t gs_t(const hhg_mesh* M, int level, int op, T* x, T* y, const T
     if (!backward) {
         k_low_gs<T><<<gl, NT, 0, s>>>(L, op, x, f, kap, 0);
         k_low_gs<T><<<gl, NT, 0, s>>>(L, op, x, f, kap, 1);
-        if ((e = faces()) != hipSuccess || (res != 1 && res != 3)) return e;
+        if ((e = faces()) != hipSuccess || res != 1) return e;
         // residual of the edge and vertex points (all copies) from the swept y
         k_apply_low<T, 1><<<grid_for(low_items(L), MAX_LOW_BLOCKS), NT, 0, s>>>(L, op, y, f, rout, kap, nullptr);
         return hipGetLastError();
@@ -2227,13 +2340,10 @@ hipError_t launch_gs_sweep_prolong(const hhg_mesh* M, int level, int op, int dty
     return gs_t<float>(M, level, op, (float*)x, (float*)y, (const float*)f, 1, s, (const float*)uc);
 }
 
-// faces = false: the coarse face points are already done (by the restricting
-// sweep); only the edge and vertex points and the zeroing of uc remain.
 template <class T>
-static hipError_t restrict_t(const hhg_mesh* M, int level, const T* r, T* fc, T* uc, hipStream_t s,
-                             bool faces = true) {
+static hipError_t restrict_t(const hhg_mesh* M, int level, const T* r, T* fc, T* uc, hipStream_t s) {
     const LevelDev Lf = M->dev(level), Lc = M->dev(level - 1);
-    const int gf = faces ? face_grid(Lc) : 0, gl = gf + grid_for(low_items(Lc), MAX_LOW_BLOCKS);
+    const int gf = face_grid(Lc), gl = gf + grid_for(low_items(Lc), MAX_LOW_BLOCKS);
     const int gz = uc ? grid_for(Lc.total, 2048) : 0;
     k_restrict<T><<<gl + gz, NT, 0, s>>>(Lf, Lc, r, fc, uc, Lc.total, gf, gl);
     return hipGetLastError();
@@ -2253,8 +2363,11 @@ static hipError_t gs_restrict_t(const hhg_mesh* M, int level, int op, T* x, T* y
                                 T* uc, hipStream_t s) {
     const bool fused = M->m.nfaces2 == 0;
     hipError_t e = gs_t<T>(M, level, op, x, y, f, 0, s, nullptr, r, nullptr, fused ? fc : nullptr);
-    if (e != hipSuccess) return e;
-    return restrict_t<T>(M, level, r, fc, uc, s, !fused);
+    if (e != hipSuccess || !fused) return e != hipSuccess ? e : restrict_t<T>(M, level, r, fc, uc, s);
+    const LevelDev Lf = M->dev(level), Lc = M->dev(level - 1);
+    const int gl = grid_for(low_items(Lc), MAX_LOW_BLOCKS), gz = uc ? grid_for(Lc.total, 2048) : 0;
+    k_restrict_low<T><<<gl + gz, NT, 0, s>>>(Lf, Lc, op, y, f, kap_of<T>(M, level), r, fc, uc, Lc.total, gl);
+    return hipGetLastError();
 }
 
 hipError_t launch_gs_sweep_restrict(const hhg_mesh* M, int level, int op, int dtype, void* x, void* y,
@@ -2296,11 +2409,14 @@ hipError_t launch_coarse_extract(const hhg_mesh* M, int op, double* vals, hipStr
 
 template <class T>
 static hipError_t coarse_t(const hhg_mesh* M, int op, T* u, const T* f, const double* vals,
-                           hipStream_t s) {
+                           hipStream_t s, bool u_zero) {
     const int lc = M->m.lc;
-    T* r = (T*)(sizeof(T) == 8 ? M->r64[lc] : M->r32[lc]);
-    hipError_t e = residual_t<T>(M, lc, op, u, f, r, nullptr, s);
-    if (e != hipSuccess) return e;
+    // with u = 0 the residual is f itself (the solvers read the owned points)
+    T* r = u_zero ? const_cast<T*>(f) : (T*)(sizeof(T) == 8 ? M->r64[lc] : M->r32[lc]);
+    if (!u_zero) {
+        hipError_t e = residual_t<T>(M, lc, op, u, f, r, nullptr, s);
+        if (e != hipSuccess) return e;
+    }
     const int N = M->coarse.N;
     const int which = vals == M->coarse.vals ? 0 : 1;
     double* inv = M->coarse_inv[which];
@@ -2325,9 +2441,9 @@ static hipError_t coarse_t(const hhg_mesh* M, int op, T* u, const T* f, const do
 }
 
 hipError_t launch_coarse_solve(const hhg_mesh* M, int op, int dtype, void* u, const void* f,
-                               const double* vals, hipStream_t s) {
-    if (dtype == DT_F64) return coarse_t<double>(M, op, (double*)u, (const double*)f, vals, s);
-    return coarse_t<float>(M, op, (float*)u, (const float*)f, vals, s);
+                               const double* vals, hipStream_t s, bool u_zero) {
+    if (dtype == DT_F64) return coarse_t<double>(M, op, (double*)u, (const double*)f, vals, s, u_zero);
+    return coarse_t<float>(M, op, (float*)u, (const float*)f, vals, s, u_zero);
 }
 
 template <class T>
