@@ -1605,17 +1605,15 @@ __global__ __launch_bounds__(NT) void k_restrict_low(LevelDev Lf, LevelDev Lc, i
                 const int e = (int)(t / (nc - 2)), K = (int)(t % (nc - 2)) + 1;
                 const int64_t mc = edge_main(Lc, e);
                 const EdgeInfo& ei = Lf.edges[e];
-                if (ei.boundary) {
-                    fc[mc + K] = (T)0;
-                    continue;
-                }
+                // formed before the Dirichlet test (all reads stay inside the
+                // edge block), so the loads go out with the edge's metadata
                 const int64_t g0 = edge_ghost(Lf, e, 0), g1 = edge_ghost(Lf, e, 1);
                 const int k = 2 * K;
                 const T rm = edge_resid<T>(op, Lf, ei, e, x, f, kap, k - 1);
                 const T rk = edge_resid<T>(op, Lf, ei, e, x, f, kap, k);
                 const T rp = edge_resid<T>(op, Lf, ei, e, x, f, kap, k + 1);
                 const T nb = rm + rp + r[g0 + k - 1] + r[g0 + k] + r[g1 + k - 1] + r[g1 + k];
-                fc[mc + K] = rk + (T)0.5 * nb;
+                fc[mc + K] = ei.boundary ? (T)0 : rk + (T)0.5 * nb;
             } else {
                 const int v = (int)(t - ne);
                 const VertexInfo& vi = Lf.verts[v];
@@ -1630,12 +1628,16 @@ __global__ __launch_bounds__(NT) void k_restrict_low(LevelDev Lf, LevelDev Lc, i
                 const T rv = vertex_resid<T>(op, Lf, vi, deg, x, f, kap, vf);
                 T nb = (T)0;
                 for (int q0 = 0; q0 < deg; q0 += 4) {     // ring members four at a time, summed in order
+                    // formed without a branch (an edge block always has both
+                    // ghost rows, so the reads stay inside it), then masked:
+                    // the four members' loads are in flight together
                     T rq[4];
 #pragma unroll
                     for (int j = 0; j < 4; ++j) {
                         const int q = q0 + j < deg ? q0 + j : q0, e2 = vi.edge[q];
                         const EdgeInfo& e2i = Lf.edges[e2];
-                        rq[j] = e2i.boundary ? (T)0 : edge_resid<T>(op, Lf, e2i, e2, x, f, kap, vi.at_a[q] ? 1 : n - 2);
+                        const T rr = edge_resid<T>(op, Lf, e2i, e2, x, f, kap, vi.at_a[q] ? 1 : n - 2);
+                        rq[j] = e2i.boundary ? (T)0 : rr;
                     }
 #pragma unroll
                     for (int j = 0; j < 4; ++j)
