@@ -2358,14 +2358,16 @@ hipError_t launch_restrict(const hhg_mesh* M, int level, int dtype, const void* 
 }
 
 // The last pre-smoothing sweep with the restriction of its residual: on
-// meshes of three-colour faces the face points are restricted inside the
-// sweep; with two-colour faces the residual is stored and restricted after.
+// meshes of three-colour faces the coarse face points are restricted inside
+// the sweep and the coarse edge and vertex points by k_restrict_low; with
+// two-colour faces the residual is stored whole and restricted after.
 template <class T>
 static hipError_t gs_restrict_t(const hhg_mesh* M, int level, int op, T* x, T* y, const T* f, T* r, T* fc,
                                 T* uc, hipStream_t s) {
     const bool fused = M->m.nfaces2 == 0;
-    hipError_t e = gs_t<T>(M, level, op, x, y, f, 0, s, nullptr, r, nullptr, fused ? fc : nullptr);
-    if (e != hipSuccess || !fused) return e != hipSuccess ? e : restrict_t<T>(M, level, r, fc, uc, s);
+    const hipError_t e = gs_t<T>(M, level, op, x, y, f, 0, s, nullptr, r, nullptr, fused ? fc : nullptr);
+    if (e != hipSuccess) return e;
+    if (!fused) return restrict_t<T>(M, level, r, fc, uc, s);
     const LevelDev Lf = M->dev(level), Lc = M->dev(level - 1);
     const int gl = grid_for(low_items(Lc), MAX_LOW_BLOCKS), gz = uc ? grid_for(Lc.total, 2048) : 0;
     k_restrict_low<T><<<gl + gz, NT, 0, s>>>(Lf, Lc, op, y, f, kap_of<T>(M, level), r, fc, uc, Lc.total, gl);
