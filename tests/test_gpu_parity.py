@@ -121,7 +121,7 @@ def test_smooth_parity(name, L, backward, sweeps):
 @pytest.mark.parametrize("name,L,nu", [("square", 5, (2, 2)), ("annulus64", 4, (1, 1)),
                                        ("annulus64", 6, (3, 3)), ("annulus128", 4, (3, 3)),
                                        ("annulus64", 6, (2, 0)), ("annulus64", 7, (3, 3)),
-                                       ("annulus128", 7, (1, 2))])
+                                       ("annulus128", 7, (1, 2)), ("annulus64", 5, (0, 2))])
 def test_vcycle_parity(name, L, nu):
     _vcycle_parity(name, L, nu, 2)
 
