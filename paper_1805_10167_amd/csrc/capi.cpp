@@ -284,11 +284,29 @@ int vcycle_rec(const hhg_mesh* M, int level, int op, int smoother, int dt, void*
     return HHG_OK;
 }
 
-int read_scalar(const double* d, double* h, hipStream_t s) {
-    HIP_CHECK(hipMemcpyAsync(h, d, sizeof(double), hipMemcpyDeviceToHost, s), "norm readback");
-    HIP_CHECK(hipStreamSynchronize(s), "norm readback");
+// The solve loop's norm slot (allocated on first use, kept until the mesh is
+// destroyed).
+static int solve_norm_slot(hhg_mesh* M) {
+    if (M->h_norm) return HHG_OK;
+    void* h = nullptr;
+    void* d = nullptr;
+    HIP_CHECK(hipHostMalloc(&h, 64, hipHostMallocMapped), "pinned norm slot");
+    if (hipHostGetDevicePointer(&d, h, 0) != hipSuccess) {
+        (void)hipHostFree(h);
+        return fail(HHG_EHIP, "pinned norm slot has no device address");
+    }
+    M->h_norm = (double*)h;
+    M->h_norm_dev = (double*)d;
     return HHG_OK;
 }
+
+// Value of the norm slot once the stream has drained.
+static int read_norm_slot(const hhg_mesh* M, double* h, hipStream_t s) {
+    HIP_CHECK(hipStreamSynchronize(s), "norm readback");
+    *h = *(volatile const double*)M->h_norm;
+    return HHG_OK;
+}
+
 
 }  // namespace
 
@@ -360,6 +378,7 @@ int hhg_setup_mesh(const double* vxy, int32_t n_vertices, const int32_t* tri, in
 
 void hhg_destroy_mesh(hhg_mesh* mesh) {
     if (!mesh) return;
+    if (mesh->h_norm) (void)hipHostFree(mesh->h_norm);
     for (auto& ev : mesh->t_events) {
         (void)hipEventDestroy((hipEvent_t)ev.first);
         (void)hipEventDestroy((hipEvent_t)ev.second);
@@ -594,7 +613,8 @@ int hhg_solve(hhg_mesh* M, const hhg_solve_opts* o, void* u, const void* f, hhg_
     if (o->op == HHG_OP_DIFFUSION && o->mode == HHG_MODE_MP_IR && !M->kap32[L])
         return fail(HHG_EINVAL, "FP32 coefficient missing");
     hipStream_t s = (hipStream_t)stream;
-    double* dnorm = M->dscalars;
+    if ((rc = solve_norm_slot(M))) return rc;
+    double* dnorm = M->h_norm_dev;
     const int64_t nL = M->m.lv[L].total;
     const bool mp = o->mode != HHG_MODE_PLAIN_FP64;
     // Plain: u in place, norm-only residuals.  Mixed precision: the fused
@@ -609,7 +629,7 @@ int hhg_solve(hhg_mesh* M, const hhg_solve_opts* o, void* u, const void* f, hhg_
         if (mp) HIP_CHECK(launch_mp_step(M, L, o->op, cur, nullptr, (const double*)f, nullptr, r32, dnorm, s),
                           "residual");
         else HIP_CHECK(launch_residual(M, L, o->op, HHG_F64, cur, f, nullptr, dnorm, s), "residual");
-        return read_scalar(dnorm, out, s);
+        return read_norm_slot(M, out, s);
     };
     auto finish = [&](int status) -> int {
         if (cur != (double*)u)
@@ -642,12 +662,12 @@ int hhg_solve(hhg_mesh* M, const hhg_solve_opts* o, void* u, const void* f, hhg_
         if (!mp) {
             if ((rc = vcycle_rec(M, L, o->op, HHG_SMOOTH_GS, HHG_F64, u, f, o->nu1, o->nu2, s, dnorm)))
                 return rc;
-            if ((rc = read_scalar(dnorm, &rn, s))) return rc;
+            if ((rc = read_norm_slot(M, &rn, s))) return rc;
         } else {
             HIP_CHECK(launch_fill(e32, nL, HHG_F32, 0.0, s), "fill");
             if ((rc = vcycle_rec(M, L, o->op, smoother, HHG_F32, e32, r32, o->nu1, o->nu2, s))) return rc;
             HIP_CHECK(launch_mp_step(M, L, o->op, cur, e32, (const double*)f, alt, r32, dnorm, s), "update");
-            if ((rc = read_scalar(dnorm, &rn, s))) return rc;
+            if ((rc = read_norm_slot(M, &rn, s))) return rc;
             if (learned && !(rn <= prev)) {
                 // learned smoother guard: the cycle did not lower the residual
                 // (or made it non-finite): keep the previous iterate, rebuild

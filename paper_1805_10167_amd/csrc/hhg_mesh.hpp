@@ -119,6 +119,11 @@ struct hhg_mesh {
     double* partials = nullptr;   // reduction partial sums
     int64_t n_partials = 0;
     double* dscalars = nullptr;   // small device scalars (norms, dots)
+    // the solve loop's residual norm: pinned host memory mapped into the
+    // device address space, written by the reduction kernel itself, so that
+    // reading it needs no copy after the stream synchronisation
+    double* h_norm = nullptr;
+    double* h_norm_dev = nullptr;
     // timing of finest-level face smoother launches
     bool timing = false;
     int64_t t_launches = 0;
