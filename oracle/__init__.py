@@ -12,11 +12,12 @@ path computes:
   mesh.py       macro mesh -> refined levels, canonical numbering (paper
                 sec. 2.1, 3.1, 3.2)
   assemble.py   P1 stiffness / mass matrices from element matrices (sec. 4.1,
-                4.2: a stencil is a row of the stiffness matrix)
+                4.2: a stencil is a row of the stiffness matrix), injection
+                of the coefficient, and one-row-at-a-time evaluation
+                (rows_at) for sampled checks at full size
   mg.py         staged multicolour Gauss-Seidel, residual, restriction,
                 prolongation, Jacobi-PCG coarse solve, V-cycle, solve loop
                 (sec. 4.3)
-  pointwise.py  one-row-at-a-time evaluation for sampled checks at full size
   net.py        the learned smoother's forward/backward (not in the paper)
 
 Parity status of each function is stated in its docstring; functions with no
