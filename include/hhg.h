@@ -24,7 +24,10 @@
  *     The caller owns every device buffer (fields and the workspace) and
  *     every stream; the library only borrows device pointers, which must stay
  *     valid until the work enqueued on the stream has finished.  The library
- *     never allocates or frees device memory.
+ *     never allocates or frees device memory.  Its one host-side
+ *     allocation besides the mesh object is a 64-byte pinned, device-mapped
+ *     slot for the solve loop's residual norm, made by the first
+ *     hhg_bind_workspace and freed by hhg_destroy_mesh.
  *   - Streams: `stream` is a hipStream_t (NULL = the default stream).  Calls
  *     enqueue work and return, except hhg_solve, which synchronises the
  *     stream once per iteration to read an 8-byte residual norm.
@@ -233,8 +236,10 @@ int hhg_vcycle(const hhg_mesh* mesh, int32_t level, int32_t op,
  * Solve A u = f on the finest level to a relative residual opts->rtol
  * (sec. 4.3: multigrid as a solver).  u, f are FP64 fields; u holds the
  * initial guess and the Dirichlet values.  Modes: plain FP64 V-cycles;
- * mixed-precision iterative refinement (FP64 residual and update, FP32
- * V-cycle on the correction, FP64 coarse CG); learned smoother inside the
+ * mixed-precision iterative refinement (not in the paper: FP64 residual and
+ * update, FP32 V-cycle on the correction whose coarse level is solved in
+ * FP64, like hhg_vcycle's, through the stored inverse with one refinement
+ * step, or Jacobi-PCG above 2048 unknowns); learned smoother inside the
  * mixed-precision loop with Gauss-Seidel fallback: the learned smoother runs
  * only if a network is loaded and marked accepted, and a learned cycle that
  * does not lower the residual (or makes it non-finite) is undone (the
@@ -296,8 +301,9 @@ int hhg_prolong_add(const hhg_mesh* mesh, int32_t level, int32_t dtype,
 /*
  * Whole-field precision change dst = (dst_dtype) src on `level` (FP64 to
  * FP32 rounds to nearest even; FP32 to FP64 is exact), the conversion the
- * mixed-precision refinement loop applies to residuals and corrections
- * (sec. 5: FP32 inner cycles under FP64 accuracy).  Only F64 <-> F32;
+ * mixed-precision refinement loop applies to residuals and corrections.
+ * Not in the paper, which uses one precision throughout: it belongs to the
+ * mixed-precision variant layered on the method.  Only F64 <-> F32;
  * src and dst must not overlap.
  */
 int hhg_convert(const hhg_mesh* mesh, int32_t level, int32_t src_dtype,

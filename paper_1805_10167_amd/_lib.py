@@ -81,6 +81,10 @@ def lib():
     if _lib is None:
         if not os.path.exists(LIB_PATH):
             raise ImportError("libhhg.so is not built; run `python -m paper_1805_10167_amd.build`")
+        # torch first: its HIP runtime then satisfies the library's dependency,
+        # so both share one runtime (loaded the other way round, torch would
+        # bring a second copy, and the library's copy would see no device)
+        import torch  # noqa: F401
         L = _c.CDLL(LIB_PATH)
         for name, (res, args) in _SIGS.items():
             fn = getattr(L, name)

@@ -284,13 +284,14 @@ int vcycle_rec(const hhg_mesh* M, int level, int op, int smoother, int dt, void*
     return HHG_OK;
 }
 
-// The solve loop's norm slot (allocated on first use, kept until the mesh is
-// destroyed).
+// The solve loop's norm slot: 64 bytes of pinned, coherent host memory
+// mapped into the device address space, allocated when the first workspace
+// is bound and kept until the mesh is destroyed.
 static int solve_norm_slot(hhg_mesh* M) {
     if (M->h_norm) return HHG_OK;
     void* h = nullptr;
     void* d = nullptr;
-    HIP_CHECK(hipHostMalloc(&h, 64, hipHostMallocMapped), "pinned norm slot");
+    HIP_CHECK(hipHostMalloc(&h, 64, hipHostMallocMapped | hipHostMallocCoherent), "pinned norm slot");
     if (hipHostGetDevicePointer(&d, h, 0) != hipSuccess) {
         (void)hipHostFree(h);
         return fail(HHG_EHIP, "pinned norm slot has no device address");
@@ -411,6 +412,7 @@ int hhg_bind_workspace(hhg_mesh* M, uint32_t features, void* dptr, size_t bytes,
     // zero once, so that entries no kernel writes (row and block padding)
     // hold zeros in every workspace field, whatever the memory held before
     HIP_CHECK(hipMemsetAsync(dptr, 0, need, s), "workspace clear");
+    if ((rc = solve_norm_slot(M))) return rc;
     Carver c(dptr);
     carve(M, features, c);
     MeshData& m = M->m;
@@ -613,7 +615,7 @@ int hhg_solve(hhg_mesh* M, const hhg_solve_opts* o, void* u, const void* f, hhg_
     if (o->op == HHG_OP_DIFFUSION && o->mode == HHG_MODE_MP_IR && !M->kap32[L])
         return fail(HHG_EINVAL, "FP32 coefficient missing");
     hipStream_t s = (hipStream_t)stream;
-    if ((rc = solve_norm_slot(M))) return rc;
+    if (!M->h_norm) return fail(HHG_ENOMEM, "no norm slot: bind a workspace first");
     double* dnorm = M->h_norm_dev;
     const int64_t nL = M->m.lv[L].total;
     const bool mp = o->mode != HHG_MODE_PLAIN_FP64;
