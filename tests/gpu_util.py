@@ -8,6 +8,17 @@ import numpy as np
 import hhg_inputs as hi
 
 
+# Bounds of the reduced-precision paths against the FP64 oracle (relative,
+# max norm).  FP32 V-cycle on FP32-representable inputs: unit roundoff 6e-8
+# times a growth factor of about 30 (7-term stencil sums, rounding damped by
+# the smoother rather than accumulated over the sweeps).  Mixed-precision
+# refinement to a relative residual of 1e-8: the final error against an
+# oracle solve to 1e-12 is the algebraic error of that residual, of order
+# 1e-8 times the error-to-residual ratio of a few, so 1e-7.
+F32_VCYCLE_TOL = 2e-6
+MP_TOL = 1e-7
+
+
 def rel_err(a, b):
     """max |a - b| / max |b| (b = oracle)."""
     a = np.asarray(a, dtype=np.float64)

@@ -1,0 +1,125 @@
+"""Element-wise parity at level 9 of the 64-face annulus (8.4M unknowns), the
+largest size the oracle runs in seconds.  With 513 points along a macro-edge
+each face holds three columns of smoother tiles and up to 22 tile rows, and
+many tiles lie clear of every macro-edge, as at the benchmark's level 10.
+The calls here run every variant of the fused face sweep on such tiles: the
+plain sweep (forward and backward), the sweep that restricts its residual,
+the one that starts from the prolongated correction, and, inside the solve
+loop, the one that forms the residual norm.
+
+FP64: 1e-12 relative in the max norm.  FP32 V-cycle on FP32-representable
+inputs: 2e-6 against the FP64 oracle (unit roundoff 6e-8 times a growth
+factor of about 30 for the 7-term stencil sums over a few sweeps, which the
+smoother damps rather than accumulates)."""
+import numpy as np
+import pytest
+
+import hhg_inputs as hi
+from gpu_util import log, rel_err, to_np
+
+pytestmark = pytest.mark.gpu
+
+L = 9
+NAME = "annulus64"
+F64_TOL = 1e-12
+_CACHE = {}
+
+
+def setup(op):
+    """(library mesh, oracle hierarchy) for the Laplacian or for a variable
+    coefficient k = exp(g), g a 64-feature random Fourier field (seed 7)."""
+    import torch
+
+    import paper_1805_10167_amd as P
+    from oracle.mesh import Level, MacroMesh
+    from oracle.mg import Hierarchy
+    if op not in _CACHE:
+        vxy, tri = hi.mesh_by_name(NAME)
+        m = MacroMesh(vxy, tri)
+        kap = None
+        if op == "diffusion":
+            kap = np.exp(hi.grf_eval(Level(m, L).xy, 7, m=64))
+        log("level-9 oracle hierarchy (%s)" % op)
+        H = Hierarchy(m, L, 2, kap)
+        feats = P.HHG_FEAT_F64 | P.HHG_FEAT_MP | (P.HHG_FEAT_VARK if kap is not None else 0)
+        g = P.Mesh(vxy, tri, L, 2, feats)
+        if kap is not None:
+            P.hhg_set_coefficient(g.h, torch.tensor(kap, dtype=torch.float64, device="cuda"))
+        _CACHE[op] = (g, H)
+    return _CACHE[op]
+
+
+def _op(P, op):
+    return P.HHG_OP_LAPLACE if op == "laplace" else P.HHG_OP_DIFFUSION
+
+
+@pytest.mark.parametrize("backward,sweeps", [(0, 1), (1, 2)])
+def test_smooth_level9(backward, sweeps):
+    import paper_1805_10167_amd as P
+    log("smooth L=9 bwd=%d sweeps=%d" % (backward, sweeps))
+    g, H = setup("laplace")
+    lv = H.levels[L]
+    u, f = hi.uniform_vector(lv.n_all, 3), hi.uniform_vector(lv.n_all, 4)
+    uf, ff = g.from_canonical(L, u), g.from_canonical(L, f)
+    P.hhg_smooth(g.h, L, P.HHG_OP_LAPLACE, P.HHG_SMOOTH_GS, P.HHG_F64, uf, ff, sweeps, backward)
+    ug = to_np(g.to_canonical(L, uf))
+    err = rel_err(ug, H.smooth(L, u.copy(), f, sweeps, backward=bool(backward)))
+    log("  rel err %.2e" % err)
+    assert err <= F64_TOL
+
+
+@pytest.mark.parametrize("op", ["laplace", "diffusion"])
+def test_vcycle_level9(op):
+    import paper_1805_10167_amd as P
+    log("vcycle L=9 %s" % op)
+    g, H = setup(op)
+    lv = H.levels[L]
+    u, f = hi.uniform_vector(lv.n_all, 5), hi.uniform_vector(lv.n_all, 6)
+    uf, ff = g.from_canonical(L, u), g.from_canonical(L, f)
+    P.hhg_vcycle(g.h, L, _op(P, op), P.HHG_SMOOTH_GS, P.HHG_F64, uf, ff, 3, 3)
+    ug = to_np(g.to_canonical(L, uf))
+    err = rel_err(ug, H.vcycle(L, u.copy(), f, 3, 3))
+    log("  rel err %.2e" % err)
+    assert err <= F64_TOL
+    assert np.array_equal(ug[lv.dirichlet], u[lv.dirichlet])
+
+
+@pytest.mark.parametrize("cycles", [1, 2])
+def test_solve_loop_level9(cycles):
+    """Cycles of the solve loop, whose last post-smoothing sweep forms the
+    residual norm on the tiles: the residual history and the iterate against
+    the oracle's V-cycles and norms.  After one cycle the iterate is held to
+    1e-12.  From the second cycle on, the residual that drives the cycle is
+    f - A u with |A u| near |f|: the rounding of either side's summation
+    order (relative 1e-16 of |A u|) is a larger part of it, and the cycle
+    carries it into the iterate scaled by the condition number of the
+    correction (about 4^9 here), so the second iterate is held to 1e-10 and
+    the norms, which the cancellation does not reach, to 1e-12."""
+    import paper_1805_10167_amd as P
+    log("solve loop L=9 cycles=%d" % cycles)
+    g, H = setup("laplace")
+    lv = H.levels[L]
+    f = hi.uniform_rhs(lv.n_all, 1)
+    u0 = np.zeros(lv.n_all)
+    uf, ff = g.from_canonical(L, u0), g.from_canonical(L, f)
+    rc, st, hist = P.hhg_solve(g.h, uf, ff, rtol=1e-30, max_iters=cycles)
+    assert rc == P.HHG_ENOTCONV and st["iters"] == cycles
+    uo, ho = H.solve(u0.copy(), f, 1e-30, 3, 3, max_iters=cycles)
+    err = rel_err(to_np(g.to_canonical(L, uf)), uo)
+    log("  history %s vs %s, iterate rel err %.2e" % (np.asarray(hist), np.asarray(ho), err))
+    assert rel_err(hist, ho) <= F64_TOL
+    assert err <= (F64_TOL if cycles == 1 else 1e-10)
+
+
+def test_fp32_vcycle_level9():
+    import paper_1805_10167_amd as P
+    log("fp32 vcycle L=9")
+    g, H = setup("laplace")
+    lv = H.levels[L]
+    cast = lambda x: x.astype(np.float32).astype(np.float64)   # noqa: E731
+    u, f = cast(hi.uniform_vector(lv.n_all, 5)), cast(hi.uniform_vector(lv.n_all, 6))
+    uf, ff = g.from_canonical(L, u, P.HHG_F32), g.from_canonical(L, f, P.HHG_F32)
+    P.hhg_vcycle(g.h, L, P.HHG_OP_LAPLACE, P.HHG_SMOOTH_GS, P.HHG_F32, uf, ff, 3, 3)
+    err = rel_err(to_np(g.to_canonical(L, uf, P.HHG_F32)), H.vcycle(L, u.copy(), f, 3, 3))
+    log("  rel err %.2e" % err)
+    assert err <= 2e-6

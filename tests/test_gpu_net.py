@@ -190,3 +190,44 @@ def test_learned_solve_rejection_and_guard():
                                rtol=1e-8, max_iters=200)
     log("bad-net solve: iters %d fallback %d" % (st["iters"], st["fallback"]))
     assert rc == 0 and st["fallback"] == 1 and st["rel_res"] <= 1e-8
+
+
+@pytest.mark.parametrize("name,L", CASES)
+@pytest.mark.parametrize("precision", ["f32", "bf16"])
+@pytest.mark.parametrize("backward", [0, 1])
+def test_net_smoother_with_random_weights(name, L, precision, backward):
+    """The production learned sweep (hhg_smooth with HHG_SMOOTH_NET: edge
+    and vertex stages, the fused face step that forms rho = D^-1 (f - A u)
+    in its tile, runs the network and adds its output) against the oracle's
+    net_smooth, with seeded random weights on all 7 taps of all 16 channels,
+    so every tap offset, channel and the rho ring reach the output.  FP32
+    arithmetic of the same kernels: 1e-5; BF16 MFMA operands: the increment
+    u_new - u within 2e-2 in the 2-norm (the forward bound)."""
+    import paper_1805_10167_amd as P
+    log("net smoother random weights %s L=%d %s bwd=%d" % (name, L, precision, backward))
+    g, H = mesh_net(name, L)
+    lv = H.levels[L]
+    W1, W2 = random_weights(4, scale=0.3)
+    w32 = onet.pack(W1, W2).astype(np.float32)
+    W1r, W2r = onet.unpack(w32.astype(np.float64))
+    assert (W1r != 0).all() and (W2r != 0).all()
+    P.hhg_net_set_weights(g.h, w32)
+    P.hhg_net_set_options(g.h, P.HHG_F32 if precision == "f32" else P.HHG_BF16, 0)
+    u = hi.uniform_vector(lv.n_all, 41).astype(np.float32).astype(np.float64)
+    f = hi.uniform_vector(lv.n_all, 42).astype(np.float32).astype(np.float64)
+    uf, ff = g.from_canonical(L, u, P.HHG_F32), g.from_canonical(L, f, P.HHG_F32)
+    P.hhg_smooth(g.h, L, P.HHG_OP_DIFFUSION, P.HHG_SMOOTH_NET, P.HHG_F32, uf, ff, 1, backward)
+    got = to_np(g.to_canonical(L, uf, P.HHG_F32))
+    ref = onet.net_smooth(H, L, u.copy(), f, W1r, W2r, 1, bool(backward))
+    inc = rel2(got - u, ref - u)
+    log("  max rel %.2e  increment rel2 %.2e" % (rel_err(got, ref), inc))
+    if precision == "f32":
+        assert rel_err(got, ref) <= 1e-5 and inc <= 1e-5
+    else:
+        assert inc <= 2e-2
+    assert np.array_equal(got[lv.dirichlet], u[lv.dirichlet])
+    # copies are consistent: the library's operator on the result equals the
+    # oracle's operator on its canonical values
+    y = g.field(L, P.HHG_F32)
+    P.hhg_apply(g.h, L, P.HHG_OP_DIFFUSION, P.HHG_F32, uf, y)
+    assert rel_err(to_np(g.to_canonical(L, y, P.HHG_F32)), H.apply(L, got)) <= 2e-5
