@@ -22,12 +22,20 @@ import os
 from collections import defaultdict
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-KERNEL_SOURCE = os.path.join(HERE, "csrc", "kernels.hip")
+CSRC = os.path.join(HERE, "csrc")
+HEADERS = ["hhg_internal.hpp", "hhg_kernels.hpp", "hhg_mesh.hpp"]
+# the files a profiled kernel is built from, by the source file holding it
+SOURCES = {"kernels.hip": ["kernels.hip"] + HEADERS, "net.hip": ["net.hip"] + HEADERS}
 COPY_KERNEL = "__amd_rocclr_copyBuffer"
 
 
-def source_hash():
-    return hashlib.sha256(open(KERNEL_SOURCE, "rb").read()).hexdigest()[:16]
+def source_hash(files=("kernels.hip",)):
+    """Hash of the given csrc files (the kernel's source and its headers)."""
+    h = hashlib.sha256()
+    for name in files:
+        h.update(name.encode())
+        h.update(open(os.path.join(CSRC, name), "rb").read())
+    return h.hexdigest()[:16]
 
 
 def _csv(d, suffix):
@@ -61,7 +69,7 @@ def _largest(d, name):
     return max(keys, key=lambda k: k[1])
 
 
-def summarize(stats_dir, fetch_dir, write_dir, kernel, copy_bytes, cmd):
+def summarize(stats_dir, fetch_dir, write_dir, kernel, copy_bytes, cmd, source="kernels.hip"):
     dur = kernel_durations(stats_dir)
     fetch = counter_values(fetch_dir)
     write = counter_values(write_dir)
@@ -79,7 +87,8 @@ def summarize(stats_dir, fetch_dir, write_dir, kernel, copy_bytes, cmd):
         "avg_duration_us": mean(dur[kd]) / 1e3,
         "fetch_bytes": fetch_b, "write_bytes": write_b, "traffic_bytes": fetch_b + write_b,
         "fetch_scale": fetch_scale, "write_scale": write_scale,
-        "copy_bytes": copy_bytes, "source_hash": source_hash(), "command": cmd,
+        "copy_bytes": copy_bytes, "source_files": SOURCES[source],
+        "source_hash": source_hash(SOURCES[source]), "command": cmd,
         "top_kernels_us": [[k[0].split("(")[0][:80], k[1], len(v), sum(v) / 1e3, mean(v) / 1e3]
                            for k, v in top],
     }
@@ -87,7 +96,8 @@ def summarize(stats_dir, fetch_dir, write_dir, kernel, copy_bytes, cmd):
 
 def write_summary(s, path):
     lines = ["# rocprofv3 summary: %s (grid %d)" % (s["kernel"], s["grid"]), "",
-             "command: %s" % s["command"], "kernel source hash: %s" % s["source_hash"], "",
+             "command: %s" % s["command"],
+             "kernel source hash: %s (%s)" % (s["source_hash"], ", ".join(s["source_files"])), "",
              "average duration: %.2f us over %d dispatches" % (s["avg_duration_us"], s["dispatches"]),
              "HBM fetch: %.1f MB, write: %.1f MB per dispatch" % (s["fetch_bytes"] / 1e6,
                                                                  s["write_bytes"] / 1e6),
@@ -108,7 +118,8 @@ def traffic_for(path):
     for line in open(path):
         if line.startswith("json: "):
             s = json.loads(line[6:])
-            return s["traffic_bytes"] if s.get("source_hash") == source_hash() else None
+            files = s.get("source_files", ["kernels.hip"])
+            return s["traffic_bytes"] if s.get("source_hash") == source_hash(files) else None
     return None
 
 
@@ -120,7 +131,7 @@ def counter_table(pmc_dir):
     return out
 
 
-def counters_summary(stats_dir, pmc_dirs, kernel, cmd, out):
+def counters_summary(stats_dir, pmc_dirs, kernel, cmd, out, source="net.hip"):
     """Average duration and counters of the largest-grid dispatches of
     `kernel`; MFMA operation counters (units of 512 flops) are turned into
     achieved matrix-core TFLOP/s."""
@@ -134,14 +145,14 @@ def counters_summary(stats_dir, pmc_dirs, kernel, cmd, out):
         for name, v in tab[kk].items():
             vals[name] = sum(v) / len(v)
     lines = ["# rocprofv3 counters: %s (grid %d)" % (kd[0], kd[1]), "",
-             "command: " + cmd, "kernel source hash: " + source_hash(), "",
+             "command: " + cmd, "kernel source hash: " + source_hash(SOURCES[source]), "",
              "average duration: %.2f us over %d dispatches" % (avg_ns / 1e3, len(dur[kd])), "",
              "counters (average per dispatch):"]
     for name in sorted(vals):
         lines.append("  %-34s %.4g" % (name, vals[name]))
     mops = [v for n, v in vals.items() if n.startswith("SQ_INSTS_VALU_MFMA_MOPS_")]
     rec = {"kernel": kd[0], "grid": kd[1], "avg_duration_us": avg_ns / 1e3, "counters": vals,
-           "command": cmd, "source_hash": source_hash()}
+           "command": cmd, "source_files": SOURCES[source], "source_hash": source_hash(SOURCES[source])}
     if mops:
         flops = 512.0 * sum(mops)
         rec["mfma_flops"] = flops
@@ -163,13 +174,15 @@ def main():
     ap.add_argument("--kernel", required=True)
     ap.add_argument("--copy-bytes", type=int, default=0)
     ap.add_argument("--cmd", default="")
+    ap.add_argument("--source", default=None, help="csrc file holding the kernel")
     ap.add_argument("--out", required=True)
     a = ap.parse_args()
     if a.mode == "summarize":
-        s = summarize(a.stats, a.fetch, a.write, a.kernel, a.copy_bytes, a.cmd)
+        s = summarize(a.stats, a.fetch, a.write, a.kernel, a.copy_bytes, a.cmd,
+                      a.source or "kernels.hip")
         write_summary(s, a.out)
     else:
-        counters_summary(a.stats, a.pmc, a.kernel, a.cmd, a.out)
+        counters_summary(a.stats, a.pmc, a.kernel, a.cmd, a.out, a.source or "net.hip")
     print(open(a.out).read())
 
 
