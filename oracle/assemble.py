@@ -40,8 +40,17 @@ def micro_triangles(lv):
     return t
 
 
-def element_matrices(xy, tris, kappa=None):
-    """Stiffness and mass element matrices, shape [T, 3, 3] each."""
+def micro_triangle_faces(lv):
+    """Macro-face of each micro-triangle, in the order of micro_triangles."""
+    n = lv.n
+    per_face = (n - 1) * n // 2 + (n - 2) * (n - 1) // 2     # up + down = (n - 1)^2
+    return np.repeat(np.arange(len(lv.loc)), per_face)
+
+
+def element_matrices(xy, tris, kappa=None, elem_coef=None):
+    """Stiffness and mass element matrices, shape [T, 3, 3] each.  kappa:
+    nodal coefficient (vertex mean per triangle); elem_coef: an extra factor
+    per triangle (a coefficient constant on each macro-face)."""
     p = xy[tris]                       # [T, 3, 2]
     x, y = p[..., 0], p[..., 1]
     # b_a = y_{a+1} - y_{a+2}, c_a = x_{a+2} - x_{a+1}; grad phi_a = (b_a, c_a)/(2|T|)
@@ -53,15 +62,20 @@ def element_matrices(xy, tris, kappa=None):
     if kappa is not None:
         kbar = kappa[tris].mean(axis=1)
         K = K * kbar[:, None, None]
+    if elem_coef is not None:
+        K = K * np.asarray(elem_coef, dtype=np.float64)[:, None, None]
     M = (area / 12.0)[:, None, None] * (np.ones((3, 3)) + np.eye(3))[None]
     return K, M
 
 
-def assemble(lv, kappa=None, want=("A", "M")):
+def assemble(lv, kappa=None, want=("A", "M"), face_coef=None):
     """Global (Neumann, i.e. before any boundary treatment) stiffness A and
-    mass M as CSR matrices over all canonical points."""
+    mass M as CSR matrices over all canonical points.  face_coef[F]: a
+    coefficient constant on each macro-face multiplying the stiffness,
+    -div(face_coef grad u) (with kappa: -div(face_coef kappa grad u))."""
     tris = micro_triangles(lv)
-    K, M = element_matrices(lv.xy, tris, kappa)
+    ec = None if face_coef is None else np.asarray(face_coef, dtype=np.float64)[micro_triangle_faces(lv)]
+    K, M = element_matrices(lv.xy, tris, kappa, ec)
     rows = np.repeat(tris, 3, axis=1).ravel()
     cols = np.tile(tris, (1, 3)).ravel()
     out = {}

@@ -133,9 +133,11 @@ class Hierarchy:
 
     op: "laplace" (k = 1) or "diffusion" (nodal k at the finest level,
     injected to coarser levels).  coarse: "direct" or "pcg" (sec. 4.3 allows
-    either on the coarse grid)."""
+    either on the coarse grid).  face_coef[F]: a coefficient constant on each
+    macro-face multiplying the stiffness on every level (the same on all
+    levels, so the coarse operators stay the Galerkin products)."""
 
-    def __init__(self, mesh, L, lc=2, kappa_fine=None, coarse="direct"):
+    def __init__(self, mesh, L, lc=2, kappa_fine=None, coarse="direct", face_coef=None):
         self.mesh = mesh
         self.L = L
         self.lc = lc
@@ -154,7 +156,7 @@ class Hierarchy:
         self.stages = {}
         self.diag = {}
         for l, lv in self.levels.items():
-            mats = assemble(lv, self.kappa.get(l))
+            mats = assemble(lv, self.kappa.get(l), face_coef=face_coef)
             self.A[l] = mats["A"]
             self.M[l] = mats["M"]
             self.diag[l] = self.A[l].diagonal()
