@@ -70,7 +70,8 @@ __device__ __forceinline__ int64_t nedge_ghost(const LevelDev& L, int e, int s) 
 template <bool MFMA>
 __device__ __forceinline__ void net_hidden(int n, int i0, int j0, const float* __restrict__ W,
                                            float (*rs)[RW], float (*zs)[NZR][RW]) {
-    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int lane = threadIdx.x & 63;
+    const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     if (MFMA) {
         const int q4 = lane >> 4, l16 = lane & 15;
         float a1[4], a2[4];
@@ -138,6 +139,39 @@ __device__ __forceinline__ void net_hidden(int n, int i0, int j0, const float* _
     }
 }
 
+// Per-tile constants of the face: FP32 cotangents (and the constant-k
+// centre weight), and for each side the start of the ghost row that holds
+// copies of the face's near-side row (-1 on a Dirichlet side) with its
+// direction.  Loaded once per tile, outside divergent code.
+struct NetFace {
+    float c0, c1, c2, wc;
+    int64_t g[3];
+    int rev[3];
+};
+__device__ __forceinline__ NetFace net_face(const LevelDev& L, const FaceInfo& fi) {
+    NetFace t;
+    t.c0 = (float)fi.cot[0];
+    t.c1 = (float)fi.cot[1];
+    t.c2 = (float)fi.cot[2];
+    t.wc = (float)(2.0 * (fi.cot[0] + fi.cot[1] + fi.cot[2]));
+#pragma unroll
+    for (int s = 0; s < 3; ++s) {
+        t.g[s] = fi.bside[s] ? -1 : nedge_ghost(L, fi.edge[s], fi.slot[s]);
+        t.rev[s] = fi.rev[s];
+    }
+    return t;
+}
+
+// Store of an output value with its copies in the ghost rows of the face's
+// edges (near-side rows j = 1, i = 1, i + j = n - 2).
+__device__ __forceinline__ void net_store(float* __restrict__ y, const NetFace& nf, int64_t p, int n, int i,
+                                          int j, float val) {
+    y[p] = val;
+    if (j == 1 && i <= n - 2 && nf.g[0] >= 0) y[nf.g[0] + (nf.rev[0] ? n - 2 - i : i)] = val;
+    if (i == 1 && j <= n - 2 && nf.g[1] >= 0) y[nf.g[1] + (nf.rev[1] ? n - 2 - j : j)] = val;
+    if (i + j == n - 2 && nf.g[2] >= 0) y[nf.g[2] + (nf.rev[2] ? n - 2 - j : j)] = val;
+}
+
 // out at output pixel (i0 + c, j0 + r) from the z planes.
 __device__ __forceinline__ float net_out(float (*zs)[NZR][RW], int r, int c) {
     float o = 0.f;
@@ -161,28 +195,30 @@ __global__ __launch_bounds__(NET_NT) void k_net_forward(LevelDev L, const T* __r
     __shared__ float rs[NRR + 1][RW];
     __shared__ float zs[7][NZR][RW];
     const int n = L.n;
-    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int lane = threadIdx.x & 63, wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int ntile = L.F * L.n_net_tiles;
     for (int tile = blockIdx.x; tile < ntile; tile += gridDim.x) {
     __syncthreads();                                   // LDS of the previous tile is free
     const int face = tile / L.n_net_tiles;
     const int2 tl = L.net_tiles[tile % L.n_net_tiles];
     const int i0 = tl.x * NET_TI, j0 = tl.y * NET_TJ;
-    const FaceInfo& fi = L.faces[face];
+    const NetFace nf = net_face(L, L.faces[face]);
     const int64_t fb = nface_base(L, face);
     float v[NLR];
 #pragma unroll
     for (int k = 0; k < NLR; ++k) {
         const int r = wv + NWV * k, j = j0 - 2 + r, i = i0 - 2 + lane;
-        const bool in = r < NRR && lane < NRW && j >= 0 && j < n && i >= 0 && i <= n - 1 - j;
-        v[k] = in ? (float)rho[fb + nrow_start(n, in ? j : 0) + i] : 0.f;
+        const bool row_ok = r < NRR && j >= 0 && j < n;
+        const bool in = row_ok && lane < NRW && i >= 0 && i <= n - 1 - j;
+        v[k] = in ? (float)rho[fb + nrow_start(n, row_ok ? j : 0) + i] : 0.f;
     }
     float yo[NOR];
 #pragma unroll
     for (int k = 0; k < NOR; ++k) {
         const int r = wv + NWV * k, j = j0 + r, i = i0 + lane;
-        const bool ok = r < NET_TJ && lane < NET_TI && j >= 1 && i >= 1 && i + j <= n - 2;
-        yo[k] = (ok && mode == 1) ? (float)y[fb + nrow_start(n, ok ? j : 0) + i] : 0.f;
+        const bool row_ok = r < NET_TJ && j >= 1;
+        const bool ok = row_ok && lane < NET_TI && i >= 1 && i + j <= n - 2;
+        yo[k] = (ok && mode == 1) ? (float)y[fb + nrow_start(n, row_ok ? j : 0) + i] : 0.f;
     }
 #pragma unroll
     for (int k = 0; k < NLR; ++k) {
@@ -198,13 +234,11 @@ __global__ __launch_bounds__(NET_NT) void k_net_forward(LevelDev L, const T* __r
         const int r = wv + NWV * k, j = j0 + r, i = i0 + lane;
         if (!(r < NET_TJ && lane < NET_TI && j >= 1 && i >= 1 && i + j <= n - 2)) continue;
         const T val = (T)(yo[k] + net_out(zs, r, lane));
-        y[fb + nrow_start(n, j) + i] = val;
-        if (j == 1 && i <= n - 2 && !fi.bside[0])
-            y[nedge_ghost(L, fi.edge[0], fi.slot[0]) + (fi.rev[0] ? n - 2 - i : i)] = val;
-        if (i == 1 && j <= n - 2 && !fi.bside[1])
-            y[nedge_ghost(L, fi.edge[1], fi.slot[1]) + (fi.rev[1] ? n - 2 - j : j)] = val;
-        if (i + j == n - 2 && !fi.bside[2])
-            y[nedge_ghost(L, fi.edge[2], fi.slot[2]) + (fi.rev[2] ? n - 2 - j : j)] = val;
+        const int64_t p = fb + nrow_start(n, j) + i;
+        y[p] = val;
+        if (j == 1 && i <= n - 2 && nf.g[0] >= 0) y[nf.g[0] + (nf.rev[0] ? n - 2 - i : i)] = val;
+        if (i == 1 && j <= n - 2 && nf.g[1] >= 0) y[nf.g[1] + (nf.rev[1] ? n - 2 - j : j)] = val;
+        if (i + j == n - 2 && nf.g[2] >= 0) y[nf.g[2] + (nf.rev[2] ? n - 2 - j : j)] = val;
     }
     }
 }
@@ -223,14 +257,14 @@ constexpr int NS_COPY_BLOCKS = 32;
 constexpr int NXL = (NXR + NWV - 1) / NWV;      // x rows per wave
 
 template <bool VARK>
-__device__ __forceinline__ float net_rho_point(const FaceInfo& fi, float (*xs)[RW], float (*ks)[RW],
+__device__ __forceinline__ float net_rho_point(const NetFace& nf, float (*xs)[RW], float (*ks)[RW],
                                                int r, int c, float fv) {
     const float uE = xs[r][c + 1], uW = xs[r][c - 1], uN = xs[r + 1][c], uS = xs[r - 1][c];
     const float uSE = xs[r - 1][c + 1], uNW = xs[r + 1][c - 1], u0 = xs[r][c];
-    const float c0 = (float)fi.cot[0], c1 = (float)fi.cot[1], c2 = (float)fi.cot[2];
+    const float c0 = nf.c0, c1 = nf.c1, c2 = nf.c2;
     float we, ww, wn, ws, wse, wnw, wc;
     if (!VARK) {
-        wc = (float)(2.0 * (fi.cot[0] + fi.cot[1] + fi.cot[2]));
+        wc = nf.wc;
         we = ww = -c2;
         wn = ws = -c1;
         wse = wnw = -c0;
@@ -250,7 +284,9 @@ __device__ __forceinline__ float net_rho_point(const FaceInfo& fi, float (*xs)[R
         wc = -(we + ww + wn + ws + wse + wnw);
     }
     const float ax = wc * u0 + we * uE + ww * uW + wn * uN + ws * uS + wse * uSE + wnw * uNW;
-    return (fv - ax) / wc;
+    // FP32 Jacobi scaling by the hardware reciprocal (1 ulp): the learned
+    // step's rounding is set by its BF16 operands, far coarser
+    return (fv - ax) * __builtin_amdgcn_rcpf(wc);
 }
 
 template <bool VARK, bool MFMA>
@@ -295,22 +331,24 @@ __global__ __launch_bounds__(NET_NT) void k_net_step(LevelDev L, const float* __
         }
         return;
     }
-    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int lane = threadIdx.x & 63, wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int ntile = L.F * L.n_net_tiles;
     for (int tile = blockIdx.x; tile < ntile; tile += nblk_tiles) {
     __syncthreads();                                   // LDS of the previous tile is free
     const int face = tile / L.n_net_tiles;
     const int2 tl = L.net_tiles[tile % L.n_net_tiles];
     const int i0 = tl.x * NET_TI, j0 = tl.y * NET_TJ;
-    const FaceInfo& fi = L.faces[face];
+    const NetFace nf = net_face(L, L.faces[face]);
     const int64_t fb = nface_base(L, face);
-    // x (and k) over the tile grown by 3: row r of wave wv + NWV k, column = lane
+    // x (and k) over the tile grown by 3: row r of wave wv + NWV k, column =
+    // lane; the row (and its start) is the same for the whole wave
     float xv[NXL], kv[VARK ? NXL : 1];
 #pragma unroll
     for (int k = 0; k < NXL; ++k) {
         const int r = wv + NWV * k, j = j0 - 3 + r, i = i0 - 3 + lane;
-        const bool in = r < NXR && j >= 0 && j < n && i >= 0 && i <= n - 1 - j;
-        const int64_t p = fb + nrow_start(n, in ? j : 0) + i;
+        const bool row_ok = r < NXR && j >= 0 && j < n;
+        const bool in = row_ok && i >= 0 && i <= n - 1 - j;
+        const int64_t p = fb + nrow_start(n, row_ok ? j : 0) + i;
         xv[k] = in ? x[p] : 0.f;
         if (VARK) kv[k] = in ? kap[p] : 0.f;
     }
@@ -319,9 +357,10 @@ __global__ __launch_bounds__(NET_NT) void k_net_step(LevelDev L, const float* __
 #pragma unroll
     for (int k = 0; k < NLR; ++k) {
         const int r = wv + NWV * k, j = j0 - 2 + r, i = i0 - 2 + lane;
-        const bool in = r < NRR && lane < NRW && j >= 0 && j < n && i >= 0 && i <= n - 1 - j;
+        const bool row_ok = r < NRR && j >= 0 && j < n;
+        const bool in = row_ok && lane < NRW && i >= 0 && i <= n - 1 - j;
         const bool interior = in && j >= 1 && i >= 1 && i + j <= n - 2;
-        const int64_t p = fb + nrow_start(n, in ? j : 0) + i;
+        const int64_t p = fb + nrow_start(n, row_ok ? j : 0) + i;
         fv[k] = interior ? f[p] : (in ? rho_ring[p] : 0.f);
     }
 #pragma unroll
@@ -338,7 +377,7 @@ __global__ __launch_bounds__(NET_NT) void k_net_step(LevelDev L, const float* __
         const int r = wv + NWV * k, j = j0 - 2 + r, i = i0 - 2 + lane;
         if (r >= NRR) continue;
         const bool interior = lane < NRW && j >= 1 && i >= 1 && i + j <= n - 2;
-        rs[r][lane] = interior ? net_rho_point<VARK>(fi, xs, VARK ? ks : nullptr, r + 1, lane + 1, fv[k]) : fv[k];
+        rs[r][lane] = interior ? net_rho_point<VARK>(nf, xs, VARK ? ks : nullptr, r + 1, lane + 1, fv[k]) : fv[k];
     }
     if (wv == 0) rs[NRR][lane] = 0.f;
     __syncthreads();
@@ -349,13 +388,7 @@ __global__ __launch_bounds__(NET_NT) void k_net_step(LevelDev L, const float* __
         const int r = wv + NWV * k, j = j0 + r, i = i0 + lane;
         if (!(r < NET_TJ && lane < NET_TI && j >= 1 && i >= 1 && i + j <= n - 2)) continue;
         const float val = xs[r + 3][lane + 3] + net_out(zs, r, lane);
-        y[fb + nrow_start(n, j) + i] = val;
-        if (j == 1 && i <= n - 2 && !fi.bside[0])
-            y[nedge_ghost(L, fi.edge[0], fi.slot[0]) + (fi.rev[0] ? n - 2 - i : i)] = val;
-        if (i == 1 && j <= n - 2 && !fi.bside[1])
-            y[nedge_ghost(L, fi.edge[1], fi.slot[1]) + (fi.rev[1] ? n - 2 - j : j)] = val;
-        if (i + j == n - 2 && !fi.bside[2])
-            y[nedge_ghost(L, fi.edge[2], fi.slot[2]) + (fi.rev[2] ? n - 2 - j : j)] = val;
+        net_store(y, nf, fb + nrow_start(n, j) + i, n, i, j, val);
     }
     }
 }
