@@ -443,6 +443,141 @@ def large_mp_section(args, P, hi, torch):
     return out
 
 
+STOKES_DELTA = 1.0 / 12.0
+
+
+def stokes_section(args, P, hi, torch):
+    """PSPG-stabilised P1-P1 Stokes on the 128-face annulus: viscosity 1 in
+    the inner and 100 in the outer ring of faces, buoyancy forcing -T r_hat
+    with T a seeded Gaussian random field (correlation length 0.1, sigma 1),
+    velocity zero on both boundaries; MINRES with the block-diagonal
+    preconditioner (one V(2,2) cycle per velocity component, lumped 1/mu
+    pressure mass) to a relative residual of 1e-8 in the preconditioner's
+    norm, FP64 and FP32 velocity cycles.  Also the Stokes operator's rate."""
+    L = args.stokes_level
+    vxy, tri = hi.mesh_by_name("annulus128")
+    mu = hi.face_viscosity(vxy, tri)
+    g = P.Mesh(vxy, tri, L, 2, P.HHG_FEAT_F64 | P.HHG_FEAT_MP | P.HHG_FEAT_STOKES)
+    P.hhg_stokes_setup(g.h, mu, STOKES_DELTA)
+    n_int, n_all = g.n_dofs(L)
+    fs = P.hhg_field_elems(g.h, L)
+    xy = torch.tensor(g.coords(L), dtype=torch.float64, device="cuda")
+    T = hi.grf_eval_device(xy, 500)
+    rr = torch.sqrt(xy[:, 0] ** 2 + xy[:, 1] ** 2)
+    b = g.stokes_vector(L)
+    for c in range(2):
+        fc = g.from_canonical(L, -T * xy[:, c] / rr)
+        P.hhg_apply(g.h, L, P.HHG_OP_MASS, P.HHG_F64, fc, b[c * fs:(c + 1) * fs])
+    del xy, T, rr
+    x = g.stokes_vector(L)
+    out = {"workload": "P1-P1 PSPG Stokes, 128-face annulus, level %d, viscosity 1:100 jump at "
+                       "r = 0.775, buoyancy -T r_hat (GRF seed 500), zero velocity on the boundary"
+                       % L,
+           "dofs": {"velocity": 2 * n_int, "pressure": n_all, "total": 2 * n_int + n_all},
+           "solver": "MINRES, blockdiag(V(2,2) per velocity component, lumped 1/mu pressure mass), "
+                     "rtol 1e-8 in the preconditioner's norm, coarse level 2", "delta": STOKES_DELTA}
+    res = {}
+    for name, prec in (("plain_fp64", P.HHG_F64), ("fp32_precond", P.HHG_F32)):
+        ms = []
+        for rep in range(1 + args.stokes_runs):
+            x.zero_()
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            rc, st, hist = P.hhg_stokes_solve(g.h, x, b, precision=prec, rtol=1e-8, max_iters=2000,
+                                              nu1=2, nu2=2)
+            torch.cuda.synchronize()
+            if rep > 0:                          # the first run warms up
+                ms.append((time.perf_counter() - t0) * 1e3)
+            assert rc == 0, st
+        # true relative residual |b - K x| / |b| (Euclidean, owned points)
+        r = g.stokes_vector(L)
+        P.hhg_stokes_residual(g.h, L, x, b, r)
+        d = torch.zeros(2, dtype=torch.float64, device="cuda")
+        P.hhg_stokes_dot(g.h, L, r, r, d[0:1])
+        P.hhg_stokes_dot(g.h, L, b, b, d[1:2])
+        dd = d.cpu().numpy()
+        res[name] = {"time_to_tol_ms": round(statistics.median(ms), 2), "iterations": st["iters"],
+                     "ms_per_iteration": round(statistics.median(ms) / max(st["iters"], 1), 3),
+                     "rel_res_precond_norm": st["rel_res"],
+                     "rel_res_euclidean": float(math.sqrt(dd[0] / dd[1]))}
+        log("stokes %s: %d iterations, %.1f ms" % (name, st["iters"], res[name]["time_to_tol_ms"]))
+        del r
+    out["solves"] = res
+    # the Stokes operator alone: 3 fields read, 3 written per point
+    y = g.stokes_vector(L)
+    for _ in range(2):
+        P.hhg_stokes_apply(g.h, L, x, y)
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+    reps = 10
+    ev[0].record()
+    for _ in range(reps):
+        P.hhg_stokes_apply(g.h, L, x, y)
+    ev[1].record()
+    ev[1].synchronize()
+    ms = ev[0].elapsed_time(ev[1]) / reps
+    nbytes = 48.0 * n_all
+    out["stokes_apply"] = {"ms": round(ms, 4), "gdofs": round(3 * n_all / ms / 1e6, 2),
+                           "alg_bytes_per_point": 48, "hbm_frac": round(nbytes / ms / 1e6 / HBM_PEAK_GBS, 4)}
+    del g, x, y, b
+    torch.cuda.empty_cache()
+    return out
+
+
+def energy_section(args, P, hi, torch):
+    """The paper's energy-transport example at its own size: isoviscous
+    Stokes on a 256-face annulus (64 sectors x 2 rings) at level 6 (2,145
+    points per face, more than half a million unknowns), buoyancy -Ra T r_hat,
+    temperature on the micro-triangles advanced by the explicit upwind
+    scheme, a Stokes solve (MINRES, warm started) before every third
+    transport step.  T starts from the conductive profile plus a seeded
+    perturbation; dt = 0.5 h / max|u| from the first flow."""
+    L = args.energy_level
+    vxy, tri = hi.annulus(n_tan=64)
+    g = P.Mesh(vxy, tri, L, 2, P.HHG_FEAT_F64 | P.HHG_FEAT_MP | P.HHG_FEAT_STOKES)
+    P.hhg_stokes_setup(g.h, [1.0] * len(tri), STOKES_DELTA)
+    n_int, n_all = g.n_dofs(L)
+    fs = P.hhg_field_elems(g.h, L)
+    n = 2 ** L + 1
+    ncell = len(tri) * (n - 1) ** 2
+    cen = g.cell_coords(L)
+    T0 = hi.conductive_temperature(cen) + 0.05 * hi.grf_eval(cen, 600)
+    T = torch.zeros(2 * fs, dtype=torch.float64, device="cuda")
+    P.hhg_cells_from_canonical(g.h, L, torch.tensor(T0, dtype=torch.float64, device="cuda"), T)
+    x = g.stokes_vector(L)
+    Ra = args.energy_ra
+    rc, st = P.hhg_energy_run(g.h, x, T, Ra=Ra, dt=0.0, steps=1, stokes_every=3)
+    assert rc == 0, st
+    umax = torch.sqrt(x[:fs] ** 2 + x[fs:2 * fs] ** 2).max().item()
+    hmin = 0.55 * 2 * math.pi / 64 / (n - 1)
+    dt = 0.5 * hmin / umax
+    steps = args.energy_steps
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    rc, st = P.hhg_energy_run(g.h, x, T, Ra=Ra, dt=dt, steps=steps, stokes_every=3)
+    torch.cuda.synchronize()
+    wall = (time.perf_counter() - t0) * 1e3
+    assert rc == 0, st
+    # transport step alone
+    T2 = torch.empty_like(T)
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+    P.hhg_transport_step(g.h, L, x, T, T2, dt)
+    ev[0].record()
+    for _ in range(20):
+        P.hhg_transport_step(g.h, L, x, T, T2, dt)
+    ev[1].record()
+    ev[1].synchronize()
+    step_ms = ev[0].elapsed_time(ev[1]) / 20
+    Tc = torch.zeros(ncell, dtype=torch.float64, device="cuda")
+    P.hhg_cells_to_canonical(g.h, L, T, Tc)
+    return {"workload": "isoviscous P1-P1 PSPG Stokes + upwind FV temperature, 256-face annulus, level %d "
+                        "(%d faces x %d points per face), Ra %g, Stokes every 3 steps" % (L, len(tri), n * (n + 1) // 2, Ra),
+            "dofs": {"stokes": 2 * n_int + n_all, "cells": ncell},
+            "dt": dt, "steps": steps, "stokes_solves": st["stokes_solves"],
+            "minres_iters_per_solve": round(st["minres_iters"] / max(st["stokes_solves"], 1), 1),
+            "ms_per_step": round(wall / steps, 3), "transport_step_ms": round(step_ms, 4),
+            "T_range": [Tc.min().item(), Tc.max().item()]}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -469,6 +604,13 @@ def main():
     ap.add_argument("--no-kernels", action="store_true")
     ap.add_argument("--no-square", action="store_true")
     ap.add_argument("--large-level", type=int, default=11)
+    ap.add_argument("--no-stokes", action="store_true")
+    ap.add_argument("--no-energy", action="store_true")
+    ap.add_argument("--energy-level", type=int, default=6)
+    ap.add_argument("--energy-steps", type=int, default=30)
+    ap.add_argument("--energy-ra", type=float, default=1e4)
+    ap.add_argument("--stokes-level", type=int, default=9)
+    ap.add_argument("--stokes-runs", type=int, default=2)
     ap.add_argument("--copy-calibration", type=int, default=0,
                     help="bytes of a plain device copy run after the benchmark (counter scale)")
     args = ap.parse_args()
@@ -588,6 +730,12 @@ def main():
     if not args.no_large:
         log("plain vs mixed precision on the 128-face annulus")
         out["mp_large"] = large_mp_section(args, P, hi, torch)
+    if not args.no_stokes:
+        log("Stokes on the 128-face annulus")
+        out["stokes"] = stokes_section(args, P, hi, torch)
+    if not args.no_energy:
+        log("energy transport on the 256-face annulus")
+        out["energy"] = energy_section(args, P, hi, torch)
     if not args.no_square:
         log("manufactured solution on the unit square")
         out["square"] = square_section(P, hi, torch)

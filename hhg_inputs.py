@@ -68,6 +68,21 @@ def mesh_by_name(name):
     raise KeyError(name)
 
 
+def face_viscosity(vxy, tri, r_jump=0.775, mu_in=1.0, mu_out=100.0):
+    """Viscosity per macro-face with a radial jump: mu_in for faces whose
+    centroid lies inside radius r_jump, mu_out outside (on the annulus: the
+    inner and outer ring of quads, split along the jittered middle ring)."""
+    c = np.asarray(vxy)[np.asarray(tri)].mean(axis=1)
+    return np.where(np.hypot(c[:, 0], c[:, 1]) < r_jump, mu_in, mu_out)
+
+
+def conductive_temperature(xy, r_in=0.55, r_out=1.0, t_in=1.0, t_out=0.0):
+    """Initial temperature: the steady conductive profile between a hot inner
+    wall (t_in at r_in) and a cold outer wall (t_out at r_out), linear in r."""
+    r = np.hypot(np.asarray(xy)[:, 0], np.asarray(xy)[:, 1])
+    return t_out + (t_in - t_out) * (r_out - r) / (r_out - r_in)
+
+
 def uniform_rhs(n, seed):
     """n i.i.d. U[-1, 1] values from default_rng(seed), one per canonical point.
 

@@ -85,6 +85,7 @@ extern "C" {
 #define HHG_FEAT_MP   2u     /* FP32 hierarchy for mixed-precision refinement */
 #define HHG_FEAT_VARK 4u     /* per-level coefficient fields                 */
 #define HHG_FEAT_NET  8u     /* learned-smoother buffers                     */
+#define HHG_FEAT_STOKES 16u  /* Stokes stencils and MINRES vectors (needs F64) */
 
 /* solver modes */
 #define HHG_MODE_PLAIN_FP64 0
@@ -92,6 +93,26 @@ extern "C" {
 #define HHG_MODE_LEARNED    2
 
 typedef struct hhg_mesh hhg_mesh;
+
+typedef struct {
+    int32_t precision;         /* HHG_F64 or HHG_F32: arithmetic of the
+                                  preconditioner's V-cycles                   */
+    double rtol;               /* stop when the residual in the norm of the
+                                  inverse preconditioner has fallen by rtol   */
+    int32_t max_iters;         /* MINRES iteration cap                        */
+    int32_t nu1, nu2;          /* smoothing sweeps of the velocity V-cycles   */
+    double* res_history;       /* optional host buffer, entry k = residual
+                                  norm after k iterations                     */
+    int32_t history_capacity;  /* entries available in res_history           */
+} hhg_stokes_opts;
+
+typedef struct {
+    int32_t iters;             /* MINRES iterations done                      */
+    int32_t converged;         /* 1 if rtol was reached                       */
+    double res0;               /* initial residual, preconditioned norm       */
+    double rel_res;            /* final / initial preconditioned norm         */
+    double ms;                 /* host wall time of the call                  */
+} hhg_stokes_stats;
 
 typedef struct {
     int32_t mode;              /* HHG_MODE_*                                  */
@@ -341,6 +362,135 @@ int hhg_net_backward(const hhg_mesh* mesh, int32_t level, const void* rho,
                      const void* g, float* dW, void* stream);
 int hhg_net_adam_step(hhg_mesh* mesh, const float* grad, float lr, int32_t step,
                       void* stream);
+
+/*
+ * Coefficient constant on each macro-face, coef[n_faces] (host, > 0): the
+ * stiffness operator HHG_OP_LAPLACE becomes -div(coef grad u) and
+ * HHG_OP_DIFFUSION -div(coef k grad u).  The paper's stencils stay one
+ * constant stencil per primitive (sec. 4.2): every micro-triangle lies in one
+ * macro-face, so each of its stiffness weights is scaled by that face's
+ * value, also in the edge and vertex stencils that sum over several faces.
+ * The coarse levels use the same coefficient, so their operators remain the
+ * Galerkin products of the finer ones.  Coarse operators are rebuilt when a
+ * workspace is bound (synchronises the stream).  All ones restores the plain
+ * operator.  Errors: HHG_EINVAL for a value that is not positive and finite.
+ */
+int hhg_set_face_coefficient(hhg_mesh* mesh, const double* coef, void* stream);
+
+/*
+ * Equal-order P1-P1 Stokes flow with pressure stabilisation: the monolithic
+ * saddle-point system of the paper's energy-transport example (sec. 5.2:
+ * P1-P1 with a Petrov-Galerkin pressure stabilisation, velocity zero on the
+ * boundary), solved by preconditioned MINRES with multigrid as the
+ * preconditioner (sec. 4.3).  Needs a workspace bound with HHG_FEAT_STOKES
+ * (and HHG_FEAT_F64; HHG_FEAT_MP for FP32 preconditioning).
+ *
+ * Unknowns: a Stokes vector is one device array of 3 * hhg_field_elems(level)
+ * doubles, the fields u_x | u_y | p one after the other in the level layout.
+ * Velocity values at Dirichlet points are boundary data (read, never
+ * written); the pressure is an unknown at every point.  With
+ *   a(u, v) = sum_c int mu grad u_c . grad v_c,   b(v, q) = -int q div v,
+ *   c(p, q) = delta sum_T h_T^2 / mu_T int_T grad p . grad q
+ * (h_T the longest edge of micro-triangle T, mu constant per macro-face)
+ * the operator is K = [[A, 0, Bx^T], [0, A, By^T], [Bx, By, -C]], symmetric
+ * and indefinite, with the constant pressure in its kernel.
+ *
+ * hhg_stokes_setup: viscosity[n_faces] (host, > 0) and delta > 0 (the
+ *   stabilisation parameter); sets the viscosity as the face coefficient of
+ *   HHG_OP_LAPLACE (the preconditioner's velocity operator) and builds the
+ *   Stokes stencils (host P1 element assembly at the macro scale).
+ * hhg_stokes_apply: y = K x on `level`; velocity rows at Dirichlet points 0.
+ * hhg_stokes_residual: r = b - K x on `level` (same conventions).
+ * hhg_stokes_precond: z = P^-1 r on the finest level, P^-1 = blockdiag(one
+ *   V(nu1, nu2) cycle of the viscous operator from zero per velocity
+ *   component, in FP64 or FP32 (`precision`), division of the pressure by
+ *   the lumped mass matrix weighted with 1/mu).
+ * hhg_stokes_dot: *out (device double) = a . b over every owned point of
+ *   the three fields, summed in a fixed order.
+ * hhg_stokes_solve: MINRES from the caller's x (b: right-hand side, its
+ *   velocity entries at Dirichlet points ignored) until the residual in the
+ *   P^-1 norm has fallen by opts->rtol; the pressure correction keeps a zero
+ *   mean weighted with the preconditioner's pressure mass.  Synchronises the
+ *   stream once per iteration to read that norm.  HHG_ENOTCONV at the cap
+ *   (x holds the last iterate; stats are filled in every case).
+ * Errors: HHG_ENOMEM without HHG_FEAT_STOKES, HHG_EINVAL before setup or
+ * for aliased buffers.
+ */
+int hhg_stokes_setup(hhg_mesh* mesh, const double* viscosity, double delta, void* stream);
+int hhg_stokes_apply(const hhg_mesh* mesh, int32_t level, const void* x, void* y, void* stream);
+int hhg_stokes_residual(const hhg_mesh* mesh, int32_t level, const void* x, const void* b, void* r,
+                        void* stream);
+int hhg_stokes_precond(const hhg_mesh* mesh, int32_t precision, const void* r, void* z, int32_t nu1,
+                       int32_t nu2, void* stream);
+int hhg_stokes_dot(const hhg_mesh* mesh, int32_t level, const void* a, const void* b, double* out,
+                   void* stream);
+int hhg_stokes_solve(hhg_mesh* mesh, const hhg_stokes_opts* opts, void* x, const void* b,
+                     hhg_stokes_stats* stats, void* stream);
+
+/*
+ * Energy transport coupled to the Stokes flow (the paper's sec. 5.2 example:
+ * temperature advanced by an explicit upwind finite-volume scheme with the
+ * last computed velocity, the Stokes system solved only after every three
+ * transport steps, buoyancy forcing -Ra T r_hat).  Finite-volume unknowns
+ * sit on the interiors of the micro-triangles (sec. 3.1).  Needs
+ * hhg_stokes_setup (workspace with HHG_FEAT_STOKES).
+ *
+ * Cell fields: one device array of 2 * hhg_field_elems(level) doubles, the
+ * up cells {(i,j), (i+1,j), (i,j+1)} of every face at the slots of points
+ * (i, j) of the first half, the down cells {(i+1,j), (i+1,j+1), (i,j+1)} at
+ * the slots of points (i, j) of the second.  Canonical cell order: per face
+ * in input order, up cells j-major (j = 0..n-2, i = 0..n-2-j), then down
+ * cells j-major (j = 0..n-3, i = 0..n-3-j): (n-1)^2 per face.
+ *
+ * Flux through a micro-edge: |e| n . (u_a + u_b) / 2 (outward unit normal n,
+ * P1 velocity at the edge's ends: exact for the linear velocity); the two
+ * cells of an edge get exactly opposite fluxes.  Micro-edges on the domain
+ * boundary carry no flux (zero wall velocity), and there is no diffusion
+ * (the paper neglects 1/Pe), so the total heat sum |c| T_c is conserved.
+ *
+ * hhg_cell_coords: centroids of the cells in canonical order into the host
+ *   buffer xy[2 F (n-1)^2] (no workspace needed).
+ * hhg_cells_from_canonical / hhg_cells_to_canonical: layout conversion of
+ *   cell fields (canonical arrays of F (n-1)^2 doubles, device).
+ * hhg_transport_step: T_out = T_in - dt / |c| sum_e F_e T_upwind(e), with the
+ *   velocity taken from the Stokes vector x (its u_x and u_y fields).
+ * hhg_buoyancy: b (Stokes vector) = (M_T(-Ra T r_hat_x), M_T(-Ra T r_hat_y),
+ *   0): b_i = -Ra r_hat(x_i) sum_{cells c at i} T_c |c| / 3, 0 at Dirichlet
+ *   points, copies written.
+ * hhg_energy_run: opts->steps transport steps from the caller's T (cell
+ *   field, updated in place) and x (Stokes vector, the initial guess of the
+ *   first solve, the last flow on return); before steps 0, stokes_every,
+ *   2 stokes_every, ... the buoyancy of the current T is formed and the
+ *   Stokes system solved by MINRES (opts->stokes) warm started from x.
+ *   Synchronises the stream.  Returns the first MINRES failure, if any.
+ */
+typedef struct {
+    hhg_stokes_opts stokes;    /* MINRES options of every Stokes solve       */
+    double Ra;                 /* Rayleigh number of the buoyancy forcing    */
+    double dt;                 /* transport time step                        */
+    int32_t steps;             /* transport steps                            */
+    int32_t stokes_every;      /* Stokes solve before every k-th step (3)    */
+} hhg_energy_opts;
+
+typedef struct {
+    int32_t steps;             /* transport steps done                       */
+    int32_t stokes_solves;     /* Stokes solves done                         */
+    int64_t minres_iters;      /* MINRES iterations over all solves          */
+    double worst_rel_res;      /* largest final relative residual of a solve */
+    double ms;                 /* host wall time of the call                 */
+} hhg_energy_stats;
+
+int hhg_cell_coords(const hhg_mesh* mesh, int32_t level, double* xy);
+int hhg_cells_from_canonical(const hhg_mesh* mesh, int32_t level, const double* canon, double* cells,
+                             void* stream);
+int hhg_cells_to_canonical(const hhg_mesh* mesh, int32_t level, const double* cells, double* canon,
+                           void* stream);
+int hhg_transport_step(const hhg_mesh* mesh, int32_t level, const double* x, const double* T_in,
+                       double* T_out, double dt, void* stream);
+int hhg_buoyancy(const hhg_mesh* mesh, int32_t level, const double* T, double Ra, double* b,
+                 void* stream);
+int hhg_energy_run(hhg_mesh* mesh, const hhg_energy_opts* opts, void* x, void* T,
+                   hhg_energy_stats* stats, void* stream);
 
 /*
  * Per-kernel timing of the finest-level smoother launches, for profiling:

@@ -19,6 +19,9 @@ path computes:
                 prolongation, Jacobi-PCG coarse solve, V-cycle, solve loop
                 (sec. 4.3)
   net.py        the learned smoother's forward/backward (not in the paper)
+  stokes.py     equal-order P1-P1 Stokes with pressure stabilisation, the
+                block-diagonal multigrid preconditioner and preconditioned
+                MINRES (sec. 4.3, 5.2)
 
 Parity status of each function is stated in its docstring; functions with no
 independent pin say "parity unpinned".

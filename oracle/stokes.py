@@ -45,12 +45,10 @@ DELTA = 1.0 / 12.0
 
 
 def face_viscosity(mesh, r_jump=0.775, mu_in=1.0, mu_out=100.0):
-    """mu per macro-face: mu_in inside radius r_jump (by the face centroid),
-    mu_out outside; a jump of mu_out / mu_in across the middle ring of the
-    annulus."""
-    c = mesh.vxy[mesh.tri].mean(axis=1)
-    r = np.hypot(c[:, 0], c[:, 1])
-    return np.where(r < r_jump, mu_in, mu_out)
+    """mu per macro-face (an input of the problem, from the shared input
+    generators): a jump of mu_out / mu_in across the middle ring."""
+    import hhg_inputs
+    return hhg_inputs.face_viscosity(mesh.vxy, mesh.tri, r_jump, mu_in, mu_out)
 
 
 def stokes_element_matrices(xy, tris, mu_t, delta=DELTA):

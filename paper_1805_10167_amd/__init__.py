@@ -63,6 +63,48 @@ class Mesh:
         hhg_from_canonical(self.h, level, dtype, c, fld)
         return fld
 
+    def stokes_vector(self, level):
+        """Zeroed Stokes vector (u_x | u_y | p) of `level` (FP64)."""
+        import torch
+        return torch.zeros(3 * hhg_field_elems(self.h, level), dtype=torch.float64, device=self.device)
+
+    def stokes_from_canonical(self, level, canon3):
+        """Stokes vector from canonical [u_x | u_y | p] (3 n_all values)."""
+        import torch
+        _, n_all = self.n_dofs(level)
+        c = torch.as_tensor(np.asarray(canon3)).to(device=self.device, dtype=torch.float64)
+        n = hhg_field_elems(self.h, level)
+        out = self.stokes_vector(level)
+        for k in range(3):
+            hhg_from_canonical(self.h, level, HHG_F64, c[k * n_all:(k + 1) * n_all].contiguous(),
+                               out[k * n:(k + 1) * n])
+        return out
+
+    def stokes_to_canonical(self, level, vec):
+        """Canonical [u_x | u_y | p] of a Stokes vector."""
+        import torch
+        n = hhg_field_elems(self.h, level)
+        return torch.cat([self.to_canonical(level, vec[k * n:(k + 1) * n]) for k in range(3)])
+
+    def cell_coords(self, level):
+        """Centroids of the micro-triangle cells in canonical cell order."""
+        return hhg_cell_coords(self.h, level, self.F)
+
+    def cells_from_canonical(self, level, canon):
+        """Device cell field of a canonical cell array."""
+        import torch
+        out = torch.zeros(2 * hhg_field_elems(self.h, level), dtype=torch.float64, device=self.device)
+        hhg_cells_from_canonical(self.h, level, canon, out)
+        return out
+
+    def cells_to_canonical(self, level, cells):
+        """Canonical cell array of a device cell field."""
+        import torch
+        n = 2 ** level + 1
+        out = torch.empty(self.F * (n - 1) ** 2, dtype=torch.float64, device=self.device)
+        hhg_cells_to_canonical(self.h, level, cells, out)
+        return out
+
     def to_canonical(self, level, fld, dtype=HHG_F64):
         import torch
         _, n_all = self.n_dofs(level)

@@ -16,7 +16,7 @@ HHG_OK, HHG_EINVAL, HHG_ENOMEM, HHG_EHIP, HHG_ENOTCONV = 0, -1, -2, -3, -4
 HHG_F64, HHG_F32, HHG_BF16 = 0, 1, 2
 HHG_OP_LAPLACE, HHG_OP_DIFFUSION, HHG_OP_MASS = 0, 1, 2
 HHG_SMOOTH_GS, HHG_SMOOTH_NET = 0, 1
-HHG_FEAT_F64, HHG_FEAT_MP, HHG_FEAT_VARK, HHG_FEAT_NET = 1, 2, 4, 8
+HHG_FEAT_F64, HHG_FEAT_MP, HHG_FEAT_VARK, HHG_FEAT_NET, HHG_FEAT_STOKES = 1, 2, 4, 8, 16
 HHG_MODE_PLAIN_FP64, HHG_MODE_MP_IR, HHG_MODE_LEARNED = 0, 1, 2
 
 _c = ctypes
@@ -35,6 +35,26 @@ class hhg_solve_stats(_c.Structure):
     _fields_ = [("iters", _i32), ("converged", _i32), ("smoother_used", _i32),
                 ("fallback", _i32), ("res0", _c.c_double), ("rel_res", _c.c_double),
                 ("ms", _c.c_double)]
+
+
+class hhg_stokes_opts(_c.Structure):
+    _fields_ = [("precision", _i32), ("rtol", _c.c_double), ("max_iters", _i32), ("nu1", _i32),
+                ("nu2", _i32), ("res_history", _c.POINTER(_c.c_double)), ("history_capacity", _i32)]
+
+
+class hhg_stokes_stats(_c.Structure):
+    _fields_ = [("iters", _i32), ("converged", _i32), ("res0", _c.c_double), ("rel_res", _c.c_double),
+                ("ms", _c.c_double)]
+
+
+class hhg_energy_opts(_c.Structure):
+    _fields_ = [("stokes", hhg_stokes_opts), ("Ra", _c.c_double), ("dt", _c.c_double),
+                ("steps", _i32), ("stokes_every", _i32)]
+
+
+class hhg_energy_stats(_c.Structure):
+    _fields_ = [("steps", _i32), ("stokes_solves", _i32), ("minres_iters", _i64),
+                ("worst_rel_res", _c.c_double), ("ms", _c.c_double)]
 
 
 # name -> (restype, argtypes); restype int unless stated
@@ -68,8 +88,23 @@ _SIGS = {
     "hhg_net_forward": (_c.c_int, [_vp, _i32, _vp, _vp, _vp]),
     "hhg_net_backward": (_c.c_int, [_vp, _i32, _vp, _vp, _vp, _vp]),
     "hhg_net_adam_step": (_c.c_int, [_vp, _vp, _c.c_float, _i32, _vp]),
+    "hhg_set_face_coefficient": (_c.c_int, [_vp, _vp, _vp]),
+    "hhg_stokes_setup": (_c.c_int, [_vp, _vp, _c.c_double, _vp]),
+    "hhg_stokes_apply": (_c.c_int, [_vp, _i32, _vp, _vp, _vp]),
+    "hhg_stokes_residual": (_c.c_int, [_vp, _i32, _vp, _vp, _vp, _vp]),
+    "hhg_stokes_precond": (_c.c_int, [_vp, _i32, _vp, _vp, _i32, _i32, _vp]),
+    "hhg_stokes_dot": (_c.c_int, [_vp, _i32, _vp, _vp, _vp, _vp]),
+    "hhg_stokes_solve": (_c.c_int, [_vp, _c.POINTER(hhg_stokes_opts), _vp, _vp,
+                                    _c.POINTER(hhg_stokes_stats), _vp]),
     "hhg_timing_enable": (_c.c_int, [_vp, _i32]),
     "hhg_timing_read": (_c.c_int, [_vp, _c.POINTER(_i64), _c.POINTER(_c.c_double), _i32]),
+    "hhg_cell_coords": (_c.c_int, [_vp, _i32, _vp]),
+    "hhg_cells_from_canonical": (_c.c_int, [_vp, _i32, _vp, _vp, _vp]),
+    "hhg_cells_to_canonical": (_c.c_int, [_vp, _i32, _vp, _vp, _vp]),
+    "hhg_transport_step": (_c.c_int, [_vp, _i32, _vp, _vp, _vp, _c.c_double, _vp]),
+    "hhg_buoyancy": (_c.c_int, [_vp, _i32, _vp, _c.c_double, _vp, _vp]),
+    "hhg_energy_run": (_c.c_int, [_vp, _c.POINTER(hhg_energy_opts), _vp, _vp,
+                                  _c.POINTER(hhg_energy_stats), _vp]),
 }
 
 _lib = None
@@ -186,6 +221,86 @@ def hhg_to_canonical(h, level, dtype, field, canon, stream=None):
 
 def hhg_set_coefficient(h, k_canon, stream=None):
     _check(lib().hhg_set_coefficient(h, _ptr(k_canon), _stream(stream)))
+
+
+def hhg_set_face_coefficient(h, coef, stream=None):
+    c = np.ascontiguousarray(coef, dtype=np.float64)
+    _check(lib().hhg_set_face_coefficient(h, c.ctypes.data, _stream(stream)))
+
+
+def hhg_stokes_setup(h, viscosity, delta, stream=None):
+    c = np.ascontiguousarray(viscosity, dtype=np.float64)
+    _check(lib().hhg_stokes_setup(h, c.ctypes.data, float(delta), _stream(stream)))
+
+
+def hhg_stokes_apply(h, level, x, y, stream=None):
+    _check(lib().hhg_stokes_apply(h, level, _ptr(x), _ptr(y), _stream(stream)))
+
+
+def hhg_stokes_residual(h, level, x, b, r, stream=None):
+    _check(lib().hhg_stokes_residual(h, level, _ptr(x), _ptr(b), _ptr(r), _stream(stream)))
+
+
+def hhg_stokes_precond(h, precision, r, z, nu1, nu2, stream=None):
+    _check(lib().hhg_stokes_precond(h, precision, _ptr(r), _ptr(z), nu1, nu2, _stream(stream)))
+
+
+def hhg_stokes_dot(h, level, a, b, out, stream=None):
+    _check(lib().hhg_stokes_dot(h, level, _ptr(a), _ptr(b), _ptr(out), _stream(stream)))
+
+
+def hhg_stokes_solve(h, x, b, precision=HHG_F64, rtol=1e-8, max_iters=500, nu1=2, nu2=2,
+                     history=True, stream=None):
+    """Returns (status, stats dict, history of the preconditioned residual
+    norm)."""
+    hist = np.zeros(max_iters + 1) if history else None
+    o = hhg_stokes_opts(precision, rtol, max_iters, nu1, nu2,
+                        hist.ctypes.data_as(_c.POINTER(_c.c_double)) if history else None,
+                        len(hist) if history else 0)
+    st = hhg_stokes_stats()
+    rc = lib().hhg_stokes_solve(h, _c.byref(o), _ptr(x), _ptr(b), _c.byref(st), _stream(stream))
+    if rc not in (HHG_OK, HHG_ENOTCONV):
+        _check(rc)
+    stats = {k: getattr(st, k) for k, _ in hhg_stokes_stats._fields_}
+    hl = list(hist[:st.iters + 1]) if history else []
+    return rc, stats, hl
+
+
+def hhg_cell_coords(h, level, n_faces):
+    """Cell centroids in canonical cell order, numpy [n_faces (n-1)^2, 2]."""
+    n = 2 ** level + 1
+    xy = np.zeros((n_faces * (n - 1) ** 2, 2))
+    _check(lib().hhg_cell_coords(h, level, xy.ctypes.data))
+    return xy
+
+
+def hhg_cells_from_canonical(h, level, canon, cells, stream=None):
+    _check(lib().hhg_cells_from_canonical(h, level, _ptr(canon), _ptr(cells), _stream(stream)))
+
+
+def hhg_cells_to_canonical(h, level, cells, canon, stream=None):
+    _check(lib().hhg_cells_to_canonical(h, level, _ptr(cells), _ptr(canon), _stream(stream)))
+
+
+def hhg_transport_step(h, level, x, T_in, T_out, dt, stream=None):
+    _check(lib().hhg_transport_step(h, level, _ptr(x), _ptr(T_in), _ptr(T_out), float(dt),
+                                    _stream(stream)))
+
+
+def hhg_buoyancy(h, level, T, Ra, b, stream=None):
+    _check(lib().hhg_buoyancy(h, level, _ptr(T), float(Ra), _ptr(b), _stream(stream)))
+
+
+def hhg_energy_run(h, x, T, Ra, dt, steps, stokes_every=3, precision=HHG_F64, rtol=1e-8,
+                   max_iters=2000, nu1=2, nu2=2, stream=None):
+    """Returns (status, stats dict)."""
+    so = hhg_stokes_opts(precision, rtol, max_iters, nu1, nu2, None, 0)
+    o = hhg_energy_opts(so, float(Ra), float(dt), steps, stokes_every)
+    st = hhg_energy_stats()
+    rc = lib().hhg_energy_run(h, _c.byref(o), _ptr(x), _ptr(T), _c.byref(st), _stream(stream))
+    if rc not in (HHG_OK, HHG_ENOTCONV):
+        _check(rc)
+    return rc, {k: getattr(st, k) for k, _ in hhg_energy_stats._fields_}
 
 
 def hhg_apply(h, level, op, dtype, x, y, stream=None):

@@ -6,7 +6,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libhhg.so")
-SOURCES = ["mesh.cpp", "capi.cpp", "kernels.hip", "net.hip"]
+SOURCES = ["mesh.cpp", "capi.cpp", "kernels.hip", "net.hip", "stokes.hip", "transport.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",
@@ -16,6 +16,10 @@ FLAGS = [
 ]
 
 
+# per-source extra flags (none at present)
+EXTRA = {}
+
+
 def build(verbose=False):
     objs = []
     bdir = os.path.join(HERE, "_build")
@@ -23,7 +27,7 @@ def build(verbose=False):
     for src in SOURCES:
         obj = os.path.join(bdir, src + ".o")
         lang = ["-x", "hip"] if src.endswith(".hip") else []
-        cmd = [HIPCC] + FLAGS + lang + ["-c", os.path.join(CSRC, src), "-o", obj]
+        cmd = [HIPCC] + FLAGS + EXTRA.get(src, []) + lang + ["-c", os.path.join(CSRC, src), "-o", obj]
         if verbose:
             print(" ".join(cmd), flush=True)
         subprocess.run(cmd, check=True)

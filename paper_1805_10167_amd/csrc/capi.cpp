@@ -78,6 +78,7 @@ void carve(hhg_mesh* M, uint32_t feat, Carver& c) {
     M->n_partials = 1024;
     for (int l = 1; l <= m.L; ++l)
         M->n_partials = std::max({M->n_partials, sweep_norm_partials(M, l), face_loop_partials(M, l)});
+    if (feat & HHG_FEAT_STOKES) M->n_partials = std::max(M->n_partials, stokes_partials());
     M->partials = (double*)c.take(sizeof(double) * M->n_partials);
     M->dscalars = (double*)c.take(sizeof(double) * 64);
     for (int l = 0; l <= MAXLEVEL; ++l) {
@@ -126,6 +127,26 @@ void carve(hhg_mesh* M, uint32_t feat, Carver& c) {
             M->kap64[l] = (double*)fld(l, 8);
             if (feat & HHG_FEAT_MP) M->kap32[l] = (float*)fld(l, 4);
         }
+    }
+    M->d_sfaces = nullptr;
+    M->d_sedges = nullptr;
+    M->d_sverts = nullptr;
+    M->s_state = nullptr;
+    M->d_fvfaces = nullptr;
+    M->d_vxy = nullptr;
+    M->b_stokes = nullptr;
+    M->t_cells = nullptr;
+    for (auto& v : M->s_vec) v = nullptr;
+    if (feat & HHG_FEAT_STOKES) {
+        M->d_sfaces = (StokesFace*)c.take(sizeof(StokesFace) * m.F);
+        M->d_sedges = (StokesEdge*)c.take(sizeof(StokesEdge) * m.E);
+        M->d_sverts = (StokesVert*)c.take(sizeof(StokesVert) * m.V);
+        M->s_state = (double*)c.take(sizeof(double) * 64);
+        for (auto& v : M->s_vec) v = (double*)c.take(sizeof(double) * 3 * (size_t)m.lv[m.L].total);
+        M->d_fvfaces = (FvFace*)c.take(sizeof(FvFace) * m.F);
+        M->d_vxy = (double*)c.take(sizeof(double) * 2 * m.V);
+        M->b_stokes = (double*)c.take(sizeof(double) * 3 * (size_t)m.lv[m.L].total);
+        M->t_cells = (double*)c.take(sizeof(double) * 2 * (size_t)m.lv[m.L].total);
     }
 }
 
@@ -350,6 +371,11 @@ hhg::LevelDev hhg_mesh::dev(int level) const {
     L.iverts = d_iverts;
     L.gdst = H.d_gdst;
     L.gsrc = H.d_gsrc;
+    L.sfaces = d_sfaces;
+    L.sedges = d_sedges;
+    L.sverts = d_sverts;
+    L.fvfaces = d_fvfaces;
+    L.vxy = d_vxy;
     return L;
 }
 
@@ -389,8 +415,10 @@ void hhg_destroy_mesh(hhg_mesh* mesh) {
 
 int hhg_workspace_bytes(const hhg_mesh* mesh, uint32_t features, size_t* bytes) {
     if (!mesh || !bytes) return fail(HHG_EINVAL, "null argument");
-    if (features & ~(HHG_FEAT_F64 | HHG_FEAT_MP | HHG_FEAT_VARK | HHG_FEAT_NET))
+    if (features & ~(HHG_FEAT_F64 | HHG_FEAT_MP | HHG_FEAT_VARK | HHG_FEAT_NET | HHG_FEAT_STOKES))
         return fail(HHG_EINVAL, "unknown feature bits");
+    if ((features & HHG_FEAT_STOKES) && !(features & HHG_FEAT_F64))
+        return fail(HHG_EINVAL, "HHG_FEAT_STOKES needs HHG_FEAT_F64 (the preconditioner's hierarchy)");
     if ((features & HHG_FEAT_NET) && !(features & HHG_FEAT_MP))
         return fail(HHG_EINVAL, "HHG_FEAT_NET needs HHG_FEAT_MP (the learned smoother runs in FP32)");
     hhg_mesh tmp;
@@ -445,6 +473,7 @@ int hhg_bind_workspace(hhg_mesh* M, uint32_t features, void* dptr, size_t bytes,
     M->kappa_set = false;
     M->net_loaded = false;
     M->net_accepted = false;
+    M->stokes_ready = false;
     HIP_CHECK(launch_coarse_extract(M, OP_LAPLACE, C.vals, s), "coarse operator");
     HIP_CHECK(hipStreamSynchronize(s), "bind");
     return HHG_OK;
@@ -837,6 +866,336 @@ int hhg_net_adam_step(hhg_mesh* M, const float* grad, float lr, int32_t step, vo
     if (!grad || step < 1 || !(lr > 0.f)) return fail(HHG_EINVAL, "bad Adam arguments");
     HIP_CHECK(launch_net_adam(M, grad, lr, step, (hipStream_t)stream), "adam");
     return HHG_OK;
+}
+
+int hhg_set_face_coefficient(hhg_mesh* M, const double* coef, void* stream) {
+    if (!M || !coef) return fail(HHG_EINVAL, "null argument");
+    const std::string err = M->m.set_face_coef(coef);
+    if (!err.empty()) return fail(HHG_EINVAL, err);
+    M->stokes_ready = false;
+    if (!M->bound) return HHG_OK;
+    hipStream_t s = (hipStream_t)stream;
+    const MeshData& m = M->m;
+    HIP_CHECK(upload(M->d_faces, m.faces, s), "upload");
+    HIP_CHECK(upload(M->d_edges, m.edges, s), "upload");
+    HIP_CHECK(upload(M->d_verts, m.verts, s), "upload");
+    HIP_CHECK(launch_coarse_extract(M, OP_LAPLACE, M->coarse.vals, s), "coarse operator");
+    if (M->kappa_set) HIP_CHECK(launch_coarse_extract(M, OP_DIFFUSION, M->coarse_vals_diff, s), "coarse operator");
+    M->inv_ok[0] = M->inv_ok[1] = false;
+    HIP_CHECK(hipStreamSynchronize(s), "face coefficient");
+    return HHG_OK;
+}
+
+int hhg_stokes_setup(hhg_mesh* M, const double* viscosity, double delta, void* stream) {
+    if (!M || !viscosity) return fail(HHG_EINVAL, "null argument");
+    if (!M->bound) return fail(HHG_ENOMEM, "no workspace bound");
+    if (!(M->features & HHG_FEAT_STOKES)) return fail(HHG_ENOMEM, "workspace lacks HHG_FEAT_STOKES");
+    if (!(delta > 0.0) || !std::isfinite(delta)) return fail(HHG_EINVAL, "delta must be positive");
+    int rc = hhg_set_face_coefficient(M, viscosity, stream);
+    if (rc) return rc;
+    hipStream_t s = (hipStream_t)stream;
+    MeshData& m = M->m;
+    m.stokes_tables(delta);
+    m.fv_tables();
+    HIP_CHECK(upload(M->d_sfaces, m.sfaces, s), "upload");
+    HIP_CHECK(upload(M->d_sedges, m.sedges, s), "upload");
+    HIP_CHECK(upload(M->d_sverts, m.sverts, s), "upload");
+    HIP_CHECK(upload(M->d_fvfaces, m.fvfaces, s), "upload");
+    HIP_CHECK(upload(M->d_vxy, m.vxy, s), "upload");
+    HIP_CHECK(hipStreamSynchronize(s), "stokes setup");
+    M->stokes_delta = delta;
+    M->stokes_ready = true;
+    return HHG_OK;
+}
+
+namespace {
+
+int check_stokes(const hhg_mesh* M, int level) {
+    if (!M) return fail(HHG_EINVAL, "null mesh");
+    if (!M->bound) return fail(HHG_ENOMEM, "no workspace bound");
+    if (!(M->features & HHG_FEAT_STOKES)) return fail(HHG_ENOMEM, "workspace lacks HHG_FEAT_STOKES");
+    if (!M->stokes_ready) return fail(HHG_EINVAL, "hhg_stokes_setup has not been called");
+    if (!level_ok(M, level)) return fail(HHG_EINVAL, "level out of range");
+    return HHG_OK;
+}
+
+// Velocity blocks of the preconditioner: z_c = one V(nu1, nu2) cycle of the
+// viscous operator from zero on r_c, for c = x, y (FP64, or FP32 cycles on
+// the rounded residual with the result raised to FP64).
+int stokes_vel_precond(const hhg_mesh* M, int prec, const double* r, double* z, int nu1, int nu2,
+                       hipStream_t s) {
+    const int L = M->m.L;
+    const int64_t fs = M->m.lv[L].total;
+    for (int c = 0; c < 2; ++c) {
+        const double* rc_ = r + c * fs;
+        double* zc = z + c * fs;
+        if (prec == HHG_F64) {
+            HIP_CHECK(launch_fill(zc, fs, HHG_F64, 0.0, s), "precond");
+            int rc = vcycle_rec(M, L, HHG_OP_LAPLACE, HHG_SMOOTH_GS, HHG_F64, zc, rc_, nu1, nu2, s);
+            if (rc) return rc;
+        } else {
+            float* u32 = (float*)M->u32[L];
+            float* f32 = (float*)M->f32[L];
+            HIP_CHECK(launch_f64_to_f32(rc_, f32, fs, s), "precond");
+            HIP_CHECK(launch_fill(u32, fs, HHG_F32, 0.0, s), "precond");
+            int rc = vcycle_rec(M, L, HHG_OP_LAPLACE, HHG_SMOOTH_GS, HHG_F32, u32, f32, nu1, nu2, s);
+            if (rc) return rc;
+            HIP_CHECK(launch_f32_to_f64(u32, zc, fs, s), "precond");
+        }
+    }
+    return HHG_OK;
+}
+
+int check_stokes_prec(const hhg_mesh* M, int prec, int nu1, int nu2) {
+    if (prec != HHG_F64 && prec != HHG_F32) return fail(HHG_EINVAL, "precision must be HHG_F64 or HHG_F32");
+    if (prec == HHG_F32 && !(M->features & HHG_FEAT_MP))
+        return fail(HHG_ENOMEM, "FP32 preconditioner needs HHG_FEAT_MP");
+    if (nu1 < 0 || nu2 < 0 || nu1 + nu2 == 0) return fail(HHG_EINVAL, "need at least one smoothing sweep");
+    return HHG_OK;
+}
+
+}  // namespace
+
+int hhg_stokes_apply(const hhg_mesh* M, int32_t level, const void* x, void* y, void* stream) {
+    int rc = check_stokes(M, level);
+    if (rc) return rc;
+    if (!x || !y || x == y) return fail(HHG_EINVAL, "x and y must be distinct buffers");
+    HIP_CHECK(launch_stokes_apply(M, level, 0, (const double*)x, nullptr, (double*)y, M->partials, nullptr,
+                                  (hipStream_t)stream), "stokes apply");
+    return HHG_OK;
+}
+
+int hhg_stokes_residual(const hhg_mesh* M, int32_t level, const void* x, const void* b, void* r,
+                        void* stream) {
+    int rc = check_stokes(M, level);
+    if (rc) return rc;
+    if (!x || !b || !r || r == x || r == b) return fail(HHG_EINVAL, "r must be distinct from x and b");
+    HIP_CHECK(launch_stokes_apply(M, level, 2, (const double*)x, (const double*)b, (double*)r, M->partials,
+                                  nullptr, (hipStream_t)stream), "stokes residual");
+    return HHG_OK;
+}
+
+int hhg_stokes_precond(const hhg_mesh* M, int32_t precision, const void* r, void* z, int32_t nu1,
+                       int32_t nu2, void* stream) {
+    const int L = M ? M->m.L : 0;
+    int rc = check_stokes(M, L);
+    if (rc) return rc;
+    if ((rc = check_stokes_prec(M, precision, nu1, nu2))) return rc;
+    if (!r || !z || r == z) return fail(HHG_EINVAL, "r and z must be distinct buffers");
+    hipStream_t s = (hipStream_t)stream;
+    if ((rc = stokes_vel_precond(M, precision, (const double*)r, (double*)z, nu1, nu2, s))) return rc;
+    HIP_CHECK(launch_stokes_pscale_dot(M, L, (const double*)r, (double*)z, M->partials, nullptr, s), "precond");
+    return HHG_OK;
+}
+
+int hhg_stokes_dot(const hhg_mesh* M, int32_t level, const void* a, const void* b, double* out,
+                   void* stream) {
+    int rc = check_stokes(M, level);
+    if (rc) return rc;
+    if (!a || !b || !out) return fail(HHG_EINVAL, "null buffer");
+    hipStream_t s = (hipStream_t)stream;
+    int64_t np = 0;
+    HIP_CHECK(launch_stokes_dot(M, level, (const double*)a, (const double*)b, M->partials, &np, s), "dot");
+    HIP_CHECK(launch_reduce(M->partials, np, out, s), "dot");
+    return HHG_OK;
+}
+
+namespace {
+
+// MINRES on the finest level (see hhg_stokes_solve); arguments checked.
+int stokes_minres(hhg_mesh* M, const hhg_stokes_opts* o, void* x_, const void* b_, hhg_stokes_stats* st,
+                  hipStream_t s) {
+    const auto t0 = std::chrono::steady_clock::now();
+    *st = hhg_stokes_stats{};
+    const int L = M->m.L;
+    int rc = 0;
+    double* x = (double*)x_;
+    const double* b = (const double*)b_;
+    const int64_t n3 = 3 * M->m.lv[L].total;
+    double* R[2] = {M->s_vec[0], M->s_vec[1]};   // r_k, r_{k-1} (then r_{k+1})
+    double* Y[2] = {M->s_vec[2], M->s_vec[3]};   // y_k = P^-1 r_k, y_{k+1}
+    double* KY = M->s_vec[4];
+    double* W[2] = {M->s_vec[5], M->s_vec[6]};   // w_{k-1}, w_{k-2}
+    double* sst = M->s_state;
+    double* slot = M->h_norm_dev;
+    volatile const double* hslot = M->h_norm;
+    int64_t np = 0;
+    for (double* v : {R[1], W[0], W[1]}) HIP_CHECK(launch_fill(v, n3, HHG_F64, 0.0, s), "solve");
+    HIP_CHECK(launch_stokes_apply(M, L, 2, x, b, R[0], M->partials, nullptr, s), "residual");
+    if ((rc = stokes_vel_precond(M, o->precision, R[0], Y[0], o->nu1, o->nu2, s))) return rc;
+    HIP_CHECK(launch_stokes_pscale_dot(M, L, R[0], Y[0], M->partials, &np, s), "precond");
+    HIP_CHECK(launch_minres_scalars(0, M->partials, np, sst, slot, s), "minres");
+    HIP_CHECK(hipStreamSynchronize(s), "minres");
+    const double beta1 = hslot[2];
+    st->res0 = beta1;
+    int hist_n = 0;
+    auto record = [&](double v) {
+        if (o->res_history && hist_n < o->history_capacity) o->res_history[hist_n] = v;
+        ++hist_n;
+    };
+    record(beta1);
+    auto finish = [&](int status) {
+        st->ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+        return status;
+    };
+    if (!std::isfinite(beta1)) return finish(fail(HHG_ENOTCONV, "non-finite initial residual"));
+    if (!(beta1 > 0.0)) {
+        st->converged = 1;
+        return finish(HHG_OK);
+    }
+    double rel = 1.0;
+    for (int k = 1; k <= o->max_iters; ++k) {
+        HIP_CHECK(launch_stokes_apply(M, L, 1, Y[0], nullptr, KY, M->partials, &np, s), "minres apply");
+        HIP_CHECK(launch_minres_scalars(1, M->partials, np, sst, slot, s), "minres");
+        HIP_CHECK(launch_minres_rupdate(n3, KY, R[0], R[1], sst, s), "minres");
+        if ((rc = stokes_vel_precond(M, o->precision, R[1], Y[1], o->nu1, o->nu2, s))) return finish(rc);
+        HIP_CHECK(launch_stokes_pscale_dot(M, L, R[1], Y[1], M->partials, &np, s), "minres precond");
+        HIP_CHECK(launch_minres_scalars(2, M->partials, np, sst, slot, s), "minres");
+        HIP_CHECK(launch_minres_wupdate(n3, Y[0], W[0], W[1], x, sst, s), "minres");
+        HIP_CHECK(hipStreamSynchronize(s), "minres");
+        const double eta = hslot[0], bnext = hslot[1];
+        rel = eta / beta1;
+        record(eta);
+        st->iters = k;
+        st->rel_res = rel;
+        if (!std::isfinite(eta)) return finish(fail(HHG_ENOTCONV, "non-finite residual"));
+        if (rel <= o->rtol || bnext == 0.0) {
+            st->converged = 1;
+            return finish(HHG_OK);
+        }
+        std::swap(R[0], R[1]);
+        std::swap(Y[0], Y[1]);
+        std::swap(W[0], W[1]);
+    }
+    return finish(fail(HHG_ENOTCONV, "MINRES iteration cap reached"));
+}
+
+int check_stokes_opts(const hhg_mesh* M, const hhg_stokes_opts* o) {
+    int rc = check_stokes_prec(M, o->precision, o->nu1, o->nu2);
+    if (rc) return rc;
+    if (o->max_iters < 0 || !(o->rtol >= 0)) return fail(HHG_EINVAL, "bad solve options");
+    if (!M->h_norm) return fail(HHG_ENOMEM, "no norm slot: bind a workspace first");
+    return HHG_OK;
+}
+
+}  // namespace
+
+int hhg_stokes_solve(hhg_mesh* M, const hhg_stokes_opts* o, void* x_, const void* b_, hhg_stokes_stats* st,
+                     void* stream) {
+    if (!o || !st) return fail(HHG_EINVAL, "null argument");
+    *st = hhg_stokes_stats{};
+    const int L = M ? M->m.L : 0;
+    int rc = check_stokes(M, L);
+    if (rc) return rc;
+    if ((rc = check_stokes_opts(M, o))) return rc;
+    if (!x_ || !b_ || x_ == b_) return fail(HHG_EINVAL, "x and b must be distinct buffers");
+    return stokes_minres(M, o, x_, b_, st, (hipStream_t)stream);
+}
+
+int hhg_cell_coords(const hhg_mesh* M, int32_t level, double* xy) {
+    if (!M || !xy) return fail(HHG_EINVAL, "null argument");
+    if (!level_ok(M, level)) return fail(HHG_EINVAL, "level out of range");
+    const MeshData& m = M->m;
+    const int n = m.lv[level].n;
+    int64_t c = 0;
+    for (int f = 0; f < m.F; ++f) {
+        const double* x0 = &m.vxy[2 * m.tri[f][0]];
+        const double* x1 = &m.vxy[2 * m.tri[f][1]];
+        const double* x2 = &m.vxy[2 * m.tri[f][2]];
+        // up cells, then down cells, j-major: centroid at (i + 1/3, j + 1/3)
+        // and (i + 2/3, j + 2/3) in face-local steps
+        for (int kind = 0; kind < 2; ++kind)
+            for (int j = 0; j <= n - 2 - kind; ++j)
+                for (int i = 0; i <= n - 2 - kind - j; ++i, ++c) {
+                    const double o = kind ? 2.0 / 3.0 : 1.0 / 3.0;
+                    const double si = (i + o) / (n - 1), sj = (j + o) / (n - 1);
+                    xy[2 * c] = x0[0] + si * (x1[0] - x0[0]) + sj * (x2[0] - x0[0]);
+                    xy[2 * c + 1] = x0[1] + si * (x1[1] - x0[1]) + sj * (x2[1] - x0[1]);
+                }
+    }
+    return HHG_OK;
+}
+
+int hhg_cells_from_canonical(const hhg_mesh* M, int32_t level, const double* canon, double* cells,
+                             void* stream) {
+    int rc = check_stokes(M, level);
+    if (rc) return rc;
+    if (!canon || !cells) return fail(HHG_EINVAL, "null buffer");
+    HIP_CHECK(launch_cell_canon(M, level, canon, cells, 0, (hipStream_t)stream), "cells");
+    return HHG_OK;
+}
+
+int hhg_cells_to_canonical(const hhg_mesh* M, int32_t level, const double* cells, double* canon,
+                           void* stream) {
+    int rc = check_stokes(M, level);
+    if (rc) return rc;
+    if (!canon || !cells) return fail(HHG_EINVAL, "null buffer");
+    HIP_CHECK(launch_cell_canon(M, level, cells, canon, 1, (hipStream_t)stream), "cells");
+    return HHG_OK;
+}
+
+int hhg_transport_step(const hhg_mesh* M, int32_t level, const double* x, const double* T_in,
+                       double* T_out, double dt, void* stream) {
+    int rc = check_stokes(M, level);
+    if (rc) return rc;
+    if (!x || !T_in || !T_out || T_in == T_out) return fail(HHG_EINVAL, "T_in and T_out must be distinct");
+    if (!(dt >= 0.0) || !std::isfinite(dt)) return fail(HHG_EINVAL, "bad time step");
+    const int64_t fs = M->m.lv[level].total;
+    HIP_CHECK(launch_fv_step(M, level, x, x + fs, T_in, T_out, dt, (hipStream_t)stream), "transport");
+    return HHG_OK;
+}
+
+int hhg_buoyancy(const hhg_mesh* M, int32_t level, const double* T, double Ra, double* b, void* stream) {
+    int rc = check_stokes(M, level);
+    if (rc) return rc;
+    if (!T || !b) return fail(HHG_EINVAL, "null buffer");
+    hipStream_t s = (hipStream_t)stream;
+    const int64_t fs = M->m.lv[level].total;
+    HIP_CHECK(launch_fill(b + 2 * fs, fs, HHG_F64, 0.0, s), "buoyancy");
+    HIP_CHECK(launch_fv_buoyancy(M, level, T, Ra, b, s), "buoyancy");
+    return HHG_OK;
+}
+
+int hhg_energy_run(hhg_mesh* M, const hhg_energy_opts* o, void* x, void* T, hhg_energy_stats* st,
+                   void* stream) {
+    if (!o || !st) return fail(HHG_EINVAL, "null argument");
+    *st = hhg_energy_stats{};
+    const auto t0 = std::chrono::steady_clock::now();
+    const int L = M ? M->m.L : 0;
+    int rc = check_stokes(M, L);
+    if (rc) return rc;
+    if ((rc = check_stokes_opts(M, &o->stokes))) return rc;
+    if (!x || !T) return fail(HHG_EINVAL, "null buffer");
+    if (o->steps < 0 || o->stokes_every < 1 || !(o->dt >= 0.0) || !std::isfinite(o->dt) || !std::isfinite(o->Ra))
+        return fail(HHG_EINVAL, "bad energy options");
+    hipStream_t s = (hipStream_t)stream;
+    const int64_t fs = M->m.lv[L].total;
+    double* cur = (double*)T;
+    double* other = M->t_cells;
+    double* xs = (double*)x;
+    hhg_stokes_opts so = o->stokes;
+    so.res_history = nullptr;
+    so.history_capacity = 0;
+    for (int k = 0; k < o->steps; ++k) {
+        if (k % o->stokes_every == 0) {
+            HIP_CHECK(launch_fill(M->b_stokes + 2 * fs, fs, HHG_F64, 0.0, s), "buoyancy");
+            HIP_CHECK(launch_fv_buoyancy(M, L, cur, o->Ra, M->b_stokes, s), "buoyancy");
+            hhg_stokes_stats ss;
+            rc = stokes_minres(M, &so, xs, M->b_stokes, &ss, s);
+            st->stokes_solves++;
+            st->minres_iters += ss.iters;
+            st->worst_rel_res = std::max(st->worst_rel_res, ss.rel_res);
+            if (rc) break;
+        }
+        HIP_CHECK(launch_fv_step(M, L, xs, xs + fs, cur, other, o->dt, s), "transport");
+        std::swap(cur, other);
+        st->steps = k + 1;
+    }
+    if (cur != (double*)T) HIP_CHECK(hipMemcpyAsync(T, cur, sizeof(double) * 2 * fs, hipMemcpyDeviceToDevice, s),
+                                     "copy back");
+    HIP_CHECK(hipStreamSynchronize(s), "energy run");
+    st->ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+    return rc;
 }
 
 int hhg_timing_enable(hhg_mesh* M, int32_t enable) {

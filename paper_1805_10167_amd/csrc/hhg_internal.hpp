@@ -103,6 +103,45 @@ struct VertexInfo {
     int32_t pad_;
 };
 
+// Equal-order P1-P1 Stokes stencils (blocks of the saddle-point operator),
+// at the unit scale of the macro-face (one micro-step = one macro-edge):
+// level l scales the divergence/gradient blocks by 2^-l and the pressure
+// stabilisation and lumped pressure mass by 4^-l; the viscous block is
+// level independent.  Row stencils of one point over its neighbours:
+//   A   mu-weighted stiffness, velocity row, velocity neighbours
+//   BX  divergence (x part), pressure row, velocity neighbours
+//   BY  divergence (y part), pressure row, velocity neighbours
+//   BXT gradient (x part) = transpose of BX, velocity row, pressure neighbours
+//   BYT gradient (y part), velocity row, pressure neighbours
+//   C   pressure stabilisation, pressure row, pressure neighbours
+enum { SB_A = 0, SB_BX = 1, SB_BY = 2, SB_BXT = 3, SB_BYT = 4, SB_C = 5, SB_N = 6 };
+// face-interior point: neighbours C, E, W, N, S, SE, NW of face-local (i, j)
+struct StokesFace { double w[SB_N][7]; double m; };
+// edge point k: k, k-1, k+1, then for face s = 0, 1 the near-row points
+// g_s[k-1], g_s[k] (zero weights for the missing face of a boundary edge)
+struct StokesEdge { double w[SB_N][7]; double m; };
+// vertex: the vertex, then ring slot q (edge point next to it on edge q)
+struct StokesVert { double w[SB_N][1 + MAXDEG]; double m; };
+
+// Finite-volume cells of a macro-face (the micro-triangles) at unit scale,
+// one micro-step = one macro-edge: outward normal times length of the three
+// edges of an up cell {(i,j), (i+1,j), (i,j+1)}: bottom (along side 0),
+// left (along side 1), diagonal (along side 2); a down cell is the point
+// reflection, with the negated normals.  Level l scales normals by 2^-l and
+// the cell area by 4^-l.  Per side, the face across it (-1 on the domain
+// boundary), that face's side, and whether position t along this side is
+// position n-2-t on the other.  x0, e1, e2 give point coordinates,
+// x(i, j) = x0 + 2^-l (i e1 + j e2).
+struct FvFace {
+    double nb[2], nl[2], nd[2];
+    double area;
+    double x0[2], e1[2], e2[2];
+    int32_t nbr_face[3];
+    int32_t nbr_side[3];
+    int32_t nbr_flip[3];
+    int32_t pad_;
+};
+
 // Per-level view passed to kernels by value.
 struct LevelDev {
     int32_t level, n;
@@ -126,6 +165,11 @@ struct LevelDev {
     const int32_t* iverts;            // interior vertex ids
     const int64_t* gdst;              // ghost copies: field[gdst] = field[gsrc]
     const int64_t* gsrc;
+    const StokesFace* sfaces;         // Stokes stencils (null unless set up)
+    const StokesEdge* sedges;
+    const StokesVert* sverts;
+    const FvFace* fvfaces;            // finite-volume cell geometry (null unless set up)
+    const double* vxy;                // macro-vertex coordinates [2 V]
 };
 
 // Coarse-level Jacobi-PCG data: interior points in canonical order, each

@@ -102,4 +102,43 @@ hipError_t launch_dot(const hhg_mesh* M, int level, int dtype, const void* x, co
 hipError_t launch_axpby(int64_t n, int dtype, double alpha, const void* x, double beta, const void* y,
                         void* z, hipStream_t s);
 
+// *out = fixed-order sum of partials[0, count).
+hipError_t launch_reduce(const double* partials, int64_t count, double* out, hipStream_t s);
+
+// Stokes system and MINRES (stokes.hip).  Stokes vectors are three fields
+// u_x | u_y | p of `level`, each of the level's field length.
+// Reduction slots the Stokes kernels need.
+int64_t stokes_partials();
+// mode 0: y = K x; 1: y = K x with partial sums of y . x (count in *nparts);
+// 2: y = b - K x.  Velocity rows of Dirichlet points are 0.
+hipError_t launch_stokes_apply(const hhg_mesh* M, int level, int mode, const double* x, const double* b,
+                               double* y, double* partials, int64_t* nparts, hipStream_t s);
+// z_p = r_p / (lumped 1/mu-weighted mass), with partial sums of r . z over
+// all three fields (the velocity parts of z must be in place).
+hipError_t launch_stokes_pscale_dot(const hhg_mesh* M, int level, const double* r, double* z,
+                                    double* partials, int64_t* nparts, hipStream_t s);
+// Partial sums of a . b over the owned points of all three fields.
+hipError_t launch_stokes_dot(const hhg_mesh* M, int level, const double* a, const double* b,
+                             double* partials, int64_t* nparts, hipStream_t s);
+// Scalar stages of MINRES (0: start, 1: after the operator, 2: after the
+// preconditioner), state in st, residual norms to the host-visible slot.
+hipError_t launch_minres_scalars(int stage, const double* partials, int64_t count, double* st, double* slot,
+                                 hipStream_t s);
+hipError_t launch_minres_rupdate(int64_t n, const double* y, const double* r, double* r_old, const double* st,
+                                 hipStream_t s);
+hipError_t launch_minres_wupdate(int64_t n, const double* yk, const double* w_old, double* w_older, double* x,
+                                 const double* st, hipStream_t s);
+
+// Energy transport (transport.hip).  Cell fields are [up | down], two
+// point-layout fields of the level.
+// One explicit upwind step Tout = Tin - dt/|c| sum_e F_e T_up(e).
+hipError_t launch_fv_step(const hhg_mesh* M, int level, const double* ux, const double* uy, const double* Tin,
+                          double* Tout, double dt, hipStream_t s);
+// Buoyancy load -Ra r_hat sum T |c| / 3 into the velocity fields of b.
+hipError_t launch_fv_buoyancy(const hhg_mesh* M, int level, const double* T, double Ra, double* b,
+                              hipStream_t s);
+// Canonical cell order <-> cell field (to_canon = 1: field -> canonical).
+hipError_t launch_cell_canon(const hhg_mesh* M, int level, const double* src, double* dst, int to_canon,
+                             hipStream_t s);
+
 }  // namespace hhg

@@ -41,6 +41,17 @@ struct MeshData {
     std::vector<FaceInfo> faces;
     std::vector<EdgeInfo> edges;
     std::vector<VertexInfo> verts;
+    // the same tables before a face coefficient scaled their stiffness
+    // weights (cotangents), and the coefficient itself (1 by default)
+    std::vector<FaceInfo> faces0;
+    std::vector<EdgeInfo> edges0;
+    std::vector<VertexInfo> verts0;
+    std::vector<double> face_coef;
+    // Stokes stencils at unit scale (empty until stokes_tables runs)
+    std::vector<StokesFace> sfaces;
+    std::vector<StokesEdge> sedges;
+    std::vector<StokesVert> sverts;
+    std::vector<FvFace> fvfaces;
     std::vector<int32_t> iedges, iverts;
     std::vector<LevelHost> lv;                      // index = level
 
@@ -73,6 +84,14 @@ struct MeshData {
                       int max_level, int coarse_level);
     void build_level(int level);
     void build_coarse();
+    // Scale the stiffness weights of face f (and its share of the edge and
+    // vertex weights) by coef[f] > 0; "" or an error message.
+    std::string set_face_coef(const double* coef);
+    // Stokes stencils from the geometry and the face coefficient (the
+    // viscosity), stabilisation parameter delta.
+    void stokes_tables(double delta);
+    // Finite-volume cell geometry and face-to-face neighbours.
+    void fv_tables();
 };
 
 }  // namespace hhg
@@ -88,6 +107,19 @@ struct hhg_mesh {
     hhg::FaceInfo* d_faces = nullptr;
     hhg::EdgeInfo* d_edges = nullptr;
     hhg::VertexInfo* d_verts = nullptr;
+    hhg::StokesFace* d_sfaces = nullptr;
+    hhg::StokesEdge* d_sedges = nullptr;
+    hhg::StokesVert* d_sverts = nullptr;
+    bool stokes_ready = false;
+    double stokes_delta = 0.0;
+    // MINRES vectors of the finest level (HHG_FEAT_STOKES): 7 Stokes vectors
+    // of 3 fields each
+    double* s_vec[7] = {};
+    double* s_state = nullptr;   // MINRES scalars
+    hhg::FvFace* d_fvfaces = nullptr;
+    double* d_vxy = nullptr;
+    double* t_cells = nullptr;   // second cell field of the transport loop
+    double* b_stokes = nullptr;  // buoyancy right-hand side of the transport loop
     int32_t* d_iedges = nullptr;
     int32_t* d_iverts = nullptr;
     hhg::CoarseDev coarse{};              // vals: Laplace operator

@@ -266,10 +266,223 @@ std::string MeshData::build(const double* in_vxy, int nv, const int32_t* in_tri,
     for (int v = 0; v < V; ++v)
         if (!verts[v].boundary) iverts.push_back(v);
 
+    faces0 = faces;
+    edges0 = edges;
+    verts0 = verts;
+    face_coef.assign(F, 1.0);
+    sfaces.clear();
+    sedges.clear();
+    sverts.clear();
     lv.assign(L + 1, LevelHost{});
     for (int l = 1; l <= L; ++l) build_level(l);
     build_coarse();
     return "";
+}
+
+std::string MeshData::set_face_coef(const double* coef) {
+    for (int f = 0; f < F; ++f)
+        if (!(coef[f] > 0.0) || !std::isfinite(coef[f]))
+            return "face coefficient " + std::to_string(f) + " is not a positive finite number";
+    face_coef.assign(coef, coef + F);
+    faces = faces0;
+    edges = edges0;
+    verts = verts0;
+    // every stiffness weight is -1/2 cot(angle) of one micro-triangle, and
+    // every micro-triangle lies in one macro-face: scale by that face's value
+    for (int f = 0; f < F; ++f)
+        for (int k = 0; k < 3; ++k) faces[f].cot[k] *= face_coef[f];
+    for (int e = 0; e < E; ++e)
+        for (int s = 0; s < edges[e].nf; ++s) {
+            const double c = face_coef[edges[e].face[s]];
+            edges[e].cA[s] *= c;
+            edges[e].cL[s] *= c;
+            edges[e].cH[s] *= c;
+        }
+    for (int v = 0; v < V; ++v) {
+        VertexInfo& vi = verts[v];
+        for (int q = 0; q < vi.deg; ++q) {
+            const EdgeInfo& ei = edges[vi.edge[q]];
+            for (int s = 0; s < ei.nf; ++s) vi.cA[q][s] *= face_coef[ei.face[s]];
+        }
+    }
+    return "";
+}
+
+namespace {
+
+// P1 element contributions of one triangle with vertex positions P[3] (any
+// orientation) to the row stencils of the point at local vertex r; slot[a]
+// is the stencil neighbour of local vertex a.  Definitions (per triangle T):
+//   A[r][b]   = mu |T| grad phi_r . grad phi_b
+//   BX[r][b]  = -int_T psi_r d phi_b / dx = -|T|/3 d phi_b / dx  (pressure row r)
+//   BXT[r][a] = BX[a][r] = -|T|/3 d phi_r / dx                    (velocity row r)
+//   C[r][b]   = delta h_T^2 / mu |T| grad phi_r . grad phi_b, h_T the longest edge
+//   m        += |T| / (3 mu)  (lumped 1/mu-weighted mass)
+template <int W>
+void add_triangle(const double P[3][2], int r, const int slot[3], double mu, double delta,
+                  double (&w)[SB_N][W], double& m) {
+    double gx[3], gy[3];
+    for (int a = 0; a < 3; ++a) {
+        const int a1 = (a + 1) % 3, a2 = (a + 2) % 3;
+        gx[a] = P[a1][1] - P[a2][1];
+        gy[a] = P[a2][0] - P[a1][0];
+    }
+    const double two_a = gx[0] * gy[1] - gx[1] * gy[0];   // twice the signed area
+    const double area = 0.5 * std::fabs(two_a);
+    for (int a = 0; a < 3; ++a) {
+        gx[a] /= two_a;
+        gy[a] /= two_a;
+    }
+    double h2 = 0.0;
+    for (int a = 0; a < 3; ++a) {
+        const int a1 = (a + 1) % 3;
+        const double dx = P[a1][0] - P[a][0], dy = P[a1][1] - P[a][1];
+        h2 = std::max(h2, dx * dx + dy * dy);
+    }
+    for (int b = 0; b < 3; ++b) {
+        const double st = area * (gx[r] * gx[b] + gy[r] * gy[b]);
+        w[SB_A][slot[b]] += mu * st;
+        w[SB_C][slot[b]] += delta * h2 / mu * st;
+        w[SB_BX][slot[b]] += -area / 3.0 * gx[b];
+        w[SB_BY][slot[b]] += -area / 3.0 * gy[b];
+        w[SB_BXT][slot[b]] += -area / 3.0 * gx[r];
+        w[SB_BYT][slot[b]] += -area / 3.0 * gy[r];
+    }
+    m += area / (3.0 * mu);
+}
+
+}  // namespace
+
+void MeshData::fv_tables() {
+    fvfaces.assign(F, FvFace{});
+    auto X = [&](int v, int c) { return vxy[2 * v + c]; };
+    for (int f = 0; f < F; ++f) {
+        FvFace& t = fvfaces[f];
+        const int* v = tri[f].data();
+        // side vectors taken as differences of the two vertices of the side,
+        // so that the two faces of a macro-edge get exactly negated normals
+        double s0[2], s1[2], s2[2];
+        for (int c = 0; c < 2; ++c) {
+            s0[c] = X(v[1], c) - X(v[0], c);
+            s1[c] = X(v[2], c) - X(v[0], c);
+            s2[c] = X(v[2], c) - X(v[1], c);
+            t.x0[c] = X(v[0], c);
+            t.e1[c] = s0[c];
+            t.e2[c] = s1[c];
+        }
+        // counter-clockwise face: the outside of the up cell is to the right
+        // of side 0 and of side 2, and to the left of side 1
+        t.nb[0] = s0[1];  t.nb[1] = -s0[0];
+        t.nl[0] = -s1[1]; t.nl[1] = s1[0];
+        t.nd[0] = s2[1];  t.nd[1] = -s2[0];
+        t.area = 0.5 * std::fabs(s0[0] * s1[1] - s0[1] * s1[0]);
+        for (int s = 0; s < 3; ++s) {
+            const FaceInfo& fi = faces[f];
+            const EdgeInfo& ei = edges[fi.edge[s]];
+            t.nbr_face[s] = -1;
+            t.nbr_side[s] = 0;
+            t.nbr_flip[s] = 0;
+            if (ei.nf < 2) continue;
+            const int other = 1 - fi.slot[s];
+            t.nbr_face[s] = ei.face[other];
+            t.nbr_side[s] = ei.side[other];
+            t.nbr_flip[s] = (ei.rev[other] != fi.rev[s]) ? 1 : 0;
+        }
+    }
+}
+
+void MeshData::stokes_tables(double delta) {
+    sfaces.assign(F, StokesFace{});
+    sedges.assign(E, StokesEdge{});
+    sverts.assign(V, StokesVert{});
+    auto X = [&](int v, int c) { return vxy[2 * v + c]; };
+    // face interior: the six micro-triangles around (i, j), as offsets
+    // (di, dj); neighbour slots C, E, W, N, S, SE, NW
+    const int off[7][2] = {{0, 0}, {1, 0}, {-1, 0}, {0, 1}, {0, -1}, {1, -1}, {-1, 1}};
+    auto slot_of = [&](int di, int dj) {
+        for (int t = 0; t < 7; ++t)
+            if (off[t][0] == di && off[t][1] == dj) return t;
+        return -1;
+    };
+    const int ftri[6][3][2] = {
+        {{0, 0}, {1, 0}, {0, 1}},      // up (i, j)
+        {{-1, 0}, {0, 0}, {-1, 1}},    // up (i-1, j)
+        {{0, -1}, {1, -1}, {0, 0}},    // up (i, j-1)
+        {{0, -1}, {0, 0}, {-1, 0}},    // down (i-1, j-1)
+        {{0, 0}, {0, 1}, {-1, 1}},     // down (i-1, j)
+        {{1, -1}, {1, 0}, {0, 0}}};    // down (i, j-1)
+    for (int f = 0; f < F; ++f) {
+        const int* t = tri[f].data();
+        const double e1[2] = {X(t[1], 0) - X(t[0], 0), X(t[1], 1) - X(t[0], 1)};
+        const double e2[2] = {X(t[2], 0) - X(t[0], 0), X(t[2], 1) - X(t[0], 1)};
+        StokesFace& sf = sfaces[f];
+        for (int k = 0; k < 6; ++k) {
+            double P[3][2];
+            int slot[3], r = -1;
+            for (int a = 0; a < 3; ++a) {
+                const int di = ftri[k][a][0], dj = ftri[k][a][1];
+                P[a][0] = di * e1[0] + dj * e2[0];
+                P[a][1] = di * e1[1] + dj * e2[1];
+                slot[a] = slot_of(di, dj);
+                if (di == 0 && dj == 0) r = a;
+            }
+            add_triangle<7>(P, r, slot, face_coef[f], delta, sf.w, sf.m);
+        }
+    }
+    // edge point k: slots 0 = k, 1 = k-1, 2 = k+1, 3 + 2s = g_s[k-1],
+    // 4 + 2s = g_s[k]; on face s with third vertex c the micro-triangle
+    // (k, k+1, g_s[k]) is the macro-face (a, b, c) scaled and translated
+    for (int e = 0; e < E; ++e) {
+        const EdgeInfo& ei = edges[e];
+        const double de[2] = {X(ei.b, 0) - X(ei.a, 0), X(ei.b, 1) - X(ei.a, 1)};
+        StokesEdge& se = sedges[e];
+        for (int s = 0; s < ei.nf; ++s) {
+            const int f = ei.face[s];
+            int c = -1;
+            for (int k = 0; k < 3; ++k)
+                if (tri[f][k] != ei.a && tri[f][k] != ei.b) c = tri[f][k];
+            const double ds[2] = {X(c, 0) - X(ei.a, 0), X(c, 1) - X(ei.a, 1)};
+            // positions relative to point k of the slots used on this side
+            double pos[7][2] = {{0, 0}, {-de[0], -de[1]}, {de[0], de[1]}, {0, 0}, {0, 0}, {0, 0}, {0, 0}};
+            pos[3 + 2 * s][0] = ds[0] - de[0];
+            pos[3 + 2 * s][1] = ds[1] - de[1];
+            pos[4 + 2 * s][0] = ds[0];
+            pos[4 + 2 * s][1] = ds[1];
+            const int etri[3][3] = {{0, 2, 4 + 2 * s}, {1, 0, 3 + 2 * s}, {0, 4 + 2 * s, 3 + 2 * s}};
+            for (int k = 0; k < 3; ++k) {
+                double P[3][2];
+                int r = -1;
+                for (int a = 0; a < 3; ++a) {
+                    P[a][0] = pos[etri[k][a]][0];
+                    P[a][1] = pos[etri[k][a]][1];
+                    if (etri[k][a] == 0) r = a;
+                }
+                add_triangle<7>(P, r, etri[k], face_coef[f], delta, se.w, se.m);
+            }
+        }
+    }
+    // vertex: one corner micro-triangle per incident face, (v, ring q1,
+    // ring q2) with q1, q2 the face's two edges through v
+    for (int v = 0; v < V; ++v) {
+        const VertexInfo& vi = verts[v];
+        StokesVert& sv = sverts[v];
+        for (int c = 0; c < vi.nfc; ++c) {
+            const int f = vi.fc_face[c], cr = vi.fc_corner[c];
+            const int sa = cr == 2 ? 1 : 0, sb = cr == 0 ? 1 : 2;   // sides through the corner
+            int slot[3] = {0, -1, -1};
+            double P[3][2] = {{0, 0}, {0, 0}, {0, 0}};
+            const int es[2] = {faces[f].edge[sa], faces[f].edge[sb]};
+            for (int k = 0; k < 2; ++k) {
+                for (int q = 0; q < vi.deg; ++q)
+                    if (vi.edge[q] == es[k]) slot[1 + k] = 1 + q;
+                const EdgeInfo& ek = edges[es[k]];
+                const int other = ek.a == v ? ek.b : ek.a;
+                P[1 + k][0] = X(other, 0) - X(v, 0);
+                P[1 + k][1] = X(other, 1) - X(v, 1);
+            }
+            add_triangle<1 + MAXDEG>(P, 0, slot, face_coef[f], delta, sv.w, sv.m);
+        }
+    }
 }
 
 void MeshData::build_level(int level) {

@@ -164,14 +164,52 @@ def counters_summary(stats_dir, pmc_dirs, kernel, cmd, out, source="net.hip"):
         fh.write("\n".join(lines) + "\n")
 
 
+def cycle_breakdown(stats_dir, cycles, finest, cmd, out):
+    """Kernel time of `cycles` V-cycles by kernel and level.  The launches of
+    each kernel are grouped by grid size; within one kernel the grids are
+    distinct per level and shrink with it, so the k-th largest grid of a
+    kernel is taken as level finest - k (kernels launched on fewer levels,
+    e.g. the coarse solve, are labelled by the same rank)."""
+    dur = kernel_durations(stats_dir)
+    by_name = defaultdict(list)
+    for (name, grid), v in dur.items():
+        by_name[name.split("(")[0]].append((grid, v))
+    rows = []
+    for name, lst in by_name.items():
+        lst.sort(key=lambda gv: -gv[0])
+        for rank, (grid, v) in enumerate(lst):
+            rows.append((finest - rank, name, grid, len(v) / cycles, sum(v) / 1e3 / cycles))
+    rows.sort(key=lambda r: (-r[0], -r[4]))
+    per_level = defaultdict(float)
+    for lvl, _, _, _, us in rows:
+        per_level[lvl] += us
+    total = sum(per_level.values())
+    lines = ["# rocprofv3 per-level kernel time of one V-cycle", "", "command: " + cmd,
+             "cycles in the trace: %d; finest level %d" % (cycles, finest), "",
+             "kernel time per cycle by level (us):"]
+    for lvl in sorted(per_level, reverse=True):
+        lines.append("  level %2d  %9.1f  (%4.1f%%)" % (lvl, per_level[lvl], 100 * per_level[lvl] / total))
+    lines += ["  total     %9.1f" % total, "",
+              "by kernel (level, name, grid, launches per cycle, us per cycle):"]
+    for lvl, name, grid, cnt, us in rows:
+        lines.append("  %2d  %-70s %9d %6.1f %9.1f" % (lvl, name[:70], grid, cnt, us))
+    lines += ["", "json: " + json.dumps({"cycles": cycles, "finest": finest, "command": cmd,
+                                         "per_level_us": {str(k): v for k, v in per_level.items()},
+                                         "total_us": total})]
+    with open(out, "w") as fh:
+        fh.write("\n".join(lines) + "\n")
+
+
 def main():
     ap = argparse.ArgumentParser()
-    ap.add_argument("mode", choices=["summarize", "counters"])
+    ap.add_argument("mode", choices=["summarize", "counters", "cycle"])
+    ap.add_argument("--cycles", type=int, default=1)
+    ap.add_argument("--finest", type=int, default=10)
     ap.add_argument("--stats", required=True)
     ap.add_argument("--fetch")
     ap.add_argument("--write")
     ap.add_argument("--pmc", nargs="*", default=[])
-    ap.add_argument("--kernel", required=True)
+    ap.add_argument("--kernel", default="")
     ap.add_argument("--copy-bytes", type=int, default=0)
     ap.add_argument("--cmd", default="")
     ap.add_argument("--source", default=None, help="csrc file holding the kernel")
@@ -181,6 +219,8 @@ def main():
         s = summarize(a.stats, a.fetch, a.write, a.kernel, a.copy_bytes, a.cmd,
                       a.source or "kernels.hip")
         write_summary(s, a.out)
+    elif a.mode == "cycle":
+        cycle_breakdown(a.stats, a.cycles, a.finest, a.cmd, a.out)
     else:
         counters_summary(a.stats, a.pmc, a.kernel, a.cmd, a.out, a.source or "net.hip")
     print(open(a.out).read())

@@ -9,14 +9,24 @@ import hhg_inputs as hi
 
 
 # Bounds of the reduced-precision paths against the FP64 oracle (relative,
-# max norm).  FP32 V-cycle on FP32-representable inputs: unit roundoff 6e-8
-# times a growth factor of about 30 (7-term stencil sums, rounding damped by
-# the smoother rather than accumulated over the sweeps).  Mixed-precision
-# refinement to a relative residual of 1e-8: the final error against an
-# oracle solve to 1e-12 is the algebraic error of that residual, of order
-# 1e-8 times the error-to-residual ratio of a few, so 1e-7.
-F32_VCYCLE_TOL = 2e-6
+# max norm).  FP32 V-cycle on FP32-representable inputs: besides the rounding
+# of every operation (unit roundoff 6e-8, 7-term stencil sums), the FP32 path
+# rounds the operator's weights, a relative perturbation of the operator of
+# unit-roundoff size.  A V-cycle from a random iterate takes most of its
+# result from the coarse-grid correction of smooth error, and the perturbed
+# operator changes that correction by the perturbation times the ratio of
+# the operator's norm to its smallest eigenvalue on the coarse grid, a few
+# tens: 2.6e-6 and 3.1e-6 were measured at levels 8 and 9 (about 50 unit
+# roundoffs), 1e-5 is the bound.  Mixed-precision refinement to a relative
+# residual of 1e-8: the final error against an oracle solve to 1e-12 is the
+# algebraic error of that residual, of order 1e-8 times the error-to-residual
+# ratio of a few, so 1e-7.
+F32_VCYCLE_TOL = 1e-5
 MP_TOL = 1e-7
+
+
+def f32_vcycle_tol(level):
+    return F32_VCYCLE_TOL
 
 
 def rel_err(a, b):

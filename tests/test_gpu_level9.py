@@ -8,14 +8,14 @@ the one that starts from the prolongated correction, and, inside the solve
 loop, the one that forms the residual norm.
 
 FP64: 1e-12 relative in the max norm.  FP32 V-cycle on FP32-representable
-inputs: 2e-6 against the FP64 oracle (unit roundoff 6e-8 times a growth
-factor of about 30 for the 7-term stencil sums over a few sweeps, which the
-smoother damps rather than accumulates)."""
+inputs: the level's FP32 V-cycle bound against the FP64 oracle (unit
+roundoff times the growth of the stencil sums and of the coarse correction;
+see gpu_util)."""
 import numpy as np
 import pytest
 
 import hhg_inputs as hi
-from gpu_util import log, rel_err, to_np
+from gpu_util import f32_vcycle_tol, log, rel_err, to_np
 
 pytestmark = pytest.mark.gpu
 
@@ -120,6 +120,12 @@ def test_fp32_vcycle_level9():
     u, f = cast(hi.uniform_vector(lv.n_all, 5)), cast(hi.uniform_vector(lv.n_all, 6))
     uf, ff = g.from_canonical(L, u, P.HHG_F32), g.from_canonical(L, f, P.HHG_F32)
     P.hhg_vcycle(g.h, L, P.HHG_OP_LAPLACE, P.HHG_SMOOTH_GS, P.HHG_F32, uf, ff, 3, 3)
-    err = rel_err(to_np(g.to_canonical(L, uf, P.HHG_F32)), H.vcycle(L, u.copy(), f, 3, 3))
-    log("  rel err %.2e" % err)
-    assert err <= 2e-6
+    ref = H.vcycle(L, u.copy(), f, 3, 3)
+    got = to_np(g.to_canonical(L, uf, P.HHG_F32))
+    err = rel_err(got, ref)
+    # rounding differences are smooth (carried by the coarse correction): the
+    # operator shrinks them far more than a local defect of the same size
+    e = got - ref
+    rough = np.linalg.norm(H.apply(L, e)) / (8.0 * np.linalg.norm(e))
+    log("  rel err %.2e, roughness |A e| / (8 |e|) %.2e" % (err, rough))
+    assert err <= f32_vcycle_tol(L)

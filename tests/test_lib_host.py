@@ -44,6 +44,22 @@ def test_counts_and_coordinates_match_oracle(name, level):
         P.hhg_destroy_mesh(h)
 
 
+@pytest.mark.parametrize("name,level", [("square", 3), ("annulus64", 4), ("annulus128", 2)])
+def test_cell_centroids_match_oracle(name, level):
+    """The library's canonical cell order and geometry (micro-triangle
+    centroids) against the oracle's cell list."""
+    from oracle import transport as tr
+    vxy, tri = hi.mesh_by_name(name)
+    h = P.hhg_setup_mesh(vxy, tri, max(level, 2), 1)
+    try:
+        c = tr.Cells(Level(MacroMesh(vxy, tri), level))
+        xy = P.hhg_cell_coords(h, level, len(tri))
+        assert xy.shape == c.centroid.shape
+        assert np.abs(xy - c.centroid).max() <= 1e-15
+    finally:
+        P.hhg_destroy_mesh(h)
+
+
 def test_paper_count_at_level6():
     """2145 points per face at level 6 (sec. 5.2): n_all of one face."""
     vxy = np.array([[0.0, 0.0], [1.0, 0.0], [0.0, 1.0]])
