@@ -292,6 +292,24 @@ int hhg_dot(const hhg_mesh* mesh, int32_t level, int32_t dtype, const void* x,
             const void* y, double* out, void* stream);
 
 /*
+ * hhg_dot without the workspace's scratch, for callers that cannot allocate
+ * device memory or must not touch the workspace (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid allocation): the same
+ * kernels and summation order as hhg_dot, so the same result bit for bit,
+ * with the per-block partial sums (at most 9216 doubles, 72 KiB) in a static
+ * device array of the library.  It allocates nothing and frees nothing; each
+ * device that runs it holds its own copy of the array from the library's
+ * first use on that device (workspace binding or the first call) until the
+ * process ends.  Every call on a device shares that device's array: calls
+ * that overlap on one device (different streams or threads) race.  The
+ * tables of a bound workspace are still read (hhg_bind_workspace first).
+ * Errors: as hhg_dot; HHG_EINVAL if the level would need more partial sums
+ * than the array holds.
+ */
+int hhg_dot_noalloc(const hhg_mesh* mesh, int32_t level, int32_t dtype, const void* x,
+                    const void* y, double* out, void* stream);
+
+/*
  * z = alpha x + beta y over whole fields of `level` (sec. 4.1 Alg. 1,
  * assign; purely local, copies stay consistent).  z may alias x or y.
  */

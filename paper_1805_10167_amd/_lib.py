@@ -88,6 +88,7 @@ _SIGS = {
     "hhg_net_forward": (_c.c_int, [_vp, _i32, _vp, _vp, _vp]),
     "hhg_net_backward": (_c.c_int, [_vp, _i32, _vp, _vp, _vp, _vp]),
     "hhg_net_adam_step": (_c.c_int, [_vp, _vp, _c.c_float, _i32, _vp]),
+    "hhg_dot_noalloc": (_c.c_int, [_vp, _i32, _i32, _vp, _vp, _vp, _vp]),
     "hhg_set_face_coefficient": (_c.c_int, [_vp, _vp, _vp]),
     "hhg_stokes_setup": (_c.c_int, [_vp, _vp, _c.c_double, _vp]),
     "hhg_stokes_apply": (_c.c_int, [_vp, _i32, _vp, _vp, _vp]),
@@ -221,6 +222,10 @@ def hhg_to_canonical(h, level, dtype, field, canon, stream=None):
 
 def hhg_set_coefficient(h, k_canon, stream=None):
     _check(lib().hhg_set_coefficient(h, _ptr(k_canon), _stream(stream)))
+
+
+def hhg_dot_noalloc(h, level, dtype, x, y, out, stream=None):
+    _check(lib().hhg_dot_noalloc(h, level, dtype, _ptr(x), _ptr(y), _ptr(out), _stream(stream)))
 
 
 def hhg_set_face_coefficient(h, coef, stream=None):

@@ -441,6 +441,7 @@ int hhg_bind_workspace(hhg_mesh* M, uint32_t features, void* dptr, size_t bytes,
     // hold zeros in every workspace field, whatever the memory held before
     HIP_CHECK(hipMemsetAsync(dptr, 0, need, s), "workspace clear");
     if ((rc = solve_norm_slot(M))) return rc;
+    HIP_CHECK(scratch_init(), "static scratch");
     Carver c(dptr);
     carve(M, features, c);
     MeshData& m = M->m;
@@ -751,6 +752,17 @@ int hhg_dot(const hhg_mesh* M, int32_t level, int32_t dtype, const void* x, cons
     if (rc) return rc;
     if (!x || !y || !out) return fail(HHG_EINVAL, "null buffer");
     HIP_CHECK(launch_dot(M, level, dtype, x, y, out, (hipStream_t)stream), "dot");
+    return HHG_OK;
+}
+
+int hhg_dot_noalloc(const hhg_mesh* M, int32_t level, int32_t dtype, const void* x, const void* y,
+                    double* out, void* stream) {
+    int rc = check_common(M, level, dtype);
+    if (rc) return rc;
+    if (!x || !y || !out) return fail(HHG_EINVAL, "null buffer");
+    if (!dot_noalloc_fits(M, level))
+        return fail(HHG_EINVAL, "dot needs more partial sums than the static scratch holds");
+    HIP_CHECK(launch_dot_noalloc(M, level, dtype, x, y, out, (hipStream_t)stream), "dot (static scratch)");
     return HHG_OK;
 }
 

@@ -102,6 +102,15 @@ hipError_t launch_dot(const hhg_mesh* M, int level, int dtype, const void* x, co
 hipError_t launch_axpby(int64_t n, int dtype, double alpha, const void* x, double beta, const void* y,
                         void* z, hipStream_t s);
 
+// The dot product of launch_dot with its partial sums in the library's
+// static device scratch instead of the workspace (no allocation; calls that
+// overlap on one device share that scratch and race).
+bool dot_noalloc_fits(const hhg_mesh* M, int level);
+hipError_t launch_dot_noalloc(const hhg_mesh* M, int level, int dtype, const void* x, const void* y,
+                              double* out, hipStream_t s);
+// Device address of the static scratch on the current device (once per
+// device; later calls return at once).
+hipError_t scratch_init();
 // *out = fixed-order sum of partials[0, count).
 hipError_t launch_reduce(const double* partials, int64_t count, double* out, hipStream_t s);
 

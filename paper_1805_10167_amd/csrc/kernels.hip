@@ -16,6 +16,7 @@
 
 #include <algorithm>
 #include <cstddef>
+#include <mutex>
 
 #include <cstdint>
 
@@ -2320,6 +2321,61 @@ hipError_t launch_dot(const hhg_mesh* M, int level, int dtype, const void* x, co
     if (dtype == DT_F64) k_dot<double><<<gf + gl, NT, 0, s>>>(L, (const double*)x, (const double*)y, gf, M->partials);
     else k_dot<float><<<gf + gl, NT, 0, s>>>(L, (const float*)x, (const float*)y, gf, M->partials);
     k_reduce_final<<<1, 1024, 0, s>>>(M->partials, gf + gl, out, 0);
+    return hipGetLastError();
+}
+
+// Scratch of the allocation-free dot product: one partial sum per block of
+// k_dot (at most MAX_FACE_BLOCKS face blocks plus MAX_LOW_BLOCKS edge/vertex
+// blocks), 72 KiB per device, held from the library's first use on that
+// device until the process ends.  Host code reaches it only through the
+// device address hipGetSymbolAddress returns on each device.
+constexpr int64_t SCRATCH_PARTIALS = (int64_t)MAX_FACE_BLOCKS + MAX_LOW_BLOCKS;
+static __device__ __align__(256) double scratch[SCRATCH_PARTIALS];
+
+namespace {
+constexpr int SCRATCH_MAX_DEVICES = 64;
+std::mutex g_scratch_mu;
+double* g_scratch_ptr[SCRATCH_MAX_DEVICES] = {};
+}  // namespace
+
+hipError_t scratch_init() {
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    if (dev < 0 || dev >= SCRATCH_MAX_DEVICES) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (g_scratch_ptr[dev]) return hipSuccess;
+    void* p = nullptr;
+    e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    g_scratch_ptr[dev] = (double*)p;
+    return hipSuccess;
+}
+
+// Partial sums k_dot needs on `level`, and whether they fit the scratch.
+static int64_t dot_partials(const LevelDev& L) {
+    return (int64_t)face_grid(L) + grid_for((int64_t)L.n_iedges * (L.n - 2) + L.n_iverts, MAX_LOW_BLOCKS);
+}
+bool dot_noalloc_fits(const hhg_mesh* M, int level) { return dot_partials(M->dev(level)) <= SCRATCH_PARTIALS; }
+
+hipError_t launch_dot_noalloc(const hhg_mesh* M, int level, int dtype, const void* x, const void* y,
+                              double* out, hipStream_t s) {
+    hipError_t e = scratch_init();
+    if (e != hipSuccess) return e;
+    int dev = 0;
+    if ((e = hipGetDevice(&dev)) != hipSuccess) return e;
+    double* part = nullptr;
+    {
+        std::lock_guard<std::mutex> lock(g_scratch_mu);
+        part = g_scratch_ptr[dev];
+    }
+    const LevelDev L = M->dev(level);
+    const int gf = face_grid(L);
+    const int gl = grid_for((int64_t)L.n_iedges * (L.n - 2) + L.n_iverts, MAX_LOW_BLOCKS);
+    if ((int64_t)gf + gl > SCRATCH_PARTIALS) return hipErrorInvalidValue;   // callers check first
+    if (dtype == DT_F64) k_dot<double><<<gf + gl, NT, 0, s>>>(L, (const double*)x, (const double*)y, gf, part);
+    else k_dot<float><<<gf + gl, NT, 0, s>>>(L, (const float*)x, (const float*)y, gf, part);
+    k_reduce_final<<<1, 1024, 0, s>>>(part, gf + gl, out, 0);
     return hipGetLastError();
 }
 
