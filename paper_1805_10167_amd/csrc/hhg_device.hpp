@@ -79,12 +79,15 @@ __device__ __forceinline__ double block_sum(double v, double* sm) {
     return sm[NTH / 64];
 }
 
-// Generic loop over face-interior points in 64 x 4 tiles.
-#define FACE_TILE_LOOP(L)                                                                   \
+// Generic loop over face-interior points in 64 x 4 tiles, grid-stride over
+// the first GF blocks (the face blocks of the launch: a launch that also has
+// edge/vertex blocks passes its face-block count, a face-only launch
+// gridDim.x).
+#define FACE_TILE_LOOP(L, GF)                                                               \
     const int n = (L).n;                                                                    \
     const int ti_ = threadIdx.x & (TILE_I - 1), tj_ = wave_id();                          \
     const int64_t nitems_ = (int64_t)(L).F * (L).ntiles;                                    \
-    for (int64_t it_ = blockIdx.x; it_ < nitems_; it_ += gridDim.x) {                      \
+    for (int64_t it_ = blockIdx.x; it_ < nitems_; it_ += (GF)) {                           \
         const int face = (int)(it_ / (L).ntiles);                                           \
         const int2 tl_ = (L).tiles[it_ % (L).ntiles];                                       \
         const int i = tl_.x * TILE_I + ti_, j = tl_.y * TILE_J + tj_;                       \

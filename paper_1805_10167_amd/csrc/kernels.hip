@@ -1496,7 +1496,7 @@ __global__ __launch_bounds__(NT) void k_prolong(LevelDev Lf, LevelDev Lc, const 
 template <class T>
 __global__ __launch_bounds__(NT) void k_face_canon(LevelDev L, const T* __restrict__ src,
                                                    T* __restrict__ dst, int to_canon) {
-    FACE_TILE_LOOP(L)
+    FACE_TILE_LOOP(L, gridDim.x)
     (void)fi; (void)up; (void)dn;
     const int64_t nfi = (int64_t)(n - 2) * (n - 3) / 2;
     const int64_t before = (int64_t)(j - 1) * (n - 2) - (int64_t)(j - 1) * j / 2;
@@ -1529,7 +1529,7 @@ __global__ __launch_bounds__(NT) void k_low_canon(LevelDev L, const T* __restric
 template <class T>
 __global__ __launch_bounds__(NT) void k_face_inject(LevelDev Lf, LevelDev Lc, const T* __restrict__ kf,
                                                     T* __restrict__ kc) {
-    FACE_TILE_LOOP(Lc)
+    FACE_TILE_LOOP(Lc, gridDim.x)
     (void)fi; (void)up; (void)dn;
     kc[p] = kf[face_base(Lf, face) + row_start(Lf.n, 2 * j) + 2 * i];
     FACE_TILE_END

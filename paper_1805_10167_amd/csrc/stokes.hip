@@ -93,7 +93,7 @@ __global__ __launch_bounds__(NT) void k_stokes_apply(LevelDev L, const double* _
     double* yy_ = y + fs;
     double* yp_ = y + 2 * fs;
     if ((int)blockIdx.x < gf) {
-        FACE_TILE_LOOP(L)
+        FACE_TILE_LOOP(L, gf)
         const StokesFace& sf = L.sfaces[face];
         const FaceNbr q = face_nbr(p, up, dn);
         double ux[7], uy[7], pp[7];
@@ -201,7 +201,7 @@ __global__ __launch_bounds__(NT) void k_stokes_pscale_dot(LevelDev L, const doub
     const double* rp = r + 2 * fs;
     double* zp = z + 2 * fs;
     if ((int)blockIdx.x < gf) {
-        FACE_TILE_LOOP(L)
+        FACE_TILE_LOOP(L, gf)
         (void)up;
         (void)dn;
         const double v = rp[p] / (hC * L.sfaces[face].m);
@@ -240,7 +240,7 @@ __global__ __launch_bounds__(NT) void k_stokes_dot(LevelDev L, const double* __r
     __shared__ double sm[NT / 64 + 1];
     double acc = 0.0;
     if ((int)blockIdx.x < gf) {
-        FACE_TILE_LOOP(L)
+        FACE_TILE_LOOP(L, gf)
         (void)fi;
         (void)up;
         (void)dn;

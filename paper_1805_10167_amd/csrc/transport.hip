@@ -127,7 +127,7 @@ __global__ __launch_bounds__(NT) void k_fv_buoyancy(LevelDev L, const double* __
     double* bx = b;
     double* by = b + fs;
     if ((int)blockIdx.x < gf) {
-        FACE_TILE_LOOP(L)
+        FACE_TILE_LOOP(L, gf)
         (void)up;
         (void)dn;
         const FvFace& fv = L.fvfaces[face];

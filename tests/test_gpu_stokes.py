@@ -242,3 +242,52 @@ def test_stokes_errors():
         P.hhg_stokes_precond(g2.h, P.HHG_F32, x, y, 2, 2)   # no FP32 hierarchy
     with pytest.raises(P.HHGError):
         P.hhg_stokes_setup(g2.h, np.ones(len(tri)), 0.0)
+
+
+def test_operator_and_solve_with_more_tiles_than_face_blocks():
+    """Level 8 of the 64-face annulus has 10,560 face tiles, more than the
+    8,192 face blocks of a launch, so the face blocks loop over tiles: the
+    operator against the oracle's assembly element by element, and a MINRES
+    solve that converges in the level-independent iteration count (about
+    225 at levels 5-7)."""
+    import torch
+
+    import paper_1805_10167_amd as P
+    from oracle import stokes as S
+    from oracle.mesh import Level, MacroMesh
+    L = 8
+    vxy, tri = hi.mesh_by_name("annulus64")
+    m = MacroMesh(vxy, tri)
+    mu = S.face_viscosity(m)
+    log("stokes operator annulus64 L=%d (face grid capped)" % L)
+    lv = Level(m, L)
+    blk = S.assemble_stokes(lv, mu)
+    g = P.Mesh(vxy, tri, L, 2, P.HHG_FEAT_F64 | P.HHG_FEAT_MP | P.HHG_FEAT_STOKES)
+    P.hhg_stokes_setup(g.h, mu, S.DELTA)
+    N = lv.n_all
+    x = hi.uniform_vector(3 * N, 21)
+    x[:N][lv.dirichlet] = 0.0
+    x[N:2 * N][lv.dirichlet] = 0.0
+    y = g.stokes_vector(L)
+    P.hhg_stokes_apply(g.h, L, g.stokes_from_canonical(L, x), y)
+    ux, uy, p = x[:N], x[N:2 * N], x[2 * N:]
+    ref = np.concatenate([blk["A"] @ ux + blk["Bx"].T @ p, blk["A"] @ uy + blk["By"].T @ p,
+                          blk["Bx"] @ ux + blk["By"] @ uy - blk["C"] @ p])
+    ref[:N][lv.dirichlet] = 0.0
+    ref[N:2 * N][lv.dirichlet] = 0.0
+    err = rel_err(to_np(g.stokes_to_canonical(L, y)), ref)
+    log("  rel err %.2e" % err)
+    assert err <= F64_TOL
+    b = g.stokes_vector(L)
+    P.hhg_stokes_apply(g.h, L, g.stokes_from_canonical(L, x), b)
+    z = g.stokes_vector(L)
+    rc, st, hist = P.hhg_stokes_solve(g.h, z, b, rtol=1e-8, max_iters=600)
+    log("  MINRES: %d iterations, rel %.2e" % (st["iters"], st["rel_res"]))
+    assert rc == 0 and st["iters"] <= 300
+    r = g.stokes_vector(L)
+    P.hhg_stokes_residual(g.h, L, z, b, r)
+    d = torch.zeros(2, dtype=torch.float64, device="cuda")
+    P.hhg_stokes_dot(g.h, L, r, r, d[0:1])
+    P.hhg_stokes_dot(g.h, L, b, b, d[1:2])
+    dd = d.cpu().numpy()
+    assert np.sqrt(dd[0] / dd[1]) <= 1e-5

@@ -168,3 +168,31 @@ def test_full_size_step_and_load():
     err = rel_err(to_np(g.stokes_to_canonical(L, b)), np.concatenate([bx, by, np.zeros(lv.n_all)]))
     log("  load rel err %.2e" % err)
     assert err <= F64_TOL
+
+
+def test_buoyancy_with_more_tiles_than_face_blocks():
+    """Level 8 of the 64-face annulus (10,560 face tiles against 8,192 face
+    blocks): the load of T = 1 is -Ra r_hat_i times the integral of phi_i,
+    the row sum of the consistent mass matrix."""
+    import torch
+
+    import paper_1805_10167_amd as P
+    from oracle import stokes as S
+    from oracle.assemble import assemble
+    from oracle.mesh import Level, MacroMesh
+    L = 8
+    vxy, tri = hi.mesh_by_name("annulus64")
+    lv = Level(MacroMesh(vxy, tri), L)
+    mrow = np.asarray(assemble(lv, want=("M",))["M"].sum(axis=1)).ravel()
+    g = P.Mesh(vxy, tri, L, 2, P.HHG_FEAT_F64 | P.HHG_FEAT_MP | P.HHG_FEAT_STOKES)
+    P.hhg_stokes_setup(g.h, np.ones(len(tri)), S.DELTA)
+    T = torch.ones(2 * P.hhg_field_elems(g.h, L), dtype=torch.float64, device="cuda")
+    b = g.stokes_vector(L)
+    P.hhg_buoyancy(g.h, L, T, 3.0, b)
+    r = np.hypot(lv.xy[:, 0], lv.xy[:, 1])
+    ref = np.concatenate([-3.0 * mrow * lv.xy[:, 0] / r, -3.0 * mrow * lv.xy[:, 1] / r, np.zeros(lv.n_all)])
+    ref[:lv.n_all][lv.dirichlet] = 0.0
+    ref[lv.n_all:2 * lv.n_all][lv.dirichlet] = 0.0
+    err = rel_err(to_np(g.stokes_to_canonical(L, b)), ref)
+    log("buoyancy of T = 1 at annulus64 L=%d: rel err %.2e" % (L, err))
+    assert err <= F64_TOL
