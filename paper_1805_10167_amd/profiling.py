@@ -4,6 +4,8 @@
         --stats DIR --fetch DIR --write DIR --kernel NAME --out FILE --cmd "..."
     python -m paper_1805_10167_amd.profiling counters \
         --stats DIR --pmc DIR [DIR ...] --kernel NAME --out FILE --cmd "..."
+    python -m paper_1805_10167_amd.profiling trace \
+        --stats DIR --kernels NAME ... --alg-bytes B ... --source FILE --out FILE --cmd "..."
 
 reads the kernel-trace CSV of one run (average duration per kernel and grid
 size) and the counter CSVs of two --pmc runs (FETCH_SIZE, WRITE_SIZE, KiB
@@ -23,9 +25,9 @@ from collections import defaultdict
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
-HEADERS = ["hhg_internal.hpp", "hhg_kernels.hpp", "hhg_mesh.hpp"]
+HEADERS = ["hhg_internal.hpp", "hhg_kernels.hpp", "hhg_mesh.hpp", "hhg_device.hpp"]
 # the files a profiled kernel is built from, by the source file holding it
-SOURCES = {"kernels.hip": ["kernels.hip"] + HEADERS, "net.hip": ["net.hip"] + HEADERS}
+SOURCES = {name: [name] + HEADERS for name in ("kernels.hip", "net.hip", "stokes.hip", "transport.hip")}
 COPY_KERNEL = "__amd_rocclr_copyBuffer"
 
 
@@ -62,8 +64,13 @@ def counter_values(pmc_dir):
     return out
 
 
+def _plain(name):
+    """Kernel name without the "void " that template instances carry."""
+    return name[5:] if name.startswith("void ") else name
+
+
 def _largest(d, name):
-    keys = [k for k in d if k[0].startswith(name)]
+    keys = [k for k in d if _plain(k[0]).startswith(_plain(name))]
     if not keys:
         raise KeyError(name)
     return max(keys, key=lambda k: k[1])
@@ -92,6 +99,35 @@ def summarize(stats_dir, fetch_dir, write_dir, kernel, copy_bytes, cmd, source="
         "top_kernels_us": [[k[0].split("(")[0][:80], k[1], len(v), sum(v) / 1e3, mean(v) / 1e3]
                            for k, v in top],
     }
+
+
+def trace_summary(stats_dir, kernels, bytes_per_dispatch, cmd, out, source):
+    """Average duration of the largest-grid dispatches of each kernel in
+    `kernels`, with the achieved rate of its algorithmic bytes per dispatch
+    (0: not stated)."""
+    dur = kernel_durations(stats_dir)
+    mean = lambda v: sum(v) / len(v)
+    lines = ["# rocprofv3 kernel trace: %s" % ", ".join(kernels), "", "command: " + cmd,
+             "kernel source hash: %s (%s)" % (source_hash(SOURCES[source]), ", ".join(SOURCES[source])), "",
+             "kernel, grid, dispatches, average us, algorithmic MB per dispatch, TB/s:"]
+    rec = []
+    for name, nb in zip(kernels, bytes_per_dispatch):
+        kd = _largest(dur, name)
+        us = mean(dur[kd]) / 1e3
+        rate = nb / (us * 1e-6) / 1e12 if nb else 0.0
+        lines.append("  %-60s %8d %7d %9.2f %9.1f %6.2f" % (kd[0].split("(")[0][:60], kd[1], len(dur[kd]), us,
+                                                            nb / 1e6, rate))
+        rec.append({"kernel": kd[0].split("(")[0], "grid": kd[1], "dispatches": len(dur[kd]),
+                    "avg_duration_us": us, "alg_bytes": nb, "tb_per_s": rate})
+    top = sorted(dur.items(), key=lambda kv: -sum(kv[1]))[:16]
+    lines += ["", "top kernels by total time (name, grid, dispatches, total us, avg us):"]
+    for k, v in top:
+        lines.append("  %-70s %9d %7d %10.1f %9.2f" % (k[0].split("(")[0][:70], k[1], len(v), sum(v) / 1e3,
+                                                      mean(v) / 1e3))
+    lines += ["", "json: " + json.dumps({"kernels": rec, "command": cmd, "source_files": SOURCES[source],
+                                         "source_hash": source_hash(SOURCES[source])})]
+    with open(out, "w") as fh:
+        fh.write("\n".join(lines) + "\n")
 
 
 def write_summary(s, path):
@@ -202,7 +238,9 @@ def cycle_breakdown(stats_dir, cycles, finest, cmd, out):
 
 def main():
     ap = argparse.ArgumentParser()
-    ap.add_argument("mode", choices=["summarize", "counters", "cycle"])
+    ap.add_argument("mode", choices=["summarize", "counters", "cycle", "trace"])
+    ap.add_argument("--kernels", nargs="*", default=[])
+    ap.add_argument("--alg-bytes", nargs="*", type=float, default=[])
     ap.add_argument("--cycles", type=int, default=1)
     ap.add_argument("--finest", type=int, default=10)
     ap.add_argument("--stats", required=True)
@@ -219,6 +257,9 @@ def main():
         s = summarize(a.stats, a.fetch, a.write, a.kernel, a.copy_bytes, a.cmd,
                       a.source or "kernels.hip")
         write_summary(s, a.out)
+    elif a.mode == "trace":
+        nb = a.alg_bytes + [0.0] * (len(a.kernels) - len(a.alg_bytes))
+        trace_summary(a.stats, a.kernels, nb, a.cmd, a.out, a.source or "stokes.hip")
     elif a.mode == "cycle":
         cycle_breakdown(a.stats, a.cycles, a.finest, a.cmd, a.out)
     else:
