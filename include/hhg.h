@@ -86,6 +86,7 @@ extern "C" {
 #define HHG_FEAT_VARK 4u     /* per-level coefficient fields                 */
 #define HHG_FEAT_NET  8u     /* learned-smoother buffers                     */
 #define HHG_FEAT_STOKES 16u  /* Stokes stencils and MINRES vectors (needs F64) */
+#define HHG_FEAT_P2   32u    /* P2 stencils and boundary partials (needs F64) */
 
 /* solver modes */
 #define HHG_MODE_PLAIN_FP64 0
@@ -509,6 +510,73 @@ int hhg_buoyancy(const hhg_mesh* mesh, int32_t level, const double* T, double Ra
                  void* stream);
 int hhg_energy_run(hhg_mesh* mesh, const hhg_energy_opts* opts, void* x, void* T,
                    hhg_energy_stats* stats, void* stream);
+
+/*
+ * Quadratic (P2) elements and p-multigrid (sec. 3.1: unknowns on the
+ * micro-vertices and micro-edges, edge unknowns in three subgroups by edge
+ * direction; sec. 4.2, Fig. 8: a stencil per unknown type; sec. 4.3:
+ * transfers between P1 and P2 on the same refinement level).
+ *
+ * The P2 unknowns of level l are the points of level l + 1: a P2 field of
+ * level l is a field of the level-(l+1) layout (hhg_field_elems(l + 1)
+ * values, owned values and ghost copies, converted with
+ * hhg_from_canonical / hhg_to_canonical at level l + 1).  Face-local point
+ * (i, j) of that layout is a vertex of level l when i and j are even, else
+ * the midpoint of a micro-edge of level l: i odd, j even: i-direction edge;
+ * i even, j odd: j-direction edge; both odd: diagonal edge.  Operator: the
+ * Laplacian times the coefficient per macro-face of
+ * hhg_set_face_coefficient (1 by default); Dirichlet points as for P1.
+ * Needs a workspace bound with HHG_FEAT_P2 | HHG_FEAT_F64 on a mesh whose
+ * max_level is at least l + 1; P2 calls take the P2 level l, with
+ * 1 <= l < max_level.
+ *
+ * hhg_p2_setup: builds the P2 stencils from the current face coefficients
+ *   (host) and uploads them; again after every hhg_set_face_coefficient.
+ * hhg_p2_apply: y = A2 x on interior rows, 0 on Dirichlet rows (copies
+ *   written).  x and y distinct.
+ * hhg_p2_residual: r = f - A2 x, 0 on Dirichlet rows.
+ * hhg_p2_jacobi: y = x + omega D^-1 (f - A2 x) on interior points (damped
+ *   point Jacobi, all points from the old values), Dirichlet values copied.
+ * hhg_p2_solve: p-multigrid cycles until |f - A2 x| <= rtol |f - A2 x0|
+ *   (Euclidean norm over interior points): nu1 Jacobi sweeps, residual,
+ *   restriction to P1 on level l by the transpose of the P1 -> P2
+ *   embedding, one P1 V(vnu1, vnu2) cycle of the h-hierarchy from zero,
+ *   prolongation by the embedding and correction, nu2 Jacobi sweeps.  The
+ *   embedding coincides with the P1 interpolation from level l to level
+ *   l + 1, so the transfers are those of hhg_restrict / hhg_prolong_add at
+ *   level l + 1.  Synchronises the stream once per cycle (norm read).
+ *   Returns HHG_ENOTCONV if max_iters is reached first; x holds the last
+ *   iterate.
+ * Errors: HHG_ENOMEM without HHG_FEAT_P2 (or HHG_FEAT_F64 for the solve),
+ *   HHG_EINVAL before setup, for a level out of range or bad options.
+ */
+typedef struct {
+    int32_t level;             /* P2 level l (fields of level l + 1)         */
+    double rtol;               /* relative residual to reach                 */
+    int32_t max_iters;         /* p-multigrid cycles at most                 */
+    int32_t nu1, nu2;          /* P2 Jacobi sweeps before / after            */
+    int32_t vnu1, vnu2;        /* smoothing of the P1 V-cycle                */
+    double omega;              /* Jacobi damping (0.7 suits the Laplacian)   */
+    double* res_history;       /* optional host array of residual norms      */
+    int32_t history_capacity;  /* its length                                 */
+} hhg_p2_opts;
+
+typedef struct {
+    int32_t iters;             /* cycles done                                */
+    int32_t converged;         /* 1 if rtol was reached                      */
+    double res0;               /* initial residual norm                      */
+    double rel_res;            /* final / initial                            */
+    double ms;                 /* host wall time of the call                 */
+} hhg_p2_stats;
+
+int hhg_p2_setup(hhg_mesh* mesh, void* stream);
+int hhg_p2_apply(const hhg_mesh* mesh, int32_t level, const void* x, void* y, void* stream);
+int hhg_p2_residual(const hhg_mesh* mesh, int32_t level, const void* x, const void* f, void* r,
+                    void* stream);
+int hhg_p2_jacobi(const hhg_mesh* mesh, int32_t level, double omega, const void* x, const void* f,
+                  void* y, void* stream);
+int hhg_p2_solve(hhg_mesh* mesh, const hhg_p2_opts* opts, void* x, const void* f, hhg_p2_stats* stats,
+                 void* stream);
 
 /*
  * Per-kernel timing of the finest-level smoother launches, for profiling:

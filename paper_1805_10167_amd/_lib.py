@@ -16,7 +16,7 @@ HHG_OK, HHG_EINVAL, HHG_ENOMEM, HHG_EHIP, HHG_ENOTCONV = 0, -1, -2, -3, -4
 HHG_F64, HHG_F32, HHG_BF16 = 0, 1, 2
 HHG_OP_LAPLACE, HHG_OP_DIFFUSION, HHG_OP_MASS = 0, 1, 2
 HHG_SMOOTH_GS, HHG_SMOOTH_NET = 0, 1
-HHG_FEAT_F64, HHG_FEAT_MP, HHG_FEAT_VARK, HHG_FEAT_NET, HHG_FEAT_STOKES = 1, 2, 4, 8, 16
+HHG_FEAT_F64, HHG_FEAT_MP, HHG_FEAT_VARK, HHG_FEAT_NET, HHG_FEAT_STOKES, HHG_FEAT_P2 = 1, 2, 4, 8, 16, 32
 HHG_MODE_PLAIN_FP64, HHG_MODE_MP_IR, HHG_MODE_LEARNED = 0, 1, 2
 
 _c = ctypes
@@ -56,6 +56,17 @@ class hhg_energy_stats(_c.Structure):
     _fields_ = [("steps", _i32), ("stokes_solves", _i32), ("minres_iters", _i64),
                 ("worst_rel_res", _c.c_double), ("ms", _c.c_double)]
 
+
+
+class hhg_p2_opts(_c.Structure):
+    _fields_ = [("level", _i32), ("rtol", _c.c_double), ("max_iters", _i32), ("nu1", _i32), ("nu2", _i32),
+                ("vnu1", _i32), ("vnu2", _i32), ("omega", _c.c_double),
+                ("res_history", _c.POINTER(_c.c_double)), ("history_capacity", _i32)]
+
+
+class hhg_p2_stats(_c.Structure):
+    _fields_ = [("iters", _i32), ("converged", _i32), ("res0", _c.c_double), ("rel_res", _c.c_double),
+                ("ms", _c.c_double)]
 
 # name -> (restype, argtypes); restype int unless stated
 _SIGS = {
@@ -106,6 +117,11 @@ _SIGS = {
     "hhg_buoyancy": (_c.c_int, [_vp, _i32, _vp, _c.c_double, _vp, _vp]),
     "hhg_energy_run": (_c.c_int, [_vp, _c.POINTER(hhg_energy_opts), _vp, _vp,
                                   _c.POINTER(hhg_energy_stats), _vp]),
+    "hhg_p2_setup": (_c.c_int, [_vp, _vp]),
+    "hhg_p2_apply": (_c.c_int, [_vp, _i32, _vp, _vp, _vp]),
+    "hhg_p2_residual": (_c.c_int, [_vp, _i32, _vp, _vp, _vp, _vp]),
+    "hhg_p2_jacobi": (_c.c_int, [_vp, _i32, _c.c_double, _vp, _vp, _vp, _vp]),
+    "hhg_p2_solve": (_c.c_int, [_vp, _c.POINTER(hhg_p2_opts), _vp, _vp, _c.POINTER(hhg_p2_stats), _vp]),
 }
 
 _lib = None
@@ -306,6 +322,38 @@ def hhg_energy_run(h, x, T, Ra, dt, steps, stokes_every=3, precision=HHG_F64, rt
     if rc not in (HHG_OK, HHG_ENOTCONV):
         _check(rc)
     return rc, {k: getattr(st, k) for k, _ in hhg_energy_stats._fields_}
+
+
+def hhg_p2_setup(h, stream=None):
+    _check(lib().hhg_p2_setup(h, _stream(stream)))
+
+
+def hhg_p2_apply(h, level, x, y, stream=None):
+    _check(lib().hhg_p2_apply(h, level, _ptr(x), _ptr(y), _stream(stream)))
+
+
+def hhg_p2_residual(h, level, x, f, r, stream=None):
+    _check(lib().hhg_p2_residual(h, level, _ptr(x), _ptr(f), _ptr(r), _stream(stream)))
+
+
+def hhg_p2_jacobi(h, level, omega, x, f, y, stream=None):
+    _check(lib().hhg_p2_jacobi(h, level, float(omega), _ptr(x), _ptr(f), _ptr(y), _stream(stream)))
+
+
+def hhg_p2_solve(h, level, x, f, rtol=1e-8, max_iters=100, nu1=3, nu2=3, vnu1=2, vnu2=2, omega=0.7,
+                 history=True, stream=None):
+    """Returns (status, stats dict, residual history list)."""
+    hist = np.zeros(max_iters + 1) if history else None
+    o = hhg_p2_opts(level, rtol, max_iters, nu1, nu2, vnu1, vnu2, omega,
+                    hist.ctypes.data_as(_c.POINTER(_c.c_double)) if history else None,
+                    len(hist) if history else 0)
+    st = hhg_p2_stats()
+    rc = lib().hhg_p2_solve(h, _c.byref(o), _ptr(x), _ptr(f), _c.byref(st), _stream(stream))
+    if rc not in (HHG_OK, HHG_ENOTCONV):
+        _check(rc)
+    stats = {k: getattr(st, k) for k, _ in hhg_p2_stats._fields_}
+    hl = list(hist[:st.iters + 1]) if history else []
+    return rc, stats, hl
 
 
 def hhg_apply(h, level, op, dtype, x, y, stream=None):

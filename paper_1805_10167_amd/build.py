@@ -6,7 +6,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libhhg.so")
-SOURCES = ["mesh.cpp", "capi.cpp", "kernels.hip", "net.hip", "stokes.hip", "transport.hip"]
+SOURCES = ["mesh.cpp", "capi.cpp", "kernels.hip", "net.hip", "stokes.hip", "transport.hip", "p2.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",

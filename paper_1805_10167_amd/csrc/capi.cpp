@@ -148,6 +148,14 @@ void carve(hhg_mesh* M, uint32_t feat, Carver& c) {
         M->b_stokes = (double*)c.take(sizeof(double) * 3 * (size_t)m.lv[m.L].total);
         M->t_cells = (double*)c.take(sizeof(double) * 2 * (size_t)m.lv[m.L].total);
     }
+    M->d_p2faces = nullptr;
+    M->d_p2ediag = M->d_p2vdiag = M->p2part = nullptr;
+    if (feat & HHG_FEAT_P2) {
+        M->d_p2faces = (P2Face*)c.take(sizeof(P2Face) * m.F);
+        M->d_p2ediag = (double*)c.take(sizeof(double) * 2 * (size_t)m.E);
+        M->d_p2vdiag = (double*)c.take(sizeof(double) * m.V);
+        M->p2part = (double*)c.take(sizeof(double) * 3 * (size_t)m.F * m.lv[m.L].n);
+    }
 }
 
 template <class V>
@@ -375,6 +383,9 @@ hhg::LevelDev hhg_mesh::dev(int level) const {
     L.sedges = d_sedges;
     L.sverts = d_sverts;
     L.fvfaces = d_fvfaces;
+    L.p2faces = d_p2faces;
+    L.p2ediag = d_p2ediag;
+    L.p2vdiag = d_p2vdiag;
     L.vxy = d_vxy;
     return L;
 }
@@ -415,10 +426,12 @@ void hhg_destroy_mesh(hhg_mesh* mesh) {
 
 int hhg_workspace_bytes(const hhg_mesh* mesh, uint32_t features, size_t* bytes) {
     if (!mesh || !bytes) return fail(HHG_EINVAL, "null argument");
-    if (features & ~(HHG_FEAT_F64 | HHG_FEAT_MP | HHG_FEAT_VARK | HHG_FEAT_NET | HHG_FEAT_STOKES))
+    if (features & ~(HHG_FEAT_F64 | HHG_FEAT_MP | HHG_FEAT_VARK | HHG_FEAT_NET | HHG_FEAT_STOKES | HHG_FEAT_P2))
         return fail(HHG_EINVAL, "unknown feature bits");
     if ((features & HHG_FEAT_STOKES) && !(features & HHG_FEAT_F64))
         return fail(HHG_EINVAL, "HHG_FEAT_STOKES needs HHG_FEAT_F64 (the preconditioner's hierarchy)");
+    if ((features & HHG_FEAT_P2) && !(features & HHG_FEAT_F64))
+        return fail(HHG_EINVAL, "HHG_FEAT_P2 needs HHG_FEAT_F64 (the P1 hierarchy of the p-multigrid cycle)");
     if ((features & HHG_FEAT_NET) && !(features & HHG_FEAT_MP))
         return fail(HHG_EINVAL, "HHG_FEAT_NET needs HHG_FEAT_MP (the learned smoother runs in FP32)");
     hhg_mesh tmp;
@@ -885,6 +898,7 @@ int hhg_set_face_coefficient(hhg_mesh* M, const double* coef, void* stream) {
     const std::string err = M->m.set_face_coef(coef);
     if (!err.empty()) return fail(HHG_EINVAL, err);
     M->stokes_ready = false;
+    M->p2_ready = false;
     if (!M->bound) return HHG_OK;
     hipStream_t s = (hipStream_t)stream;
     const MeshData& m = M->m;
@@ -1208,6 +1222,152 @@ int hhg_energy_run(hhg_mesh* M, const hhg_energy_opts* o, void* x, void* T, hhg_
     HIP_CHECK(hipStreamSynchronize(s), "energy run");
     st->ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
     return rc;
+}
+
+// ------------------------------------------------------------------ P2
+
+namespace {
+
+int check_p2(const hhg_mesh* M, int level) {
+    if (!M) return fail(HHG_EINVAL, "null mesh");
+    if (!M->bound) return fail(HHG_ENOMEM, "no workspace bound");
+    if (!(M->features & HHG_FEAT_P2)) return fail(HHG_ENOMEM, "workspace lacks HHG_FEAT_P2");
+    if (!M->p2_ready) return fail(HHG_EINVAL, "hhg_p2_setup has not been called since the last coefficient change");
+    if (level < 1 || level + 1 > M->m.L) return fail(HHG_EINVAL, "P2 level must satisfy 1 <= level < max_level");
+    return HHG_OK;
+}
+
+// `sweeps` Jacobi sweeps ping-ponging between x and y; *out: the buffer
+// holding the result.
+int p2_jacobi_pp(const hhg_mesh* M, int fl, double omega, double* x, double* y, const double* f, int sweeps,
+                 hipStream_t s, double** out) {
+    double* cur = x;
+    double* other = y;
+    for (int k = 0; k < sweeps; ++k) {
+        HIP_CHECK(launch_p2(M, fl, 2, cur, f, other, M->p2part, omega, s), "P2 Jacobi");
+        std::swap(cur, other);
+    }
+    *out = cur;
+    return HHG_OK;
+}
+
+}  // namespace
+
+int hhg_p2_setup(hhg_mesh* M, void* stream) {
+    if (!M) return fail(HHG_EINVAL, "null mesh");
+    if (!M->bound) return fail(HHG_ENOMEM, "no workspace bound");
+    if (!(M->features & HHG_FEAT_P2)) return fail(HHG_ENOMEM, "workspace lacks HHG_FEAT_P2");
+    const std::string err = M->m.p2_tables();
+    if (!err.empty()) return fail(HHG_EINVAL, err);
+    hipStream_t s = (hipStream_t)stream;
+    HIP_CHECK(upload(M->d_p2faces, M->m.p2faces, s), "upload");
+    HIP_CHECK(upload(M->d_p2ediag, M->m.p2ediag, s), "upload");
+    HIP_CHECK(upload(M->d_p2vdiag, M->m.p2vdiag, s), "upload");
+    HIP_CHECK(hipStreamSynchronize(s), "P2 setup");
+    M->p2_ready = true;
+    return HHG_OK;
+}
+
+int hhg_p2_apply(const hhg_mesh* M, int32_t level, const void* x, void* y, void* stream) {
+    int rc = check_p2(M, level);
+    if (rc) return rc;
+    if (!x || !y || x == y) return fail(HHG_EINVAL, "x and y must be distinct buffers");
+    HIP_CHECK(launch_p2(M, level + 1, 0, (const double*)x, nullptr, (double*)y, M->p2part, 0.0,
+                        (hipStream_t)stream), "P2 apply");
+    return HHG_OK;
+}
+
+int hhg_p2_residual(const hhg_mesh* M, int32_t level, const void* x, const void* f, void* r, void* stream) {
+    int rc = check_p2(M, level);
+    if (rc) return rc;
+    if (!x || !f || !r || r == x || r == f) return fail(HHG_EINVAL, "r must be distinct from x and f");
+    HIP_CHECK(launch_p2(M, level + 1, 1, (const double*)x, (const double*)f, (double*)r, M->p2part, 0.0,
+                        (hipStream_t)stream), "P2 residual");
+    return HHG_OK;
+}
+
+int hhg_p2_jacobi(const hhg_mesh* M, int32_t level, double omega, const void* x, const void* f, void* y,
+                  void* stream) {
+    int rc = check_p2(M, level);
+    if (rc) return rc;
+    if (!x || !f || !y || y == x || y == f) return fail(HHG_EINVAL, "y must be distinct from x and f");
+    if (!(omega > 0.0) || !std::isfinite(omega)) return fail(HHG_EINVAL, "omega must be positive");
+    HIP_CHECK(launch_p2(M, level + 1, 2, (const double*)x, (const double*)f, (double*)y, M->p2part, omega,
+                        (hipStream_t)stream), "P2 Jacobi");
+    return HHG_OK;
+}
+
+int hhg_p2_solve(hhg_mesh* M, const hhg_p2_opts* o, void* x_, const void* f_, hhg_p2_stats* st, void* stream) {
+    if (!M || !o || !x_ || !f_ || !st) return fail(HHG_EINVAL, "null argument");
+    auto t0 = std::chrono::steady_clock::now();
+    std::memset(st, 0, sizeof(*st));
+    g_err.clear();
+    const int l = o->level, fl = l + 1;
+    int rc = check_p2(M, l);
+    if (rc) return rc;
+    if (!(M->features & HHG_FEAT_F64)) return fail(HHG_ENOMEM, "workspace lacks HHG_FEAT_F64");
+    if (l < M->m.lc) return fail(HHG_EINVAL, "P2 level below the coarse level");
+    if (o->max_iters < 0 || o->nu1 < 0 || o->nu2 < 0 || o->vnu1 < 0 || o->vnu2 < 0 || !(o->rtol >= 0) ||
+        !(o->omega > 0.0) || !std::isfinite(o->omega))
+        return fail(HHG_EINVAL, "bad P2 solve options");
+    if (o->vnu1 + o->vnu2 == 0 && l > M->m.lc) return fail(HHG_EINVAL, "the P1 cycle needs a smoothing sweep");
+    hipStream_t s = (hipStream_t)stream;
+    double* x = (double*)x_;
+    const double* f = (const double*)f_;
+    double* tmp = (double*)level_alt(M, fl, HHG_F64);
+    double* r = (double*)level_r(M, fl, HHG_F64);
+    void* uc = level_u(M, l, HHG_F64);
+    void* fc = level_f(M, l, HHG_F64);
+    const int64_t nfl = M->m.lv[fl].total;
+    auto res_norm = [&](const double* u, double* out) -> int {
+        HIP_CHECK(launch_p2(M, fl, 1, u, f, r, M->p2part, 0.0, s), "P2 residual");
+        HIP_CHECK(launch_dot(M, fl, HHG_F64, r, r, M->h_norm_dev, s), "P2 norm");
+        double sq = 0.0;
+        if ((rc = read_norm_slot(M, &sq, s))) return rc;
+        *out = std::sqrt(sq);
+        return HHG_OK;
+    };
+    double r0 = 0.0;
+    if ((rc = res_norm(x, &r0))) return rc;
+    st->res0 = r0;
+    if (o->res_history && o->history_capacity > 0) o->res_history[0] = r0;
+    int status = HHG_ENOTCONV;
+    if (r0 == 0.0) {
+        st->converged = 1;
+        status = HHG_OK;
+    }
+    for (int it = 0; status != HHG_OK && it < o->max_iters; ++it) {
+        // nu1 Jacobi sweeps, residual, restriction to P1 (zeroes uc), one P1
+        // V-cycle from zero, prolongation and correction, nu2 Jacobi sweeps
+        double* cur = nullptr;
+        if ((rc = p2_jacobi_pp(M, fl, o->omega, x, tmp, f, o->nu1, s, &cur))) return rc;
+        HIP_CHECK(launch_p2(M, fl, 1, cur, f, r, M->p2part, 0.0, s), "P2 residual");
+        HIP_CHECK(launch_restrict(M, fl, HHG_F64, r, fc, uc, s), "P2 -> P1");
+        if ((rc = vcycle_rec(M, l, HHG_OP_LAPLACE, HHG_SMOOTH_GS, HHG_F64, uc, fc, o->vnu1, o->vnu2, s, nullptr,
+                             true)))
+            return rc;
+        HIP_CHECK(launch_prolong_add(M, fl, HHG_F64, uc, cur, s), "P1 -> P2");
+        double* fin = nullptr;
+        if ((rc = p2_jacobi_pp(M, fl, o->omega, cur, cur == x ? tmp : x, f, o->nu2, s, &fin))) return rc;
+        if (fin != x)
+            HIP_CHECK(hipMemcpyAsync(x, fin, sizeof(double) * nfl, hipMemcpyDeviceToDevice, s), "copy back");
+        double rn = 0.0;
+        if ((rc = res_norm(x, &rn))) return rc;
+        st->iters = it + 1;
+        st->rel_res = rn / r0;
+        if (o->res_history && it + 1 < o->history_capacity) o->res_history[it + 1] = rn;
+        if (!std::isfinite(rn)) {
+            g_err = "residual is not finite";
+            break;
+        }
+        if (rn <= o->rtol * r0) {
+            st->converged = 1;
+            status = HHG_OK;
+        }
+    }
+    if (status == HHG_ENOTCONV && g_err.empty()) g_err = "iteration cap reached";
+    st->ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+    return status;
 }
 
 int hhg_timing_enable(hhg_mesh* M, int32_t enable) {

@@ -104,10 +104,13 @@ __device__ __forceinline__ double block_sum(double v, double* sm) {
 // process-local direct copy of the communication layer; the writer takes
 // care of the receiver's order).
 
+// Face-local (i, j) of parameter t along side `side` (0: j = 0, 1: i = 0,
+// 2: i + j = n - 1).  Written with selects: as a divergent three-way branch
+// the compiler (ROCm 7.2, -O3) dropped the side-2 assignment of j in one
+// kernel, leaving j = 0 for those lanes.
 __device__ __forceinline__ void side_point0(int side, int t, int n, int& i, int& j) {
-    if (side == 0) { i = t; j = 0; }
-    else if (side == 1) { i = 0; j = t; }
-    else { i = n - 1 - t; j = t; }
+    j = side == 0 ? 0 : t;
+    i = side == 0 ? t : (side == 1 ? 0 : n - 1 - t);
 }
 
 // Copies of edge point k = 1 or n-2 in the first/last ghost-row entry of the

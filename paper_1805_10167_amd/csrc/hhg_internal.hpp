@@ -142,6 +142,19 @@ struct FvFace {
     int32_t pad_;
 };
 
+// P2 stencils of one macro-face (Laplacian times the face coefficient) on
+// the level-(l+1) layout that holds P2 fields of level l: per point type
+// (0 vertex, 1 i-direction edge, 2 j-direction edge, 3 diagonal edge) the
+// weights of the hexagonal neighbours C, E, W, N, S, SE, NW; the vertex
+// type's couplings with the vertices two steps away ((2,0), (-2,0), (0,2),
+// (0,-2), (2,-2), (-2,2)); and the element matrix (local order v0 v1 v2
+// m01 m12 m02) for the faces' shares of boundary rows.
+struct P2Face {
+    double hex[4][7];
+    double far[6];
+    double K[6][6];
+};
+
 // Per-level view passed to kernels by value.
 struct LevelDev {
     int32_t level, n;
@@ -170,6 +183,9 @@ struct LevelDev {
     const StokesVert* sverts;
     const FvFace* fvfaces;            // finite-volume cell geometry (null unless set up)
     const double* vxy;                // macro-vertex coordinates [2 V]
+    const P2Face* p2faces;            // P2 stencils (null unless set up)
+    const double* p2ediag;            // P2 diagonal of edge points [2 E]: even, odd k
+    const double* p2vdiag;            // P2 diagonal of vertices [V]
 };
 
 // Coarse-level Jacobi-PCG data: interior points in canonical order, each

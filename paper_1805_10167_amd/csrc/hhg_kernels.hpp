@@ -62,6 +62,11 @@ hipError_t launch_restrict(const hhg_mesh* M, int level, int dtype, const void* 
 hipError_t launch_prolong_add(const hhg_mesh* M, int level, int dtype, const void* uc,
                               void* u, hipStream_t s);
 hipError_t launch_fill(void* x, int64_t n, int dtype, double v, hipStream_t s);
+// P2 operator of level fine_level - 1 on the level-fine_level layout (FP64):
+// mode 0 y = A x, 1 y = f - A x, 2 y = x + omega D^-1 (f - A x); part holds
+// the faces' partial boundary rows.
+hipError_t launch_p2(const hhg_mesh* M, int fine_level, int mode, const double* x, const double* f, double* y,
+                     double* part, double omega, hipStream_t s);
 // ELL values of the coarse operator for `op` into `vals`.
 hipError_t launch_coarse_extract(const hhg_mesh* M, int op, double* vals, hipStream_t s);
 // u += A_int^-1 (f - A u)_int on the coarse level (stored inverse and one

@@ -52,6 +52,9 @@ struct MeshData {
     std::vector<StokesEdge> sedges;
     std::vector<StokesVert> sverts;
     std::vector<FvFace> fvfaces;
+    // P2 stencils and interface diagonals (empty until p2_tables runs)
+    std::vector<P2Face> p2faces;
+    std::vector<double> p2ediag, p2vdiag;
     std::vector<int32_t> iedges, iverts;
     std::vector<LevelHost> lv;                      // index = level
 
@@ -92,6 +95,9 @@ struct MeshData {
     void stokes_tables(double delta);
     // Finite-volume cell geometry and face-to-face neighbours.
     void fv_tables();
+    // P2 stencils from the face cotangents (times the face coefficient);
+    // "" or an error message.
+    std::string p2_tables();
 };
 
 }  // namespace hhg
@@ -120,6 +126,12 @@ struct hhg_mesh {
     double* d_vxy = nullptr;
     double* t_cells = nullptr;   // second cell field of the transport loop
     double* b_stokes = nullptr;  // buoyancy right-hand side of the transport loop
+    // P2 (HHG_FEAT_P2): tables and the faces' partial boundary rows
+    hhg::P2Face* d_p2faces = nullptr;
+    double* d_p2ediag = nullptr;
+    double* d_p2vdiag = nullptr;
+    double* p2part = nullptr;     // [F][3][n of the finest level]
+    bool p2_ready = false;
     int32_t* d_iedges = nullptr;
     int32_t* d_iverts = nullptr;
     hhg::CoarseDev coarse{};              // vals: Laplace operator

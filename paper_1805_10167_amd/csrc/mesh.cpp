@@ -353,6 +353,117 @@ void add_triangle(const double P[3][2], int r, const int slot[3], double mu, dou
 
 }  // namespace
 
+namespace {
+
+// P2 element stiffness of a face from the cotangents c[k] of its angles
+// (already times the face coefficient), local order v0 v1 v2 m01 m12 m02.
+// With the P1 element stiffness K1 (K1_aa = (c_b + c_c) / 2, K1_ab = -c_c / 2,
+// c the angle opposite the edge ab) and the integrals of barycentric
+// monomials over the triangle, the quadratic basis lam_a (2 lam_a - 1) and
+// 4 lam_a lam_b gives:
+//   vertex a, itself:          K1_aa
+//   vertices a, b:             -K1_ab / 3          =  c_c / 6
+//   vertex a, midpoint of ab:  4 K1_ab / 3         = -2 c_c / 3
+//   vertex a, midpoint of bc:  0
+//   midpoint of ab, itself:    8 (K1_aa + K1_bb + K1_ab) / 3 = 4 (c_0 + c_1 + c_2) / 3
+//   midpoints of ab and bc:    8 K1_ac / 3         = -4 c_b / 3 (b the shared vertex)
+void p2_element(const double c[3], double K[6][6]) {
+    for (int a = 0; a < 6; ++a)
+        for (int b = 0; b < 6; ++b) K[a][b] = 0.0;
+    const int mid[3][3] = {{-1, 3, 5}, {3, -1, 4}, {5, 4, -1}};   // node of the midpoint of (a, b)
+    for (int a = 0; a < 3; ++a) {
+        const int b = (a + 1) % 3, cc = (a + 2) % 3;
+        K[a][a] = 0.5 * (c[b] + c[cc]);
+        K[a][b] = K[b][a] = c[cc] / 6.0;
+        // vertex a with the midpoints of its two edges
+        K[a][mid[a][b]] = K[mid[a][b]][a] = -2.0 * c[cc] / 3.0;
+        K[a][mid[a][cc]] = K[mid[a][cc]][a] = -2.0 * c[b] / 3.0;
+    }
+    const double all = c[0] + c[1] + c[2];
+    for (int m = 3; m < 6; ++m) K[m][m] = 4.0 * all / 3.0;
+    // pairs of midpoints and their shared vertex: (m01, m12) at 1, (m01, m02) at 0, (m12, m02) at 2
+    const int pr[3][3] = {{3, 4, 1}, {3, 5, 0}, {4, 5, 2}};
+    for (auto& q : pr) K[q[0]][q[1]] = K[q[1]][q[0]] = -4.0 * c[q[2]] / 3.0;
+}
+
+// Level-(l+1) offsets of the local nodes of the up (kind 0) and down (kind
+// 1) element of coarse position (a, b), relative to (2a, 2b).
+const int P2OFF[2][6][2] = {{{0, 0}, {2, 0}, {0, 2}, {1, 0}, {1, 1}, {0, 1}},
+                            {{2, 2}, {0, 2}, {2, 0}, {1, 2}, {1, 1}, {2, 1}}};
+
+// Row of point (I, J) of a face with nc coarse points per side, restricted
+// to the face's own elements: weight per neighbour offset, summed over the
+// elements containing the point.
+std::map<std::pair<int, int>, double> p2_face_row(const double K[6][6], int nc, int I, int J) {
+    std::map<std::pair<int, int>, double> w;
+    for (int kind = 0; kind < 2; ++kind)
+        for (int r = 0; r < 6; ++r) {
+            const int dx = I - P2OFF[kind][r][0], dy = J - P2OFF[kind][r][1];
+            if ((dx & 1) || (dy & 1)) continue;
+            const int a = dx / 2, b = dy / 2;
+            if (a < 0 || b < 0 || a + b > nc - 2 - kind) continue;
+            for (int q = 0; q < 6; ++q)
+                w[{2 * a + P2OFF[kind][q][0] - I, 2 * b + P2OFF[kind][q][1] - J}] += K[r][q];
+        }
+    return w;
+}
+
+}  // namespace
+
+std::string MeshData::p2_tables() {
+    p2faces.assign(F, P2Face{});
+    p2ediag.assign(2 * (size_t)E, 0.0);
+    p2vdiag.assign(V, 0.0);
+    // stencil slots: C E W N S SE NW, and the vertex type's far vertices
+    const int hex[7][2] = {{0, 0}, {1, 0}, {-1, 0}, {0, 1}, {0, -1}, {1, -1}, {-1, 1}};
+    const int far[6][2] = {{2, 0}, {-2, 0}, {0, 2}, {0, -2}, {2, -2}, {-2, 2}};
+    const int NC = 65, NV = 2 * NC - 1;   // a face large enough that interior rows see all elements
+    std::vector<std::array<double, 3>> corner_d(F);
+    std::vector<std::array<std::array<double, 2>, 3>> side_d(F);
+    for (int f = 0; f < F; ++f) {
+        P2Face& t = p2faces[f];
+        p2_element(faces[f].cot, t.K);
+        for (int type = 0; type < 4; ++type) {
+            auto w = p2_face_row(t.K, NC, 16 + (type & 1), 16 + (type >> 1));
+            for (int s = 0; s < 7; ++s) {
+                auto it = w.find({hex[s][0], hex[s][1]});
+                t.hex[type][s] = it == w.end() ? 0.0 : it->second;
+                if (it != w.end()) w.erase(it);
+            }
+            for (int s = 0; s < 6; ++s) {
+                auto it = w.find({far[s][0], far[s][1]});
+                const double v = it == w.end() ? 0.0 : it->second;
+                if (it != w.end()) w.erase(it);
+                if (type == 0) t.far[s] = v;
+                else if (v != 0.0) return "P2 edge stencil reaches a far vertex";
+            }
+            for (auto& kv : w)
+                if (kv.second != 0.0) return "P2 stencil has an unexpected neighbour";
+        }
+        // diagonals of the face's share of boundary rows: side points (even,
+        // odd parameter) and corners
+        for (int side = 0; side < 3; ++side)
+            for (int par = 0; par < 2; ++par) {
+                int I, J;
+                side_point(side, 2 + par, 0, NV, I, J);
+                side_d[f][side][par] = p2_face_row(t.K, NC, I, J)[{0, 0}];
+            }
+        corner_d[f][0] = p2_face_row(t.K, NC, 0, 0)[{0, 0}];
+        corner_d[f][1] = p2_face_row(t.K, NC, NV - 1, 0)[{0, 0}];
+        corner_d[f][2] = p2_face_row(t.K, NC, 0, NV - 1)[{0, 0}];
+    }
+    for (int e = 0; e < E; ++e) {
+        const EdgeInfo& ei = edges[e];
+        for (int par = 0; par < 2; ++par)
+            for (int s = 0; s < ei.nf; ++s) p2ediag[2 * e + par] += side_d[ei.face[s]][ei.side[s]][par];
+    }
+    for (int v = 0; v < V; ++v) {
+        const VertexInfo& vi = verts[v];
+        for (int c = 0; c < vi.nfc; ++c) p2vdiag[v] += corner_d[vi.fc_face[c]][vi.fc_corner[c]];
+    }
+    return "";
+}
+
 void MeshData::fv_tables() {
     fvfaces.assign(F, FvFace{});
     auto X = [&](int v, int c) { return vxy[2 * v + c]; };

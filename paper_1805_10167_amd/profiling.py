@@ -27,7 +27,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 HEADERS = ["hhg_internal.hpp", "hhg_kernels.hpp", "hhg_mesh.hpp", "hhg_device.hpp"]
 # the files a profiled kernel is built from, by the source file holding it
-SOURCES = {name: [name] + HEADERS for name in ("kernels.hip", "net.hip", "stokes.hip", "transport.hip")}
+SOURCES = {name: [name] + HEADERS for name in ("kernels.hip", "net.hip", "stokes.hip", "transport.hip", "p2.hip")}
 COPY_KERNEL = "__amd_rocclr_copyBuffer"
 
 
