@@ -22,6 +22,10 @@ path computes:
   stokes.py     equal-order P1-P1 Stokes with pressure stabilisation, the
                 block-diagonal multigrid preconditioner and preconditioned
                 MINRES (sec. 4.3, 5.2)
+  transport.py  finite-volume upwind transport of the temperature on the
+                micro-triangles and its coupling to Stokes (sec. 3.1, 5.2)
+  p2.py         quadratic elements on the refined faces and p-multigrid with
+                the P1 hierarchy (sec. 3.1, 4.2, 4.3)
 
 Parity status of each function is stated in its docstring; functions with no
 independent pin say "parity unpinned".
