@@ -66,41 +66,111 @@ __device__ __forceinline__ double p2_elem_rows(const LevelDev& L, const P2Face& 
     return acc;
 }
 
+// Face tiles: the smoother's TI x TJ tiles (halo-3 tile list, TI = 186,
+// TJ = 24) loaded with a two-point halo into LDS in one round of independent
+// loads (f of the block's points into registers alongside), every interior
+// row then formed from LDS.  A row (fixed j) holds two point types, chosen
+// per lane by selects.
+constexpr int P2_NT = 512, P2_NW = P2_NT / 64, P2_H = 2;
+constexpr int P2_TJ = GS_TJ, P2_TI = GS_W - 2 * GS_H;
+constexpr int P2_RA = P2_TJ + 2 * P2_H, P2_RPW = (P2_RA + P2_NW - 1) / P2_NW, P2_KR = P2_TJ / P2_NW;
+static_assert(P2_TI + 2 * P2_H <= GS_W, "tile with halo must fit an LDS row");
+static_assert(P2_TJ % P2_NW == 0, "tile rows must split evenly over the waves");
+
 // MODE 0: y = A x; 1: y = f - A x; 2: y = x + omega D^-1 (f - A x).  Blocks
-// [0, gf) take face tiles (interior rows, with their ghost-row copies), the
+// [0, gt) take face tiles (interior rows, with their ghost-row copies), the
 // rest the boundary partials of every face.
 template <int MODE>
-__global__ __launch_bounds__(NT) void k_p2_face(LevelDev L, const double* __restrict__ x,
-                                                const double* __restrict__ f, double* __restrict__ y,
-                                                double* __restrict__ part, double omega, int gf) {
-    if ((int)blockIdx.x < gf) {
-        FACE_TILE_LOOP(L, gf)
+__global__ __launch_bounds__(P2_NT) void k_p2_face(LevelDev L, const double* __restrict__ x,
+                                                   const double* __restrict__ f, double* __restrict__ y,
+                                                   double* __restrict__ part, double omega, int ntiles, int gt) {
+    __shared__ double xs[P2_RA][GS_W];
+    const int b = blockIdx.x, n = L.n;
+    if (b < gt) {
+        const int logical = (b & 7) * (gt >> 3) + (b >> 3);   // contiguous tiles per XCD
+        if (logical >= ntiles) return;
+        const int wv = wave_id(), lane = threadIdx.x & 63;
+        const int ntl = L.n_gs_tl[0][0];
+        const int face = logical / ntl;
+        const FaceInfo& fi = L.faces[face];
         const P2Face& pf = L.p2faces[face];
-        const int type = (i & 1) | ((j & 1) << 1);
-        const int64_t o[7] = {p, p + 1, p - 1, p + up, p - dn, p - dn + 1, p + up - 1};
-        double ax = 0.0;
+        const int2 tl = L.gs_tl[0][0][logical % ntl];
+        const int i0 = tl.x * P2_TI - P2_H, j0 = tl.y * P2_TJ - P2_H;   // LDS origin
+        const int64_t fb = face_base(L, face);
+        double xr[P2_RPW][3];
 #pragma unroll
-        for (int t = 0; t < 7; ++t) ax += pf.hex[type][t] * x[o[t]];
-        if (type == 0) {
-            // vertices two steps away: (2,0) (-2,0) (0,2) (0,-2) (2,-2) (-2,2)
-            const int64_t up2 = row_start(n, j + 2) - row_start(n, j);
-            const int64_t dn2 = row_start(n, j) - row_start(n, j - 2);
-            const int64_t q[6] = {p + 2, p - 2, p + up2, p - dn2, p - dn2 + 2, p + up2 - 2};
+        for (int q = 0; q < P2_RPW; ++q) {
+            const int r = wv + P2_NW * q, j = j0 + r;
+            const int64_t rb = fb + row_start(n, j < 0 ? 0 : (j > n ? n : j));
 #pragma unroll
-            for (int t = 0; t < 6; ++t) ax += pf.far[t] * x[q[t]];
+            for (int c = 0; c < 3; ++c) {
+                const int tx = lane + 64 * c, i = i0 + tx;
+                const bool in = r < P2_RA && tx < P2_TI + 2 * P2_H && j >= 0 && j < n && i >= 0 && i <= n - 1 - j;
+                xr[q][c] = in ? x[rb + i] : 0.0;
+            }
         }
-        double v;
-        if (MODE == 0) v = ax;
-        else if (MODE == 1) v = f[p] - ax;
-        else v = x[p] + omega * (f[p] - ax) / pf.hex[type][0];
-        y[p] = v;
-        push_face_near(L, y, fi, i, j, v);
-        FACE_TILE_END
+        double fr[P2_KR][3];
+#pragma unroll
+        for (int k = 0; k < P2_KR; ++k) {
+            const int r = P2_H + wv + P2_NW * k, j = j0 + r;
+#pragma unroll
+            for (int c = 0; c < 3; ++c) {
+                const int tx = lane + 64 * c, i = i0 + tx;
+                const bool pt = MODE >= 1 && tx >= P2_H && tx < P2_H + P2_TI && j >= 1 && i >= 1 && i + j <= n - 2;
+                fr[k][c] = pt ? f[fb + row_start(n, pt ? j : 0) + i] : 0.0;
+            }
+        }
+#pragma unroll
+        for (int q = 0; q < P2_RPW; ++q) {
+            const int r = wv + P2_NW * q;
+            if (r >= P2_RA) continue;
+#pragma unroll
+            for (int c = 0; c < 3; ++c) xs[r][lane + 64 * c] = xr[q][c];
+        }
+        __syncthreads();
+#pragma unroll
+        for (int k = 0; k < P2_KR; ++k) {
+            const int r = P2_H + wv + P2_NW * k, j = j0 + r;
+            // the row's two types (wave-uniform): even rows vertex / i-edge,
+            // odd rows j-edge / diagonal; lanes pick by the parity of i
+            const int ta = (j & 1) << 1;
+            double wa[7], wb[7];
+#pragma unroll
+            for (int t = 0; t < 7; ++t) {
+                wa[t] = pf.hex[ta][t];
+                wb[t] = pf.hex[ta | 1][t];
+            }
+            const bool even_row = (j & 1) == 0;
+#pragma unroll
+            for (int c = 0; c < 3; ++c) {
+                const int tx0 = lane + 64 * c, i = i0 + tx0;
+                // lanes outside the tile read inside it (their result is dropped)
+                const int tx = tx0 >= P2_H && tx0 < P2_H + P2_TI ? tx0 : P2_H;
+                const bool odd_i = (i & 1) != 0;
+                double w[7];
+#pragma unroll
+                for (int t = 0; t < 7; ++t) w[t] = odd_i ? wb[t] : wa[t];
+                double ax = w[0] * xs[r][tx] + w[1] * xs[r][tx + 1] + w[2] * xs[r][tx - 1] + w[3] * xs[r + 1][tx] +
+                            w[4] * xs[r - 1][tx] + w[5] * xs[r - 1][tx + 1] + w[6] * xs[r + 1][tx - 1];
+                if (even_row) {
+                    const double far = pf.far[0] * xs[r][tx + 2] + pf.far[1] * xs[r][tx - 2] +
+                                       pf.far[2] * xs[r + 2][tx] + pf.far[3] * xs[r - 2][tx] +
+                                       pf.far[4] * xs[r - 2][tx + 2] + pf.far[5] * xs[r + 2][tx - 2];
+                    ax += odd_i ? 0.0 : far;
+                }
+                double v;
+                if (MODE == 0) v = ax;
+                else if (MODE == 1) v = fr[k][c] - ax;
+                else v = xs[r][tx] + omega * (fr[k][c] - ax) / w[0];
+                if (!(tx0 >= P2_H && tx0 < P2_H + P2_TI && j >= 1 && i >= 1 && i + j <= n - 2)) continue;
+                y[fb + row_start(n, j) + i] = v;
+                push_face_near(L, y, fi, i, j, v);
+            }
+        }
     } else {
-        const int n = L.n;
         const int64_t nb = (int64_t)L.F * 3 * n;
-        for (int64_t t = (int64_t)(blockIdx.x - gf) * NT + threadIdx.x; t < nb;
-             t += (int64_t)(gridDim.x - gf) * NT) {
+        for (int64_t t = (int64_t)(b - gt) * P2_NT + threadIdx.x; t < nb;
+             t += (int64_t)(gridDim.x - gt) * P2_NT) {
             const int face = (int)(t / (3 * n)), side = (int)(t / n % 3), s = (int)(t % n);
             int I, J;
             side_point0(side, s, n, I, J);
@@ -163,19 +233,21 @@ __global__ __launch_bounds__(NT) void k_p2_low(LevelDev L, const double* __restr
 hipError_t launch_p2(const hhg_mesh* M, int fine_level, int mode, const double* x, const double* f, double* y,
                      double* part, double omega, hipStream_t s) {
     const LevelDev L = M->dev(fine_level);
-    const int gf = (int)std::max<int64_t>(1, std::min<int64_t>((int64_t)L.F * L.ntiles, MAX_FACE_BLOCKS));
+    // one block per tile (a multiple of 8 for the XCD order), then partial blocks
+    const int ntiles = L.F * L.n_gs_tl[0][0];
+    const int gt = (ntiles + 7) / 8 * 8;
     const int64_t nb = (int64_t)L.F * 3 * L.n;
-    const int gb = (int)std::max<int64_t>(1, std::min<int64_t>((nb + NT - 1) / NT, MAX_LOW_BLOCKS));
+    const int gb = (int)std::max<int64_t>(1, std::min<int64_t>((nb + P2_NT - 1) / P2_NT, MAX_LOW_BLOCKS));
     int64_t gl = ((int64_t)L.E * (L.n - 2) + L.V + NT - 1) / NT;
     gl = std::max<int64_t>(1, std::min<int64_t>(gl, MAX_LOW_BLOCKS));
     if (mode == 0) {
-        k_p2_face<0><<<gf + gb, NT, 0, s>>>(L, x, f, y, part, omega, gf);
+        k_p2_face<0><<<gt + gb, P2_NT, 0, s>>>(L, x, f, y, part, omega, ntiles, gt);
         k_p2_low<0><<<(int)gl, NT, 0, s>>>(L, x, f, y, part, omega);
     } else if (mode == 1) {
-        k_p2_face<1><<<gf + gb, NT, 0, s>>>(L, x, f, y, part, omega, gf);
+        k_p2_face<1><<<gt + gb, P2_NT, 0, s>>>(L, x, f, y, part, omega, ntiles, gt);
         k_p2_low<1><<<(int)gl, NT, 0, s>>>(L, x, f, y, part, omega);
     } else {
-        k_p2_face<2><<<gf + gb, NT, 0, s>>>(L, x, f, y, part, omega, gf);
+        k_p2_face<2><<<gt + gb, P2_NT, 0, s>>>(L, x, f, y, part, omega, ntiles, gt);
         k_p2_low<2><<<(int)gl, NT, 0, s>>>(L, x, f, y, part, omega);
     }
     return hipGetLastError();
