@@ -189,6 +189,18 @@ int hhg_n_dofs(const hhg_mesh* mesh, int32_t level, int64_t* n_interior,
 int hhg_coords(const hhg_mesh* mesh, int32_t level, double* xy);
 
 /*
+ * Copy table of the level layout (sec. 2.2, 3.3: every unknown has one
+ * owner; ghost layers hold copies in the receiver's order): n_copies
+ * receives the number of copy slots; with dst and src (host arrays of that
+ * length, or null to query the count) the field offsets of every copy slot
+ * and of the owned value it copies (face rings from edges and vertices, edge
+ * end slots from vertices, edge ghost rows from face near-edge rows, vertex
+ * ring slots from edge points).  Every library call leaves field[dst] ==
+ * field[src] in its outputs.  Host only: needs no workspace.
+ */
+int hhg_ghost_table(const hhg_mesh* mesh, int32_t level, int64_t* n_copies, int64_t* dst, int64_t* src);
+
+/*
  * Layout conversion (sec. 3.2: the indexing function maps the topological
  * enumeration to memory).  `canon` is a device array of n_all values of
  * `dtype`; `field` a device field of the same dtype.  from_canonical writes
@@ -200,10 +212,13 @@ int hhg_to_canonical(const hhg_mesh* mesh, int32_t level, int32_t dtype,
                      const void* field, void* canon, void* stream);
 
 /*
- * Nodal coefficient k > 0 of -div(k grad u) at the finest level, a device
+ * Nodal coefficient k of -div(k grad u) at the finest level, a device
  * array of n_all(max_level) doubles in canonical order.  Coarser levels take
  * it by injection.  Needs a workspace bound with HHG_FEAT_VARK.  Enables
- * HHG_OP_DIFFUSION (on-the-fly stencils, paper sec. 1.1 and 4.2).
+ * HHG_OP_DIFFUSION (on-the-fly stencils, paper sec. 1.1 and 4.2).  k > 0
+ * gives a symmetric positive definite operator; other values are taken as
+ * given (an indefinite operator, on which smoothing and solves may diverge:
+ * hhg_solve stops after three cycles of rising residual).
  */
 int hhg_set_coefficient(hhg_mesh* mesh, const double* k_canon, void* stream);
 

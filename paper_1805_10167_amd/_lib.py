@@ -110,6 +110,7 @@ _SIGS = {
                                     _c.POINTER(hhg_stokes_stats), _vp]),
     "hhg_timing_enable": (_c.c_int, [_vp, _i32]),
     "hhg_timing_read": (_c.c_int, [_vp, _c.POINTER(_i64), _c.POINTER(_c.c_double), _i32]),
+    "hhg_ghost_table": (_c.c_int, [_vp, _i32, _c.POINTER(_i64), _vp, _vp]),
     "hhg_cell_coords": (_c.c_int, [_vp, _i32, _vp]),
     "hhg_cells_from_canonical": (_c.c_int, [_vp, _i32, _vp, _vp, _vp]),
     "hhg_cells_to_canonical": (_c.c_int, [_vp, _i32, _vp, _vp, _vp]),
@@ -285,6 +286,16 @@ def hhg_stokes_solve(h, x, b, precision=HHG_F64, rtol=1e-8, max_iters=500, nu1=2
     stats = {k: getattr(st, k) for k, _ in hhg_stokes_stats._fields_}
     hl = list(hist[:st.iters + 1]) if history else []
     return rc, stats, hl
+
+
+def hhg_ghost_table(h, level):
+    """(dst, src): field offsets of every copy slot and of the value it copies."""
+    n = _i64()
+    _check(lib().hhg_ghost_table(h, level, _c.byref(n), None, None))
+    dst = np.zeros(n.value, dtype=np.int64)
+    src = np.zeros(n.value, dtype=np.int64)
+    _check(lib().hhg_ghost_table(h, level, _c.byref(n), dst.ctypes.data, src.ctypes.data))
+    return dst, src
 
 
 def hhg_cell_coords(h, level, n_faces):

@@ -544,6 +544,16 @@ int hhg_coords(const hhg_mesh* M, int32_t level, double* xy) {
     return HHG_OK;
 }
 
+int hhg_ghost_table(const hhg_mesh* M, int32_t level, int64_t* n_copies, int64_t* dst, int64_t* src) {
+    if (!M || !n_copies) return fail(HHG_EINVAL, "null argument");
+    if (!level_ok(M, level)) return fail(HHG_EINVAL, "level out of range");
+    const LevelHost& H = M->m.lv[level];
+    *n_copies = (int64_t)H.gdst.size();
+    if (dst) std::copy(H.gdst.begin(), H.gdst.end(), dst);
+    if (src) std::copy(H.gsrc.begin(), H.gsrc.end(), src);
+    return HHG_OK;
+}
+
 int hhg_from_canonical(const hhg_mesh* M, int32_t level, int32_t dtype, const void* canon,
                        void* field, void* stream) {
     int rc = check_common(M, level, dtype);
@@ -794,6 +804,9 @@ int hhg_restrict(const hhg_mesh* M, int32_t level, int32_t dtype, const void* r,
     if (level < 2) return fail(HHG_EINVAL, "restriction needs level >= 2");
     if (!r || !fc || r == fc) return fail(HHG_EINVAL, "bad buffers");
     HIP_CHECK(launch_restrict(M, level, dtype, r, fc, nullptr, (hipStream_t)stream), "restrict");
+    // the kernel writes owned coarse values (all the V-cycle reads); the call
+    // also leaves fc's copies consistent
+    HIP_CHECK(launch_sync(M, level - 1, dtype, fc, GM_ALL, (hipStream_t)stream), "restrict copies");
     return HHG_OK;
 }
 

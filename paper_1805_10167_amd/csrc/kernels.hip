@@ -1453,7 +1453,8 @@ __global__ __launch_bounds__(NT) void k_restrict_low(LevelDev Lf, LevelDev Lc, i
 // of a coarse micro-edge.  Every holder of a copy updates it from its own
 // coarse copies (same operands, so the copies stay identical): faces their
 // whole triangle except Dirichlet points, pushing near-edge rows; edges
-// their points and end slots; vertices their value and ghost copies.
+// their points and end slots; vertices their value and ghost copies (the
+// ring copies of Dirichlet vertices too).
 template <class T>
 __global__ __launch_bounds__(NT) void k_prolong(LevelDev Lf, LevelDev Lc, const T* __restrict__ uc,
                                                 T* __restrict__ u, int gf) {
@@ -1470,7 +1471,7 @@ __global__ __launch_bounds__(NT) void k_prolong(LevelDev Lf, LevelDev Lc, const 
     } else {
         const int n = Lf.n;
         const int64_t ne = (int64_t)Lf.n_iedges * (n - 2);
-        for (int64_t t = (int64_t)(blockIdx.x - gf) * NT + threadIdx.x; t < ne + Lf.n_iverts;
+        for (int64_t t = (int64_t)(blockIdx.x - gf) * NT + threadIdx.x; t < ne + Lf.V;
              t += (int64_t)(gridDim.x - gf) * NT) {
             if (t < ne) {
                 const int e = Lf.iedges[t / (n - 2)], k = (int)(t % (n - 2)) + 1;
@@ -1481,12 +1482,17 @@ __global__ __launch_bounds__(NT) void k_prolong(LevelDev Lf, LevelDev Lc, const 
                 if (k == 1 && !Lf.verts[ei.a].boundary) u[m] += uc[mc];
                 if (k == n - 2 && !Lf.verts[ei.b].boundary) u[m + n - 1] += uc[mc + Lc.n - 1];
             } else {
-                const int v = Lf.iverts[t - ne];
+                // every vertex: an interior one updates its value and ring; a
+                // Dirichlet one keeps its value but updates the ring copies of
+                // the first points of its interior edges, which the edge
+                // blocks update (same operands, so the copies stay identical)
+                const int v = (int)(t - ne);
                 const VertexInfo& vi = Lf.verts[v];
                 const int64_t vf = vert_off(Lf, v), vc = vert_off(Lc, v);
                 const T cv = uc[vc];
-                u[vf] += cv;
-                for (int q = 0; q < vi.deg; ++q) u[vf + 1 + q] += (T)0.5 * (cv + uc[vc + 1 + q]);
+                if (!vi.boundary) u[vf] += cv;
+                for (int q = 0; q < vi.deg; ++q)
+                    if (!vi.boundary || !Lf.edges[vi.edge[q]].boundary) u[vf + 1 + q] += (T)0.5 * (cv + uc[vc + 1 + q]);
             }
         }
     }
@@ -2183,7 +2189,7 @@ template <class T>
 static hipError_t prolong_t(const hhg_mesh* M, int level, const T* uc, T* u, hipStream_t s) {
     const LevelDev Lf = M->dev(level), Lc = M->dev(level - 1);
     const int gf = face_grid(Lf);
-    const int gl = grid_for((int64_t)Lf.n_iedges * (Lf.n - 2) + Lf.n_iverts, MAX_LOW_BLOCKS);
+    const int gl = grid_for((int64_t)Lf.n_iedges * (Lf.n - 2) + Lf.V, MAX_LOW_BLOCKS);
     k_prolong<T><<<gf + gl, NT, 0, s>>>(Lf, Lc, uc, u, gf);
     return hipGetLastError();
 }

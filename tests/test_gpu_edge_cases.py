@@ -1,8 +1,9 @@
 """Degenerate and boundary cases of the method on the GPU against the
 oracle: a single macro-face (no interior edges or vertices), coarse level 1,
 a cycle that is only the coarse solve, level 1 (faces without interior
-points), zero right-hand sides, an iteration cap of zero, non-finite input,
-and argument errors of the C ABI."""
+points), zero right-hand sides, an iteration cap of zero, non-finite input, a
+diverging solve (indefinite coefficient), and argument errors of the C
+ABI."""
 import numpy as np
 import pytest
 
@@ -146,3 +147,35 @@ def test_solve_history_small_levels(case):
     assert rc == 0 and st["iters"] == len(ho) - 1
     assert rel_err(hist, ho) <= 1e-10
     assert rel_err(to_np(g.to_canonical(L, uf)), uo) <= F64_TOL
+
+
+def test_solve_stops_when_the_residual_keeps_growing():
+    """An indefinite operator: k = -0.3 on a seeded fifth of the points that
+    only the finest level has (so the injected coarse coefficients, and the
+    coarse operators, stay positive), k = 1 elsewhere.  Gauss-Seidel then
+    diverges (the oracle's residuals: 1.0e2, 2.0e9, 1.5e18, 1.1e27), and the
+    solve loop stops after three cycles of rising residual with
+    HHG_ENOTCONV, before max_iters, its history finite and rising."""
+    import torch
+
+    import paper_1805_10167_amd as P
+    from oracle.mesh import Level, MacroMesh
+    L = 5
+    vxy, tri = hi.mesh_by_name("annulus64")
+    lv = Level(MacroMesh(vxy, tri), L)
+    fine_only = (((lv.kind == 2) & ((lv.kidx % 2 == 1) | (lv.jidx % 2 == 1)))
+                 | ((lv.kind == 1) & (lv.kidx % 2 == 1)))
+    kap = np.where(fine_only & (hi.uniform_vector(lv.n_all, 1) > 0.6), -0.3, 1.0)
+    g = P.Mesh(vxy, tri, L, 2, P.HHG_FEAT_F64 | P.HHG_FEAT_VARK)
+    P.hhg_set_coefficient(g.h, torch.tensor(kap, device="cuda"))
+    f = hi.uniform_vector(lv.n_all, 3)
+    f[lv.dirichlet] = 0.0
+    u = g.field(L)
+    rc, st, hist = P.hhg_solve(g.h, u, g.from_canonical(L, f), op=P.HHG_OP_DIFFUSION, rtol=1e-8,
+                               max_iters=30)
+    log("diverging solve: rc %d, %d cycles, history %s, error %r" % (rc, st["iters"], hist,
+                                                                   P.hhg_last_error()))
+    assert rc == P.HHG_ENOTCONV
+    assert "grew" in P.hhg_last_error()
+    assert st["iters"] == 3 and st["converged"] == 0
+    assert np.all(np.isfinite(hist)) and hist[1] < hist[2] < hist[3]

@@ -60,6 +60,31 @@ def test_cell_centroids_match_oracle(name, level):
         P.hhg_destroy_mesh(h)
 
 
+@pytest.mark.parametrize("name,level", [("square", 3), ("annulus64", 4), ("annulus128", 2)])
+def test_ghost_table(name, level):
+    """One entry per copy slot: face rings (3 corners and 3 (n-2) side
+    points per face), edge end slots (2 per edge), ghost rows (n-1 per face
+    of an interior edge), vertex ring slots (one per incident edge); every
+    destination distinct and never an owned slot (owners are sources)."""
+    vxy, tri = hi.mesh_by_name(name)
+    m = MacroMesh(vxy, tri)
+    h = P.hhg_setup_mesh(vxy, tri, max(level, 2), 1)
+    try:
+        dst, src = P.hhg_ghost_table(h, level)
+        n = 2 ** level + 1
+        interior_edges = [fs for e, fs in enumerate(m.edge_faces) if not m.edge_boundary[e]]
+        degree = np.zeros(m.V, dtype=int)
+        for a, b in m.edges:
+            degree[a] += 1
+            degree[b] += 1
+        expect = m.F * (3 + 3 * (n - 2)) + 2 * m.E + sum(len(fs) for fs in interior_edges) * (n - 1) + degree.sum()
+        assert len(dst) == expect
+        assert len(np.unique(dst)) == len(dst)
+        assert not np.isin(src, dst).any()
+    finally:
+        P.hhg_destroy_mesh(h)
+
+
 def test_paper_count_at_level6():
     """2145 points per face at level 6 (sec. 5.2): n_all of one face."""
     vxy = np.array([[0.0, 0.0], [1.0, 0.0], [0.0, 1.0]])
