@@ -78,12 +78,146 @@ __device__ __forceinline__ void stokes_rows(const double (&w)[SB_N][W], int cnt,
 //   MODE 0: y = K x
 //   MODE 1: y = K x and per-block sums of y . x over owned points
 //   MODE 2: y = b - K x (velocity rows of Dirichlet points 0)
-// Blocks [0, gf) take face tiles, the rest edge points and vertices.
+// k_stokes_apply takes the face-interior rows over the smoother's TI x TJ
+// tiles (halo-3 tile list, grid-stride over gf blocks), each in three
+// sub-tiles of ST_SJ rows whose three fields are staged with a one-point
+// halo in LDS (one round of independent loads, LDS stores after); a wave
+// forms one row of a sub-tile.  k_stokes_apply_low takes the edge points and
+// vertices in a launch of its own (their ring arrays would otherwise size
+// the face kernel's registers), its block sums after the face blocks'.
+constexpr int ST_NT = 512, ST_NW = ST_NT / 64, ST_SJ = ST_NW;
+constexpr int ST_TI = GS_W - 2 * GS_H, ST_TJ = GS_TJ, ST_RA = ST_SJ + 2;
+constexpr int ST_RPW = (ST_RA + ST_NW - 1) / ST_NW;
+static_assert(ST_TJ % ST_SJ == 0, "sub-tiles must split the tile rows");
+static_assert(ST_TI + 2 <= GS_W, "tile with halo must fit an LDS row");
+
+// LDS offsets of the neighbours C, E, W, N, S, SE, NW in a GS_W-wide tile
+__constant__ int c_st_off[7] = {0, 1, -1, GS_W, -GS_W, -GS_W + 1, GS_W - 1};
+
 template <int MODE>
-__global__ __launch_bounds__(NT) void k_stokes_apply(LevelDev L, const double* __restrict__ x,
-                                                     const double* __restrict__ b, double* __restrict__ y,
-                                                     int64_t fs, double hB, double hC, int gf,
-                                                     double* __restrict__ partials) {
+__global__ __launch_bounds__(ST_NT) void k_stokes_apply(LevelDev L, const double* __restrict__ x,
+                                                        const double* __restrict__ b, double* __restrict__ y,
+                                                        int64_t fs, double hB, double hC, int gf,
+                                                        double* __restrict__ partials) {
+    __shared__ double xs[3][ST_RA][GS_W];
+    __shared__ double ws[SB_N][7];                 // the face's stencils (broadcast reads)
+    __shared__ double sm[ST_NW + 1];
+    double acc = 0.0;
+    const double* xx = x;
+    const double* xy = x + fs;
+    const double* xp = x + 2 * fs;
+    double* yx_ = y;
+    double* yy_ = y + fs;
+    double* yp_ = y + 2 * fs;
+    const int n = L.n;
+    {
+        const int wv = wave_id(), lane = threadIdx.x & 63;
+        const int ntl = L.n_gs_tl[0][0];
+        const int ntiles = L.F * ntl;
+        for (int tile = blockIdx.x; tile < ntiles; tile += gf) {
+            const int face = tile / ntl;
+            const int2 tl = L.gs_tl[0][0][tile % ntl];
+            const FaceInfo& fi = L.faces[face];
+            const int64_t fb = face_base(L, face);
+            if (threadIdx.x < SB_N * 7) (&ws[0][0])[threadIdx.x] = (&L.sfaces[face].w[0][0])[threadIdx.x];
+            for (int sub = 0; sub < ST_TJ / ST_SJ; ++sub) {
+                const int i0 = tl.x * ST_TI - 1, j0 = tl.y * ST_TJ + sub * ST_SJ - 1;   // LDS origin
+                if (j0 + 1 > n - 3) break;                 // no interior rows left (block-uniform)
+                double xr[3][ST_RPW][3];
+#pragma unroll
+                for (int q = 0; q < ST_RPW; ++q) {
+                    const int r = wv + ST_NW * q, j = j0 + r;
+                    const int64_t rb = fb + row_start(n, j < 0 ? 0 : (j > n ? n : j));
+#pragma unroll
+                    for (int c = 0; c < 3; ++c) {
+                        const int tx = lane + 64 * c, i = i0 + tx;
+                        const bool in = r < ST_RA && tx < ST_TI + 2 && j >= 0 && j < n && i >= 0 && i <= n - 1 - j;
+                        xr[0][q][c] = in ? xx[rb + i] : 0.0;
+                        xr[1][q][c] = in ? xy[rb + i] : 0.0;
+                        xr[2][q][c] = in ? xp[rb + i] : 0.0;
+                    }
+                }
+                const int r = 1 + wv, j = j0 + r;           // this wave's output row
+                double br[3][3];
+#pragma unroll
+                for (int c = 0; c < 3; ++c) {
+                    const int tx = lane + 64 * c, i = i0 + tx;
+                    const bool pt = MODE == 2 && tx >= 1 && tx <= ST_TI && j >= 1 && i >= 1 && i + j <= n - 2;
+                    const int64_t pb = fb + row_start(n, pt ? j : 0) + i;
+                    br[0][c] = pt ? b[pb] : 0.0;
+                    br[1][c] = pt ? b[fs + pb] : 0.0;
+                    br[2][c] = pt ? b[2 * fs + pb] : 0.0;
+                }
+                __syncthreads();                           // the previous sub-tile's LDS reads are done
+#pragma unroll
+                for (int q = 0; q < ST_RPW; ++q) {
+                    const int rr = wv + ST_NW * q;
+                    if (rr >= ST_RA) continue;
+#pragma unroll
+                    for (int c = 0; c < 3; ++c) {
+                        xs[0][rr][lane + 64 * c] = xr[0][q][c];
+                        xs[1][rr][lane + 64 * c] = xr[1][q][c];
+                        xs[2][rr][lane + 64 * c] = xr[2][q][c];
+                    }
+                }
+                __syncthreads();
+                const int64_t rowb = fb + row_start(n, j >= 1 && j <= n - 3 ? j : 1);
+                // one column at a time: unrolled, the three columns' 63 LDS
+                // reads are hoisted together and the registers triple
+#pragma unroll 1
+                for (int c = 0; c < 3; ++c) {
+                    const int tx = lane + 64 * c, i = i0 + tx;
+                    if (!(tx >= 1 && tx <= ST_TI && j >= 1 && i >= 1 && i + j <= n - 2)) continue;
+                    // the seven sums of stokes_rows, tap by tap (neighbours C, E,
+                    // W, N, S, SE, NW): few values live at a time
+                    const double* x0 = &xs[0][r][tx];
+                    const double* x1 = &xs[1][r][tx];
+                    const double* x2 = &xs[2][r][tx];
+                    double ax = 0.0, ay = 0.0, gx = 0.0, gy = 0.0, dx = 0.0, dy = 0.0, cp = 0.0;
+                    double u0 = 0.0, v0 = 0.0, p0 = 0.0;
+#pragma unroll 1
+                    for (int t = 0; t < 7; ++t) {
+                        const int o = c_st_off[t];
+                        const double a = x0[o], bq = x1[o], pq = x2[o];
+                        if (t == 0) { u0 = a; v0 = bq; p0 = pq; }
+                        ax += ws[SB_A][t] * a;
+                        ay += ws[SB_A][t] * bq;
+                        gx += ws[SB_BXT][t] * pq;
+                        gy += ws[SB_BYT][t] * pq;
+                        dx += ws[SB_BX][t] * a;
+                        dy += ws[SB_BY][t] * bq;
+                        cp += ws[SB_C][t] * pq;
+                    }
+                    double vx = ax + hB * gx, vy = ay + hB * gy, vp = hB * (dx + dy) - hC * cp;
+                    if (MODE == 2) {
+                        vx = (c == 0 ? br[0][0] : c == 1 ? br[0][1] : br[0][2]) - vx;
+                        vy = (c == 0 ? br[1][0] : c == 1 ? br[1][1] : br[1][2]) - vy;
+                        vp = (c == 0 ? br[2][0] : c == 1 ? br[2][1] : br[2][2]) - vp;
+                    }
+                    if (MODE == 1) acc += vx * u0 + vy * v0 + vp * p0;
+                    const int64_t p = rowb + i;
+                    yx_[p] = vx;
+                    yy_[p] = vy;
+                    yp_[p] = vp;
+                    push_face_near(L, yx_, fi, i, j, vx);
+                    push_face_near(L, yy_, fi, i, j, vy);
+                    push_face_near(L, yp_, fi, i, j, vp);
+                }
+            }
+            __syncthreads();                               // LDS free for the next tile
+        }
+    }
+    if (MODE == 1) {
+        const double sblk = block_sum<ST_NT>(acc, sm);
+        if (threadIdx.x == 0) partials[blockIdx.x] = sblk;
+    }
+}
+
+template <int MODE>
+__global__ __launch_bounds__(NT) void k_stokes_apply_low(LevelDev L, const double* __restrict__ x,
+                                                        const double* __restrict__ b, double* __restrict__ y,
+                                                        int64_t fs, double hB, double hC,
+                                                        double* __restrict__ partials) {
     __shared__ double sm[NT / 64 + 1];
     double acc = 0.0;
     const double* xx = x;
@@ -92,38 +226,14 @@ __global__ __launch_bounds__(NT) void k_stokes_apply(LevelDev L, const double* _
     double* yx_ = y;
     double* yy_ = y + fs;
     double* yp_ = y + 2 * fs;
-    if ((int)blockIdx.x < gf) {
-        FACE_TILE_LOOP(L, gf)
-        const StokesFace& sf = L.sfaces[face];
-        const FaceNbr q = face_nbr(p, up, dn);
-        double ux[7], uy[7], pp[7];
-#pragma unroll
-        for (int t = 0; t < 7; ++t) {
-            ux[t] = xx[q.o[t]];
-            uy[t] = xy[q.o[t]];
-            pp[t] = xp[q.o[t]];
-        }
-        double vx, vy, vp;
-        stokes_rows<7>(sf.w, 7, ux, uy, pp, hB, hC, vx, vy, vp);
-        if (MODE == 2) {
-            vx = b[p] - vx;
-            vy = b[fs + p] - vy;
-            vp = b[2 * fs + p] - vp;
-        }
-        if (MODE == 1) acc += vx * ux[0] + vy * uy[0] + vp * pp[0];
-        yx_[p] = vx;
-        yy_[p] = vy;
-        yp_[p] = vp;
-        push_face_near(L, yx_, fi, i, j, vx);
-        push_face_near(L, yy_, fi, i, j, vy);
-        push_face_near(L, yp_, fi, i, j, vp);
-        FACE_TILE_END
-    } else {
-        LOW_LOOP(L, gf) {
+    const int n = L.n;
+    {
+        const int64_t ne = (int64_t)L.E * (n - 2);
+        for (int64_t t = (int64_t)blockIdx.x * NT + threadIdx.x; t < ne + L.V; t += (int64_t)gridDim.x * NT) {
             double ux[1 + MAXDEG], uy[1 + MAXDEG], pp[1 + MAXDEG];
             double vx, vy, vp;
-            if (t < ne_) {
-                const int e = (int)(t / (nl_ - 2)), k = (int)(t % (nl_ - 2)) + 1;
+            if (t < ne) {
+                const int e = (int)(t / (n - 2)), k = (int)(t % (n - 2)) + 1;
                 const EdgeInfo& ei = L.edges[e];
                 const StokesEdge& se = L.sedges[e];
                 const int64_t m = edge_main(L, e) + k;
@@ -156,7 +266,7 @@ __global__ __launch_bounds__(NT) void k_stokes_apply(LevelDev L, const double* _
                 push_edge(L, yy_, ei, k, vy, true);
                 push_edge(L, yp_, ei, k, vp, true);
             } else {
-                const int v = (int)(t - ne_);
+                const int v = (int)(t - ne);
                 const VertexInfo& vi = L.verts[v];
                 const StokesVert& sv = L.sverts[v];
                 const int64_t vb = vert_off(L, v);
@@ -387,15 +497,22 @@ int64_t stokes_partials() { return (int64_t)MAX_FACE_BLOCKS + MAX_LOW_BLOCKS; }
 hipError_t launch_stokes_apply(const hhg_mesh* M, int level, int mode, const double* x, const double* b,
                                double* y, double* partials, int64_t* nparts, hipStream_t s) {
     const LevelDev L = M->dev(level);
-    const StGrid g = st_grid(L);
+    StGrid g;
+    g.gf = (int)std::max<int64_t>(1, std::min<int64_t>((int64_t)L.F * L.n_gs_tl[0][0], MAX_FACE_BLOCKS));
+    g.gl = st_grid_for((int64_t)L.E * (L.n - 2) + L.V, MAX_LOW_BLOCKS);
+    double* lp = partials ? partials + g.gf : nullptr;
     const int64_t fs = L.total;
     const double hB = std::ldexp(1.0, -level), hC = L.inv4l;
-    if (mode == 0)
-        k_stokes_apply<0><<<g.gf + g.gl, NT, 0, s>>>(L, x, b, y, fs, hB, hC, g.gf, partials);
-    else if (mode == 1)
-        k_stokes_apply<1><<<g.gf + g.gl, NT, 0, s>>>(L, x, b, y, fs, hB, hC, g.gf, partials);
-    else
-        k_stokes_apply<2><<<g.gf + g.gl, NT, 0, s>>>(L, x, b, y, fs, hB, hC, g.gf, partials);
+    if (mode == 0) {
+        k_stokes_apply<0><<<g.gf, ST_NT, 0, s>>>(L, x, b, y, fs, hB, hC, g.gf, partials);
+        k_stokes_apply_low<0><<<g.gl, NT, 0, s>>>(L, x, b, y, fs, hB, hC, lp);
+    } else if (mode == 1) {
+        k_stokes_apply<1><<<g.gf, ST_NT, 0, s>>>(L, x, b, y, fs, hB, hC, g.gf, partials);
+        k_stokes_apply_low<1><<<g.gl, NT, 0, s>>>(L, x, b, y, fs, hB, hC, lp);
+    } else {
+        k_stokes_apply<2><<<g.gf, ST_NT, 0, s>>>(L, x, b, y, fs, hB, hC, g.gf, partials);
+        k_stokes_apply_low<2><<<g.gl, NT, 0, s>>>(L, x, b, y, fs, hB, hC, lp);
+    }
     if (nparts) *nparts = g.gf + g.gl;
     return hipGetLastError();
 }
