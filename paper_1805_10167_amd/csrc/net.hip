@@ -33,6 +33,11 @@ constexpr int NXW = NET_TI + 6, NXR = NET_TJ + 6;     // x region of the fused s
 // pixels is four MFMA groups of 16 (4 slots unused).
 constexpr int RW = 64;
 static_assert(NXW == RW, "x region row = one wave");
+// The z planes (one per tap) are NZR rows of RW values, RW * NZR = 0 mod 64
+// dwords; padded to 8 mod 64, the 16-byte stores of the seven tap lanes of an
+// MFMA result land in disjoint banks (unpadded they all hit one bank).
+constexpr int ZPS = NZR * RW + 8;
+static_assert((NZR * RW) % 64 == 0 && ZPS % 4 == 0, "z plane padding assumes rows of whole banks");
 
 __constant__ int c_di[7] = {0, 1, -1, 0, 0, 1, -1};
 __constant__ int c_dj[7] = {0, 0, 0, 1, -1, -1, 1};
@@ -63,13 +68,13 @@ __device__ __forceinline__ int64_t nedge_ghost(const LevelDev& L, int e, int s) 
 }
 
 // z_t over the hidden region (tile grown by 1): MFMA (BF16) or FP32.
-// rs[r][c]: rho at (i0 - 2 + c, j0 - 2 + r); zs[t][r][c]: z_t at hidden
+// rs[r][c]: rho at (i0 - 2 + c, j0 - 2 + r); zs[t][r * RW + c]: z_t at hidden
 // pixel (i0 - 1 + c, j0 - 1 + r).  A wave takes whole hidden rows; in an
 // MFMA group lane l16 is pixel 16 q + l16 of the row and lane group q4
 // holds taps (layer 1) or channels (layer 2) 4 q4 .. 4 q4 + 3.
 template <bool MFMA>
 __device__ __forceinline__ void net_hidden(int n, int i0, int j0, const float* __restrict__ W,
-                                           float (*rs)[RW], float (*zs)[NZR][RW]) {
+                                           float (*rs)[RW], float (*zs)[ZPS]) {
     const int lane = threadIdx.x & 63;
     const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     if (MFMA) {
@@ -112,11 +117,7 @@ __device__ __forceinline__ void net_hidden(int n, int i0, int j0, const float* _
                 float4v z = {0.f, 0.f, 0.f, 0.f};
                 z = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(hop, w2op, z, 0, 0, 0);
                 // lane holds z for tap l16 of pixels 16 q + 4 q4 + e
-                if (l16 < 7) {
-                    float* zr = &zs[l16][row][16 * q + 4 * q4];
-#pragma unroll
-                    for (int e = 0; e < 4; ++e) zr[e] = z[e];
-                }
+                if (l16 < 7) *reinterpret_cast<float4v*>(&zs[l16][row * RW + 16 * q + 4 * q4]) = z;
             }
         }
     } else {
@@ -134,7 +135,7 @@ __device__ __forceinline__ void net_hidden(int n, int i0, int j0, const float* _
                     for (int t = 0; t < 7; ++t) z[t] += W[112 + c * 7 + t] * h;
                 }
             }
-            for (int t = 0; t < 7; ++t) zs[t][row][cc] = z[t];
+            for (int t = 0; t < 7; ++t) zs[t][row * RW + cc] = z[t];
         }
     }
 }
@@ -173,10 +174,10 @@ __device__ __forceinline__ void net_store(float* __restrict__ y, const NetFace& 
 }
 
 // out at output pixel (i0 + c, j0 + r) from the z planes.
-__device__ __forceinline__ float net_out(float (*zs)[NZR][RW], int r, int c) {
+__device__ __forceinline__ float net_out(float (*zs)[ZPS], int r, int c) {
     float o = 0.f;
 #pragma unroll
-    for (int t = 0; t < 7; ++t) o += zs[t][r + 1 + c_dj[t]][c + 1 + c_di[t]];
+    for (int t = 0; t < 7; ++t) o += zs[t][(r + 1 + c_dj[t]) * RW + c + 1 + c_di[t]];
     return o;
 }
 
@@ -193,7 +194,7 @@ __global__ __launch_bounds__(NET_NT) void k_net_forward(LevelDev L, const T* __r
                                                         T* __restrict__ y, const float* __restrict__ W,
                                                         int mode) {
     __shared__ float rs[NRR + 1][RW];
-    __shared__ float zs[7][NZR][RW];
+    __shared__ __align__(16) float zs[7][ZPS];
     const int n = L.n;
     const int lane = threadIdx.x & 63, wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int ntile = L.F * L.n_net_tiles;
@@ -298,7 +299,7 @@ __global__ __launch_bounds__(NET_NT) void k_net_step(LevelDev L, const float* __
     __shared__ float xs[NXR][RW];
     __shared__ float ks[VARK ? NXR : 1][RW];
     __shared__ float rs[NRR + 1][RW];
-    __shared__ float zs[7][NZR][RW];
+    __shared__ __align__(16) float zs[7][ZPS];
     const int n = L.n;
     if ((int)blockIdx.x >= nblk_tiles) {
         // copies x -> y: edge main (k = 0..n-1), vertex blocks, face rings,
