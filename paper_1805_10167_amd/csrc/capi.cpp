@@ -52,6 +52,7 @@ void carve(hhg_mesh* M, uint32_t feat, Carver& c) {
             for (int t = 0; t < 2; ++t)
                 H.d_gs_tl[e][t] = (int2*)c.take(sizeof(int2) * (H.gs_tl[e][t].size() + 1));
         H.d_net_tiles = (int2*)c.take(sizeof(int2) * (H.net_tiles.size() + 1));
+        H.d_net_strips = (int2*)c.take(sizeof(int2) * (H.net_strips.size() + 1));
         H.d_gdst = (int64_t*)c.take(sizeof(int64_t) * (H.gdst.size() + 1));
         H.d_gsrc = (int64_t*)c.take(sizeof(int64_t) * (H.gsrc.size() + 1));
     }
@@ -356,6 +357,7 @@ hhg::LevelDev hhg_mesh::dev(int level) const {
             L.gs_tl[e][t] = H.d_gs_tl[e][t];
         }
     L.n_net_tiles = (int32_t)H.net_tiles.size();
+    L.n_net_strips = (int32_t)H.net_strips.size();
     L.n_iedges = (int32_t)m.iedges.size();
     L.n_iverts = (int32_t)m.iverts.size();
     L.face_stride = H.face_stride;
@@ -372,6 +374,7 @@ hhg::LevelDev hhg_mesh::dev(int level) const {
     L.row_off = H.d_row_off;
     L.tiles = H.d_tiles;
     L.net_tiles = H.d_net_tiles;
+    L.net_strips = H.d_net_strips;
     L.faces = d_faces;
     L.edges = d_edges;
     L.verts = d_verts;
@@ -470,6 +473,7 @@ int hhg_bind_workspace(hhg_mesh* M, uint32_t features, void* dptr, size_t bytes,
         for (int e = 0; e < GS_NHALO; ++e)
             for (int t = 0; t < 2; ++t) HIP_CHECK(upload(H.d_gs_tl[e][t], H.gs_tl[e][t], s), "upload");
         HIP_CHECK(upload(H.d_net_tiles, H.net_tiles, s), "upload");
+        HIP_CHECK(upload(H.d_net_strips, H.net_strips, s), "upload");
         HIP_CHECK(upload(H.d_gdst, H.gdst, s), "upload");
         HIP_CHECK(upload(H.d_gsrc, H.gsrc, s), "upload");
     }

@@ -35,6 +35,8 @@ constexpr int gs_tile_width(int halo) { return GS_W - 2 * halo; }
 // learned-smoother tile: NET_TI x NET_TJ output points
 constexpr int NET_TI = 58;
 constexpr int NET_TJ = 12;
+// fused learned step: one wave streams NET_SR output rows of a NET_TI-wide strip
+constexpr int NET_SR = 32;
 constexpr int COARSE_DENSE_MAXN = 2048;   // coarse systems solved with a stored inverse
 constexpr int NET_NW = 224;     // weights: W1[16][7] then W2[16][7]
 
@@ -160,7 +162,7 @@ struct LevelDev {
     int32_t level, n;
     int32_t F, E, V;
     int32_t ghost_off, ghost_stride, vert_stride;
-    int32_t ntiles, n_iedges, n_iverts, n_net_tiles;
+    int32_t ntiles, n_iedges, n_iverts, n_net_tiles, n_net_strips;
     int32_t n_gs_tl[GS_NHALO][2];    // smoother tiles per face, [halo][GS_TJ16 rows]
     int64_t face_stride, edge_stride;
     int64_t face_base, edge_base, vert_base, total;
@@ -171,6 +173,7 @@ struct LevelDev {
     const int2* tiles;                // 64 x 4 tiles covering the whole face
     const int2* gs_tl[GS_NHALO][2];   // smoother tiles covering the whole face
     const int2* net_tiles;            // learned-smoother tiles meeting the interior
+    const int2* net_strips;           // learned-step strip pieces meeting the interior
     const FaceInfo* faces;
     const EdgeInfo* edges;
     const VertexInfo* verts;
@@ -211,6 +214,7 @@ struct LevelHost {
     std::vector<int2> tiles;
     std::vector<int2> gs_tl[GS_NHALO][2];   // [halo][GS_TJ16 rows]
     std::vector<int2> net_tiles;
+    std::vector<int2> net_strips;
     std::vector<int64_t> gdst, gsrc;
     int64_t gcls[G_NCLS + 1] = {0, 0, 0, 0, 0};
     int64_t n_all = 0, n_int = 0, can_edge_base = 0, can_face_base = 0;
@@ -219,6 +223,7 @@ struct LevelHost {
     int2* d_tiles = nullptr;
     int2* d_gs_tl[GS_NHALO][2] = {};
     int2* d_net_tiles = nullptr;
+    int2* d_net_strips = nullptr;
     int64_t* d_gdst = nullptr;
     int64_t* d_gsrc = nullptr;
 };

@@ -644,6 +644,14 @@ void MeshData::build_level(int level) {
             int imin = std::max(ti * NET_TI, 1), jmin = std::max(tj * NET_TJ, 1);
             if (imin + jmin <= n - 2) H.net_tiles.push_back(make_int2(ti, tj));
         }
+    // learned-step strip pieces (NET_TI columns, NET_SR rows) that contain
+    // interior points; a strip's pieces are consecutive, top to bottom
+    H.net_strips.clear();
+    for (int ti = 0; ti * NET_TI <= n - 3; ++ti)
+        for (int tj = 0; tj * NET_SR <= n - 3; ++tj) {
+            int imin = std::max(ti * NET_TI, 1), jmin = std::max(tj * NET_SR, 1);
+            if (imin + jmin <= n - 2) H.net_strips.push_back(make_int2(ti, tj));
+        }
 
     // ghost table
     std::vector<std::tuple<int, int64_t, int64_t>> ent;

@@ -18,6 +18,7 @@
 
 #include <algorithm>
 #include <cstdint>
+#include <type_traits>
 
 #include "hhg_kernels.hpp"
 
@@ -27,12 +28,12 @@ constexpr int NET_NT = 256;
 constexpr int NWV = NET_NT / 64;                      // waves per block
 constexpr int NZ = NET_TI + 2, NZR = NET_TJ + 2;      // hidden/z region (tile + 1)
 constexpr int NRW = NET_TI + 4, NRR = NET_TJ + 4;     // rho region (tile + 2)
-constexpr int NXW = NET_TI + 6, NXR = NET_TJ + 6;     // x region of the fused step (tile + 3)
+constexpr int NXW = NET_TI + 6;                       // x columns of a fused-step strip (tile + 3)
 // LDS rows of every region are 64 values: one per lane of a wave, so a wave
 // works on whole rows with wave-uniform row offsets.  The hidden row of 60
 // pixels is four MFMA groups of 16 (4 slots unused).
 constexpr int RW = 64;
-static_assert(NXW == RW, "x region row = one wave");
+static_assert(NXW == RW, "x row of a strip = one wave");
 // The z planes (one per tap) are NZR rows of RW values, RW * NZR = 0 mod 64
 // dwords; padded to 8 mod 64, the 16-byte stores of the seven tap lanes of an
 // MFMA result land in disjoint banks (unpadded they all hit one bank).
@@ -244,24 +245,63 @@ __global__ __launch_bounds__(NET_NT) void k_net_forward(LevelDev L, const T* __r
     }
 }
 
-// Face step of the learned sweep in one pass, from x to y:
-//   rho = D^-1 (f - A x) on the tile grown by 2 (face-interior points from an
-//   LDS tile of x grown by 3; ring points from rho_ring, written beforehand
-//   by the edge/vertex Jacobi pass; 0 outside the triangle),
-//   y = x + N(rho) on the tile's face-interior points, with their near-row
+// Face step of the learned sweep, from x to y:
+//   rho = D^-1 (f - A x) on face-interior points (ring points take rho_ring,
+//   written beforehand by the edge/vertex Jacobi pass; 0 outside the
+//   triangle), y = x + N(rho) on face-interior points, with their near-row
 //   copies in y's ghost rows.
+// One wave per strip piece: output columns i0 <= i < i0 + NET_TI and rows
+// j0 <= j < j0 + NET_SR of one face, lane c standing for column
+// i = i0 - 3 + c.  The wave walks down the rows; at row s it
+//   - takes x of row s + 3 and f (or rho_ring) of row s + 2 from a register
+//     queue filled three rows ahead,
+//   - forms rho of row s + 2 from the x rows s + 1 .. s + 3 held in
+//     registers (east and west neighbours by whole-wave lane shifts),
+//   - forms the hidden layer and z of row s + 1 from rho rows s .. s + 2,
+//   - forms out of row s from z rows s - 1 .. s + 1 and writes y = x + out.
+// rho and z live in rings of three rows in the wave's own LDS: a wave never
+// waits for another, and every row of every stage is formed once.
 // Extra blocks copy what the face step leaves unchanged from x to y: edge
 // and vertex blocks, face rings and the ghost-row corner entries, so y is a
-// complete field.  Reading x and writing y keeps the halo reads of
-// neighbouring tiles free of updated values.
+// complete field.  Reading x and writing y keeps the rows that neighbouring
+// pieces read free of updated values.
 constexpr int NS_COPY_BLOCKS = 32;
-constexpr int NXL = (NXR + NWV - 1) / NWV;      // x rows per wave
+constexpr int NS_RW = 72;              // rho ring row: pixel p at p + 4
+constexpr int NS_ZP = 3 * RW + 4;      // z ring of one tap: three rows of RW pixels, planes 4 mod 64 banks apart
+struct NetRing {
+    float rho[3][NS_RW];
+    float z[7][NS_ZP];
+};
+static_assert((3 * NS_RW) % 4 == 0 && NS_ZP % 4 == 0 && RW % 4 == 0, "16-byte aligned z stores");
 
+__host__ __device__ constexpr int tap_di(int t) { return (t == 1 || t == 5) ? 1 : ((t == 2 || t == 6) ? -1 : 0); }
+__host__ __device__ constexpr int tap_dj(int t) { return (t == 3 || t == 6) ? 1 : ((t == 4 || t == 5) ? -1 : 0); }
+
+// Value held by lane c + 1 (lane_next) or c - 1 (lane_prev) of the wave, 0
+// where that lane does not exist.
+__device__ __forceinline__ float lane_next(float v) {
+    return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v), 0x130, 0xf, 0xf, false));
+}
+__device__ __forceinline__ float lane_prev(float v) {
+    return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v), 0x138, 0xf, 0xf, false));
+}
+
+// LDS written by some lanes of a wave and read by others of the same wave:
+// the DS instructions of one wave execute in order, so only the compiler has
+// to keep them in program order.
+__device__ __forceinline__ void wave_lds_order() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// rho at the lane's point of the middle row from x (and k) of the rows
+// below (S), at (0) and above (N) it.
 template <bool VARK>
-__device__ __forceinline__ float net_rho_point(const NetFace& nf, float (*xs)[RW], float (*ks)[RW],
-                                               int r, int c, float fv) {
-    const float uE = xs[r][c + 1], uW = xs[r][c - 1], uN = xs[r + 1][c], uS = xs[r - 1][c];
-    const float uSE = xs[r - 1][c + 1], uNW = xs[r + 1][c - 1], u0 = xs[r][c];
+__device__ __forceinline__ float net_rho_rows(const NetFace& nf, float xS, float x0, float xN, float kS_,
+                                              float k0_, float kN_, float fv) {
+    const float uE = lane_next(x0), uW = lane_prev(x0), uN = xN, uS = xS;
+    const float uSE = lane_next(xS), uNW = lane_prev(xN), u0 = x0;
     const float c0 = nf.c0, c1 = nf.c1, c2 = nf.c2;
     float we, ww, wn, ws, wse, wnw, wc;
     if (!VARK) {
@@ -270,8 +310,8 @@ __device__ __forceinline__ float net_rho_point(const NetFace& nf, float (*xs)[RW
         wn = ws = -c1;
         wse = wnw = -c0;
     } else {
-        const float k0 = ks[r][c], kE = ks[r][c + 1], kW = ks[r][c - 1], kN = ks[r + 1][c];
-        const float kS = ks[r - 1][c], kSE = ks[r - 1][c + 1], kNW = ks[r + 1][c - 1];
+        const float k0 = k0_, kE = lane_next(k0_), kW = lane_prev(k0_), kN = kN_;
+        const float kS = kS_, kSE = lane_next(kS_), kNW = lane_prev(kN_);
         const float third = 1.0f / 3.0f, h = 0.5f;
         const float t1 = (k0 + kE + kN) * third, t2 = (kSE + kE + k0) * third;
         const float t3 = (kW + k0 + kNW) * third, t4 = (kS + k0 + kW) * third;
@@ -295,16 +335,13 @@ __global__ __launch_bounds__(NET_NT) void k_net_step(LevelDev L, const float* __
                                                      float* __restrict__ y, const float* __restrict__ f,
                                                      const float* __restrict__ kap,
                                                      const float* __restrict__ rho_ring,
-                                                     const float* __restrict__ W, int nblk_tiles) {
-    __shared__ float xs[NXR][RW];
-    __shared__ float ks[VARK ? NXR : 1][RW];
-    __shared__ float rs[NRR + 1][RW];
-    __shared__ __align__(16) float zs[7][ZPS];
+                                                     const float* __restrict__ W, int nblk) {
+    __shared__ __align__(16) NetRing rings[NWV];
     const int n = L.n;
-    if ((int)blockIdx.x >= nblk_tiles) {
+    if ((int)blockIdx.x >= nblk) {
         // copies x -> y: edge main (k = 0..n-1), vertex blocks, face rings,
         // ghost-row corner entries
-        const int cb = blockIdx.x - nblk_tiles, ncb = gridDim.x - nblk_tiles;
+        const int cb = blockIdx.x - nblk, ncb = gridDim.x - nblk;
         const int64_t ne = (int64_t)L.E * n, nv = (int64_t)L.V * L.vert_stride;
         const int64_t nr = (int64_t)L.F * 3 * (n - 1), ng = (int64_t)L.E * 4;
         for (int64_t t = (int64_t)cb * NET_NT + threadIdx.x; t < ne + nv + nr + ng; t += (int64_t)ncb * NET_NT) {
@@ -333,64 +370,166 @@ __global__ __launch_bounds__(NET_NT) void k_net_step(LevelDev L, const float* __
         return;
     }
     const int lane = threadIdx.x & 63, wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    const int ntile = L.F * L.n_net_tiles;
-    for (int tile = blockIdx.x; tile < ntile; tile += nblk_tiles) {
-    __syncthreads();                                   // LDS of the previous tile is free
-    const int face = tile / L.n_net_tiles;
-    const int2 tl = L.net_tiles[tile % L.n_net_tiles];
-    const int i0 = tl.x * NET_TI, j0 = tl.y * NET_TJ;
+    // consecutive logical blocks (neighbouring pieces, which share halo rows)
+    // on one XCD: hardware block b runs on XCD b mod 8
+    const int b = blockIdx.x, lb = (b & 7) * (nblk >> 3) + (b >> 3);
+    const int task = lb * NWV + wv;
+    if (task >= L.F * L.n_net_strips) return;          // the whole wave
+    NetRing& R = rings[wv];
+    const int face = task / L.n_net_strips;
+    const int2 st = L.net_strips[task % L.n_net_strips];
+    const int i0 = st.x * NET_TI, j0 = st.y * NET_SR;
+    const int s_end = min(j0 + NET_SR, n - 1 - max(i0, 1));   // last output row + 1
     const NetFace nf = net_face(L, L.faces[face]);
     const int64_t fb = nface_base(L, face);
-    // x (and k) over the tile grown by 3: row r of wave wv + NWV k, column =
-    // lane; the row (and its start) is the same for the whole wave
-    float xv[NXL], kv[VARK ? NXL : 1];
-#pragma unroll
-    for (int k = 0; k < NXL; ++k) {
-        const int r = wv + NWV * k, j = j0 - 3 + r, i = i0 - 3 + lane;
-        const bool row_ok = r < NXR && j >= 0 && j < n;
-        const bool in = row_ok && i >= 0 && i <= n - 1 - j;
-        const int64_t p = fb + nrow_start(n, row_ok ? j : 0) + i;
-        xv[k] = in ? x[p] : 0.f;
-        if (VARK) kv[k] = in ? kap[p] : 0.f;
-    }
-    // f at the rho region's interior points, rho at its ring points
-    float fv[NLR];
-#pragma unroll
-    for (int k = 0; k < NLR; ++k) {
-        const int r = wv + NWV * k, j = j0 - 2 + r, i = i0 - 2 + lane;
-        const bool row_ok = r < NRR && j >= 0 && j < n;
-        const bool in = row_ok && lane < NRW && i >= 0 && i <= n - 1 - j;
-        const bool interior = in && j >= 1 && i >= 1 && i + j <= n - 2;
-        const int64_t p = fb + nrow_start(n, row_ok ? j : 0) + i;
-        fv[k] = interior ? f[p] : (in ? rho_ring[p] : 0.f);
-    }
-#pragma unroll
-    for (int k = 0; k < NXL; ++k) {
-        const int r = wv + NWV * k;
-        if (r < NXR) {
-            xs[r][lane] = xv[k];
-            if (VARK) ks[r][lane] = kv[k];
+    const int ic = i0 - 3 + lane;
+    const int q4 = lane >> 4, l16 = lane & 15;
+    if (lane < 24) R.rho[lane >> 3][(lane & 7) < 4 ? (lane & 7) : NS_RW - 8 + (lane & 7)] = 0.f;
+
+    auto load_x = [&](int j, float& xv, float& kv) {
+        xv = 0.f;
+        kv = 0.f;
+        if (j >= 0 && j < n && ic >= 0 && ic <= n - 1 - j) {
+            const int64_t p = fb + nrow_start(n, j) + ic;
+            xv = x[p];
+            if (VARK) kv = kap[p];
         }
-    }
-    __syncthreads();
+    };
+    auto load_f = [&](int j) {
+        float v = 0.f;
+        if (j >= 0 && j < n && ic >= 0 && ic <= n - 1 - j) {
+            const int64_t p = fb + nrow_start(n, j) + ic;
+            const float* src = (j >= 1 && ic >= 1 && ic + j <= n - 2) ? f : rho_ring;
+            v = src[p];
+        }
+        return v;
+    };
+
+    // weights as MFMA operands (layer 1: A[c][tap], layer 2: B[c][tap]) and
+    // each lane's four rho tap offsets for the three ring phases; the lanes
+    // of unused taps (weight 0) read a used tap's value
+    short4v w1op = {0, 0, 0, 0}, w2op = {0, 0, 0, 0};
+    int toff[3][4];
+    if (MFMA) {
+        float a1[4], a2[4];
 #pragma unroll
-    for (int k = 0; k < NLR; ++k) {
-        const int r = wv + NWV * k, j = j0 - 2 + r, i = i0 - 2 + lane;
-        if (r >= NRR) continue;
-        const bool interior = lane < NRW && j >= 1 && i >= 1 && i + j <= n - 2;
-        rs[r][lane] = interior ? net_rho_point<VARK>(nf, xs, VARK ? ks : nullptr, r + 1, lane + 1, fv[k]) : fv[k];
-    }
-    if (wv == 0) rs[NRR][lane] = 0.f;
-    __syncthreads();
-    net_hidden<MFMA>(n, i0, j0, W, rs, zs);
-    __syncthreads();
+        for (int e = 0; e < 4; ++e) {
+            const int t = 4 * q4 + e, tt = t < 7 ? t : e;
+            a1[e] = t < 7 ? W[l16 * 7 + t] : 0.f;
+            a2[e] = l16 < 7 ? W[112 + t * 7 + l16] : 0.f;
 #pragma unroll
-    for (int k = 0; k < NOR; ++k) {
-        const int r = wv + NWV * k, j = j0 + r, i = i0 + lane;
-        if (!(r < NET_TJ && lane < NET_TI && j >= 1 && i >= 1 && i + j <= n - 2)) continue;
-        const float val = xs[r + 3][lane + 3] + net_out(zs, r, lane);
-        net_store(y, nf, fb + nrow_start(n, j) + i, n, i, j, val);
+            for (int ph = 0; ph < 3; ++ph)
+                toff[ph][e] = ((ph + 1 + tap_dj(tt) + 3) % 3) * NS_RW + 4 + l16 + tap_di(tt);
+        }
+        w1op = to_bf16x4(a1[0], a1[1], a1[2], a1[3]);
+        w2op = to_bf16x4(a2[0], a2[1], a2[2], a2[3]);
     }
+    const float* rho_flat = &R.rho[0][0];
+    float* z_flat = &R.z[0][0];
+
+    // x (k) of rows s, s + 1, s + 2; queue: x rows s + 3 + q, f rows s + 2 + q
+    int s = j0 - 4;
+    float X0 = 0.f, X1, X2, K0 = 0.f, K1, K2;
+    float xq[3], kq[3], fq[3];
+    load_x(s + 1, X1, K1);
+    load_x(s + 2, X2, K2);
+#pragma unroll
+    for (int q = 0; q < 3; ++q) {
+        load_x(s + 3 + q, xq[q], kq[q]);
+        fq[q] = load_f(s + 2 + q);
+    }
+    (void)K0;
+
+    auto step = [&](auto phase) {
+        constexpr int PH = decltype(phase)::value;
+        const float X3 = xq[PH], K3 = kq[PH], F2 = fq[PH];
+        // refill: x is needed up to row s_end + 2, f up to row s_end + 1
+        if (s + 6 <= s_end + 2) load_x(s + 6, xq[PH], kq[PH]);
+        if (s + 5 <= s_end + 1) fq[PH] = load_f(s + 5);
+        {   // rho of row s + 2
+            const int j = s + 2;
+            const float r = net_rho_rows<VARK>(nf, X1, X2, X3, K1, K2, K3, F2);
+            const bool interior = j >= 1 && ic >= 1 && ic + j <= n - 2;
+            R.rho[(PH + 2) % 3][lane + 4] = interior ? r : F2;
+        }
+        wave_lds_order();
+        if (s >= j0 - 2) {   // hidden layer and z of row s + 1
+            const int j = s + 1;
+            float* zrow = z_flat + ((PH + 1) % 3) * RW;
+            if (MFMA) {
+                float* zdst = zrow + l16 * NS_ZP + 4 * q4;
+                if (j >= 1 && j <= n - 3) {
+                    const unsigned lim = (unsigned)(n - 3 - j);
+#pragma unroll
+                    for (int q = 0; q < 4; ++q) {
+                        float v[4];
+#pragma unroll
+                        for (int e = 0; e < 4; ++e) v[e] = rho_flat[toff[PH][e] + 16 * q];
+                        float4v acc = {0.f, 0.f, 0.f, 0.f};
+                        acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(w1op, to_bf16x4(v[0], v[1], v[2], v[3]),
+                                                                        acc, 0, 0, 0);
+                        // lane holds a for channels 4 q4 + e of pixel 16 q + l16; the
+                        // hidden layer exists on interior pixels only
+                        const float cap = (unsigned)(i0 - 4 + l16 + 16 * q) <= lim ? __builtin_inff() : 0.f;
+                        const short4v hop = to_bf16x4(__builtin_amdgcn_fmed3f(acc[0], 0.f, cap),
+                                                      __builtin_amdgcn_fmed3f(acc[1], 0.f, cap),
+                                                      __builtin_amdgcn_fmed3f(acc[2], 0.f, cap),
+                                                      __builtin_amdgcn_fmed3f(acc[3], 0.f, cap));
+                        float4v z = {0.f, 0.f, 0.f, 0.f};
+                        z = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(hop, w2op, z, 0, 0, 0);
+                        // lane holds z for tap l16 of pixels 16 q + 4 q4 + e
+                        if (l16 < 7) *reinterpret_cast<float4v*>(zdst + 16 * q) = z;
+                    }
+                } else {
+                    const float4v zero = {0.f, 0.f, 0.f, 0.f};
+                    if (l16 < 7) {
+#pragma unroll
+                        for (int q = 0; q < 4; ++q) *reinterpret_cast<float4v*>(zdst + 16 * q) = zero;
+                    }
+                }
+            } else {
+                float z[7] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+                if (j >= 1 && ic >= 1 && ic + j <= n - 2) {
+                    float rt[7];
+#pragma unroll
+                    for (int t = 0; t < 7; ++t)
+                        rt[t] = rho_flat[((PH + 1 + tap_dj(t) + 3) % 3) * NS_RW + lane + 4 + tap_di(t)];
+                    for (int c = 0; c < 16; ++c) {
+                        float a = 0.f;
+#pragma unroll
+                        for (int t = 0; t < 7; ++t) a += W[c * 7 + t] * rt[t];
+                        const float h = fmaxf(a, 0.f);
+#pragma unroll
+                        for (int t = 0; t < 7; ++t) z[t] += W[112 + c * 7 + t] * h;
+                    }
+                }
+#pragma unroll
+                for (int t = 0; t < 7; ++t) zrow[t * NS_ZP + lane] = z[t];
+            }
+            wave_lds_order();
+        }
+        if (s >= j0 && lane >= 3 && lane < 3 + NET_TI && s >= 1 && ic >= 1 && ic + s <= n - 2) {
+            // out of row s from z rows s - 1 .. s + 1
+            const float* zb = z_flat + lane;
+            float o = 0.f;
+#pragma unroll
+            for (int t = 0; t < 7; ++t) o += zb[t * NS_ZP + ((PH + tap_dj(t) + 3) % 3) * RW + tap_di(t)];
+            net_store(y, nf, fb + nrow_start(n, s) + ic, n, ic, s, X0 + o);
+        }
+        X0 = X1;
+        X1 = X2;
+        X2 = X3;
+        K1 = K2;
+        K2 = K3;
+        ++s;
+    };
+    for (;;) {
+        if (s >= s_end) break;
+        step(std::integral_constant<int, 0>());
+        if (s >= s_end) break;
+        step(std::integral_constant<int, 1>());
+        if (s >= s_end) break;
+        step(std::integral_constant<int, 2>());
     }
 }
 
@@ -493,15 +632,16 @@ hipError_t launch_net_forward(const hhg_mesh* M, int level, const float* rho, fl
 hipError_t launch_net_step(const hhg_mesh* M, int level, int op, const float* x, float* y, const float* f,
                            const float* rho_ring, bool mfma, hipStream_t s) {
     const LevelDev L = M->dev(level);
-    const int nt = L.F * L.n_net_tiles;
-    const int g = nt + NS_COPY_BLOCKS;
+    const int nt = L.F * L.n_net_strips;
+    const int nblk = (int)pad_up((nt + NWV - 1) / NWV, 8);   // whole XCD rounds
+    const int g = nblk + NS_COPY_BLOCKS;
     const float* kap = M->kap32[level];
     if (op == OP_DIFFUSION) {
-        if (mfma) k_net_step<true, true><<<g, NET_NT, 0, s>>>(L, x, y, f, kap, rho_ring, M->net_w, nt);
-        else k_net_step<true, false><<<g, NET_NT, 0, s>>>(L, x, y, f, kap, rho_ring, M->net_w, nt);
+        if (mfma) k_net_step<true, true><<<g, NET_NT, 0, s>>>(L, x, y, f, kap, rho_ring, M->net_w, nblk);
+        else k_net_step<true, false><<<g, NET_NT, 0, s>>>(L, x, y, f, kap, rho_ring, M->net_w, nblk);
     } else {
-        if (mfma) k_net_step<false, true><<<g, NET_NT, 0, s>>>(L, x, y, f, kap, rho_ring, M->net_w, nt);
-        else k_net_step<false, false><<<g, NET_NT, 0, s>>>(L, x, y, f, kap, rho_ring, M->net_w, nt);
+        if (mfma) k_net_step<false, true><<<g, NET_NT, 0, s>>>(L, x, y, f, kap, rho_ring, M->net_w, nblk);
+        else k_net_step<false, false><<<g, NET_NT, 0, s>>>(L, x, y, f, kap, rho_ring, M->net_w, nblk);
     }
     return hipGetLastError();
 }
