@@ -16,8 +16,9 @@ FLAGS = [
 ]
 
 
-# per-source extra flags (none at present)
-EXTRA = {}
+# per-source extra flags: MFMA results of the learned step go straight to
+# VGPRs (its activations are post-processed by vector instructions at once)
+EXTRA = {"net.hip": ["-mllvm", "-amdgpu-mfma-vgpr-form"]}
 
 
 def build(verbose=False):

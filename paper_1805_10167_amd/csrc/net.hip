@@ -48,11 +48,15 @@ typedef float float4v __attribute__((ext_vector_type(4)));
 typedef float float2v __attribute__((ext_vector_type(2)));
 typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
 typedef __bf16 bf16x4 __attribute__((ext_vector_type(4)));
+typedef unsigned uint2v __attribute__((ext_vector_type(2)));
 
-// Round to nearest even BF16 (the hardware conversion).
+// Round to nearest even BF16 (the hardware conversion), packed in pairs so
+// that each pair is one v_cvt_pk_bf16_f32.
 __device__ __forceinline__ short4v to_bf16x4(float a, float b, float c, float d) {
-    const float4v f = {a, b, c, d};
-    return __builtin_bit_cast(short4v, __builtin_convertvector(f, bf16x4));
+    const float2v f0 = {a, b}, f1 = {c, d};
+    const uint2v u = {__builtin_bit_cast(unsigned, __builtin_convertvector(f0, bf16x2)),
+                      __builtin_bit_cast(unsigned, __builtin_convertvector(f1, bf16x2))};
+    return __builtin_bit_cast(short4v, u);
 }
 __device__ __forceinline__ float bf16_round(float x) { return (float)(__bf16)x; }
 
@@ -266,6 +270,8 @@ __global__ __launch_bounds__(NET_NT) void k_net_forward(LevelDev L, const T* __r
 // complete field.  Reading x and writing y keeps the rows that neighbouring
 // pieces read free of updated values.
 constexpr int NS_COPY_BLOCKS = 32;
+constexpr int NS_U = 6;                // register ring rows (a multiple of 3); loads NS_U - 4 rows ahead
+static_assert(NS_U % 3 == 0 && (NS_U == 6 || NS_U == 9), "the step loop is written for 6 or 9 ring rows");
 constexpr int NS_RW = 72;              // rho ring row: pixel p at p + 4
 constexpr int NS_ZP = 3 * RW + 4;      // z ring of one tap: three rows of RW pixels, planes 4 mod 64 banks apart
 struct NetRing {
@@ -276,6 +282,16 @@ static_assert((3 * NS_RW) % 4 == 0 && NS_ZP % 4 == 0 && RW % 4 == 0, "16-byte al
 
 __host__ __device__ constexpr int tap_di(int t) { return (t == 1 || t == 5) ? 1 : ((t == 2 || t == 6) ? -1 : 0); }
 __host__ __device__ constexpr int tap_dj(int t) { return (t == 3 || t == 6) ? 1 : ((t == 4 || t == 5) ? -1 : 0); }
+// Layer-1 contraction index k -> tap (-1: unused): C E N S | W - NW SE, so
+// that k and k + 4 have the same row offset k_dj(k % 4).
+__host__ __device__ constexpr int k_tap(int k) {
+    return k == 0 ? 0 : k == 1 ? 1 : k == 2 ? 3 : k == 3 ? 4 : k == 4 ? 2 : k == 6 ? 6 : k == 7 ? 5 : -1;
+}
+__host__ __device__ constexpr int k_dj(int e) { return e == 2 ? 1 : (e == 3 ? -1 : 0); }
+static_assert(tap_dj(k_tap(0)) == k_dj(0) && tap_dj(k_tap(4)) == k_dj(0) && tap_dj(k_tap(1)) == k_dj(1) &&
+                  tap_dj(k_tap(2)) == k_dj(2) && tap_dj(k_tap(6)) == k_dj(2) && tap_dj(k_tap(3)) == k_dj(3) &&
+                  tap_dj(k_tap(7)) == k_dj(3),
+              "one row offset per slot");
 
 // Value held by lane c + 1 (lane_next) or c - 1 (lane_prev) of the wave, 0
 // where that lane does not exist.
@@ -386,40 +402,39 @@ __global__ __launch_bounds__(NET_NT) void k_net_step(LevelDev L, const float* __
     const int q4 = lane >> 4, l16 = lane & 15;
     if (lane < 24) R.rho[lane >> 3][(lane & 7) < 4 ? (lane & 7) : NS_RW - 8 + (lane & 7)] = 0.f;
 
+    // Loads from addresses clamped into the face's triangle are always
+    // issued, so no register ever waits on a load it does not need: x (and
+    // k) outside the triangle reach only rho of non-interior points, which
+    // is replaced, and f is zeroed where it is consumed.
+    auto row_addr = [&](int j) {
+        const int jj = min(max(j, 0), n - 1);
+        return fb + nrow_start(n, jj) + min(max(ic, 0), n - 1 - jj);
+    };
     auto load_x = [&](int j, float& xv, float& kv) {
-        xv = 0.f;
-        kv = 0.f;
-        if (j >= 0 && j < n && ic >= 0 && ic <= n - 1 - j) {
-            const int64_t p = fb + nrow_start(n, j) + ic;
-            xv = x[p];
-            if (VARK) kv = kap[p];
-        }
+        const int64_t p = row_addr(j);
+        xv = x[p];
+        if (VARK) kv = kap[p];
     };
     auto load_f = [&](int j) {
-        float v = 0.f;
-        if (j >= 0 && j < n && ic >= 0 && ic <= n - 1 - j) {
-            const int64_t p = fb + nrow_start(n, j) + ic;
-            const float* src = (j >= 1 && ic >= 1 && ic + j <= n - 2) ? f : rho_ring;
-            v = src[p];
-        }
-        return v;
+        const float* src = (j >= 1 && ic >= 1 && ic + j <= n - 2) ? f : rho_ring;
+        return src[row_addr(j)];
     };
 
-    // weights as MFMA operands (layer 1: A[c][tap], layer 2: B[c][tap]) and
-    // each lane's four rho tap offsets for the three ring phases; the lanes
-    // of unused taps (weight 0) read a used tap's value
+    // Weights as MFMA operands.  Layer 1 contracts over k = 4 q4 + e with
+    // the taps ordered C E N S | W - NW SE (k_tap), so that slot e of every
+    // lane reads rho of one row offset: lane bases differ only in the column
+    // and the row of a ring phase is an instruction offset.  Lanes of unused
+    // k (weight 0) read the q4 = 0 tap of their slot.
     short4v w1op = {0, 0, 0, 0}, w2op = {0, 0, 0, 0};
-    int toff[3][4];
+    int tbase[4];
     if (MFMA) {
         float a1[4], a2[4];
 #pragma unroll
         for (int e = 0; e < 4; ++e) {
-            const int t = 4 * q4 + e, tt = t < 7 ? t : e;
-            a1[e] = t < 7 ? W[l16 * 7 + t] : 0.f;
-            a2[e] = l16 < 7 ? W[112 + t * 7 + l16] : 0.f;
-#pragma unroll
-            for (int ph = 0; ph < 3; ++ph)
-                toff[ph][e] = ((ph + 1 + tap_dj(tt) + 3) % 3) * NS_RW + 4 + l16 + tap_di(tt);
+            const int t = k_tap(4 * q4 + e), tt = t >= 0 ? t : k_tap(e);
+            a1[e] = t >= 0 ? W[l16 * 7 + t] : 0.f;            // A[c = l16][k]
+            a2[e] = l16 < 7 ? W[112 + (4 * q4 + e) * 7 + l16] : 0.f;   // B[c = 4 q4 + e][tap l16]
+            tbase[e] = 4 + l16 + tap_di(tt);
         }
         w1op = to_bf16x4(a1[0], a1[1], a1[2], a1[3]);
         w2op = to_bf16x4(a2[0], a2[1], a2[2], a2[3]);
@@ -427,27 +442,36 @@ __global__ __launch_bounds__(NET_NT) void k_net_step(LevelDev L, const float* __
     const float* rho_flat = &R.rho[0][0];
     float* z_flat = &R.z[0][0];
 
-    // x (k) of rows s, s + 1, s + 2; queue: x rows s + 3 + q, f rows s + 2 + q
-    int s = j0 - 4;
-    float X0 = 0.f, X1, X2, K0 = 0.f, K1, K2;
-    float xq[3], kq[3], fq[3];
-    load_x(s + 1, X1, K1);
-    load_x(s + 2, X2, K2);
+    // Register rings of NS_U rows: x (k) of row r in xr[(r - s0) % NS_U], f of
+    // row r in fr[(r - s0) % NS_U].  At step s the window is x rows s .. s + 3
+    // and f row s + 2; x row s + NS_U - 1 and f row s + NS_U - 2 are loaded
+    // into the slots that just fell out of use, NS_U - 4 steps ahead.  The
+    // loop is unrolled NS_U times so that every slot stays one register, and
+    // runs whole rounds (steps past the piece's last row skip their work):
+    // a loop exit between steps would make the compiler copy ring registers
+    // whose loads are still in flight.
+    const int s0 = j0 - 4;
+    float xr[NS_U], kr[NS_U], fr[NS_U];
 #pragma unroll
-    for (int q = 0; q < 3; ++q) {
-        load_x(s + 3 + q, xq[q], kq[q]);
-        fq[q] = load_f(s + 2 + q);
-    }
-    (void)K0;
+    for (int q = 1; q < NS_U - 1; ++q) load_x(s0 + q, xr[q], kr[q]);
+    xr[0] = kr[0] = xr[NS_U - 1] = kr[NS_U - 1] = 0.f;
+#pragma unroll
+    for (int q = 0; q < NS_U; ++q) fr[q] = 0.f;
+#pragma unroll
+    for (int q = 2; q < NS_U - 2; ++q) fr[q] = load_f(s0 + q);
 
-    auto step = [&](auto phase) {
-        constexpr int PH = decltype(phase)::value;
-        const float X3 = xq[PH], K3 = kq[PH], F2 = fq[PH];
-        // refill: x is needed up to row s_end + 2, f up to row s_end + 1
-        if (s + 6 <= s_end + 2) load_x(s + 6, xq[PH], kq[PH]);
-        if (s + 5 <= s_end + 1) fq[PH] = load_f(s + 5);
+    auto step = [&](auto phase, int s) {
+        constexpr int P = decltype(phase)::value;
+        load_x(s + NS_U - 1, xr[(P + NS_U - 1) % NS_U], kr[(P + NS_U - 1) % NS_U]);
+        fr[(P + NS_U - 2) % NS_U] = load_f(s + NS_U - 2);
+        if (s >= s_end) return;
+        const float X0 = xr[P], X1 = xr[(P + 1) % NS_U], X2 = xr[(P + 2) % NS_U], X3 = xr[(P + 3) % NS_U];
+        const float K1 = kr[(P + 1) % NS_U], K2 = kr[(P + 2) % NS_U], K3 = kr[(P + 3) % NS_U];
+        constexpr int PH = P % 3;   // ring row of row s in the LDS rings (NS_U is a multiple of 3)
         {   // rho of row s + 2
             const int j = s + 2;
+            const bool in = j >= 0 && j < n && ic >= 0 && ic <= n - 1 - j;
+            const float F2 = in ? fr[(P + 2) % NS_U] : 0.f;
             const float r = net_rho_rows<VARK>(nf, X1, X2, X3, K1, K2, K3, F2);
             const bool interior = j >= 1 && ic >= 1 && ic + j <= n - 2;
             R.rho[(PH + 2) % 3][lane + 4] = interior ? r : F2;
@@ -460,14 +484,17 @@ __global__ __launch_bounds__(NET_NT) void k_net_step(LevelDev L, const float* __
                 float* zdst = zrow + l16 * NS_ZP + 4 * q4;
                 if (j >= 1 && j <= n - 3) {
                     const unsigned lim = (unsigned)(n - 3 - j);
+                    float v[4][4];
+#pragma unroll
+                    for (int q = 0; q < 4; ++q)
+#pragma unroll
+                        for (int e = 0; e < 4; ++e)
+                            v[q][e] = rho_flat[tbase[e] + ((PH + 1 + k_dj(e) + 3) % 3) * NS_RW + 16 * q];
 #pragma unroll
                     for (int q = 0; q < 4; ++q) {
-                        float v[4];
-#pragma unroll
-                        for (int e = 0; e < 4; ++e) v[e] = rho_flat[toff[PH][e] + 16 * q];
                         float4v acc = {0.f, 0.f, 0.f, 0.f};
-                        acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(w1op, to_bf16x4(v[0], v[1], v[2], v[3]),
-                                                                        acc, 0, 0, 0);
+                        acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(
+                            w1op, to_bf16x4(v[q][0], v[q][1], v[q][2], v[q][3]), acc, 0, 0, 0);
                         // lane holds a for channels 4 q4 + e of pixel 16 q + l16; the
                         // hidden layer exists on interior pixels only
                         const float cap = (unsigned)(i0 - 4 + l16 + 16 * q) <= lim ? __builtin_inff() : 0.f;
@@ -516,20 +543,21 @@ __global__ __launch_bounds__(NET_NT) void k_net_step(LevelDev L, const float* __
             for (int t = 0; t < 7; ++t) o += zb[t * NS_ZP + ((PH + tap_dj(t) + 3) % 3) * RW + tap_di(t)];
             net_store(y, nf, fb + nrow_start(n, s) + ic, n, ic, s, X0 + o);
         }
-        X0 = X1;
-        X1 = X2;
-        X2 = X3;
-        K1 = K2;
-        K2 = K3;
-        ++s;
     };
-    for (;;) {
-        if (s >= s_end) break;
-        step(std::integral_constant<int, 0>());
-        if (s >= s_end) break;
-        step(std::integral_constant<int, 1>());
-        if (s >= s_end) break;
-        step(std::integral_constant<int, 2>());
+    const int rounds = (s_end - s0 + NS_U - 1) / NS_U;
+    for (int k = 0; k < rounds; ++k) {
+        const int s = s0 + k * NS_U;
+        step(std::integral_constant<int, 0>(), s);
+        step(std::integral_constant<int, 1>(), s + 1);
+        step(std::integral_constant<int, 2>(), s + 2);
+        step(std::integral_constant<int, 3>(), s + 3);
+        step(std::integral_constant<int, 4>(), s + 4);
+        step(std::integral_constant<int, 5>(), s + 5);
+        if (NS_U > 6) {
+            step(std::integral_constant<int, 6 % NS_U>(), s + 6);
+            step(std::integral_constant<int, 7 % NS_U>(), s + 7);
+            step(std::integral_constant<int, 8 % NS_U>(), s + 8);
+        }
     }
 }
 
