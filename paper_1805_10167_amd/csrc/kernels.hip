@@ -990,6 +990,273 @@ __global__ __launch_bounds__(GS_NT) void k_face_gs_fused(LevelDev L, const T* __
     }
 }
 
+// Streamed multicolour face sweep (plain sweep of the three-colour faces).
+// One wave per smoother tile (TI = GS_W - 2 GS_H columns from i0, GS_TJ
+// rows from j0); lane l keeps columns i0 - 3 + 3 l .. i0 - 1 + 3 l of the
+// rows it holds in registers, so that in every colour stage it updates
+// exactly one point of a row (colour (i - j) mod 3, i0 a multiple of 3).
+// Walking up the rows, at row s the wave applies the first stage to row
+// s + 2, the second to row s + 1 and the third to row s, in place: a stage
+// reads only points of the other two colours, which then hold the values
+// that separate colour passes over the whole face would give them, so row s
+// is final and is stored.  The east and west neighbours of a lane's outer
+// columns come from the neighbouring lanes by whole-wave shifts; the three
+// outer columns on each side are the strip's halo, wrong after the first
+// stage but never read by the stored columns.  Rows live in register rings
+// of NU rows (the window s - 1 .. s + 3 plus rows loaded NU - 5 steps
+// ahead; f rows s .. s + 2 plus rows loaded NU - 3 steps ahead), loaded from
+// clamped addresses so that no load is waited on before its row is used.
+// Reads uin and writes uout like the tile sweep (extra blocks copy edges and
+// vertex blocks; the face rings are stored with the rows); no LDS, no
+// barrier.  The arithmetic of a point is that of gs_point.
+template <class T>
+__device__ __forceinline__ T gs_lane_next(T v) {
+    if constexpr (sizeof(T) == 4) {
+        return __builtin_bit_cast(T, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v), 0x130, 0xf, 0xf, false));
+    } else {
+        typedef int int2v __attribute__((ext_vector_type(2)));
+        const int2v a = __builtin_bit_cast(int2v, v);
+        const int2v r = {__builtin_amdgcn_update_dpp(0, a[0], 0x130, 0xf, 0xf, false),
+                         __builtin_amdgcn_update_dpp(0, a[1], 0x130, 0xf, 0xf, false)};
+        return __builtin_bit_cast(T, r);
+    }
+}
+template <class T>
+__device__ __forceinline__ T gs_lane_prev(T v) {
+    if constexpr (sizeof(T) == 4) {
+        return __builtin_bit_cast(T, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v), 0x138, 0xf, 0xf, false));
+    } else {
+        typedef int int2v __attribute__((ext_vector_type(2)));
+        const int2v a = __builtin_bit_cast(int2v, v);
+        const int2v r = {__builtin_amdgcn_update_dpp(0, a[0], 0x138, 0xf, 0xf, false),
+                         __builtin_amdgcn_update_dpp(0, a[1], 0x138, 0xf, 0xf, false)};
+        return __builtin_bit_cast(T, r);
+    }
+}
+
+// New value of the lane's column M of row c (rows s below, nn above; k rows
+// likewise for the variable coefficient).
+template <class T, bool VARK, int M>
+__device__ __forceinline__ T gs_stream_point(const T* cot, const W7<T>& w, T invc, T fv, const T* rs,
+                                             const T* rc, const T* rn, const T* ks, const T* kc, const T* kn) {
+    const T uW = M == 0 ? gs_lane_prev(rc[2]) : rc[M == 0 ? 0 : M - 1];
+    const T uE = M == 2 ? gs_lane_next(rc[0]) : rc[M == 2 ? 2 : M + 1];
+    const T uS = rs[M], uN = rn[M];
+    const T uSE = M == 2 ? gs_lane_next(rs[0]) : rs[M == 2 ? 2 : M + 1];
+    const T uNW = M == 0 ? gs_lane_prev(rn[2]) : rn[M == 0 ? 0 : M - 1];
+    if (!VARK) return (fv - (w.e * (uE + uW) + w.n * (uN + uS) + w.se * (uSE + uNW))) * invc;
+    const T k0 = kc[M], kN = kn[M], kS = ks[M];
+    const T kW = M == 0 ? gs_lane_prev(kc[2]) : kc[M == 0 ? 0 : M - 1];
+    const T kE = M == 2 ? gs_lane_next(kc[0]) : kc[M == 2 ? 2 : M + 1];
+    const T kSE = M == 2 ? gs_lane_next(ks[0]) : ks[M == 2 ? 2 : M + 1];
+    const T kNW = M == 0 ? gs_lane_prev(kn[2]) : kn[M == 0 ? 0 : M - 1];
+    const T c0 = cot[0], c1 = cot[1], c2 = cot[2];
+    const T third = (T)(1.0 / 3.0), hf = (T)0.5;
+    const T t1 = (k0 + kE + kN) * third, t2 = (kSE + kE + k0) * third;
+    const T t3 = (kW + k0 + kNW) * third, t4 = (kS + k0 + kW) * third;
+    const T t5 = (k0 + kN + kNW) * third, t6 = (kS + kSE + k0) * third;
+    W7<T> v;
+    v.e = -hf * c2 * (t1 + t2);
+    v.w = -hf * c2 * (t3 + t4);
+    v.n = -hf * c1 * (t1 + t5);
+    v.s = -hf * c1 * (t6 + t4);
+    v.se = -hf * c0 * (t6 + t2);
+    v.nw = -hf * c0 * (t3 + t5);
+    v.c = -(v.e + v.w + v.n + v.s + v.se + v.nw);
+    return (fv - (v.e * uE + v.w * uW + v.n * uN + v.s * uS + v.se * uSE + v.nw * uNW)) / v.c;
+}
+
+template <class T>
+struct alignas(sizeof(T)) GsTrip { T v[3]; };   // a lane's three columns of a row
+
+constexpr int GS_SNT = 256;     // threads per block of the streamed sweep (independent waves)
+constexpr bool GS_STREAM = true; // plain FP32 sweeps of three-colour faces use the streamed kernel
+constexpr int GS_NU = 6;         // its register ring rows
+
+template <class T, bool VARK, bool BACK, int NU>
+__global__ __launch_bounds__(GS_SNT) void k_face_gs_stream(LevelDev L, const T* __restrict__ uin,
+                                                           T* __restrict__ uout, const T* __restrict__ f,
+                                                           const T* __restrict__ kap, int nblk) {
+    constexpr int TI = GS_W - 2 * GS_H, TJ = GS_TJ;
+    static_assert(TI % 3 == 0 && TJ % 3 == 0 && NU % 3 == 0 && NU >= 6 && NU <= 9,
+                  "colour positions repeat every three rows and the loop is written for 6 or 9 ring rows");
+    const int n = L.n;
+    if ((int)blockIdx.x >= nblk) {
+        // edge points (k = 0..n-1) and vertex blocks
+        const int cb = blockIdx.x - nblk, ncb = gridDim.x - nblk;
+        const int64_t ne = (int64_t)L.E * n, nv = (int64_t)L.V * L.vert_stride;
+        for (int64_t t = (int64_t)cb * GS_SNT + threadIdx.x; t < ne + nv; t += (int64_t)ncb * GS_SNT) {
+            const int64_t off = t < ne ? L.edge_base + (t / n) * L.edge_stride + (t % n) : L.vert_base + (t - ne);
+            uout[off] = uin[off];
+        }
+        return;
+    }
+    const int lane = threadIdx.x & 63, wv = wave_id();
+    // consecutive logical blocks on one XCD (hardware block b runs on XCD b mod 8)
+    const int b = blockIdx.x, lb = (b & 7) * (nblk >> 3) + (b >> 3);
+    const int ntl = L.n_gs_tl[0][0];
+    const int task = lb * (GS_SNT / 64) + wv;
+    if (task >= L.F * ntl) return;                      // the whole wave
+    const int face = task / ntl;
+    const FaceInfo& fi = L.faces[face];
+    if (fi.ncolours != 3) return;
+    const int2 tl = L.gs_tl[0][0][task % ntl];
+    const int i0 = tl.x * TI, j0 = tl.y * TJ;
+    const int s_end = min(j0 + TJ, n - i0);            // rows that hold a point of the strip
+    const int64_t fb = face_base(L, face);
+    const int xc = i0 - 3 + 3 * lane;                  // the lane's first column
+    const W7<T> w = face_weights<T>(OP_LAPLACE, fi, L.inv4l, (const T*)nullptr, 0, 0, 0);
+    const T invc = (T)1 / w.c;
+    // face data the rows need, read once into registers (read in divergent
+    // code they would be vector loads, and waiting for one waits for every
+    // row load in flight)
+    const T cot[3] = {(T)fi.cot[0], (T)fi.cot[1], (T)fi.cot[2]};
+    int64_t gh[3];
+    int ghr[3];
+#pragma unroll
+    for (int q = 0; q < 3; ++q) {
+        gh[q] = fi.bside[q] ? -1 : edge_ghost(L, fi.edge[q], fi.slot[q]);
+        ghr[q] = fi.rev[q];
+    }
+
+    // Row j of a field (j clamped into the face): the lane's three values in
+    // one vector load.  A lane holding a point of the row loads from its own
+    // first column (its last values may lie past the row's padding, inside
+    // the next row of the face); any other lane loads the row's first three
+    // slots.  Values outside the triangle are never read by an update or
+    // stored.
+    // The row starts of the three row streams (u and k loads, f loads,
+    // stores) advance by one row per step; a stream's row is clamped into
+    // the face (0 .. n - 1) for its start.
+    struct RowPos {
+        int j, rs;   // row and the start of clamp(j, 0, n - 1)
+    };
+    auto row_at = [&](int j) { return RowPos{j, row_start(n, min(max(j, 0), n - 1))}; };
+    auto advance = [&](RowPos& r) {
+        const int jn = r.j + 1;
+        r.rs = jn <= 0 ? 0 : (jn >= n ? r.rs : r.rs + 16 * ((n - r.j + 15) >> 4));
+        r.j = jn;
+    };
+    const T* ub = uin + fb;
+    const T* kb = VARK ? kap + fb : nullptr;
+    const T* fbp = f + fb;
+    auto load_row = [&](const T* __restrict__ base, const RowPos& r, T* v) {
+        const int st = (xc >= 0 && xc <= n - 1 - min(max(r.j, 0), n - 1)) ? xc : 0;
+        const GsTrip<T> t = *reinterpret_cast<const GsTrip<T>*>(base + r.rs + st);
+        v[0] = t.v[0];
+        v[1] = t.v[1];
+        v[2] = t.v[2];
+    };
+    // ring slot of row r: (r - s0 + 1) mod NU, for u, k and f alike
+    const int s0 = j0 - 4;
+    T ur[NU][3], kr[VARK ? NU : 1][3], fr[NU][3];
+#pragma unroll
+    for (int q = 0; q < NU; ++q)
+#pragma unroll
+        for (int m = 0; m < 3; ++m) {
+            ur[q][m] = fr[q][m] = (T)0;
+            if (VARK) kr[q][m] = (T)0;
+        }
+    RowPos pu = row_at(s0 + 1), pf = row_at(s0 + 2), ps = row_at(j0);
+#pragma unroll
+    for (int q = 2; q <= NU - 2; ++q) {                 // u (k) rows s0 + 1 .. s0 + NU - 3
+        load_row(ub, pu, ur[q]);
+        if (VARK) load_row(kb, pu, kr[VARK ? q : 0]);
+        advance(pu);
+    }
+#pragma unroll
+    for (int q = 3; q <= NU - 1; ++q) {                 // f rows s0 + 2 .. s0 + NU - 2
+        load_row(fbp, pf, fr[q]);
+        advance(pf);
+    }
+
+    auto step = [&](auto phase, int s) {
+        constexpr int P = decltype(phase)::value;
+        constexpr int SL = (P + NU - 1) % NU;           // slot of u row s - 2 (free): row s + NU - 2
+        load_row(ub, pu, ur[SL]);                       // row s + NU - 2
+        if (VARK) load_row(kb, pu, kr[VARK ? SL : 0]);
+        load_row(fbp, pf, fr[P]);                       // row s + NU - 1 into the slot of f row s - 1
+        advance(pu);
+        advance(pf);
+        if (s >= s_end) return;
+        constexpr int SM = (2 + P) % 3;                 // s mod 3 (s0 = 2 mod 3)
+        constexpr int C0 = BACK ? 2 : 0, C1 = 1, C2 = BACK ? 0 : 2;
+        auto stage = [&](auto col, auto dj) {
+            // stage of colour C on row s + DJ
+            constexpr int C = decltype(col)::value, DJ = decltype(dj)::value;
+            constexpr int M = (C + SM + DJ) % 3;       // the lane's column of colour C in that row
+            constexpr int RC = (P + DJ + 1) % NU, RS = (P + DJ) % NU, RN = (P + DJ + 2) % NU;
+            const int j = s + DJ, x = xc + M;
+            const T v = gs_stream_point<T, VARK, M>(cot, w, invc, fr[RC][M], ur[RS], ur[RC], ur[RN],
+                                                    VARK ? kr[VARK ? RS : 0] : nullptr,
+                                                    VARK ? kr[VARK ? RC : 0] : nullptr,
+                                                    VARK ? kr[VARK ? RN : 0] : nullptr);
+            // interior points only: 1 <= x <= n - 2 - j on rows 1 <= j <= n - 3
+            // (cnt = number of interior points of the row, 0 on other rows)
+            const int cnt = (j >= 1 && j <= n - 3) ? n - 2 - j : 0;
+            ur[RC][M] = (unsigned)(x - 1) < (unsigned)cnt ? v : ur[RC][M];
+        };
+        stage(std::integral_constant<int, C0>(), std::integral_constant<int, 2>());
+        if (s >= j0 - 2) stage(std::integral_constant<int, C1>(), std::integral_constant<int, 1>());
+        if (s >= j0) {
+            stage(std::integral_constant<int, C2>(), std::integral_constant<int, 0>());
+            // row s is final: store the strip's columns (lanes 1 .. 62; one
+            // vector store where all three lie in the triangle) and the
+            // near-edge copies
+            T* rp = uout + fb + ps.rs;
+            advance(ps);
+            T* row = ur[(P + 1) % NU];
+            const int xe = n - 1 - s;                   // last column of row s
+            GsTrip<T> t;
+            t.v[0] = row[0];
+            t.v[1] = row[1];
+            t.v[2] = row[2];
+            const bool mid = lane >= 1 && lane <= 62;
+            if (xe >= i0 + TI - 1) {                    // the whole strip lies in the row
+                if (mid) *reinterpret_cast<GsTrip<T>*>(rp + xc) = t;
+            } else if (mid && xc <= xe) {
+                if (xc + 2 <= xe) {
+                    *reinterpret_cast<GsTrip<T>*>(rp + xc) = t;
+                } else {
+                    rp[xc] = row[0];
+                    if (xc + 1 <= xe) rp[xc + 1] = row[1];
+                }
+            }
+            // copies in the edge ghost rows (rows j = 1, i = 1, i + j = n - 2),
+            // each behind a test that is uniform over the wave
+            if (s == 1 && gh[0] >= 0) {
+#pragma unroll
+                for (int m = 0; m < 3; ++m) {
+                    const int x = xc + m;
+                    if (mid && x <= n - 2) uout[gh[0] + (ghr[0] ? n - 2 - x : x)] = row[m];
+                }
+            }
+            if (i0 == 0 && s <= n - 2 && gh[1] >= 0) {
+                if (lane == 1) uout[gh[1] + (ghr[1] ? n - 2 - s : s)] = row[1];   // x = 1
+            }
+            if (n - 2 - s >= i0 && n - 2 - s < i0 + TI && gh[2] >= 0) {
+                const int m = n - 2 - s - xc;               // the lane holding x = n - 2 - s
+                if (m >= 0 && m < 3) uout[gh[2] + (ghr[2] ? n - 2 - s : s)] = m == 0 ? row[0] : (m == 1 ? row[1] : row[2]);
+            }
+        }
+    };
+    const int rounds = (s_end - s0 + NU - 1) / NU;
+    for (int k = 0; k < rounds; ++k) {
+        const int s = s0 + k * NU;
+        step(std::integral_constant<int, 0>(), s);
+        step(std::integral_constant<int, 1>(), s + 1);
+        step(std::integral_constant<int, 2>(), s + 2);
+        step(std::integral_constant<int, 3 % NU>(), s + 3);
+        step(std::integral_constant<int, 4 % NU>(), s + 4);
+        step(std::integral_constant<int, 5 % NU>(), s + 5);
+        if constexpr (NU == 9) {
+            step(std::integral_constant<int, 6 % NU>(), s + 6);
+            step(std::integral_constant<int, 7 % NU>(), s + 7);
+            step(std::integral_constant<int, 8 % NU>(), s + 8);
+        }
+    }
+}
+
 // The point operator of k_apply_low extended to the face points, taken from LDS tiles:
 // the smoother's TI x TJ tiles, each loaded with a one-point halo in one
 // round of independent row loads (f of the block's points into registers
@@ -2057,6 +2324,26 @@ static hipError_t gs_t(const hhg_mesh* M, int level, int op, T* x, T* y, const T
 #define HHG_FACE_LAUNCH_R(VK, TJ)                                                                   \
     k_face_gs_fused<T, VK, 3, false, TJ, 3><<<g, GS_NT, 0, s>>>(L, x, y, f, kap, backward, ntile_blocks, 1, \
                                                                Lc, uc, rout, part, fcout)
+        if constexpr (GS_STREAM && sizeof(T) == 4) if (res == 0 && !uc) {
+            // plain FP32 sweep: streamed kernel on the three-colour faces,
+            // tiles on the faces with a right angle (in FP64 the rows take
+            // twice the registers and the tile sweep is faster)
+            const int ntask = L.F * L.n_gs_tl[0][0];
+            const int nb = (int)pad_up((ntask + GS_SNT / 64 - 1) / (GS_SNT / 64), 8);
+            const int gsb = nb + GS_COPY_BLOCKS;
+#define HHG_STREAM_LAUNCH(VK)                                                                       \
+    do {                                                                                            \
+        if (backward) k_face_gs_stream<T, VK, true, GS_NU><<<gsb, GS_SNT, 0, s>>>(L, x, y, f, kap, nb);  \
+        else k_face_gs_stream<T, VK, false, GS_NU><<<gsb, GS_SNT, 0, s>>>(L, x, y, f, kap, nb);          \
+        if (has2)                                                                                   \
+            k_face_gs_fused<T, VK, 2, false, (VK && sizeof(T) == 8) ? GS_TJ16 : GS_TJ, 0>             \
+                <<<g2, GS_NT, 0, s>>>(L, x, y, f, kap, backward, ntile_blocks, 0, Lc, uc, rout, part, nullptr); \
+    } while (0)
+            if (op == OP_DIFFUSION) HHG_STREAM_LAUNCH(true);
+            else HHG_STREAM_LAUNCH(false);
+#undef HHG_STREAM_LAUNCH
+            return hipGetLastError();
+        }
         if (op == OP_DIFFUSION) {
             constexpr int TJV = sizeof(T) == 8 ? GS_TJ16 : GS_TJ;
             if (uc) HHG_FACE_LAUNCH(true, true, TJV, 0);

@@ -168,16 +168,6 @@ __device__ __forceinline__ NetFace net_face(const LevelDev& L, const FaceInfo& f
     return t;
 }
 
-// Store of an output value with its copies in the ghost rows of the face's
-// edges (near-side rows j = 1, i = 1, i + j = n - 2).
-__device__ __forceinline__ void net_store(float* __restrict__ y, const NetFace& nf, int64_t p, int n, int i,
-                                          int j, float val) {
-    y[p] = val;
-    if (j == 1 && i <= n - 2 && nf.g[0] >= 0) y[nf.g[0] + (nf.rev[0] ? n - 2 - i : i)] = val;
-    if (i == 1 && j <= n - 2 && nf.g[1] >= 0) y[nf.g[1] + (nf.rev[1] ? n - 2 - j : j)] = val;
-    if (i + j == n - 2 && nf.g[2] >= 0) y[nf.g[2] + (nf.rev[2] ? n - 2 - j : j)] = val;
-}
-
 // out at output pixel (i0 + c, j0 + r) from the z planes.
 __device__ __forceinline__ float net_out(float (*zs)[ZPS], int r, int c) {
     float o = 0.f;
@@ -535,13 +525,29 @@ __global__ __launch_bounds__(NET_NT) void k_net_step(LevelDev L, const float* __
             }
             wave_lds_order();
         }
-        if (s >= j0 && lane >= 3 && lane < 3 + NET_TI && s >= 1 && ic >= 1 && ic + s <= n - 2) {
-            // out of row s from z rows s - 1 .. s + 1
+        if (s >= j0 && s >= 1 && s <= n - 3) {
+            // out of row s (a row with interior points) from z rows s - 1 .. s + 1;
+            // every lane forms it (its z reads stay inside the wave's rings),
+            // the interior ones store it
             const float* zb = z_flat + lane;
             float o = 0.f;
 #pragma unroll
             for (int t = 0; t < 7; ++t) o += zb[t * NS_ZP + ((PH + tap_dj(t) + 3) % 3) * RW + tap_di(t)];
-            net_store(y, nf, fb + nrow_start(n, s) + ic, n, ic, s, X0 + o);
+            const float val = X0 + o;
+            const bool ok = lane >= 3 && lane < 3 + NET_TI && (unsigned)(ic - 1) < (unsigned)(n - 2 - s);
+            if (ok) y[fb + nrow_start(n, s) + ic] = val;
+            // copies in the ghost rows of the face's edges (rows j = 1, i = 1,
+            // i + j = n - 2), each behind a test that is uniform over the wave
+            if (s == 1 && nf.g[0] >= 0) {
+                if (ok) y[nf.g[0] + (nf.rev[0] ? n - 2 - ic : ic)] = val;
+            }
+            if (i0 == 0 && nf.g[1] >= 0) {
+                if (lane == 4) y[nf.g[1] + (nf.rev[1] ? n - 2 - s : s)] = val;   // i = 1
+            }
+            const int ld = n - 2 - s - i0 + 3;           // lane of i = n - 2 - s
+            if (ld >= 3 && ld < 3 + NET_TI && nf.g[2] >= 0) {
+                if (lane == ld) y[nf.g[2] + (nf.rev[2] ? n - 2 - s : s)] = val;
+            }
         }
     };
     const int rounds = (s_end - s0 + NS_U - 1) / NS_U;
