@@ -358,6 +358,7 @@ hhg::LevelDev hhg_mesh::dev(int level) const {
         }
     L.n_net_tiles = (int32_t)H.net_tiles.size();
     L.n_net_strips = (int32_t)H.net_strips.size();
+    L.net_sr = net_strip_rows(H.n);
     L.n_iedges = (int32_t)m.iedges.size();
     L.n_iverts = (int32_t)m.iverts.size();
     L.face_stride = H.face_stride;

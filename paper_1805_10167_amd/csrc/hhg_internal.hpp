@@ -35,8 +35,11 @@ constexpr int gs_tile_width(int halo) { return GS_W - 2 * halo; }
 // learned-smoother tile: NET_TI x NET_TJ output points
 constexpr int NET_TI = 58;
 constexpr int NET_TJ = 12;
-// fused learned step: one wave streams NET_SR output rows of a NET_TI-wide strip
-constexpr int NET_SR = 32;
+// fused learned step: one wave streams the output rows of a piece of a
+// NET_TI-wide strip; tall pieces on large levels (fewer start-up rows per
+// row), short ones on small levels (a wave's chain of row steps is their
+// latency)
+inline int net_strip_rows(int n) { return n >= 1025 ? 32 : (n >= 513 ? 16 : 8); }
 constexpr int COARSE_DENSE_MAXN = 2048;   // coarse systems solved with a stored inverse
 constexpr int NET_NW = 224;     // weights: W1[16][7] then W2[16][7]
 
@@ -162,7 +165,7 @@ struct LevelDev {
     int32_t level, n;
     int32_t F, E, V;
     int32_t ghost_off, ghost_stride, vert_stride;
-    int32_t ntiles, n_iedges, n_iverts, n_net_tiles, n_net_strips;
+    int32_t ntiles, n_iedges, n_iverts, n_net_tiles, n_net_strips, net_sr;
     int32_t n_gs_tl[GS_NHALO][2];    // smoother tiles per face, [halo][GS_TJ16 rows]
     int64_t face_stride, edge_stride;
     int64_t face_base, edge_base, vert_base, total;

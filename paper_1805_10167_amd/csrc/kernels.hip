@@ -1072,6 +1072,7 @@ struct alignas(sizeof(T)) GsTrip { T v[3]; };   // a lane's three columns of a r
 constexpr int GS_SNT = 256;     // threads per block of the streamed sweep (independent waves)
 constexpr bool GS_STREAM = true; // plain FP32 sweeps of three-colour faces use the streamed kernel
 constexpr int GS_NU = 6;         // its register ring rows
+constexpr int GS_STREAM_MIN = 4096;   // fewest tiles (waves) for which it is used
 
 template <class T, bool VARK, bool BACK, int NU>
 __global__ __launch_bounds__(GS_SNT) void k_face_gs_stream(LevelDev L, const T* __restrict__ uin,
@@ -2324,10 +2325,12 @@ static hipError_t gs_t(const hhg_mesh* M, int level, int op, T* x, T* y, const T
 #define HHG_FACE_LAUNCH_R(VK, TJ)                                                                   \
     k_face_gs_fused<T, VK, 3, false, TJ, 3><<<g, GS_NT, 0, s>>>(L, x, y, f, kap, backward, ntile_blocks, 1, \
                                                                Lc, uc, rout, part, fcout)
-        if constexpr (GS_STREAM && sizeof(T) == 4) if (res == 0 && !uc) {
-            // plain FP32 sweep: streamed kernel on the three-colour faces,
-            // tiles on the faces with a right angle (in FP64 the rows take
-            // twice the registers and the tile sweep is faster)
+        if constexpr (GS_STREAM && sizeof(T) == 4) if (res == 0 && !uc && L.F * L.n_gs_tl[0][0] >= GS_STREAM_MIN) {
+            // plain FP32 sweep of a large level: streamed kernel on the
+            // three-colour faces, tiles on the faces with a right angle (in
+            // FP64 the rows take twice the registers and the tile sweep is
+            // faster; on smaller levels a wave's chain of row steps is
+            // longer than a tile's load-stage-store)
             const int ntask = L.F * L.n_gs_tl[0][0];
             const int nb = (int)pad_up((ntask + GS_SNT / 64 - 1) / (GS_SNT / 64), 8);
             const int gsb = nb + GS_COPY_BLOCKS;

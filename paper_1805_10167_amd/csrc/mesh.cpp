@@ -644,12 +644,13 @@ void MeshData::build_level(int level) {
             int imin = std::max(ti * NET_TI, 1), jmin = std::max(tj * NET_TJ, 1);
             if (imin + jmin <= n - 2) H.net_tiles.push_back(make_int2(ti, tj));
         }
-    // learned-step strip pieces (NET_TI columns, NET_SR rows) that contain
-    // interior points; a strip's pieces are consecutive, top to bottom
+    // learned-step strip pieces (NET_TI columns, net_strip_rows rows) that
+    // contain interior points; a strip's pieces are consecutive, bottom to top
     H.net_strips.clear();
+    const int sr = net_strip_rows(n);
     for (int ti = 0; ti * NET_TI <= n - 3; ++ti)
-        for (int tj = 0; tj * NET_SR <= n - 3; ++tj) {
-            int imin = std::max(ti * NET_TI, 1), jmin = std::max(tj * NET_SR, 1);
+        for (int tj = 0; tj * sr <= n - 3; ++tj) {
+            int imin = std::max(ti * NET_TI, 1), jmin = std::max(tj * sr, 1);
             if (imin + jmin <= n - 2) H.net_strips.push_back(make_int2(ti, tj));
         }
 

@@ -245,7 +245,7 @@ __global__ __launch_bounds__(NET_NT) void k_net_forward(LevelDev L, const T* __r
 //   triangle), y = x + N(rho) on face-interior points, with their near-row
 //   copies in y's ghost rows.
 // One wave per strip piece: output columns i0 <= i < i0 + NET_TI and rows
-// j0 <= j < j0 + NET_SR of one face, lane c standing for column
+// j0 <= j < j0 + net_sr of one face, lane c standing for column
 // i = i0 - 3 + c.  The wave walks down the rows; at row s it
 //   - takes x of row s + 3 and f (or rho_ring) of row s + 2 from a register
 //     queue filled three rows ahead,
@@ -384,8 +384,8 @@ __global__ __launch_bounds__(NET_NT) void k_net_step(LevelDev L, const float* __
     NetRing& R = rings[wv];
     const int face = task / L.n_net_strips;
     const int2 st = L.net_strips[task % L.n_net_strips];
-    const int i0 = st.x * NET_TI, j0 = st.y * NET_SR;
-    const int s_end = min(j0 + NET_SR, n - 1 - max(i0, 1));   // last output row + 1
+    const int i0 = st.x * NET_TI, j0 = st.y * L.net_sr;
+    const int s_end = min(j0 + L.net_sr, n - 1 - max(i0, 1));   // last output row + 1
     const NetFace nf = net_face(L, L.faces[face]);
     const int64_t fb = nface_base(L, face);
     const int ic = i0 - 3 + lane;
