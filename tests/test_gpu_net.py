@@ -192,7 +192,13 @@ def test_learned_solve_rejection_and_guard():
     assert rc == 0 and st["fallback"] == 1 and st["rel_res"] <= 1e-8
 
 
-@pytest.mark.parametrize("name,L", CASES)
+# the fused step streams strip pieces of 8 rows below level 9, 16 at level 9
+# and 32 from level 10: the unit square at levels 9 and 10 (0.26M and 1M
+# unknowns) reaches the taller pieces within the oracle's reach
+SWEEP_CASES = CASES + [("square", 9), ("square", 10)]
+
+
+@pytest.mark.parametrize("name,L", SWEEP_CASES)
 @pytest.mark.parametrize("precision", ["f32", "bf16"])
 @pytest.mark.parametrize("backward", [0, 1])
 def test_net_smoother_with_random_weights(name, L, precision, backward):
