@@ -189,7 +189,27 @@ __device__ __forceinline__ void push_vertex(const LevelDev& L, T* x, const Verte
     }
 }
 
-// Copies of face point (i, j) in the ghost rows of the face's edges.
+// Where a face's near-edge rows are copied: for each side the start of the
+// edge's ghost row that holds them (-1 on a Dirichlet side) and whether the
+// edge runs against the side.  Read once per face in wave-uniform code, so
+// the pushes of lane-divergent code use registers: a per-lane load of the
+// face record there would be waited on together with every load in flight.
+struct FaceGhosts {
+    int64_t g[3];
+    int rev[3];
+};
+__device__ __forceinline__ FaceGhosts face_ghosts(const LevelDev& L, const FaceInfo& fi) {
+    FaceGhosts t;
+#pragma unroll
+    for (int s = 0; s < 3; ++s) {
+        t.g[s] = fi.bside[s] ? -1 : edge_ghost(L, fi.edge[s], fi.slot[s]);
+        t.rev[s] = fi.rev[s];
+    }
+    return t;
+}
+
+// Copies of face point (i, j) in the ghost rows of the face's edges, from
+// the face record (point loops, where most lanes never get here) ...
 template <class T>
 __device__ __forceinline__ void push_face_near(const LevelDev& L, T* x, const FaceInfo& fi, int i, int j,
                                                T val) {
@@ -200,6 +220,15 @@ __device__ __forceinline__ void push_face_near(const LevelDev& L, T* x, const Fa
         x[edge_ghost(L, fi.edge[1], fi.slot[1]) + (fi.rev[1] ? n - 2 - j : j)] = val;
     if (i + j == n - 2 && !fi.bside[2])
         x[edge_ghost(L, fi.edge[2], fi.slot[2]) + (fi.rev[2] ? n - 2 - j : j)] = val;
+}
+
+// ... or from the registers of FaceGhosts (tile kernels, which read it once
+// per tile)
+template <class T>
+__device__ __forceinline__ void push_face_near(const FaceGhosts& gh, int n, T* x, int i, int j, T val) {
+    if (j == 1 && i <= n - 2 && gh.g[0] >= 0) x[gh.g[0] + (gh.rev[0] ? n - 2 - i : i)] = val;
+    if (i == 1 && j <= n - 2 && gh.g[1] >= 0) x[gh.g[1] + (gh.rev[1] ? n - 2 - j : j)] = val;
+    if (i + j == n - 2 && gh.g[2] >= 0) x[gh.g[2] + (gh.rev[2] ? n - 2 - j : j)] = val;
 }
 
 // Face-point loop over the 64 x 4 tiles of every face, grid-stride over the

@@ -751,6 +751,7 @@ __device__ __forceinline__ void gs_tile2(const LevelDev& L, const FaceInfo& fi, 
     constexpr int H = RES ? GS_HE : GS_H;
     using G = GsTile<TJ, H>;
     const int rule = fi.colour_rule;
+    const FaceGhosts gh = face_ghosts(L, fi);
     T ur[G::RPW][3], kr[VARK ? G::RPW : 1][3], fr[2][G::IT2];
     gs_load_u<T, VARK, PROL, TJ, H>(n, i0, j0, fb, uin, kap, ur, kr, fi, pt, us);
 #pragma unroll
@@ -817,7 +818,7 @@ __device__ __forceinline__ void gs_tile2(const LevelDev& L, const FaceInfo& fi, 
                 continue;
             const T v = gs_resid<T, VARK>(fi, w, fr[s][it], us, ks, r, tx);
             rout[fb + row_start(n, j) + i] = v;
-            push_face_near(L, rout, fi, i, j, v);
+            push_face_near(gh, n, rout, i, j, v);
         }
     }
 }
@@ -1291,6 +1292,7 @@ __global__ __launch_bounds__(GS_NT) void k_apply_tiled(LevelDev L, int op, const
             const int ntl = L.n_gs_tl[0][TL];
             const int face = logical / ntl;
             const FaceInfo& fi = L.faces[face];
+            const FaceGhosts gh = face_ghosts(L, fi);
             const int2 tl = L.gs_tl[0][TL][logical % ntl];
             const int i0 = tl.x * TI - 1, j0 = tl.y * TJ - 1;   // LDS origin
             const int64_t fb = face_base(L, face);
@@ -1353,7 +1355,7 @@ __global__ __launch_bounds__(GS_NT) void k_apply_tiled(LevelDev L, int op, const
                     }
                     if (MODE == 4) continue;
                     y[fb + row_start(n, j) + i] = v;
-                    push_face_near(L, y, fi, i, j, v);
+                    push_face_near(gh, n, y, i, j, v);
                 }
             }
         }
@@ -1400,6 +1402,7 @@ __global__ __launch_bounds__(GS_NT) void k_mp_step_tiled(LevelDev L, int op, con
             const int ntl = L.n_gs_tl[0][TL];
             const int face = logical / ntl;
             const FaceInfo& fi = L.faces[face];
+            const FaceGhosts gh = face_ghosts(L, fi);
             const int2 tl = L.gs_tl[0][TL][logical % ntl];
             const int i0 = tl.x * TI - 1, j0 = tl.y * TJ - 1;
             const int64_t fb = face_base(L, face);
@@ -1454,10 +1457,10 @@ __global__ __launch_bounds__(GS_NT) void k_mp_step_tiled(LevelDev L, int op, con
                     acc += v * v;
                     const int64_t p = fb + row_start(n, j) + i;
                     r[p] = (float)v;
-                    push_face_near(L, r, fi, i, j, (float)v);
+                    push_face_near(gh, n, r, i, j, (float)v);
                     if (UPD) {
                         xo[p] = v0;
-                        push_face_near(L, xo, fi, i, j, v0);
+                        push_face_near(gh, n, xo, i, j, v0);
                     }
                 }
             }

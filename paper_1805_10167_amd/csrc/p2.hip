@@ -93,6 +93,7 @@ __global__ __launch_bounds__(P2_NT) void k_p2_face(LevelDev L, const double* __r
         const int ntl = L.n_gs_tl[0][0];
         const int face = logical / ntl;
         const FaceInfo& fi = L.faces[face];
+        const FaceGhosts gh = face_ghosts(L, fi);
         const P2Face& pf = L.p2faces[face];
         const int2 tl = L.gs_tl[0][0][logical % ntl];
         const int i0 = tl.x * P2_TI - P2_H, j0 = tl.y * P2_TJ - P2_H;   // LDS origin
@@ -164,7 +165,7 @@ __global__ __launch_bounds__(P2_NT) void k_p2_face(LevelDev L, const double* __r
                 else v = xs[r][tx] + omega * (fr[k][c] - ax) / w[0];
                 if (!(tx0 >= P2_H && tx0 < P2_H + P2_TI && j >= 1 && i >= 1 && i + j <= n - 2)) continue;
                 y[fb + row_start(n, j) + i] = v;
-                push_face_near(L, y, fi, i, j, v);
+                push_face_near(gh, n, y, i, j, v);
             }
         }
     } else {

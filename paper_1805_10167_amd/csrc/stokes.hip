@@ -118,6 +118,7 @@ __global__ __launch_bounds__(ST_NT) void k_stokes_apply(LevelDev L, const double
             const int face = tile / ntl;
             const int2 tl = L.gs_tl[0][0][tile % ntl];
             const FaceInfo& fi = L.faces[face];
+            const FaceGhosts gh = face_ghosts(L, fi);
             const int64_t fb = face_base(L, face);
             if (threadIdx.x < SB_N * 7) (&ws[0][0])[threadIdx.x] = (&L.sfaces[face].w[0][0])[threadIdx.x];
             for (int sub = 0; sub < ST_TJ / ST_SJ; ++sub) {
@@ -199,9 +200,9 @@ __global__ __launch_bounds__(ST_NT) void k_stokes_apply(LevelDev L, const double
                     yx_[p] = vx;
                     yy_[p] = vy;
                     yp_[p] = vp;
-                    push_face_near(L, yx_, fi, i, j, vx);
-                    push_face_near(L, yy_, fi, i, j, vy);
-                    push_face_near(L, yp_, fi, i, j, vp);
+                    push_face_near(gh, n, yx_, i, j, vx);
+                    push_face_near(gh, n, yy_, i, j, vy);
+                    push_face_near(gh, n, yp_, i, j, vp);
                 }
             }
             __syncthreads();                               // LDS free for the next tile
