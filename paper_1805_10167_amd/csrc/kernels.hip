@@ -1005,11 +1005,13 @@ __global__ __launch_bounds__(GS_NT) void k_face_gs_fused(LevelDev L, const T* __
 // outer columns on each side are the strip's halo, wrong after the first
 // stage but never read by the stored columns.  Rows live in register rings
 // of NU rows (the window s - 1 .. s + 3 plus rows loaded NU - 5 steps
-// ahead; f rows s .. s + 2 plus rows loaded NU - 3 steps ahead), loaded from
-// clamped addresses so that no load is waited on before its row is used.
-// Reads uin and writes uout like the tile sweep (extra blocks copy edges and
+// ahead; f rows s .. s + 2 plus rows loaded NU - 3 steps ahead), each lane's
+// three values in one vector load that is always issued (rows clamped into
+// the face), so that no load is waited on before its row is used.  Reads
+// uin and writes uout like the tile sweep (extra blocks copy edges and
 // vertex blocks; the face rings are stored with the rows); no LDS, no
-// barrier.  The arithmetic of a point is that of gs_point.
+// barrier.  The arithmetic of a point is that of gs_point.  Used for the
+// plain FP32 sweep of levels with at least GS_STREAM_MIN tiles.
 template <class T>
 __device__ __forceinline__ T gs_lane_next(T v) {
     if constexpr (sizeof(T) == 4) {
