@@ -246,9 +246,9 @@ __global__ __launch_bounds__(NET_NT) void k_net_forward(LevelDev L, const T* __r
 //   copies in y's ghost rows.
 // One wave per strip piece: output columns i0 <= i < i0 + NET_TI and rows
 // j0 <= j < j0 + net_sr of one face, lane c standing for column
-// i = i0 - 3 + c.  The wave walks down the rows; at row s it
-//   - takes x of row s + 3 and f (or rho_ring) of row s + 2 from a register
-//     queue filled three rows ahead,
+// i = i0 - 3 + c.  The wave walks up the rows; at row s it
+//   - takes x of row s + 3 and f (or rho_ring) of row s + 2 from register
+//     rings loaded NS_U - 4 rows ahead,
 //   - forms rho of row s + 2 from the x rows s + 1 .. s + 3 held in
 //     registers (east and west neighbours by whole-wave lane shifts),
 //   - forms the hidden layer and z of row s + 1 from rho rows s .. s + 2,
