@@ -416,6 +416,22 @@ __device__ __forceinline__ bool face_dirichlet(const FaceInfo& fi, int n, int i,
     return fi.bside[2];
 }
 
+// The same from a mask of the face's Dirichlet flags (bits 0-2 vertices,
+// 3-5 sides), read once per tile so that lane-divergent code tests registers.
+__device__ __forceinline__ int face_dirichlet_mask(const FaceInfo& fi) {
+    return (fi.bvtx[0] ? 1 : 0) | (fi.bvtx[1] ? 2 : 0) | (fi.bvtx[2] ? 4 : 0) | (fi.bside[0] ? 8 : 0) |
+           (fi.bside[1] ? 16 : 0) | (fi.bside[2] ? 32 : 0);
+}
+__device__ __forceinline__ bool face_dirichlet_m(int m, int n, int i, int j) {
+    if (i >= 1 && j >= 1 && i + j <= n - 2) return false;
+    if (j == 0 && i == 0) return m & 1;
+    if (j == 0 && i == n - 1) return m & 2;
+    if (i == 0 && j == n - 1) return m & 4;
+    if (j == 0) return m & 8;
+    if (i == 0) return m & 16;
+    return m & 32;
+}
+
 // Prolongation of one entry of the edge and vertex blocks (edge main
 // k = 0..n-1, vertex value and ghost slots): the value to add, 0 at
 // Dirichlet points and padding.
@@ -574,6 +590,7 @@ __device__ __forceinline__ void gs_load_u(int n, int i0, int j0, int64_t fb, con
     }
     __syncthreads();
     // linear interpolation as in prol_face, from LDS
+    const int dm = face_dirichlet_mask(fi);
 #pragma unroll
     for (int q = 0; q < GsTile<TJ, H>::RPW; ++q) {
         const int r = wv + GS_NW * q, j = j0 + r;
@@ -581,7 +598,7 @@ __device__ __forceinline__ void gs_load_u(int n, int i0, int j0, int64_t fb, con
         for (int c = 0; c < 3; ++c) {
             const int i = i0 + lane + 64 * c;
             const bool in = r < GsTile<TJ, H>::R && j >= 0 && j < n && i >= 0 && i <= n - 1 - j;
-            if (!in || face_dirichlet(fi, n, i, j)) continue;
+            if (!in || face_dirichlet_m(dm, n, i, j)) continue;
             const int I = (i >> 1) - Ilo, J = (j >> 1) - Jlo, io = i & 1, jo = j & 1;
             const T a = cs[J * CW + I + (io & jo)];
             const T b = cs[(J + jo) * CW + I + (io & (jo ^ 1))];
