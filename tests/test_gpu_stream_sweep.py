@@ -6,9 +6,12 @@ keep the tile kernel.  A 300-face annulus (50 sectors, 3 rings) at level 8
 (257 points along a macro-edge, 9.9M unknowns) has 14 such tiles per face,
 4,200 in all, so the streamed kernel runs on it; each face holds two strip
 columns, so strips meet at their halos, and the hypotenuse cuts through
-strip pieces.  Laplacian and variable coefficient, forward and backward
-order, one and two sweeps, plus an FP32 V(3,3) cycle whose finest-level
-plain sweeps are streamed.
+strip pieces.  A 100-face annulus (one ring) at level 9 (513 points, 13M
+unknowns) has 42 tiles per face, 4,200 in all, in three strip columns, with
+tiles that touch neither a macro-edge nor the diagonal.  Laplacian and
+variable coefficient, forward and backward order, one and two sweeps, plus
+an FP32 V(3,3) cycle on the level-8 mesh whose finest-level plain sweeps
+are streamed.
 
 Inputs are FP32-representable, so only the kernel's FP32 arithmetic differs
 from the oracle's FP64.  A point update rounds a sum of seven products and a
@@ -26,8 +29,8 @@ from gpu_util import F32_VCYCLE_TOL, log, rel_err, to_np
 
 pytestmark = pytest.mark.gpu
 
-L = 8
-N_TAN, N_RAD = 50, 3
+MESHES = [(8, 3), (9, 1)]   # (level, rings of the 50-sector annulus)
+N_TAN = 50
 SWEEP_TOL = 2e-6
 APPLY_TOL = 2e-5
 _CACHE = {}
@@ -40,14 +43,16 @@ def tiles_per_face(n, ti_w=186, tj_h=24):
                and ti * ti_w + tj * tj_h <= n - 1)
 
 
-def setup(op):
+def setup(op, L, n_rad):
     import torch
 
     import paper_1805_10167_amd as P
     from oracle.mesh import Level, MacroMesh
     from oracle.mg import Hierarchy
-    if op not in _CACHE:
-        vxy, tri = hi.annulus(n_tan=N_TAN, n_rad=N_RAD)
+    key = (op, L, n_rad)
+    if key not in _CACHE:
+        _CACHE.clear()                      # one hierarchy at a time
+        vxy, tri = hi.annulus(n_tan=N_TAN, n_rad=n_rad)
         m = MacroMesh(vxy, tri)
         kap = None
         if op == "diffusion":
@@ -58,8 +63,8 @@ def setup(op):
         g = P.Mesh(vxy, tri, L, 2, feats)
         if kap is not None:
             P.hhg_set_coefficient(g.h, torch.tensor(kap, dtype=torch.float64, device="cuda"))
-        _CACHE[op] = (g, H)
-    return _CACHE[op]
+        _CACHE[key] = (g, H)
+    return _CACHE[key]
 
 
 def f32_vector(n, seed):
@@ -70,19 +75,39 @@ def _op(P, op):
     return P.HHG_OP_LAPLACE if op == "laplace" else P.HHG_OP_DIFFUSION
 
 
-def test_level_runs_the_streamed_kernel():
-    """The mesh is above the streamed kernel's tile threshold."""
-    n = 2 ** L + 1
-    assert tiles_per_face(n) == 14
-    assert 2 * N_TAN * N_RAD * tiles_per_face(n) >= 4096
+def test_levels_run_the_streamed_kernel():
+    """Both meshes are above the streamed kernel's tile threshold."""
+    assert tiles_per_face(2 ** 8 + 1) == 14 and tiles_per_face(2 ** 9 + 1) == 42
+    for L, n_rad in MESHES:
+        assert 2 * N_TAN * n_rad * tiles_per_face(2 ** L + 1) >= 4096
 
 
-@pytest.mark.parametrize("op", ["laplace", "diffusion"])
-@pytest.mark.parametrize("backward,sweeps", [(0, 1), (1, 1), (0, 2), (1, 2)])
-def test_streamed_sweep(op, backward, sweeps):
+def test_streamed_vcycle():
+    """On the level-8 mesh (collected before the sweeps, which reuse its
+    hierarchy)."""
     import paper_1805_10167_amd as P
-    log("streamed FP32 sweep %s bwd=%d sweeps=%d" % (op, backward, sweeps))
-    g, H = setup(op)
+    L, n_rad = MESHES[0]
+    log("FP32 V(3,3) with streamed finest-level sweeps, level %d rings %d" % (L, n_rad))
+    g, H = setup("laplace", L, n_rad)
+    lv = H.levels[L]
+    u, f = f32_vector(lv.n_all, 13), f32_vector(lv.n_all, 14)
+    uf, ff = g.from_canonical(L, u, P.HHG_F32), g.from_canonical(L, f, P.HHG_F32)
+    P.hhg_vcycle(g.h, L, P.HHG_OP_LAPLACE, P.HHG_SMOOTH_GS, P.HHG_F32, uf, ff, 3, 3)
+    err = rel_err(to_np(g.to_canonical(L, uf, P.HHG_F32)), H.vcycle(L, u.copy(), f, 3, 3))
+    log("  rel err %.2e" % err)
+    assert err <= F32_VCYCLE_TOL
+
+
+# mesh by mesh and operator by operator, so that each hierarchy is built once
+SWEEP_CASES = [(L, n_rad, op, bw, sw) for L, n_rad in MESHES for op in ("laplace", "diffusion")
+               for bw, sw in ((0, 1), (1, 1), (0, 2), (1, 2))]
+
+
+@pytest.mark.parametrize("L,n_rad,op,backward,sweeps", SWEEP_CASES)
+def test_streamed_sweep(L, n_rad, op, backward, sweeps):
+    import paper_1805_10167_amd as P
+    log("streamed FP32 sweep level %d rings %d %s bwd=%d sweeps=%d" % (L, n_rad, op, backward, sweeps))
+    g, H = setup(op, L, n_rad)
     lv = H.levels[L]
     u, f = f32_vector(lv.n_all, 11), f32_vector(lv.n_all, 12)
     uf, ff = g.from_canonical(L, u, P.HHG_F32), g.from_canonical(L, f, P.HHG_F32)
@@ -98,16 +123,3 @@ def test_streamed_sweep(op, backward, sweeps):
     y = g.field(L, P.HHG_F32)
     P.hhg_apply(g.h, L, _op(P, op), P.HHG_F32, uf, y)
     assert rel_err(to_np(g.to_canonical(L, y, P.HHG_F32)), H.apply(L, got)) <= APPLY_TOL
-
-
-def test_streamed_vcycle():
-    import paper_1805_10167_amd as P
-    log("FP32 V(3,3) with streamed finest-level sweeps")
-    g, H = setup("laplace")
-    lv = H.levels[L]
-    u, f = f32_vector(lv.n_all, 13), f32_vector(lv.n_all, 14)
-    uf, ff = g.from_canonical(L, u, P.HHG_F32), g.from_canonical(L, f, P.HHG_F32)
-    P.hhg_vcycle(g.h, L, P.HHG_OP_LAPLACE, P.HHG_SMOOTH_GS, P.HHG_F32, uf, ff, 3, 3)
-    err = rel_err(to_np(g.to_canonical(L, uf, P.HHG_F32)), H.vcycle(L, u.copy(), f, 3, 3))
-    log("  rel err %.2e" % err)
-    assert err <= F32_VCYCLE_TOL
