@@ -1147,22 +1147,25 @@ __global__ __launch_bounds__(GS_SNT) void k_face_gs_stream(LevelDev L, const T* 
     // slots.  Values outside the triangle are never read by an update or
     // stored.
     // The row starts of the three row streams (u and k loads, f loads,
-    // stores) advance by one row per step; a stream's row is clamped into
-    // the face (0 .. n - 1) for its start.
+    // stores) advance by one row per step; a stream's row is clamped to
+    // 0 .. jm for its start, where jm is the last row the stream needs (the
+    // loop runs whole rounds and loads ahead, so without the cap a tile
+    // would fetch up to five rows of the next tile from memory; with it,
+    // those steps reload the cap row, which the cache still holds).
     struct RowPos {
-        int j, rs;   // row and the start of clamp(j, 0, n - 1)
+        int j, rs, jm;   // row, the start of clamp(j, 0, jm), the cap
     };
-    auto row_at = [&](int j) { return RowPos{j, row_start(n, min(max(j, 0), n - 1))}; };
+    auto row_at = [&](int j, int jm) { return RowPos{j, row_start(n, min(max(j, 0), jm)), jm}; };
     auto advance = [&](RowPos& r) {
         const int jn = r.j + 1;
-        r.rs = jn <= 0 ? 0 : (jn >= n ? r.rs : r.rs + 16 * ((n - r.j + 15) >> 4));
+        r.rs = jn <= 0 ? 0 : (jn > r.jm ? r.rs : r.rs + 16 * ((n - r.j + 15) >> 4));
         r.j = jn;
     };
     const T* ub = uin + fb;
     const T* kb = VARK ? kap + fb : nullptr;
     const T* fbp = f + fb;
     auto load_row = [&](const T* __restrict__ base, const RowPos& r, T* v) {
-        const int st = (xc >= 0 && xc <= n - 1 - min(max(r.j, 0), n - 1)) ? xc : 0;
+        const int st = (xc >= 0 && xc <= n - 1 - min(max(r.j, 0), r.jm)) ? xc : 0;
         const GsTrip<T> t = *reinterpret_cast<const GsTrip<T>*>(base + r.rs + st);
         v[0] = t.v[0];
         v[1] = t.v[1];
@@ -1178,7 +1181,10 @@ __global__ __launch_bounds__(GS_SNT) void k_face_gs_stream(LevelDev L, const T* 
             ur[q][m] = fr[q][m] = (T)0;
             if (VARK) kr[q][m] = (T)0;
         }
-    RowPos pu = row_at(s0 + 1), pf = row_at(s0 + 2), ps = row_at(j0);
+    // the last rows read: stage 1 runs up to row s_end + 1, reading u of
+    // the row above and f of its own row
+    RowPos pu = row_at(s0 + 1, min(s_end + 2, n - 1)), pf = row_at(s0 + 2, min(s_end + 1, n - 1));
+    RowPos ps = row_at(j0, n - 1);
 #pragma unroll
     for (int q = 2; q <= NU - 2; ++q) {                 // u (k) rows s0 + 1 .. s0 + NU - 3
         load_row(ub, pu, ur[q]);
