@@ -451,8 +451,8 @@ def stokes_section(args, P, hi, torch):
     the inner and 100 in the outer ring of faces, buoyancy forcing -T r_hat
     with T a seeded Gaussian random field (correlation length 0.1, sigma 1),
     velocity zero on both boundaries; MINRES with the block-diagonal
-    preconditioner (one V(2,2) cycle per velocity component, lumped 1/mu
-    pressure mass) to a relative residual of 1e-8 in the preconditioner's
+    preconditioner (one V(2,2) cycle per velocity component; pressure block
+    the lumped 1/mu mass plus 4 diag(C)) to a relative residual of 1e-8 in the preconditioner's
     norm, FP64 and FP32 velocity cycles.  Also the Stokes operator's rate."""
     L = args.stokes_level
     vxy, tri = hi.mesh_by_name("annulus128")
@@ -474,7 +474,7 @@ def stokes_section(args, P, hi, torch):
                        "r = 0.775, buoyancy -T r_hat (GRF seed 500), zero velocity on the boundary"
                        % L,
            "dofs": {"velocity": 2 * n_int, "pressure": n_all, "total": 2 * n_int + n_all},
-           "solver": "MINRES, blockdiag(V(2,2) per velocity component, lumped 1/mu pressure mass), "
+           "solver": "MINRES, blockdiag(V(2,2) per velocity component, lumped 1/mu pressure mass + 4 diag(C)), "
                      "rtol 1e-8 in the preconditioner's norm, coarse level 2", "delta": STOKES_DELTA}
     res = {}
     for name, prec in (("plain_fp64", P.HHG_F64), ("fp32_precond", P.HHG_F32)):

@@ -438,13 +438,17 @@ int hhg_set_face_coefficient(hhg_mesh* mesh, const double* coef, void* stream);
  * hhg_stokes_precond: z = P^-1 r on the finest level, P^-1 = blockdiag(one
  *   V(nu1, nu2) cycle of the viscous operator from zero per velocity
  *   component, in FP64 or FP32 (`precision`), division of the pressure by
- *   the lumped mass matrix weighted with 1/mu).
+ *   the diagonal matrix S = M_l + 4 diag(C): M_l the lumped mass matrix
+ *   weighted with 1/mu, C the stabilisation block.  The paper names a
+ *   block-diagonal multigrid preconditioner for MINRES (sec. 4.3) but not
+ *   its pressure block: the exact Schur complement is B A^-1 B^T + C, and
+ *   the C term cut MINRES steps by about a quarter).
  * hhg_stokes_dot: *out (device double) = a . b over every owned point of
  *   the three fields, summed in a fixed order.
  * hhg_stokes_solve: MINRES from the caller's x (b: right-hand side, its
  *   velocity entries at Dirichlet points ignored) until the residual in the
  *   P^-1 norm has fallen by opts->rtol; the pressure correction keeps a zero
- *   mean weighted with the preconditioner's pressure mass.  Synchronises the
+ *   mean weighted with the preconditioner's pressure block S.  Synchronises the
  *   stream once per iteration to read that norm.  HHG_ENOTCONV at the cap
  *   (x holds the last iterate; stats are filled in every case).
  * Errors: HHG_ENOMEM without HHG_FEAT_STOKES, HHG_EINVAL before setup or

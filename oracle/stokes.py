@@ -25,8 +25,15 @@ as a preconditioner.  The paper gives no parameters; the readings are:
   * preconditioner: blockdiag(V_A, V_A, S^-1) with V_A one V(nu1, nu2) cycle
     of the mu-weighted Laplacian from a zero start (forward stages before,
     backward stages after the coarse correction: a symmetric operator) and
-    S = the lumped mass matrix weighted with 1/mu (the usual spectral
-    equivalent of the pressure Schur complement);
+    S the diagonal matrix m + sigma_C diag(C): m the lumped mass matrix
+    weighted with 1/mu (the usual spectral equivalent of the pressure Schur
+    complement B A^-1 B^T), plus the diagonal of the stabilisation block,
+    which the Schur complement of the stabilised system also contains
+    (S_exact = B A^-1 B^T + C).  C's eigenvalues reach several times its
+    diagonal on oscillating pressures, hence the weight sigma_C = 4 (a
+    measured choice: on the 64-face annulus at level 5 with the 1:100
+    viscosity jump, sigma_C = 0, 1, 2, 3, 5, 8 took 197, 166, 155, 149,
+    143, 140 MINRES steps to 1e-8);
   * MINRES: the Lanczos process of the preconditioned operator with a QR
     factorisation of its tridiagonal matrix by Givens rotations; the stopping
     test is on the residual measured in the norm of the inverse
@@ -42,6 +49,7 @@ from .assemble import micro_triangle_faces, micro_triangles
 from .mg import Hierarchy
 
 DELTA = 1.0 / 12.0
+SIGMA_C = 4.0
 
 
 def face_viscosity(mesh, r_jump=0.775, mu_in=1.0, mu_out=100.0):
@@ -105,6 +113,7 @@ class Stokes:
         self.N = self.lv.n_all
         b = assemble_stokes(self.lv, mu_face, delta)
         self.A, self.Bx, self.By, self.C, self.m = b["A"], b["Bx"], b["By"], b["C"], b["m"]
+        self.s = self.m + SIGMA_C * self.C.diagonal()   # pressure block of the preconditioner
         self.dir = self.lv.dirichlet
 
     def split(self, x):
@@ -124,11 +133,11 @@ class Stokes:
 
     def precond(self, r):
         """z = P^-1 r: one V(nu1, nu2) cycle per velocity component from
-        zero, the pressure divided by the lumped 1/mu-weighted mass."""
+        zero, the pressure divided by m + sigma_C diag(C)."""
         rx, ry, rp = self.split(r)
         zx = self.H.vcycle(self.L, np.zeros(self.N), rx, *self.nu)
         zy = self.H.vcycle(self.L, np.zeros(self.N), ry, *self.nu)
-        return np.concatenate([zx, zy, rp / self.m])
+        return np.concatenate([zx, zy, rp / self.s])
 
     def rhs(self, fx, fy):
         """Load vector of nodal body-force values: (M f_x, M f_y, 0), zero at
@@ -207,9 +216,9 @@ def minres(apply, precond, b, x0, rtol=1e-8, max_iters=500, dot=np.dot):
 
 
 def pressure_mean_free(st, x):
-    """x with its pressure shifted to a zero m-weighted mean (the kernel
-    direction of K removed)."""
+    """x with its pressure shifted to a zero mean weighted with the
+    preconditioner's pressure block s (the kernel direction of K removed)."""
     x = x.copy()
     p = x[2 * st.N:]
-    p -= (st.m @ p) / st.m.sum()
+    p -= (st.s @ p) / st.s.sum()
     return x

@@ -317,7 +317,8 @@ namespace {
 //   BX[r][b]  = -int_T psi_r d phi_b / dx = -|T|/3 d phi_b / dx  (pressure row r)
 //   BXT[r][a] = BX[a][r] = -|T|/3 d phi_r / dx                    (velocity row r)
 //   C[r][b]   = delta h_T^2 / mu |T| grad phi_r . grad phi_b, h_T the longest edge
-//   m        += |T| / (3 mu)  (lumped 1/mu-weighted mass)
+//   m        += |T| / (3 mu)  (lumped 1/mu-weighted mass; the caller adds
+//               a multiple of C's centre weight afterwards)
 template <int W>
 void add_triangle(const double P[3][2], int r, const int slot[3], double mu, double delta,
                   double (&w)[SB_N][W], double& m) {
@@ -594,6 +595,15 @@ void MeshData::stokes_tables(double delta) {
             add_triangle<1 + MAXDEG>(P, 0, slot, face_coef[f], delta, sv.w, sv.m);
         }
     }
+    // Pressure block of the preconditioner: the exact Schur complement of the
+    // stabilised system is B A^-1 B^T + C.  The lumped mass stands for the
+    // first term; the diagonal of C, weighted by kStabWeight because C's
+    // largest eigenvalues are several times its diagonal on oscillating
+    // pressures, stands for the second.  The centre is slot 0 everywhere.
+    constexpr double kStabWeight = 4.0;
+    for (StokesFace& sf : sfaces) sf.m += kStabWeight * sf.w[SB_C][0];
+    for (StokesEdge& se : sedges) se.m += kStabWeight * se.w[SB_C][0];
+    for (StokesVert& sv : sverts) sv.m += kStabWeight * sv.w[SB_C][0];
 }
 
 void MeshData::build_level(int level) {

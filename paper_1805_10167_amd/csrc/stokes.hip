@@ -301,7 +301,8 @@ __global__ __launch_bounds__(NT) void k_stokes_apply_low(LevelDev L, const doubl
 }
 
 // Pressure block of the preconditioner, z_p = r_p / m (m: lumped mass
-// weighted with 1/mu, at level scale hC), with every copy of z_p, and
+// weighted with 1/mu plus 4 times the centre weight of the stabilisation C,
+// at level scale hC), with every copy of z_p, and
 // per-block sums of r . z over owned points of all three fields (the
 // velocity parts of z are already in place).
 __global__ __launch_bounds__(NT) void k_stokes_pscale_dot(LevelDev L, const double* __restrict__ r,

@@ -211,7 +211,7 @@ def test_minres_solve_to_tolerance(name, L):
         assert err <= 1e-5
         # velocity boundary data untouched, pressure mean (weighted) zero
         assert np.array_equal(xg[:st.N][st.dir], np.zeros(st.dir.sum()))
-        assert abs(st.m @ xg[2 * st.N:]) <= 1e-9 * np.abs(st.m * xg[2 * st.N:]).sum()
+        assert abs(st.s @ xg[2 * st.N:]) <= 1e-9 * np.abs(st.s * xg[2 * st.N:]).sum()
 
 
 def test_stokes_errors():

@@ -93,6 +93,25 @@ def test_lumped_pressure_mass_integrates_one_over_mu():
     assert (bl["m"] > 0).all()
 
 
+@pytest.mark.parametrize("level", [3, 4])
+def test_pressure_block_of_the_preconditioner_in_closed_form(level):
+    """On the unit square every interior point sits in six right isosceles
+    micro-triangles with legs h = 2^-level: lumped mass 6 (h^2/2) / 3 = h^2,
+    P1 stiffness diagonal 4, longest edge sqrt(2) h, so diag(C) =
+    (1/12) 2 h^2 4 = 2 h^2 / 3 and the pressure block m + 4 diag(C) is
+    11 h^2 / 3 (mu = 1)."""
+    st = S.Stokes(mesh("square"), level, 1)
+    h2 = 4.0 ** -level
+    inner = ~st.dir
+    assert inner.sum() == (2 ** level - 1) ** 2
+    assert np.abs(st.m[inner] - h2).max() <= 1e-14
+    assert np.abs(st.s[inner] - 11.0 * h2 / 3.0).max() <= 1e-14
+    # the preconditioner divides the pressure by that block
+    e = np.zeros(3 * st.N)
+    e[2 * st.N:] = 1.0
+    assert np.abs(st.precond(e)[2 * st.N:][inner] - 3.0 / (11.0 * h2)).max() <= 1e-12 / h2
+
+
 @pytest.mark.parametrize("name,level", [("annulus64", 2), ("square", 3)])
 def test_stokes_matrix_is_symmetric_with_a_constant_pressure_kernel(name, level):
     st = S.Stokes(mesh(name), level, 1, S.face_viscosity(mesh(name)) if name != "square" else None)
@@ -184,7 +203,7 @@ def test_minres_converges_to_the_direct_solution():
     rhs[k0] = 0.0
     xd = S.pressure_mean_free(st, spla.spsolve(K.tocsc(), rhs))
     # MINRES keeps the weighted pressure mean at zero by itself
-    assert abs(st.m @ x[2 * st.N:]) <= 1e-10 * np.abs(st.m * x[2 * st.N:]).sum()
+    assert abs(st.s @ x[2 * st.N:]) <= 1e-10 * np.abs(st.s * x[2 * st.N:]).sum()
     assert np.abs(x - xd).max() <= 1e-8 * np.abs(xd).max()
 
 
@@ -235,7 +254,7 @@ def test_manufactured_stokes_velocity_error_falls_as_h_squared():
                         max_iters=1000)
         x = S.pressure_mean_free(st, x)
         eu = max(np.abs(x[:st.N] - ux).max(), np.abs(x[st.N:2 * st.N] - uy).max())
-        pm = p - (st.m @ p) / st.m.sum()
+        pm = p - (st.s @ p) / st.s.sum()
         ep = np.abs(x[2 * st.N:] - pm).max()
         if prev is not None:
             ratios.append(prev[0] / eu)
