@@ -119,8 +119,6 @@ struct VertexInfo {
 //   BXT gradient (x part) = transpose of BX, velocity row, pressure neighbours
 //   BYT gradient (y part), velocity row, pressure neighbours
 //   C   pressure stabilisation, pressure row, pressure neighbours
-// m is the pressure block of the block-diagonal preconditioner at unit
-// scale: the lumped 1/mu-weighted mass plus 4 times the centre weight of C.
 enum { SB_A = 0, SB_BX = 1, SB_BY = 2, SB_BXT = 3, SB_BYT = 4, SB_C = 5, SB_N = 6 };
 // face-interior point: neighbours C, E, W, N, S, SE, NW of face-local (i, j)
 struct StokesFace { double w[SB_N][7]; double m; };
