@@ -19,6 +19,10 @@ path computes:
                 prolongation, Jacobi-PCG coarse solve, V-cycle, solve loop
                 (sec. 4.3)
   net.py        the learned smoother's forward/backward (not in the paper)
+  partition.py  the same level stored as one block per macro-primitive with
+                explicit ghost copies and a packer for the four exchange
+                directions (sec. 2.2, Alg. 3), checked against the global
+                vector
   stokes.py     equal-order P1-P1 Stokes with pressure stabilisation, the
                 block-diagonal multigrid preconditioner and preconditioned
                 MINRES (sec. 4.3, 5.2)
