@@ -84,6 +84,13 @@ def summarize(stats_dir, fetch_dir, write_dir, kernel, copy_bytes, cmd, source="
     kf, kw = _largest(fetch, kernel), _largest(write, kernel)
     cf, cw = _largest(fetch, COPY_KERNEL), _largest(write, COPY_KERNEL)
     mean = lambda v: sum(v) / len(v)
+    for tab, key, name in ((fetch, cf, "FETCH_SIZE"), (write, cw, "WRITE_SIZE")):
+        # the calibration copy must be the only copy of its grid in the run:
+        # copies of other sizes on the same grid would skew the scale
+        if max(tab[key]) > 1.01 * min(tab[key]):
+            raise ValueError("%s of the copy dispatches on grid %d ranges from %.0f to %.0f KiB: the run holds "
+                             "copies other than the calibration copy; profile without them"
+                             % (name, key[1], min(tab[key]), max(tab[key])))
     fetch_scale = copy_bytes / (mean(fetch[cf]) * 1024.0)
     write_scale = copy_bytes / (mean(write[cw]) * 1024.0)
     fetch_b = mean(fetch[kf]) * 1024.0 * fetch_scale
